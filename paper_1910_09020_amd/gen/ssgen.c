@@ -1,0 +1,334 @@
+/*
+ * Seeded synthetic workloads for the SneakySnake filter.
+ *
+ * This module only produces inputs: DNA read/reference pairs over {A,C,G,T}
+ * as ASCII bytes, their lengths and thresholds.  It contains none of the
+ * filter's arithmetic and is shared, as an input source only, by the GPU
+ * library's tests/benchmarks and by the CPU oracle's tests.
+ *
+ * Randomness: every pair (and every serving request) owns an independent
+ * SplitMix64 stream (Steele, Lea & Flood, OOPSLA 2014): the stream state is
+ * initialised from the finaliser of (seed, stream id) and advanced by the
+ * golden-ratio increment, so any pair can be regenerated alone and the
+ * output does not depend on the number of threads.
+ *
+ * Edit model for a "k-edit" reference: k events are drawn, each with a type,
+ * a position on the read (substitutions and deletions: one of the m bases;
+ * insertions: one of the m+1 gaps) and, for indels, a length.  Events are
+ * applied in one left-to-right pass in position order; events that fall in a
+ * span already deleted are dropped.  A substitution writes one of the three
+ * other bases; insertions write uniform bases.  The edited string is then cut
+ * or padded (uniform bases) at its 3' end to exactly m.  The read is the
+ * query Q, the edited string is the reference R.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <math.h>
+#include <pthread.h>
+
+static const uint8_t BASES[4] = {'A', 'C', 'G', 'T'};
+
+static inline uint64_t mix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+typedef struct { uint64_t s; } rng_t;
+
+static inline rng_t rng_stream(uint64_t seed, uint64_t stream)
+{
+    rng_t r;
+    r.s = mix64(mix64(seed ^ 0x5EED5EED5EED5EEDULL) + (stream + 1) * 0x9E3779B97F4A7C15ULL);
+    return r;
+}
+
+static inline uint64_t rng_next(rng_t* r)
+{
+    r->s += 0x9E3779B97F4A7C15ULL;
+    return mix64(r->s);
+}
+
+/* uniform integer in [0, n) by the multiply-shift reduction */
+static inline uint64_t rng_below(rng_t* r, uint64_t n)
+{
+    return (uint64_t)(((unsigned __int128)rng_next(r) * n) >> 64);
+}
+
+static inline double rng_unit(rng_t* r) { return (double)(rng_next(r) >> 11) * (1.0 / 9007199254740992.0); }
+
+static void rand_bases(rng_t* r, uint8_t* dst, int64_t n)
+{
+    int64_t i = 0;
+    while (i < n) {
+        uint64_t x = rng_next(r);
+        for (int b = 0; b < 32 && i < n; b++, i++) { dst[i] = BASES[x & 3]; x >>= 2; }
+    }
+}
+
+/* Poisson(lambda) by Knuth's product-of-uniforms method (small lambda). */
+static int rng_poisson(rng_t* r, double lambda)
+{
+    double L = exp(-lambda), p = 1.0;
+    int k = 0;
+    do { k++; p *= rng_unit(r); } while (p > L);
+    return k - 1;
+}
+
+/* Geometric(1/2) on {1,2,...}: one plus the number of failures. */
+static int rng_geom_half(rng_t* r)
+{
+    int len = 1;
+    for (;;) {
+        uint64_t x = rng_next(r);
+        for (int b = 0; b < 64; b++) { if (x & 1) return len; len++; x >>= 1; }
+    }
+}
+
+typedef struct { int32_t pos; int32_t type; int32_t len; int32_t ord; } edit_ev;
+enum { EV_SUB = 0, EV_INS = 1, EV_DEL = 2 };
+
+static int ev_cmp(const void* a, const void* b)
+{
+    const edit_ev* x = (const edit_ev*)a; const edit_ev* y = (const edit_ev*)b;
+    if (x->pos != y->pos) return x->pos < y->pos ? -1 : 1;
+    return x->ord < y->ord ? -1 : (x->ord > y->ord);
+}
+
+/* Apply sorted events to read[0..m) producing exactly m bases in out. */
+static void apply_events(rng_t* r, const uint8_t* read, int m, edit_ev* ev, int k, uint8_t* out)
+{
+    if (k > 1) qsort(ev, (size_t)k, sizeof(edit_ev), ev_cmp);
+    int o = 0, i = 0, e = 0;
+    while (o < m && (i < m || e < k)) {
+        if (e < k && ev[e].pos <= i) {
+            edit_ev* v = &ev[e++];
+            if (v->pos < i) continue;                 /* fell inside a deleted span */
+            if (v->type == EV_INS) {
+                for (int t = 0; t < v->len && o < m; t++) out[o++] = BASES[rng_below(r, 4)];
+            } else if (v->type == EV_DEL) {
+                i += v->len;
+            } else if (i < m) {                        /* substitution: one of the 3 others */
+                int code = 0;
+                while (BASES[code] != read[i]) code++;
+                out[o++] = BASES[(code + 1 + (int)rng_below(r, 3)) & 3];
+                i++;
+            }
+            continue;
+        }
+        if (i >= m) break;
+        out[o++] = read[i++];
+    }
+    if (o < m) rand_bases(r, out + o, m - o);
+}
+
+/* ---------------------------------------------------------------------------
+ * Configurations (all sizes are defaults; n can be overridden).
+ *  0: n pairs, m=100, k~U{0..10}, types 1/3 each, length-1 indels.
+ *  1: m=100; 40% k~U{0..3}, 40% k~U{4..15}, 20% unrelated (exact counts, shuffled).
+ *  2: m=250; k=min(Poisson(8),40); 20% unrelated (exact count, shuffled).
+ *  3: mixed: short pairs m~U{100,150,250} with config 1's mix, k bounds scaled
+ *     by m/100; plus long pairs (m=10000) at an edit rate ~U[500,1500] basis
+ *     points, round(rate*m/1e4) events, half substitutions, half indels
+ *     (insertion/deletion equally likely) of Geometric(1/2) length; per-pair
+ *     E = ceil(bpE*m/1e4) with bpE ~ U{100,200,500,1000} (integer arithmetic).
+ * Categories: 0 low-edit, 1 high-edit, 2 unrelated, 3 long.
+ * ------------------------------------------------------------------------- */
+enum { CAT_LOW = 0, CAT_HIGH = 1, CAT_UNREL = 2, CAT_LONG = 3 };
+
+int64_t ssgen_default_pairs(int config)
+{
+    switch (config) {
+    case 0: return 10000;
+    case 1: return 30000000;
+    case 2: return 10000000;
+    case 3: return 5020000;
+    default: return -1;
+    }
+}
+
+static int ceil_bp(int bp, int m) { return (int)(((int64_t)bp * m + 9999) / 10000); }
+
+static void shuffle_u8(uint8_t* a, int64_t n, uint64_t seed)
+{
+    rng_t r = rng_stream(seed, 0xFFFFFFFFFFFFULL);
+    for (int64_t i = n - 1; i > 0; i--) {
+        int64_t j = (int64_t)rng_below(&r, (uint64_t)(i + 1));
+        uint8_t t = a[i]; a[i] = a[j]; a[j] = t;
+    }
+}
+
+/* Per-pair plan: category, length and (config 3) threshold.  E_out gets -1
+ * for configs whose threshold is swept by the caller.  Returns 0 or -1. */
+int ssgen_plan(int config, uint64_t seed, int64_t n, int64_t n_long, uint8_t* cat, int32_t* len, int32_t* E_out)
+{
+    if (n < 0 || config < 0 || config > 3) return -1;
+    int64_t a = 0, b = 0;
+    if (config == 0) { for (int64_t i = 0; i < n; i++) cat[i] = CAT_LOW; }
+    else if (config == 1 || config == 3) {
+        int64_t ns = config == 3 ? n - n_long : n;
+        if (ns < 0) return -1;
+        a = ns * 2 / 5; b = ns * 4 / 5;
+        for (int64_t i = 0; i < n; i++)
+            cat[i] = i < a ? CAT_LOW : (i < b ? CAT_HIGH : (i < ns ? CAT_UNREL : CAT_LONG));
+        shuffle_u8(cat, n, seed);
+    } else {
+        a = n * 4 / 5;
+        for (int64_t i = 0; i < n; i++) cat[i] = i < a ? CAT_LOW : CAT_UNREL;
+        shuffle_u8(cat, n, seed);
+    }
+    static const int SHORT_M[3] = {100, 150, 250};
+    static const int BP_E[4] = {100, 200, 500, 1000};
+    for (int64_t i = 0; i < n; i++) {
+        rng_t r = rng_stream(seed, (uint64_t)i);
+        int m, E = -1;
+        if (config == 0 || config == 1) m = 100;
+        else if (config == 2) m = 250;
+        else {
+            m = cat[i] == CAT_LONG ? 10000 : SHORT_M[rng_below(&r, 3)];
+            E = ceil_bp(BP_E[rng_below(&r, 4)], m);
+        }
+        len[i] = m;
+        if (E_out) E_out[i] = E;
+    }
+    return 0;
+}
+
+/* Fill one pair; rng r continues the pair's stream after the plan draws. */
+static void fill_pair(int config, rng_t* r, uint8_t category, int m, uint8_t* Q, uint8_t* R, edit_ev* ev, int evcap)
+{
+    rand_bases(r, Q, m);
+    if (category == CAT_UNREL) { rand_bases(r, R, m); return; }
+    int k = 0;
+    int indel_geom = 0;
+    if (config == 0) k = (int)rng_below(r, 11);
+    else if (config == 1) k = category == CAT_LOW ? (int)rng_below(r, 4) : 4 + (int)rng_below(r, 12);
+    else if (config == 2) { k = rng_poisson(r, 8.0); if (k > 40) k = 40; }
+    else if (category == CAT_LONG) {
+        int bp = 500 + (int)rng_below(r, 1001);
+        k = (int)(((int64_t)bp * m + 5000) / 10000);
+        indel_geom = 1;
+    } else {
+        int lo_hi = (3 * m + 50) / 100, hi_lo = (4 * m + 50) / 100, hi_hi = (15 * m + 50) / 100;
+        k = category == CAT_LOW ? (int)rng_below(r, (uint64_t)lo_hi + 1)
+                                : hi_lo + (int)rng_below(r, (uint64_t)(hi_hi - hi_lo + 1));
+    }
+    if (k > evcap) k = evcap;
+    for (int e = 0; e < k; e++) {
+        edit_ev* v = &ev[e];
+        v->ord = e; v->len = 1;
+        if (indel_geom) {
+            if (rng_below(r, 2) == 0) v->type = EV_SUB;
+            else { v->type = rng_below(r, 2) == 0 ? EV_INS : EV_DEL; v->len = rng_geom_half(r); }
+        } else v->type = (int)rng_below(r, 3);
+        v->pos = (int)rng_below(r, (uint64_t)(v->type == EV_INS ? m + 1 : m));
+    }
+    apply_events(r, Q, m, ev, k, R);
+}
+
+typedef struct {
+    int config; uint64_t seed; int64_t lo, hi;
+    const uint8_t* cat; const int64_t* off; const int32_t* len;
+    uint8_t* reads; uint8_t* refs;
+} fill_job;
+
+static void* fill_worker(void* arg)
+{
+    fill_job* J = (fill_job*)arg;
+    int evcap = 4096;
+    edit_ev* ev = (edit_ev*)malloc(sizeof(edit_ev) * (size_t)evcap);
+    for (int64_t i = J->lo; i < J->hi; i++) {
+        rng_t r = rng_stream(J->seed, (uint64_t)i);
+        if (J->config == 3) { (void)rng_next(&r); (void)rng_next(&r); }   /* plan draws */
+        fill_pair(J->config, &r, J->cat[i], J->len[i], J->reads + J->off[i], J->refs + J->off[i], ev, evcap);
+    }
+    free(ev);
+    return NULL;
+}
+
+int ssgen_fill(int config, uint64_t seed, int64_t n, const uint8_t* cat, const int64_t* off,
+               const int32_t* len, uint8_t* reads, uint8_t* refs, int threads)
+{
+    if (config < 0 || config > 3 || n < 0) return -1;
+    if (threads < 1) threads = 1;
+    if (threads > 64) threads = 64;
+    if (n < 4096) threads = 1;
+    fill_job jobs[64];
+    pthread_t tid[64];
+    for (int t = 0; t < threads; t++) {
+        fill_job* J = &jobs[t];
+        J->config = config; J->seed = seed; J->lo = n * t / threads; J->hi = n * (t + 1) / threads;
+        J->cat = cat; J->off = off; J->len = len; J->reads = reads; J->refs = refs;
+    }
+    if (threads == 1) fill_worker(&jobs[0]);
+    else {
+        for (int t = 0; t < threads; t++) pthread_create(&tid[t], NULL, fill_worker, &jobs[t]);
+        for (int t = 0; t < threads; t++) pthread_join(tid[t], NULL);
+    }
+    return 0;
+}
+
+/* ---------------------------------------------------------------------------
+ * Serving workload: Poisson arrivals; each request owns stream (seed, id).
+ * Request: pairs = floor(exp(U(0, ln 4097))) clipped to [1, max_pairs];
+ * per-pair length floor(exp(U(ln 100, ln 10001))) clipped to [min_len, max_len];
+ * one E rate in basis points ~U{100..1000} per request, E = ceil(bp*m/1e4);
+ * pairs follow the long-pair edit model above.
+ * ------------------------------------------------------------------------- */
+int64_t ssgen_arrivals(uint64_t seed, double rate, double duration, double* t_out, int64_t cap)
+{
+    rng_t r = rng_stream(seed, 0xA771A1ULL);
+    double t = 0.0;
+    int64_t n = 0;
+    for (;;) {
+        double u = rng_unit(&r);
+        t += -log(1.0 - u) / rate;
+        if (t >= duration) break;
+        if (t_out && n < cap) t_out[n] = t;
+        n++;
+    }
+    return n;
+}
+
+int32_t ssgen_request_pairs(uint64_t seed, int64_t req, int32_t max_pairs)
+{
+    rng_t r = rng_stream(seed ^ 0x5E4B1C0ULL, (uint64_t)req);
+    int32_t n = (int32_t)floor(exp(rng_unit(&r) * log(4097.0)));
+    if (n < 1) n = 1;
+    if (n > max_pairs) n = max_pairs;
+    return n;
+}
+
+/* lengths and E for the request's n pairs; returns the request's total bases */
+int64_t ssgen_request_plan(uint64_t seed, int64_t req, int32_t n, int32_t min_len, int32_t max_len,
+                           int32_t* len, int32_t* E)
+{
+    rng_t r = rng_stream(seed ^ 0x5E4B1C0ULL, (uint64_t)req);
+    (void)rng_next(&r);                                   /* pair-count draw */
+    int bp = 100 + (int)rng_below(&r, 901);
+    int64_t tot = 0;
+    for (int32_t i = 0; i < n; i++) {
+        int m = (int)floor(exp(log(100.0) + rng_unit(&r) * (log(10001.0) - log(100.0))));
+        if (m < min_len) m = min_len;
+        if (m > max_len) m = max_len;
+        len[i] = m;
+        E[i] = ceil_bp(bp, m);
+        tot += m;
+    }
+    return tot;
+}
+
+int ssgen_request_fill(uint64_t seed, int64_t req, int32_t n, const int64_t* off, const int32_t* len,
+                       uint8_t* reads, uint8_t* refs)
+{
+    int evcap = 4096;
+    edit_ev* ev = (edit_ev*)malloc(sizeof(edit_ev) * (size_t)evcap);
+    for (int32_t i = 0; i < n; i++) {
+        rng_t r = rng_stream(seed ^ ((uint64_t)req * 0x100000001B3ULL), (uint64_t)i);
+        fill_pair(3, &r, CAT_LONG, len[i], reads + off[i], refs + off[i], ev, evcap);
+    }
+    free(ev);
+    return 0;
+}

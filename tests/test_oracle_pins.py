@@ -1,0 +1,198 @@
+"""Pins for the CPU oracle, independent of the oracle's own formulas.
+
+Each check ties the oracle to something the paper or plain mathematics fixes:
+the paper's worked example (Fig. 1 and Fig. 2 captions), Theorem 2 (greedy
+reaches the minimum obstacle count over all signal nets, checked against an
+exhaustive search), the lower-bound contract of Sections 1 and 2.1 (count <=
+edit distance, hence 0% false rejects, checked against Levenshtein DP, itself
+pinned by brute force), and special cases with textbook answers.
+"""
+import itertools
+from collections import deque
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1910_09020_amd import gen
+
+BASES = np.frombuffer(b"ACGT", dtype=np.uint8)
+
+
+def all_pairs(m):
+    """Every (read, ref) pair over {A,C,G,T}^m, concatenated."""
+    k = 4 ** m
+    idx = np.arange(k)
+    digits = np.stack([(idx >> (2 * t)) & 3 for t in range(m)], axis=1) if m else np.zeros((k, 0), int)
+    strings = BASES[digits]                       # k x m
+    a = np.repeat(strings, k, axis=0)             # read
+    b = np.tile(strings, (k, 1))                  # ref
+    n = k * k
+    return dict(reads=a.reshape(-1).copy(), refs=b.reshape(-1).copy(),
+                offsets=np.arange(n, dtype=np.int64) * m, lengths=np.full(n, m, np.int32), n=n,
+                A=a, B=b)
+
+
+# --------------------------------------------------------------------------- worked example
+
+def test_fig2_count_and_decision(golden_fig2):
+    R, Q, E = golden_fig2["R"][0], golden_fig2["Q"][0], int(golden_fig2["E"][0])
+    acc, n = oracle.pair(R, Q, E)
+    assert n == int(golden_fig2["obstacles"][0])
+    assert acc == int(golden_fig2["accept"][0])
+
+
+def test_fig2_column6(golden_fig2):
+    R, Q, E = golden_fig2["R"][0], golden_fig2["Q"][0], int(golden_fig2["E"][0])
+    col = [oracle.cell(R, Q, E, i, 6) for i in range(1, 2 * E + 2)]
+    assert col == [int(v) for v in golden_fig2["column6"]]
+
+
+def test_fig1_net_shape(golden_fig2):
+    R, Q, E = golden_fig2["R"][0], golden_fig2["Q"][0], int(golden_fig2["E"][0])
+    z = oracle.maze(R, Q, E)
+    assert z.shape == (int(golden_fig2["rows"][0]), int(golden_fig2["cols"][0]))
+    acc, n, segs = oracle.pair(R, Q, E, segments=True)
+    assert len(segs) == int(golden_fig2["segments"][0])
+    # each segment ends in an obstacle on its own row
+    for row, end in segs:
+        assert z[row - 1, end - 1] == 1
+    # first->second through a via (row change), second->third on the same track
+    assert segs[0][0] != segs[1][0]
+    assert segs[1][0] == segs[2][0]
+    assert segs[-1][1] == len(R)      # the last obstacle sits in the last column and counts
+
+
+# --------------------------------------------------------------------------- Levenshtein pinned by brute force
+
+def _bfs_dist(src, alphabet="ACGT", maxlen=4):
+    """Unit-cost edit distance from src to every string of length <= maxlen by BFS."""
+    dist = {src: 0}
+    dq = deque([src])
+    while dq:
+        s = dq.popleft()
+        d = dist[s]
+        nbrs = []
+        for i in range(len(s)):
+            nbrs.append(s[:i] + s[i + 1:])
+            for c in alphabet:
+                if c != s[i]:
+                    nbrs.append(s[:i] + c + s[i + 1:])
+        if len(s) < maxlen:
+            for i in range(len(s) + 1):
+                for c in alphabet:
+                    nbrs.append(s[:i] + c + s[i:])
+        for t in nbrs:
+            if t not in dist:
+                dist[t] = d + 1
+                dq.append(t)
+    return dist
+
+
+def test_levenshtein_textbook():
+    assert oracle.levenshtein("kitten", "sitting") == 3
+    assert oracle.levenshtein("flaw", "lawn") == 2
+    assert oracle.levenshtein("", "ACGT") == 4
+    assert oracle.levenshtein("GATTACA", "GATTACA") == 0
+    assert oracle.levenshtein("ACGT", "TGCA") == 4
+
+
+def test_levenshtein_brute_force():
+    strings = ["".join(p) for L in range(0, 4) for p in itertools.product("ACGT", repeat=L)]
+    for s in strings:
+        dist = _bfs_dist(s)
+        for t in strings:
+            assert oracle.levenshtein(s, t) == dist[t], (s, t)
+
+
+# --------------------------------------------------------------------------- exhaustive properties on tiny inputs
+
+@pytest.mark.parametrize("m", [1, 2, 3, 4])
+def test_exhaustive_tiny(m):
+    d = all_pairs(m)
+    ed = oracle.levenshtein_batch(d["reads"], d["refs"], d["offsets"], d["lengths"])
+    equal = np.all(d["A"] == d["B"], axis=1)
+    ham = np.sum(d["A"] != d["B"], axis=1)
+    rev = all_pairs(m)
+    rev_reads = d["A"][:, ::-1].reshape(-1).copy()
+    rev_refs = d["B"][:, ::-1].reshape(-1).copy()
+    prev_full = None
+    for E in range(0, 5):
+        tr = oracle.batch(d["reads"], d["refs"], d["offsets"], d["lengths"], E=E)
+        full = oracle.batch(d["reads"], d["refs"], d["offsets"], d["lengths"], E=E, stop_early=False)
+        opt = oracle.min_obstacles_batch(d["reads"], d["refs"], d["offsets"], d["lengths"], E=E)
+        n = full["edits"]
+        # Theorem 2: the greedy net has the minimum number of obstacles
+        np.testing.assert_array_equal(n, opt)
+        # the early stop of step 4 reports min(full count, E+1)
+        np.testing.assert_array_equal(tr["edits"], np.minimum(n, E + 1))
+        np.testing.assert_array_equal(tr["accept"], (n <= E).astype(np.uint8))
+        # lower bound on the edit distance for every pair within the threshold,
+        # hence no similar pair is rejected; the reported (stopped) count never
+        # exceeds the edit distance at all
+        assert np.all(n[ed <= E] <= ed[ed <= E])
+        assert np.all(tr["edits"] <= ed)
+        assert np.all(tr["accept"][ed <= E] == 1)
+        # main diagonal alone is a net: count <= Hamming distance
+        assert np.all(n <= ham)
+        # zero obstacles exactly for identical sequences
+        np.testing.assert_array_equal(n == 0, equal)
+        if E == 0:
+            np.testing.assert_array_equal(tr["accept"] == 1, equal)
+        # more rows can only lengthen runs
+        if prev_full is not None:
+            assert np.all(n <= prev_full)
+        prev_full = n
+        # reversing both sequences reverses every run: same count
+        rv = oracle.batch(rev_reads, rev_refs, rev["offsets"], rev["lengths"], E=E, stop_early=False)
+        np.testing.assert_array_equal(rv["edits"], n)
+
+
+def test_exhaustive_m5_theorem2():
+    d = all_pairs(5)
+    for E in (0, 1, 2, 3):
+        full = oracle.batch(d["reads"], d["refs"], d["offsets"], d["lengths"], E=E, stop_early=False)
+        opt = oracle.min_obstacles_batch(d["reads"], d["refs"], d["offsets"], d["lengths"], E=E)
+        np.testing.assert_array_equal(full["edits"], opt)
+
+
+# --------------------------------------------------------------------------- special cases
+
+def test_edge_cases():
+    assert oracle.pair("", "", 3) == (1, 0)               # empty pair: nothing to cross
+    assert oracle.pair("A", "A", 0) == (1, 0)
+    assert oracle.pair("A", "C", 0) == (0, 1)
+    assert oracle.pair("A", "C", 5) == (1, 1)               # E > m: rows beyond m are all obstacles
+    assert oracle.pair("AAAA", "CCCC", 1) == (0, 2)          # all-mismatch: one obstacle per column until E+1
+    assert oracle.pair("AAAA", "CCCC", 10, stop_early=False) == (1, 4)
+    # a single substitution in the last column is counted (obstacle at column m)
+    assert oracle.pair("ACGTACGT", "ACGTACGA", 0) == (0, 1)
+    assert oracle.pair("ACGTACGT", "ACGTACGA", 1) == (1, 1)
+    # a one-base shift: the shifted diagonal carries the run, the edge costs one
+    assert oracle.pair("ACGTTGCA", "CGTTGCAG", 1) == (1, 1)
+    assert oracle.pair("ACGTTGCA", "CGTTGCAG", 0) == (0, 1)
+
+
+def test_case_folding():
+    assert oracle.pair("acgtAC", "ACGTac", 0) == (1, 0)
+
+
+# --------------------------------------------------------------------------- generated workload, lower-bound contract
+
+def test_config0_lower_bound():
+    d = gen.make(0)
+    tr = oracle.batch(d["reads"], d["refs"], d["offsets"], d["lengths"], E=5)
+    full = oracle.batch(d["reads"], d["refs"], d["offsets"], d["lengths"], E=5, stop_early=False)
+    ed = oracle.levenshtein_batch(d["reads"], d["refs"], d["offsets"], d["lengths"])
+    assert np.all(tr["edits"] <= ed)
+    assert np.all(full["edits"][ed <= 5] <= ed[ed <= 5])
+    assert np.all(tr["accept"][ed <= 5] == 1)          # 0% false rejects
+    np.testing.assert_array_equal(tr["edits"], np.minimum(full["edits"], 6))
+
+
+def test_threads_do_not_change_results():
+    d = gen.make(1, n=20000)
+    a = oracle.batch(d["reads"], d["refs"], d["offsets"], d["lengths"], E=4, threads=1)
+    b = oracle.batch(d["reads"], d["refs"], d["offsets"], d["lengths"], E=4, threads=4)
+    np.testing.assert_array_equal(a["edits"], b["edits"])
+    np.testing.assert_array_equal(a["accept"], b["accept"])
