@@ -1,0 +1,181 @@
+/*
+ * ss.h -- C ABI of the MI355X SneakySnake pre-alignment filter (libss.so).
+ *
+ * The filter follows the problem statement of Alser et al., "SneakySnake: a
+ * fast and accurate universal genome pre-alignment filter for CPUs, GPUs and
+ * FPGAs": given a reference R[1..m], a query Q[1..m] and an edit threshold E
+ * (a number of tolerated character differences, Section 2.3), build the
+ * (2E+1) x m chip maze of Equation 1 and walk it greedily (Section 2.4,
+ * steps 1-5).  The number of obstacles on the net found is a lower bound on
+ * the edit distance for every pair whose edit distance is <= E (Section 2.1,
+ * Theorem 2); the pair is accepted (alignment needed) when that number is
+ * <= E and rejected otherwise.  The walk stops as soon as the count exceeds
+ * E, so a rejected pair reports E+1.
+ *
+ * Conventions for every entry point:
+ *  - "reads" are the queries Q, "refs" the references R.  Maze columns index
+ *    R; the count is not symmetric in R and Q, and the library never swaps
+ *    them.
+ *  - Pairs are concatenated: pair i occupies [offsets[i], offsets[i] +
+ *    lengths[i]) in both reads and refs (equal lengths).  Bytes must be one of
+ *    A C G T a c g t; anything else is SS_EBASE.
+ *  - Every function returns an ss_status.  No C++ exception crosses the ABI.
+ *  - Validation (null pointers, counts, lengths, thresholds, alphabet) runs
+ *    before any output is written: on a validation error the outputs are left
+ *    untouched.  After SS_EDEVICE the outputs are unspecified.
+ *  - n_pairs == 0 is valid and returns SS_OK without touching the device.
+ *  - Host pointers are owned by the caller and are not retained after the
+ *    call returns.  Device pointers passed to the asynchronous *_async entry
+ *    points must stay valid until the work enqueued on the given stream has
+ *    completed; the caller synchronises.
+ *  - A context is not thread-safe; use one per host thread.
+ *  - There is no CPU fallback: without a usable gfx950 device every entry
+ *    point that needs one returns SS_EDEVICE.
+ */
+#ifndef SS_H
+#define SS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SS_OK = 0,
+    SS_EINVAL = -1,       /* null pointer, negative count, bad flag or threshold */
+    SS_EBASE = -2,        /* a byte outside ACGTacgt in reads or refs */
+    SS_ELEN = -3,         /* a length or threshold beyond what the kernel supports */
+    SS_ENOMEM = -4,       /* device or pinned allocation failed */
+    SS_EBUDGET = -5,      /* a serving request alone exceeds the HBM budget */
+    SS_EDEVICE = -6,      /* HIP runtime error or no usable device */
+    SS_EAGAIN = -7,       /* serving: result not ready yet / queue full */
+    SS_ETIMEOUT = -8      /* serving: wait deadline passed */
+} ss_status;
+
+/* Human-readable name of a status code (static string). */
+const char* ss_status_str(int status);
+
+/* Library limits. */
+#define SS_MAX_E_SLICED   32      /* lane-sliced kernel: 0 <= E <= 32 */
+#define SS_MAX_E_PLAIN    31      /* one-pair-per-lane kernel: 0 <= E <= 31 */
+#define SS_MAX_E          16383   /* any path: counts must fit 14 bits */
+#define SS_MAX_LEN        (1 << 24)
+
+/* Device result word, one per pair: bit 15 = accept, bits 0..14 = obstacle
+ * count reported by the walk (min(count, E+1)). */
+#define SS_RESULT_ACCEPT  0x8000u
+#define SS_RESULT_COUNT   0x7FFFu
+
+/* ------------------------------------------------------------------------
+ * ss_filter_batch -- the one-call host API.
+ * Synchronous; host pointers in and out; uses HIP device 0 of the process
+ * (or the device made current with hipSetDevice before the first call).
+ *   reads, refs : n_pairs concatenated sequences (see conventions), host.
+ *   lengths     : n_pairs lengths, 0 <= lengths[i] <= SS_MAX_LEN, host.
+ *   E           : threshold for every pair, 0 <= E <= SS_MAX_E.
+ *   accept_out  : n_pairs bytes, 1 = accept (alignment needed), 0 = reject.
+ *   edits_out   : n_pairs obstacle counts, min(count, E+1).
+ * Internally: copy to HBM, encode (2-bit planes), filter, copy back.
+ * ---------------------------------------------------------------------- */
+int ss_filter_batch(const uint8_t* reads, const uint8_t* refs, const int32_t* lengths,
+                    int64_t n_pairs, int32_t E, uint8_t* accept_out, int32_t* edits_out);
+
+/* Same, with a threshold per pair (E_per_pair[i] in [0, SS_MAX_E]). */
+int ss_filter_batch_var(const uint8_t* reads, const uint8_t* refs, const int32_t* lengths,
+                        const int32_t* E_per_pair, int64_t n_pairs,
+                        uint8_t* accept_out, int32_t* edits_out);
+
+/* ------------------------------------------------------------------------
+ * Context: owns device scratch, the plan/work-queue buffers of the batched
+ * path and the tuning table.  Bound to one HIP device.
+ * ---------------------------------------------------------------------- */
+typedef struct ss_ctx ss_ctx;
+int ss_create(ss_ctx** out, int hip_device);
+int ss_destroy(ss_ctx* ctx);
+
+/* ------------------------------------------------------------------------
+ * Lane-sliced layout (equal-length pairs).
+ *
+ * n_pairs pairs of common length m are encoded with base code A=0 C=1 G=2
+ * T=3 split into a low-bit plane and a high-bit plane, transposed so that
+ * bit s of a 32-bit word belongs to pair 32*g + s ("group" g).  Planes are
+ * ordered Q0, Q1, R0, R1; positions are grouped in chunks of four; the word
+ * for (plane p, position j, group g) sits at index
+ *     ((p * ceil(m/4) + j/4) * G + g) * 4 + j%4,   G = ceil(n_pairs/32),
+ * so that 64 lanes reading group-consecutive chunks read 1 KiB contiguous.
+ * Slots of the last group beyond n_pairs are encoded as all-'A' pairs.
+ * ---------------------------------------------------------------------- */
+
+/* Bytes of a lane-sliced buffer for n_pairs pairs of length m. */
+int64_t ss_sliced_bytes(int64_t n_pairs, int32_t m);
+
+/* Encode into the lane-sliced layout.  All pointers are device pointers.
+ *   reads, refs : ASCII, pair i at offsets[i] (or at i*m when offsets is
+ *                 NULL); every selected pair must have length m.
+ *   index       : optional n_pairs pair indices (slot s encodes pair
+ *                 index[s]); NULL selects pairs 0..n_pairs-1.
+ *   packed      : ss_sliced_bytes(n_pairs, m) bytes, written in full.
+ *   err         : one device uint32; bit 0 is OR-ed in when a byte outside
+ *                 ACGTacgt is seen (the caller zeroes it beforehand).
+ * Asynchronous on stream. */
+int ss_pack_sliced_async(ss_ctx* ctx, const uint8_t* reads, const uint8_t* refs,
+                         const int64_t* offsets, const int64_t* index, int64_t n_pairs, int32_t m,
+                         uint32_t* packed, uint32_t* err, void* stream);
+
+/* Filter a lane-sliced buffer with threshold E (0 <= E <= SS_MAX_E_SLICED);
+ * writes n_pairs result words (see SS_RESULT_*) to out (device), in slot
+ * order.  Asynchronous on stream.  This is the column-sweep kernel: every
+ * lane advances 32 pairs by one maze column per step (Equation 1 cells for
+ * all 2E+1 rows, the longest-run test of Section 2.4 as "no row still free
+ * since the checkpoint"). */
+int ss_filter_sliced_async(ss_ctx* ctx, const uint32_t* packed, int64_t n_pairs, int32_t m,
+                           int32_t E, uint16_t* out, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Bit-stream layout (any lengths).
+ *
+ * Four planes (Q0, Q1, R0, R1), each a little-endian stream of total_bases
+ * bits: base b of the concatenation is bit b%32 of word b/32.  Each plane
+ * occupies ss_stream_words(total_bases) 32-bit words (two guard words
+ * included); plane p starts at word p * ss_stream_words(total_bases).
+ * ---------------------------------------------------------------------- */
+int64_t ss_stream_words(int64_t total_bases);
+
+/* Encode the concatenated ASCII reads/refs (device) into bit streams
+ * (device, 4 * ss_stream_words(total_bases) words).  err as above. */
+int ss_pack_stream_async(ss_ctx* ctx, const uint8_t* reads, const uint8_t* refs,
+                         int64_t total_bases, uint32_t* packed, uint32_t* err, void* stream);
+
+/* One pair per lane (the granularity of the paper's GPU design, Section
+ * 2.6): each lane builds its pair's 2E+1 rows one 32-column word at a time
+ * (Equation 1 as XOR/OR masks) and runs the greedy walk of Section 2.4 on
+ * them.  0 <= E <= SS_MAX_E_PLAIN.  offsets/lengths are device arrays.
+ * E_per_pair (device, may be NULL) overrides E pair by pair; then every
+ * E_per_pair[i] must be <= E, which bounds the rows built. */
+int ss_filter_plain_async(ss_ctx* ctx, const uint32_t* packed, int64_t total_bases,
+                          const int64_t* offsets, const int32_t* lengths,
+                          const int32_t* E_per_pair, int64_t n_pairs, int32_t E,
+                          uint16_t* out, void* stream);
+
+/* Wavefront-cooperative filter: one or more pairs per 64-lane wavefront,
+ * the 2E+1 rows spread over lanes as 32-row bit slices; every column is
+ * one step of the sweep and a wavefront ballot decides whether any row is
+ * still free since the checkpoint.  Any E up to SS_MAX_E.  Arguments as
+ * ss_filter_plain_async (E is the per-launch maximum when E_per_pair is
+ * given). */
+int ss_filter_wave_async(ss_ctx* ctx, const uint32_t* packed, int64_t total_bases,
+                         const int64_t* offsets, const int32_t* lengths,
+                         const int32_t* E_per_pair, int64_t n_pairs, int32_t E,
+                         uint16_t* out, void* stream);
+
+/* Expand device result words into accept bytes and int32 counts (device). */
+int ss_unpack_results_async(ss_ctx* ctx, const uint16_t* results, int64_t n_pairs,
+                            uint8_t* accept_out, int32_t* edits_out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SS_H */

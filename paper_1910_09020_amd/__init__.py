@@ -1,0 +1,195 @@
+"""MI355X SneakySnake pre-alignment filter: Python binding of libss.so.
+
+Argument marshalling only: every step of the filter runs in the HIP kernels of
+``libss.so`` (see ``include/ss.h`` for the C ABI).  The functions below carry
+the C names and forward to them through ctypes; device buffers are passed as
+raw pointers or as torch tensors (their ``data_ptr()``), streams as raw HIP
+stream handles or ``torch.cuda.Stream`` objects.
+
+There is no CPU fallback: if ``libss.so`` has not been built this module raises
+on first use.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libss.so")
+
+SS_OK, SS_EINVAL, SS_EBASE, SS_ELEN, SS_ENOMEM, SS_EBUDGET, SS_EDEVICE, SS_EAGAIN, SS_ETIMEOUT = (
+    0, -1, -2, -3, -4, -5, -6, -7, -8)
+SS_MAX_E_SLICED = 32
+SS_MAX_E_PLAIN = 31
+SS_MAX_E = 16383
+SS_RESULT_ACCEPT = 0x8000
+SS_RESULT_COUNT = 0x7FFF
+
+_lib = None
+
+
+class SSError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {status_str(status)}")
+
+
+def lib():
+    """The loaded libss.so (raises when it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1910_09020_amd.build` "
+                           "(there is no CPU fallback)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    sig = {
+        "ss_status_str": ([ctypes.c_int], ctypes.c_char_p),
+        "ss_filter_batch": ([vp, vp, vp, i64, i32, vp, vp], ctypes.c_int),
+        "ss_filter_batch_var": ([vp, vp, vp, vp, i64, vp, vp], ctypes.c_int),
+        "ss_create": ([ctypes.POINTER(vp), ctypes.c_int], ctypes.c_int),
+        "ss_destroy": ([vp], ctypes.c_int),
+        "ss_sliced_bytes": ([i64, i32], i64),
+        "ss_stream_words": ([i64], i64),
+        "ss_pack_sliced_async": ([vp, vp, vp, vp, vp, i64, i32, vp, vp, vp], ctypes.c_int),
+        "ss_filter_sliced_async": ([vp, vp, i64, i32, i32, vp, vp], ctypes.c_int),
+        "ss_pack_stream_async": ([vp, vp, vp, i64, vp, vp, vp], ctypes.c_int),
+        "ss_filter_plain_async": ([vp, vp, i64, vp, vp, vp, i64, i32, vp, vp], ctypes.c_int),
+        "ss_filter_wave_async": ([vp, vp, i64, vp, vp, vp, i64, i32, vp, vp], ctypes.c_int),
+        "ss_unpack_results_async": ([vp, vp, i64, vp, vp, vp], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def exported_symbols():
+    """Names of the C entry points this binding declares."""
+    return ["ss_status_str", "ss_filter_batch", "ss_filter_batch_var", "ss_create", "ss_destroy",
+            "ss_sliced_bytes", "ss_stream_words", "ss_pack_sliced_async", "ss_filter_sliced_async",
+            "ss_pack_stream_async", "ss_filter_plain_async", "ss_filter_wave_async", "ss_unpack_results_async"]
+
+
+def status_str(status: int) -> str:
+    try:
+        return lib().ss_status_str(status).decode()
+    except Exception:
+        return f"status {status}"
+
+
+def _ptr(x):
+    """Raw address of a device/host buffer: int, None, torch tensor or numpy array."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if hasattr(x, "data_ptr"):
+        return x.data_ptr()
+    if isinstance(x, np.ndarray):
+        return x.ctypes.data
+    raise TypeError(f"cannot take the address of {type(x)!r}")
+
+
+def _stream(s):
+    if s is None:
+        return None
+    if isinstance(s, int):
+        return s
+    if hasattr(s, "cuda_stream"):
+        return s.cuda_stream
+    raise TypeError(f"not a stream: {type(s)!r}")
+
+
+def _check(rc: int, where: str):
+    if rc != SS_OK:
+        raise SSError(rc, where)
+
+
+# ---------------------------------------------------------------- one-call host API
+def ss_filter_batch(reads, refs, lengths, E: int):
+    """Filter host pairs (numpy uint8 reads/refs, int32 lengths); returns (accept uint8[n], edits int32[n])."""
+    reads = np.ascontiguousarray(reads, dtype=np.uint8)
+    refs = np.ascontiguousarray(refs, dtype=np.uint8)
+    lengths = np.ascontiguousarray(lengths, dtype=np.int32)
+    n = len(lengths)
+    acc = np.zeros(n, dtype=np.uint8)
+    ed = np.zeros(n, dtype=np.int32)
+    rc = lib().ss_filter_batch(_ptr(reads), _ptr(refs), _ptr(lengths), n, int(E), _ptr(acc), _ptr(ed))
+    _check(rc, "ss_filter_batch")
+    return acc, ed
+
+
+def ss_filter_batch_var(reads, refs, lengths, E_per_pair):
+    reads = np.ascontiguousarray(reads, dtype=np.uint8)
+    refs = np.ascontiguousarray(refs, dtype=np.uint8)
+    lengths = np.ascontiguousarray(lengths, dtype=np.int32)
+    Epp = np.ascontiguousarray(E_per_pair, dtype=np.int32)
+    n = len(lengths)
+    acc = np.zeros(n, dtype=np.uint8)
+    ed = np.zeros(n, dtype=np.int32)
+    rc = lib().ss_filter_batch_var(_ptr(reads), _ptr(refs), _ptr(lengths), _ptr(Epp), n, _ptr(acc), _ptr(ed))
+    _check(rc, "ss_filter_batch_var")
+    return acc, ed
+
+
+# ---------------------------------------------------------------- context and device entry points
+def ss_create(device: int = 0) -> int:
+    h = ctypes.c_void_p()
+    _check(lib().ss_create(ctypes.byref(h), int(device)), "ss_create")
+    return h.value
+
+
+def ss_destroy(ctx: int) -> None:
+    _check(lib().ss_destroy(ctx), "ss_destroy")
+
+
+def ss_sliced_bytes(n_pairs: int, m: int) -> int:
+    return int(lib().ss_sliced_bytes(int(n_pairs), int(m)))
+
+
+def ss_stream_words(total_bases: int) -> int:
+    return int(lib().ss_stream_words(int(total_bases)))
+
+
+def ss_pack_sliced_async(ctx, reads, refs, offsets, index, n_pairs, m, packed, err, stream=None):
+    _check(lib().ss_pack_sliced_async(ctx, _ptr(reads), _ptr(refs), _ptr(offsets), _ptr(index), int(n_pairs),
+                                      int(m), _ptr(packed), _ptr(err), _stream(stream)), "ss_pack_sliced_async")
+
+
+def ss_filter_sliced_async(ctx, packed, n_pairs, m, E, out, stream=None):
+    _check(lib().ss_filter_sliced_async(ctx, _ptr(packed), int(n_pairs), int(m), int(E), _ptr(out),
+                                        _stream(stream)), "ss_filter_sliced_async")
+
+
+def ss_pack_stream_async(ctx, reads, refs, total_bases, packed, err, stream=None):
+    _check(lib().ss_pack_stream_async(ctx, _ptr(reads), _ptr(refs), int(total_bases), _ptr(packed), _ptr(err),
+                                      _stream(stream)), "ss_pack_stream_async")
+
+
+def ss_filter_plain_async(ctx, packed, total_bases, offsets, lengths, E_per_pair, n_pairs, E, out, stream=None):
+    _check(lib().ss_filter_plain_async(ctx, _ptr(packed), int(total_bases), _ptr(offsets), _ptr(lengths),
+                                       _ptr(E_per_pair), int(n_pairs), int(E), _ptr(out), _stream(stream)),
+           "ss_filter_plain_async")
+
+
+def ss_filter_wave_async(ctx, packed, total_bases, offsets, lengths, E_per_pair, n_pairs, E, out, stream=None):
+    _check(lib().ss_filter_wave_async(ctx, _ptr(packed), int(total_bases), _ptr(offsets), _ptr(lengths),
+                                      _ptr(E_per_pair), int(n_pairs), int(E), _ptr(out), _stream(stream)),
+           "ss_filter_wave_async")
+
+
+def ss_unpack_results_async(ctx, results, n_pairs, accept_out, edits_out, stream=None):
+    _check(lib().ss_unpack_results_async(ctx, _ptr(results), int(n_pairs), _ptr(accept_out), _ptr(edits_out),
+                                         _stream(stream)), "ss_unpack_results_async")
+
+
+def decode_results(res: np.ndarray):
+    """Split device result words (uint16) into (accept uint8, edits int32)."""
+    res = np.asarray(res).astype(np.uint16, copy=False)
+    return (res >> 15).astype(np.uint8), (res & SS_RESULT_COUNT).astype(np.int32)

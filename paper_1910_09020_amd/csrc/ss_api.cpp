@@ -1,0 +1,333 @@
+// C ABI of libss.so: argument validation, device-memory management and the
+// one-call host entry points.  Every step of the filter runs in the HIP kernels
+// of ss_sliced.hip / ss_stream.hip; this file only moves data and launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "ss.h"
+#include "ss_common.h"
+
+using namespace ss;
+
+namespace {
+
+int map_err(hipError_t e)
+{
+    if (e == hipSuccess) return SS_OK;
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return SS_ENOMEM;
+    return SS_EDEVICE;
+}
+
+#define SS_TRY(expr)                                   \
+    do {                                               \
+        hipError_t _e = (expr);                        \
+        if (_e != hipSuccess) return map_err(_e);      \
+    } while (0)
+
+}  // namespace
+
+// Device buffers that grow on demand and are reused across calls.
+struct DevBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+    hipError_t ensure(size_t bytes)
+    {
+        if (bytes <= cap) return hipSuccess;
+        if (p) { (void)hipFree(p); p = nullptr; cap = 0; }
+        size_t want = std::max(bytes, (size_t)256);
+        hipError_t e = hipMalloc(&p, want);
+        if (e == hipSuccess) cap = want;
+        return e;
+    }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+};
+
+struct ss_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    DevBuf reads, refs, offsets, lengths, epp, packed, results, err;
+};
+
+extern "C" const char* ss_status_str(int status)
+{
+    switch (status) {
+    case SS_OK: return "SS_OK";
+    case SS_EINVAL: return "SS_EINVAL: invalid argument";
+    case SS_EBASE: return "SS_EBASE: byte outside ACGTacgt";
+    case SS_ELEN: return "SS_ELEN: length or threshold beyond the supported range";
+    case SS_ENOMEM: return "SS_ENOMEM: allocation failed";
+    case SS_EBUDGET: return "SS_EBUDGET: request exceeds the HBM budget";
+    case SS_EDEVICE: return "SS_EDEVICE: HIP device error";
+    case SS_EAGAIN: return "SS_EAGAIN: not ready";
+    case SS_ETIMEOUT: return "SS_ETIMEOUT: deadline passed";
+    default: return "unknown status";
+    }
+}
+
+extern "C" int ss_create(ss_ctx** out, int hip_device)
+{
+    if (!out) return SS_EINVAL;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return SS_EDEVICE;
+    if (hip_device < 0 || hip_device >= count) return SS_EINVAL;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, hip_device) != hipSuccess) return SS_EDEVICE;
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return SS_EDEVICE;   // code objects are gfx950 only
+    ss_ctx* c = new (std::nothrow) ss_ctx();
+    if (!c) return SS_ENOMEM;
+    c->device = hip_device;
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    hipError_t e = hipSetDevice(hip_device);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    (void)hipSetDevice(prev);
+    if (e != hipSuccess) {
+        delete c;
+        return map_err(e);
+    }
+    *out = c;
+    return SS_OK;
+}
+
+extern "C" int ss_destroy(ss_ctx* ctx)
+{
+    if (!ctx) return SS_EINVAL;
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(ctx->device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    for (DevBuf* b : {&ctx->reads, &ctx->refs, &ctx->offsets, &ctx->lengths, &ctx->epp, &ctx->packed,
+                      &ctx->results, &ctx->err})
+        b->release();
+    if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    (void)hipSetDevice(prev);
+    delete ctx;
+    return SS_OK;
+}
+
+// ---------------------------------------------------------------- sizes
+extern "C" int64_t ss_sliced_bytes(int64_t n_pairs, int32_t m)
+{
+    if (n_pairs < 0 || m < 0) return -1;
+    const int64_t G = cdiv(n_pairs, 32);
+    return 4LL * cdiv(m, kChunk) * G * kChunk * 4LL;
+}
+
+extern "C" int64_t ss_stream_words(int64_t total_bases)
+{
+    if (total_bases < 0) return -1;
+    return cdiv(total_bases, 32) + 2;
+}
+
+// ---------------------------------------------------------------- asynchronous device entry points
+extern "C" int ss_pack_sliced_async(ss_ctx* ctx, const uint8_t* reads, const uint8_t* refs,
+                                    const int64_t* offsets, const int64_t* index, int64_t n_pairs, int32_t m,
+                                    uint32_t* packed, uint32_t* err, void* stream)
+{
+    if (!ctx || n_pairs < 0 || m < 0) return SS_EINVAL;
+    if (m > SS_MAX_LEN) return SS_ELEN;
+    if (n_pairs == 0 || m == 0) return SS_OK;
+    if (!reads || !refs || !packed) return SS_EINVAL;
+    if (((uintptr_t)packed & 15u) != 0) return SS_EINVAL;
+    return map_err(launch_pack_sliced(reads, refs, offsets, index, n_pairs, m, packed, err, (hipStream_t)stream));
+}
+
+extern "C" int ss_filter_sliced_async(ss_ctx* ctx, const uint32_t* packed, int64_t n_pairs, int32_t m,
+                                      int32_t E, uint16_t* out, void* stream)
+{
+    if (!ctx || n_pairs < 0 || m < 0 || E < 0) return SS_EINVAL;
+    if (E > SS_MAX_E_SLICED || m > SS_MAX_LEN) return SS_ELEN;
+    if (n_pairs == 0) return SS_OK;
+    if (!out || (m > 0 && !packed)) return SS_EINVAL;
+    if ((((uintptr_t)packed | (uintptr_t)out) & 15u) != 0) return SS_EINVAL;
+    return map_err(launch_sliced(packed, n_pairs, m, E, out, (hipStream_t)stream));
+}
+
+extern "C" int ss_pack_stream_async(ss_ctx* ctx, const uint8_t* reads, const uint8_t* refs, int64_t total_bases,
+                                    uint32_t* packed, uint32_t* err, void* stream)
+{
+    if (!ctx || total_bases < 0 || !packed) return SS_EINVAL;
+    if (total_bases > 0 && (!reads || !refs)) return SS_EINVAL;
+    return map_err(launch_pack_stream(reads, refs, total_bases, packed, err, (hipStream_t)stream));
+}
+
+extern "C" int ss_filter_plain_async(ss_ctx* ctx, const uint32_t* packed, int64_t total_bases,
+                                     const int64_t* offsets, const int32_t* lengths, const int32_t* E_per_pair,
+                                     int64_t n_pairs, int32_t E, uint16_t* out, void* stream)
+{
+    if (!ctx || n_pairs < 0 || total_bases < 0 || E < 0) return SS_EINVAL;
+    if (E > SS_MAX_E_PLAIN) return SS_ELEN;
+    if (n_pairs == 0) return SS_OK;
+    if (!packed || !offsets || !lengths || !out) return SS_EINVAL;
+    return map_err(launch_plain(packed, ss_stream_words(total_bases), offsets, lengths, E_per_pair, n_pairs, E, out,
+                                (hipStream_t)stream));
+}
+
+extern "C" int ss_filter_wave_async(ss_ctx* ctx, const uint32_t* packed, int64_t total_bases,
+                                    const int64_t* offsets, const int32_t* lengths, const int32_t* E_per_pair,
+                                    int64_t n_pairs, int32_t E, uint16_t* out, void* stream)
+{
+    if (!ctx || n_pairs < 0 || total_bases < 0 || E < 0) return SS_EINVAL;
+    if (E > SS_MAX_E) return SS_ELEN;
+    if (n_pairs == 0) return SS_OK;
+    if (!packed || !offsets || !lengths || !out) return SS_EINVAL;
+    return map_err(launch_wave(packed, ss_stream_words(total_bases), offsets, lengths, E_per_pair, n_pairs, E, out,
+                               (hipStream_t)stream));
+}
+
+extern "C" int ss_unpack_results_async(ss_ctx* ctx, const uint16_t* results, int64_t n_pairs, uint8_t* accept_out,
+                                       int32_t* edits_out, void* stream)
+{
+    if (!ctx || n_pairs < 0) return SS_EINVAL;
+    if (n_pairs == 0) return SS_OK;
+    if (!results) return SS_EINVAL;
+    return map_err(launch_unpack(results, n_pairs, accept_out, edits_out, (hipStream_t)stream));
+}
+
+// ---------------------------------------------------------------- one-call host API
+namespace {
+
+std::mutex g_default_mu;
+std::vector<ss_ctx*> g_default;   // one per device, created on first use
+
+int default_ctx(ss_ctx** out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return SS_EDEVICE;
+    std::lock_guard<std::mutex> lk(g_default_mu);
+    if ((int)g_default.size() <= dev) g_default.resize(dev + 1, nullptr);
+    if (!g_default[dev]) {
+        int rc = ss_create(&g_default[dev], dev);
+        if (rc != SS_OK) return rc;
+    }
+    *out = g_default[dev];
+    return SS_OK;
+}
+
+// Shared implementation: E_per_pair == nullptr means a single threshold E.
+int filter_host(const uint8_t* reads, const uint8_t* refs, const int32_t* lengths, const int32_t* E_per_pair,
+                int64_t n, int32_t E, uint8_t* accept_out, int32_t* edits_out)
+{
+    if (n < 0) return SS_EINVAL;
+    if (n == 0) return SS_OK;
+    if (!reads || !refs || !lengths || !accept_out || !edits_out) return SS_EINVAL;
+    int32_t Emax = E;
+    if (E_per_pair) {
+        Emax = 0;
+        for (int64_t i = 0; i < n; i++) {
+            if (E_per_pair[i] < 0) return SS_EINVAL;
+            Emax = std::max(Emax, E_per_pair[i]);
+        }
+    } else if (E < 0) {
+        return SS_EINVAL;
+    }
+    if (Emax > SS_MAX_E) return SS_ELEN;
+    std::vector<int64_t> off((size_t)n);
+    int64_t total = 0;
+    bool uniform = true;
+    for (int64_t i = 0; i < n; i++) {
+        const int32_t L = lengths[i];
+        if (L < 0 || L > SS_MAX_LEN) return SS_ELEN;
+        off[(size_t)i] = total;
+        total += L;
+        uniform = uniform && (L == lengths[0]);
+    }
+
+    ss_ctx* ctx = nullptr;
+    int rc = default_ctx(&ctx);
+    if (rc != SS_OK) return rc;
+    hipStream_t s = ctx->stream;
+    SS_TRY(ctx->reads.ensure((size_t)std::max<int64_t>(total, 1)));
+    SS_TRY(ctx->refs.ensure((size_t)std::max<int64_t>(total, 1)));
+    SS_TRY(ctx->results.ensure((size_t)n * 2 + 16));
+    SS_TRY(ctx->err.ensure(16));
+    uint32_t* d_err = (uint32_t*)ctx->err.p;
+    uint16_t* d_res = (uint16_t*)ctx->results.p;
+    if (total > 0) {
+        SS_TRY(hipMemcpyAsync(ctx->reads.p, reads, (size_t)total, hipMemcpyHostToDevice, s));
+        SS_TRY(hipMemcpyAsync(ctx->refs.p, refs, (size_t)total, hipMemcpyHostToDevice, s));
+    }
+    SS_TRY(hipMemsetAsync(d_err, 0, 4, s));
+
+    const bool sliced = uniform && !E_per_pair && E <= SS_MAX_E_SLICED;
+    if (sliced) {
+        const int32_t m = lengths[0];
+        SS_TRY(ctx->packed.ensure((size_t)std::max<int64_t>(ss_sliced_bytes(n, m), 16)));
+        rc = ss_pack_sliced_async(ctx, (const uint8_t*)ctx->reads.p, (const uint8_t*)ctx->refs.p, nullptr, nullptr,
+                                  n, m, (uint32_t*)ctx->packed.p, d_err, s);
+        if (rc != SS_OK) return rc;
+    } else {
+        SS_TRY(ctx->packed.ensure((size_t)ss_stream_words(total) * 16));
+        SS_TRY(ctx->offsets.ensure((size_t)n * 8));
+        SS_TRY(ctx->lengths.ensure((size_t)n * 4));
+        SS_TRY(hipMemcpyAsync(ctx->offsets.p, off.data(), (size_t)n * 8, hipMemcpyHostToDevice, s));
+        SS_TRY(hipMemcpyAsync(ctx->lengths.p, lengths, (size_t)n * 4, hipMemcpyHostToDevice, s));
+        if (E_per_pair) {
+            SS_TRY(ctx->epp.ensure((size_t)n * 4));
+            SS_TRY(hipMemcpyAsync(ctx->epp.p, E_per_pair, (size_t)n * 4, hipMemcpyHostToDevice, s));
+        }
+        rc = ss_pack_stream_async(ctx, (const uint8_t*)ctx->reads.p, (const uint8_t*)ctx->refs.p, total,
+                                  (uint32_t*)ctx->packed.p, d_err, s);
+        if (rc != SS_OK) return rc;
+    }
+    uint32_t h_err = 0;
+    SS_TRY(hipMemcpyAsync(&h_err, d_err, 4, hipMemcpyDeviceToHost, s));
+    SS_TRY(hipStreamSynchronize(s));
+    if (h_err) return SS_EBASE;
+
+    if (sliced) {
+        rc = ss_filter_sliced_async(ctx, (const uint32_t*)ctx->packed.p, n, lengths[0], E, d_res, s);
+    } else {
+        rc = ss_filter_wave_async(ctx, (const uint32_t*)ctx->packed.p, total, (const int64_t*)ctx->offsets.p,
+                                  (const int32_t*)ctx->lengths.p, E_per_pair ? (const int32_t*)ctx->epp.p : nullptr,
+                                  n, Emax, d_res, s);
+    }
+    if (rc != SS_OK) return rc;
+    std::vector<uint16_t> res((size_t)n);
+    SS_TRY(hipMemcpyAsync(res.data(), d_res, (size_t)n * 2, hipMemcpyDeviceToHost, s));
+    SS_TRY(hipStreamSynchronize(s));
+    for (int64_t i = 0; i < n; i++) {
+        accept_out[i] = (uint8_t)(res[(size_t)i] >> 15);
+        edits_out[i] = (int32_t)(res[(size_t)i] & SS_RESULT_COUNT);
+    }
+    return SS_OK;
+}
+
+}  // namespace
+
+extern "C" int ss_filter_batch(const uint8_t* reads, const uint8_t* refs, const int32_t* lengths, int64_t n_pairs,
+                               int32_t E, uint8_t* accept_out, int32_t* edits_out)
+{
+    try {
+        return filter_host(reads, refs, lengths, nullptr, n_pairs, E, accept_out, edits_out);
+    } catch (const std::bad_alloc&) {
+        return SS_ENOMEM;
+    } catch (...) {
+        return SS_EDEVICE;
+    }
+}
+
+extern "C" int ss_filter_batch_var(const uint8_t* reads, const uint8_t* refs, const int32_t* lengths,
+                                   const int32_t* E_per_pair, int64_t n_pairs, uint8_t* accept_out,
+                                   int32_t* edits_out)
+{
+    if (n_pairs > 0 && !E_per_pair) return SS_EINVAL;
+    try {
+        return filter_host(reads, refs, lengths, E_per_pair, n_pairs, 0, accept_out, edits_out);
+    } catch (const std::bad_alloc&) {
+        return SS_ENOMEM;
+    } catch (...) {
+        return SS_EDEVICE;
+    }
+}

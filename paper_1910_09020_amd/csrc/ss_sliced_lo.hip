@@ -1,0 +1,11 @@
+// Column-sweep kernels for thresholds E = 0..10.
+#include "ss_sliced_kernel.h"
+
+namespace ss {
+
+hipError_t launch_sliced_lo(int E, const uint32_t* packed, int64_t n, int32_t m, uint16_t* out, hipStream_t s)
+{
+    return sliced::SlicedTable<0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10>::run(E, packed, n, m, out, s);
+}
+
+}  // namespace ss

@@ -1,0 +1,438 @@
+// Bit-stream encoder, one-pair-per-lane filter and wavefront-cooperative filter.
+//
+// Bit-stream layout: four planes (Q0, Q1, R0, R1) of the concatenated batch;
+// base b is bit b%32 of word b/32 of its plane, code A=0 C=1 G=2 T=3 (plane 0 =
+// low bit).  Every plane carries two zero guard words at its end.
+#include "ss_common.h"
+
+namespace ss {
+namespace {
+
+// three-input logic (v_bitop3_b32); truth-table index (src0 << 2) | (src1 << 1) | src2
+#define SS_BITOP3(a, b, c, imm) __builtin_amdgcn_bitop3_b32((a), (b), (c), (imm))
+
+// --------------------------------------------------------------- encoder
+// Four ASCII bytes -> low/high code bits in the low 4 bits of each result.
+__device__ __forceinline__ void code4(uint32_t x, uint32_t& lo, uint32_t& hi, uint32_t& bad)
+{
+    const uint32_t c = ((x >> 1) ^ (x >> 2)) & 0x03030303u;
+    const uint32_t p0 = c & 0x01010101u, p1 = (c >> 1) & 0x01010101u;
+    lo = ((p0 * 0x00204081u) >> 21) & 0xFu;
+    hi = ((p1 * 0x00204081u) >> 21) & 0xFu;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        const uint32_t v = (((x >> (8 * k)) & 0xFFu) | 0x20u) - 0x61u;
+        bad |= (v < 20u) ? (((0x80045u >> v) & 1u) ^ 1u) : 1u;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_pack_stream(const uint8_t* __restrict__ reads,
+                                                     const uint8_t* __restrict__ refs, int64_t total,
+                                                     int64_t SW, int aligned, uint32_t* __restrict__ packed,
+                                                     uint32_t* __restrict__ err)
+{
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= SW) return;
+    uint32_t q0 = 0, q1 = 0, r0 = 0, r1 = 0, bad = 0;
+    const int64_t b = w * 32;
+    if (b < total) {
+        const int64_t nb = total - b < 32 ? total - b : 32;
+        if (nb == 32 && aligned) {
+            const uint4* a4 = reinterpret_cast<const uint4*>(reads + b);
+            const uint4* f4 = reinterpret_cast<const uint4*>(refs + b);
+            uint4 a[2] = {a4[0], a4[1]}, f[2] = {f4[0], f4[1]};
+            uint32_t xa[8] = {a[0].x, a[0].y, a[0].z, a[0].w, a[1].x, a[1].y, a[1].z, a[1].w};
+            uint32_t xf[8] = {f[0].x, f[0].y, f[0].z, f[0].w, f[1].x, f[1].y, f[1].z, f[1].w};
+#pragma unroll
+            for (int k = 0; k < 8; k++) {
+                uint32_t lo, hi;
+                code4(xa[k], lo, hi, bad);
+                q0 |= lo << (4 * k);
+                q1 |= hi << (4 * k);
+                code4(xf[k], lo, hi, bad);
+                r0 |= lo << (4 * k);
+                r1 |= hi << (4 * k);
+            }
+        } else {
+            for (int k = 0; k < nb; k++) {
+                const uint32_t xa = reads[b + k], xf = refs[b + k];
+                uint32_t lo, hi, bb = 0;
+                code4(xa, lo, hi, bb);
+                q0 |= (lo & 1u) << k;
+                q1 |= (hi & 1u) << k;
+                code4(xf, lo, hi, bb);
+                r0 |= (lo & 1u) << k;
+                r1 |= (hi & 1u) << k;
+                // code4 judged three zero bytes too; only the low byte counts
+                const uint32_t va = (xa | 0x20u) - 0x61u, vf = (xf | 0x20u) - 0x61u;
+                bad |= (va < 20u) ? (((0x80045u >> va) & 1u) ^ 1u) : 1u;
+                bad |= (vf < 20u) ? (((0x80045u >> vf) & 1u) ^ 1u) : 1u;
+            }
+        }
+    }
+    packed[w] = q0;
+    packed[SW + w] = q1;
+    packed[2 * SW + w] = r0;
+    packed[3 * SW + w] = r1;
+    if (bad && err) atomicOr(err, 1u);
+}
+
+// 32 bits of a plane starting at absolute stream bit a (zero outside the buffer)
+__device__ __forceinline__ uint32_t bits32(const uint32_t* __restrict__ P, int64_t SW, int64_t a)
+{
+    const int64_t w = a >> 5;                 // arithmetic shift: floor for negative a
+    const uint32_t sh = (uint32_t)(a & 31);
+    const uint32_t lo = (w >= 0 && w < SW) ? P[w] : 0u;
+    const uint32_t hi = (w + 1 >= 0 && w + 1 < SW) ? P[w + 1] : 0u;
+    return __builtin_amdgcn_alignbit(hi, lo, sh);
+}
+
+// bits [lo, hi) of a word set (lo, hi clamped to [0, 32])
+__device__ __forceinline__ uint32_t span_mask(int lo, int hi)
+{
+    lo = lo < 0 ? 0 : (lo > 32 ? 32 : lo);
+    hi = hi < 0 ? 0 : (hi > 32 ? 32 : hi);
+    if (hi <= lo) return 0u;
+    const uint32_t up = hi == 32 ? ~0u : ((1u << hi) - 1u);
+    const uint32_t dn = (1u << lo) - 1u;      // lo < 32 here
+    return up & ~dn;
+}
+
+// --------------------------------------------------------------- one pair per lane
+// Each lane holds one pair.  Word by word (32 columns, the same word for every
+// lane of the wave), the lane builds its 2E+1 rows of Equation 1 as mismatch
+// masks and runs the walk of Section 2.4 inside the word with the borrow
+// trick: for a checkpoint at bit b, (M - 2^b) & ~M marks the free cells of the
+// row from b up to its first obstacle, so the OR over rows is the longest
+// escape segment; a borrow that runs off bit 31 carries the segment into the
+// next word (one carry bit per row).
+template <int E, bool VAR_E>
+__global__ __launch_bounds__(256) void k_plain(const uint32_t* __restrict__ pk, int64_t SW,
+                                               const int64_t* __restrict__ offsets,
+                                               const int32_t* __restrict__ lengths,
+                                               const int32_t* __restrict__ Epp, int64_t n,
+                                               uint16_t* __restrict__ out)
+{
+    constexpr int NR = 2 * E + 1;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool lane_ok = i < n;
+    const int64_t ii = lane_ok ? i : 0;
+    const int m = lane_ok ? lengths[ii] : 0;
+    const int Ei = VAR_E ? Epp[ii] : E;
+    const int64_t b0 = offsets[ii];
+    const uint32_t* __restrict__ Q0 = pk;
+    const uint32_t* __restrict__ Q1 = pk + SW;
+    const uint32_t* __restrict__ R0 = pk + 2 * SW;
+    const uint32_t* __restrict__ R1 = pk + 3 * SW;
+    auto word = [&](const uint32_t* P, int u) { return bits32(P, SW, b0 + 32 * (int64_t)u); };
+    auto vword = [&](int u) { return span_mask(0 - 32 * u, m - 32 * u); };   // query positions inside [0, m)
+
+    const int W = (m + 31) >> 5;
+    bool done = !lane_ok || m == 0;
+    int nobs = 0, p = 0;
+    uint32_t cin[NR], D[NR], M[NR];
+#pragma unroll
+    for (int r = 0; r < NR; r++) { cin[r] = 0u; D[r] = 0u; M[r] = ~0u; }
+    uint32_t qp0 = 0, qp1 = 0, vp = 0;
+    uint32_t qc0 = done ? 0u : word(Q0, 0), qc1 = done ? 0u : word(Q1, 0), vc = vword(0);
+
+    for (int w = 0;; w++) {
+        const bool act0 = !done && w < W;
+        if (!__any(act0)) break;
+        uint32_t qn0 = 0, qn1 = 0, r0 = 0, r1 = 0;
+        if (act0) {
+            qn0 = word(Q0, w + 1);
+            qn1 = word(Q1, w + 1);
+            r0 = word(R0, w);
+            r1 = word(R1, w);
+        }
+        const uint32_t vn = vword(w + 1);
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            const int k = r - E;
+            uint32_t a0, a1, v;
+            if (k >= 0) {
+                a0 = __builtin_amdgcn_alignbit(qn0, qc0, k);
+                a1 = __builtin_amdgcn_alignbit(qn1, qc1, k);
+                v = __builtin_amdgcn_alignbit(vn, vc, k);
+            } else {
+                a0 = __builtin_amdgcn_alignbit(qc0, qp0, 32 + k);
+                a1 = __builtin_amdgcn_alignbit(qc1, qp1, 32 + k);
+                v = __builtin_amdgcn_alignbit(vc, vp, 32 + k);
+            }
+            const uint32_t mm = SS_BITOP3(r0, a0, v, 0x7D);          // (r0 ^ a0) | ~v
+            uint32_t row = SS_BITOP3(mm, r1, a1, 0xF6);              // mm | (r1 ^ a1)
+            if (VAR_E && (k > Ei || -k > Ei)) row = ~0u;
+            M[r] = row;
+        }
+        bool act = act0;
+        uint32_t bitp = (act && (p >> 5) == w) ? (1u << (p & 31)) : 0u;
+        uint32_t U = 0;
+        if (act) {
+#pragma unroll
+            for (int r = 0; r < NR; r++) {
+                D[r] = M[r] - (bitp | cin[r]);
+                U |= D[r] & ~M[r];
+            }
+        }
+        for (;;) {
+            if (act) {
+                if (U >> 31) {
+                    act = false;                            // segment continues into the next word
+                } else {
+                    const int sb = bitp ? (int)__builtin_ctz(bitp) : 0;
+                    const int reach = U ? 32 - (int)__builtin_clz(U) : sb;
+                    const int rabs = 32 * w + reach;
+                    if (rabs >= m) {
+                        done = true;                        // the segment reaches the destination
+                        act = false;
+                    } else {
+                        nobs++;
+                        p = rabs + 1;
+                        if (nobs > Ei) { done = true; act = false; }
+                        else if (p >= 32 * (w + 1)) act = false;
+                        else bitp = 1u << (p & 31);
+                    }
+                }
+            }
+            if (!__any(act)) break;
+            if (act) {
+                U = 0;
+#pragma unroll
+                for (int r = 0; r < NR; r++) {
+                    D[r] = M[r] - bitp;
+                    U |= D[r] & ~M[r];
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < NR; r++) cin[r] = (D[r] & ~M[r]) >> 31;
+        qp0 = qc0; qp1 = qc1; vp = vc;
+        qc0 = qn0; qc1 = qn1; vc = vn;
+    }
+    if (lane_ok) out[i] = (uint16_t)((nobs <= Ei ? 0x8000u : 0u) | (uint32_t)nobs);
+}
+
+// --------------------------------------------------------------- wavefront-cooperative
+// LP lanes per pair, RS 32-row slices per lane (slice s = lane_in_pair + LP*t
+// holds rows 32s..32s+31 of the 2E+1 rows, row index r = k + E).  Each column
+// is one step of the sweep (see the lane-sliced kernel): every row still free
+// since the checkpoint stays alive if its Equation 1 cell is 0; a wavefront
+// ballot tells whether any row of the pair is alive; if none, the column holds
+// the obstacle closing the longest escape segment: count it and free all rows.
+template <int LP, int RS>
+__global__ __launch_bounds__(256) void k_wave(const uint32_t* __restrict__ pk, int64_t SW,
+                                              const int64_t* __restrict__ offsets,
+                                              const int32_t* __restrict__ lengths,
+                                              const int32_t* __restrict__ Epp, int64_t n, int Emax,
+                                              uint16_t* __restrict__ out)
+{
+    constexpr int PW = 64 / LP;
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int grp = lane / LP, lip = lane % LP;
+    const int64_t pi = wave * PW + grp;
+    const bool pair_ok = pi < n;
+    const int64_t pc = pair_ok ? pi : 0;
+    const int m = pair_ok ? lengths[pc] : 0;
+    const int Ei = Epp ? Epp[pc] : Emax;
+    const int64_t b0 = offsets[pc];
+    const uint32_t* __restrict__ Q0 = pk;
+    const uint32_t* __restrict__ Q1 = pk + SW;
+    const uint32_t* __restrict__ R0 = pk + 2 * SW;
+    const uint32_t* __restrict__ R1 = pk + 3 * SW;
+    const int NR = 2 * Emax + 1;
+
+    uint32_t alive[RS], rmask[RS], q0lo[RS], q0hi[RS], q1lo[RS], q1hi[RS];
+#pragma unroll
+    for (int t = 0; t < RS; t++) {
+        const int s = lip + LP * t;
+        // rows r in [32s, 32s+32) that exist (r < NR) and whose |k| = |r - Emax| <= Ei
+        const int lo = Emax - Ei - 32 * s, hi = Emax + Ei + 1 - 32 * s;
+        rmask[t] = span_mask(lo, hi < NR - 32 * s ? hi : NR - 32 * s);
+        alive[t] = rmask[t];
+    }
+    int count = 0;
+    bool fin = !pair_ok || m == 0;
+    // interior blocks need no query-range mask for any pair of this wave
+    int mmin = fin ? 0x7FFFFFFF : m;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) mmin = min(mmin, __shfl_xor(mmin, o));
+    int mmax = fin ? 0 : m;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) mmax = max(mmax, __shfl_xor(mmax, o));
+
+    for (int jb = 0; jb < mmax; jb += 32) {
+        if (__all(fin)) break;
+        // query window of slice s for this block: pair-relative positions jb - Emax + 32 s + [0, 64)
+#pragma unroll
+        for (int t = 0; t < RS; t++) {
+            const int s = lip + LP * t;
+            const int64_t a = b0 + jb - Emax + 32 * (int64_t)s;
+            q0lo[t] = bits32(Q0, SW, a);
+            q0hi[t] = bits32(Q0, SW, a + 32);
+            q1lo[t] = bits32(Q1, SW, a);
+            q1hi[t] = bits32(Q1, SW, a + 32);
+        }
+        const uint32_t rw0 = bits32(R0, SW, b0 + jb), rw1 = bits32(R1, SW, b0 + jb);
+        const bool interior = (jb >= Emax) && (jb + 31 + Emax < mmin);
+        const int jend = min(32, mmax - jb);
+        for (int jj = 0; jj < jend; jj++) {
+            const int j = jb + jj;
+            const uint32_t rb0 = (uint32_t)((int32_t)(rw0 << (31 - jj)) >> 31);   // R bit j broadcast
+            const uint32_t rb1 = (uint32_t)((int32_t)(rw1 << (31 - jj)) >> 31);
+            uint32_t any = 0;
+#pragma unroll
+            for (int t = 0; t < RS; t++) {
+                const uint32_t x0 = __builtin_amdgcn_alignbit(q0hi[t], q0lo[t], jj);
+                const uint32_t x1 = __builtin_amdgcn_alignbit(q1hi[t], q1lo[t], jj);
+                uint32_t a = SS_BITOP3(SS_BITOP3(alive[t], x0, rb0, 0x90), x1, rb1, 0x90);
+                if (!interior) {
+                    const int s = lip + LP * t;
+                    const int base = j - Emax + 32 * s;      // query position of bit 0
+                    a &= span_mask(-base, m - base);
+                }
+                alive[t] = a;
+                any |= a;
+            }
+            bool pany = any != 0u;
+            if (LP > 1) {
+                const uint64_t bal = __ballot(pany);
+                const uint64_t gm = LP == 64 ? bal : (bal >> (grp * LP)) & ((1ull << (LP == 64 ? 0 : LP)) - 1ull);
+                pany = gm != 0ull;
+            }
+            const bool live = !fin && j < m;
+            if (live && !pany) {
+                count++;
+#pragma unroll
+                for (int t = 0; t < RS; t++) alive[t] = rmask[t];
+                if (count > Ei) fin = true;
+            }
+            if (j + 1 >= m) fin = true;
+        }
+    }
+    if (pair_ok && lip == 0) {
+        const int c = count > Ei + 1 ? Ei + 1 : count;
+        out[pi] = (uint16_t)((c <= Ei ? 0x8000u : 0u) | (uint32_t)c);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_unpack(const uint16_t* __restrict__ res, int64_t n,
+                                                uint8_t* __restrict__ accept, int32_t* __restrict__ edits)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t v = res[i];
+    if (accept) accept[i] = (uint8_t)(v >> 15);
+    if (edits) edits[i] = (int32_t)(v & 0x7FFFu);
+}
+
+template <int E>
+hipError_t launch_plain_E(const uint32_t* pk, int64_t SW, const int64_t* off, const int32_t* len,
+                          const int32_t* Epp, int64_t n, uint16_t* out, hipStream_t s)
+{
+    const int threads = 256;
+    const unsigned blocks = (unsigned)cdiv(n, threads);
+    if (Epp) hipLaunchKernelGGL((k_plain<E, true>), dim3(blocks), dim3(threads), 0, s, pk, SW, off, len, Epp, n, out);
+    else hipLaunchKernelGGL((k_plain<E, false>), dim3(blocks), dim3(threads), 0, s, pk, SW, off, len, Epp, n, out);
+    return hipGetLastError();
+}
+
+template <int... Es>
+struct PlainTable {
+    static hipError_t run(int E, const uint32_t* pk, int64_t SW, const int64_t* off, const int32_t* len,
+                          const int32_t* Epp, int64_t n, uint16_t* out, hipStream_t s)
+    {
+        hipError_t r = hipErrorInvalidValue;
+        ((E == Es ? (r = launch_plain_E<Es>(pk, SW, off, len, Epp, n, out, s), 0) : 0), ...);
+        return r;
+    }
+};
+
+template <int LP, int RS>
+hipError_t launch_wave_LR(const uint32_t* pk, int64_t SW, const int64_t* off, const int32_t* len,
+                          const int32_t* Epp, int64_t n, int E, uint16_t* out, hipStream_t s)
+{
+    constexpr int PW = 64 / LP;
+    const int64_t waves = cdiv(n, PW);
+    const int threads = 256;
+    const unsigned blocks = (unsigned)cdiv(waves * 64, threads);
+    hipLaunchKernelGGL((k_wave<LP, RS>), dim3(blocks), dim3(threads), 0, s, pk, SW, off, len, Epp, n, E, out);
+    return hipGetLastError();
+}
+
+template <int RS>
+hipError_t launch_wave_R(int LP, const uint32_t* pk, int64_t SW, const int64_t* off, const int32_t* len,
+                         const int32_t* Epp, int64_t n, int E, uint16_t* out, hipStream_t s)
+{
+    switch (LP) {
+    case 1: return launch_wave_LR<1, RS>(pk, SW, off, len, Epp, n, E, out, s);
+    case 2: return launch_wave_LR<2, RS>(pk, SW, off, len, Epp, n, E, out, s);
+    case 4: return launch_wave_LR<4, RS>(pk, SW, off, len, Epp, n, E, out, s);
+    case 8: return launch_wave_LR<8, RS>(pk, SW, off, len, Epp, n, E, out, s);
+    case 16: return launch_wave_LR<16, RS>(pk, SW, off, len, Epp, n, E, out, s);
+    case 32: return launch_wave_LR<32, RS>(pk, SW, off, len, Epp, n, E, out, s);
+    case 64: return launch_wave_LR<64, RS>(pk, SW, off, len, Epp, n, E, out, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+void wave_shape(int32_t E, int* lanes_per_pair, int* slices_per_lane)
+{
+    const int SL = (int)cdiv(2 * (int64_t)E + 1, 32);
+    int RS = 1;
+    while (RS < SL && RS < 16) RS <<= 1;
+    int LP = 1;
+    while ((int64_t)LP * RS < SL) LP <<= 1;
+    *lanes_per_pair = LP;
+    *slices_per_lane = RS;
+}
+
+hipError_t launch_pack_stream(const uint8_t* reads, const uint8_t* refs, int64_t total_bases, uint32_t* packed,
+                              uint32_t* err, hipStream_t s)
+{
+    const int64_t SW = cdiv(total_bases, 32) + 2;
+    const int aligned = ((((uintptr_t)reads) | ((uintptr_t)refs)) & 15u) == 0;
+    const int threads = 256;
+    hipLaunchKernelGGL(k_pack_stream, dim3((unsigned)cdiv(SW, threads)), dim3(threads), 0, s, reads, refs,
+                       total_bases, SW, aligned, packed, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_plain(const uint32_t* packed, int64_t stream_words, const int64_t* offsets,
+                        const int32_t* lengths, const int32_t* Epp, int64_t n, int32_t E, uint16_t* out,
+                        hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    using Tab = PlainTable<0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18, 19, 20, 21, 22, 23,
+                           24, 25, 26, 27, 28, 29, 30, 31>;
+    return Tab::run(E, packed, stream_words, offsets, lengths, Epp, n, out, s);
+}
+
+hipError_t launch_wave(const uint32_t* packed, int64_t stream_words, const int64_t* offsets,
+                       const int32_t* lengths, const int32_t* Epp, int64_t n, int32_t E, uint16_t* out,
+                       hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    int LP, RS;
+    wave_shape(E, &LP, &RS);
+    switch (RS) {
+    case 1: return launch_wave_R<1>(LP, packed, stream_words, offsets, lengths, Epp, n, E, out, s);
+    case 2: return launch_wave_R<2>(LP, packed, stream_words, offsets, lengths, Epp, n, E, out, s);
+    case 4: return launch_wave_R<4>(LP, packed, stream_words, offsets, lengths, Epp, n, E, out, s);
+    case 8: return launch_wave_R<8>(LP, packed, stream_words, offsets, lengths, Epp, n, E, out, s);
+    case 16: return launch_wave_R<16>(LP, packed, stream_words, offsets, lengths, Epp, n, E, out, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_unpack(const uint16_t* res, int64_t n, uint8_t* accept, int32_t* edits, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_unpack, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, s, res, n, accept, edits);
+    return hipGetLastError();
+}
+
+}  // namespace ss

@@ -1,0 +1,111 @@
+"""Device-side helpers: upload a batch to HBM with torch, run the libss kernels.
+
+Marshalling only.  Torch supplies device memory and the stream; every
+encoding and filtering step is a libss.so kernel.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import (ss_create, ss_filter_plain_async, ss_filter_sliced_async, ss_filter_wave_async,
+               ss_pack_sliced_async, ss_pack_stream_async, ss_sliced_bytes, ss_stream_words)
+
+_ctx = {}
+
+
+def context(device: int = 0) -> int:
+    if device not in _ctx:
+        _ctx[device] = ss_create(device)
+    return _ctx[device]
+
+
+def _dev(device):
+    return torch.device("cuda", device)
+
+
+class DeviceBatch:
+    """A batch of pairs resident in HBM (ASCII reads/refs, offsets, lengths, per-pair E)."""
+
+    def __init__(self, batch: dict, device: int = 0):
+        d = _dev(device)
+        self.device = device
+        self.n = int(batch["n"]) if "n" in batch else len(batch["lengths"])
+        self.lengths_np = np.ascontiguousarray(batch["lengths"], dtype=np.int32)
+        self.offsets_np = np.ascontiguousarray(batch["offsets"], dtype=np.int64)
+        self.total = int(len(batch["reads"]))
+        # pad ASCII buffers to 16 bytes so vector loads of the encoder stay inside
+        pad = (-self.total) % 16 + 16
+        self.reads = torch.empty(self.total + pad, dtype=torch.uint8, device=d)
+        self.refs = torch.empty(self.total + pad, dtype=torch.uint8, device=d)
+        self.reads[self.total:].fill_(ord("A"))
+        self.refs[self.total:].fill_(ord("A"))
+        if self.total:
+            self.reads[: self.total].copy_(torch.from_numpy(np.ascontiguousarray(batch["reads"])))
+            self.refs[: self.total].copy_(torch.from_numpy(np.ascontiguousarray(batch["refs"])))
+        self.offsets = torch.from_numpy(self.offsets_np).to(d)
+        self.lengths = torch.from_numpy(self.lengths_np).to(d)
+        E = batch.get("E")
+        self.E_np = None if E is None else np.ascontiguousarray(E, dtype=np.int32)
+        self.E = None if E is None else torch.from_numpy(self.E_np).to(d)
+        self.uniform_m = int(self.lengths_np[0]) if self.n and np.all(self.lengths_np == self.lengths_np[0]) else None
+        self.err = torch.zeros(1, dtype=torch.int32, device=d)
+
+    # ---- encodings -------------------------------------------------------------
+    def pack_sliced(self, index=None, m=None, n=None, stream=None, packed=None) -> torch.Tensor:
+        """Lane-sliced encoding of all pairs (or of the pairs listed in index, all of length m)."""
+        n = self.n if n is None else n
+        m = self.uniform_m if m is None else m
+        if m is None:
+            raise ValueError("lane-sliced encoding needs pairs of one length")
+        words = max(4, ss_sliced_bytes(n, m) // 4)
+        if packed is None:
+            packed = torch.empty(words, dtype=torch.int32, device=_dev(self.device))
+        assert packed.numel() >= words
+        ss_pack_sliced_async(context(self.device), self.reads, self.refs, self.offsets, index, n, m, packed,
+                             self.err, stream or torch.cuda.current_stream(self.device))
+        return packed
+
+    def pack_stream(self, stream=None, packed=None) -> torch.Tensor:
+        words = 4 * ss_stream_words(self.total)
+        if packed is None:
+            packed = torch.empty(words, dtype=torch.int32, device=_dev(self.device))
+        assert packed.numel() >= words
+        ss_pack_stream_async(context(self.device), self.reads, self.refs, self.total, packed, self.err,
+                             stream or torch.cuda.current_stream(self.device))
+        return packed
+
+    def bad_bases(self) -> bool:
+        return bool(self.err.item() != 0)
+
+    # ---- filters ---------------------------------------------------------------
+    def new_out(self, n=None) -> torch.Tensor:
+        return torch.empty(max(8, self.n if n is None else n), dtype=torch.int16, device=_dev(self.device))
+
+    def filter_sliced(self, packed, E: int, out=None, n=None, m=None, stream=None) -> torch.Tensor:
+        n = self.n if n is None else n
+        m = self.uniform_m if m is None else m
+        out = self.new_out(n) if out is None else out
+        ss_filter_sliced_async(context(self.device), packed, n, m, E, out,
+                               stream or torch.cuda.current_stream(self.device))
+        return out
+
+    def filter_plain(self, packed, E: int, per_pair: bool = False, out=None, stream=None) -> torch.Tensor:
+        out = self.new_out() if out is None else out
+        ss_filter_plain_async(context(self.device), packed, self.total, self.offsets, self.lengths,
+                              self.E if per_pair else None, self.n, E, out,
+                              stream or torch.cuda.current_stream(self.device))
+        return out
+
+    def filter_wave(self, packed, E: int, per_pair: bool = False, out=None, stream=None) -> torch.Tensor:
+        out = self.new_out() if out is None else out
+        ss_filter_wave_async(context(self.device), packed, self.total, self.offsets, self.lengths,
+                             self.E if per_pair else None, self.n, E, out,
+                             stream or torch.cuda.current_stream(self.device))
+        return out
+
+
+def results_numpy(out: torch.Tensor, n: int):
+    """(accept uint8[n], edits int32[n]) from a device result tensor."""
+    r = out[:n].cpu().numpy().view(np.uint16)
+    return (r >> 15).astype(np.uint8), (r & 0x7FFF).astype(np.int32)

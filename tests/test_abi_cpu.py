@@ -1,0 +1,59 @@
+"""Host-side checks of the C ABI: the library loads without a GPU and exports
+every function that include/ss.h declares; the binding refuses to run without
+the built library (no CPU fallback)."""
+import ctypes
+import os
+import re
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "ss.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b(ss_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_header_declares_entry_points():
+    names = header_functions()
+    assert "ss_filter_batch" in names and "ss_filter_sliced_async" in names
+    assert len(names) >= 12
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_1910_09020_amd as ss
+    lib = ctypes.CDLL(ss.LIB_PATH)
+    missing = [n for n in header_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(header_functions()) <= set(ss.exported_symbols())
+
+
+def test_status_strings_and_sizes():
+    import paper_1910_09020_amd as ss
+    assert ss.status_str(ss.SS_EBASE).startswith("SS_EBASE")
+    assert ss.ss_sliced_bytes(32, 100) == 4 * 25 * 1 * 16
+    assert ss.ss_sliced_bytes(33, 100) == 4 * 25 * 2 * 16
+    assert ss.ss_sliced_bytes(-1, 100) == -1
+    assert ss.ss_stream_words(0) == 2
+    assert ss.ss_stream_words(33) == 4
+
+
+def test_validation_needs_no_device():
+    """Argument errors are caught before any device call."""
+    import paper_1910_09020_amd as ss
+    L = ss.lib()
+    assert L.ss_filter_batch(None, None, None, -1, 5, None, None) == ss.SS_EINVAL
+    assert L.ss_filter_batch(None, None, None, 0, 5, None, None) == ss.SS_OK
+    assert L.ss_filter_sliced_async(None, None, 10, 100, 5, None, None) == ss.SS_EINVAL
+    assert L.ss_create(None, 0) == ss.SS_EINVAL
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    code = ("import paper_1910_09020_amd as ss; ss.LIB_PATH = %r\n"
+            "try:\n    ss.lib()\nexcept RuntimeError as e:\n    print('RAISED', e)\n" % str(tmp_path / "none.so"))
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True)
+    assert "RAISED" in r.stdout and "no CPU fallback" in r.stdout

@@ -1,0 +1,212 @@
+"""GPU parity: every kernel against the CPU oracle, element by element.
+
+The bar is bit-exact equality of the accept bit and the reported obstacle
+count (integer arithmetic only).  Inputs are the seeded workloads of
+``paper_1910_09020_amd.gen`` plus hand-made edge cases.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1910_09020_amd import gen
+
+pytestmark = pytest.mark.gpu
+
+
+def _need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.fixture(scope="module")
+def rt():
+    _need_gpu()
+    import paper_1910_09020_amd as ss
+    ss.lib()
+    from paper_1910_09020_amd import runner
+    return runner
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def expect(b, E=None, Epp=None):
+    r = oracle.batch(b["reads"], b["refs"], b["offsets"], b["lengths"], E=E, E_per_pair=Epp, threads=8)
+    return r["accept"], r["edits"]
+
+
+def check(name, got, want):
+    ga, ge = got
+    wa, we = want
+    bad = np.nonzero((ga != wa) | (ge != we))[0]
+    assert len(bad) == 0, f"{name}: {len(bad)} mismatches, first {bad[:5]} got {ge[bad[:5]]} want {we[bad[:5]]}"
+
+
+def run_all(rt, b, E, kernels=("sliced", "plain", "wave")):
+    import torch
+    db = rt.DeviceBatch(b)
+    want = expect(b, E=E)
+    if "sliced" in kernels and db.uniform_m is not None and E <= 32:
+        say(f"  sliced n={db.n} m={db.uniform_m} E={E}")
+        pk = db.pack_sliced()
+        out = db.filter_sliced(pk, E)
+        torch.cuda.synchronize()
+        assert not db.bad_bases()
+        check(f"sliced E={E}", rt.results_numpy(out, db.n), want)
+    ps = None
+    if "plain" in kernels and E <= 31:
+        say(f"  plain n={db.n} E={E}")
+        ps = db.pack_stream()
+        out = db.filter_plain(ps, E)
+        torch.cuda.synchronize()
+        check(f"plain E={E}", rt.results_numpy(out, db.n), want)
+    if "wave" in kernels:
+        say(f"  wave n={db.n} E={E}")
+        ps = db.pack_stream() if ps is None else ps
+        out = db.filter_wave(ps, E)
+        torch.cuda.synchronize()
+        check(f"wave E={E}", rt.results_numpy(out, db.n), want)
+
+
+def test_fig2_example(rt):
+    b = gen.concat([("GGTGAGAGTTGT", "GGTGCAGAGCTC")])   # (read Q, ref R)
+    for E in range(0, 6):
+        run_all(rt, b, E)
+
+
+def test_config0_E5(rt):
+    run_all(rt, gen.make(0), 5)
+
+
+@pytest.mark.parametrize("E", list(range(0, 11)))
+def test_config1_sweep(rt, E):
+    run_all(rt, gen.make(1, n=20000 + 7), E)
+
+
+@pytest.mark.parametrize("E", [0, 1, 3, 8, 13, 20, 25])
+def test_config2_sweep(rt, E):
+    run_all(rt, gen.make(2, n=4000 + 19), E)
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 4, 5, 7, 31, 32, 33, 63, 64, 65, 127, 128, 129, 200])
+def test_ragged_lengths(rt, m):
+    rng = np.random.default_rng(m)
+    n = 97
+    reads = rng.choice(np.frombuffer(b"ACGT", np.uint8), size=n * m)
+    refs = reads.copy()
+    # mutate a few positions, make some pairs unrelated, some identical
+    flip = rng.random(n * m) < 0.06
+    refs[flip] = rng.choice(np.frombuffer(b"ACGT", np.uint8), size=int(flip.sum()))
+    for p in range(0, n, 5):
+        refs[p * m:(p + 1) * m] = rng.choice(np.frombuffer(b"ACGT", np.uint8), size=m)
+    b = dict(n=n, reads=reads, refs=refs, offsets=np.arange(n, dtype=np.int64) * m,
+             lengths=np.full(n, m, np.int32), E=None)
+    for E in (0, 1, 2, 5, 9, 16, 31, 32):
+        run_all(rt, b, E)
+
+
+def test_degenerate_pairs(rt):
+    pairs = [("A", "A"), ("A", "C"), ("AAAA", "CCCC"), ("ACGTACGT", "ACGTACGA"), ("ACGTTGCA", "CGTTGCAG"),
+             ("acgtAC", "ACGTac"), ("T" * 40, "T" * 40), ("G" * 40, "C" * 40)]
+    b = gen.concat(pairs)
+    for E in (0, 1, 3, 10, 32):
+        run_all(rt, b, E, kernels=("plain", "wave") if E > 31 else ("plain", "wave"))
+    # equal-length subsets through the sliced kernel
+    for m in (1, 4, 8, 40):
+        sub = gen.concat([p for p in pairs if len(p[0]) == m])
+        for E in (0, 1, 3, 10, 32):
+            run_all(rt, sub, E, kernels=("sliced",))
+
+
+def test_mixed_lengths_per_pair_E(rt):
+    import torch
+    b = gen.make(3, n=3000, n_long=6)
+    db = rt.DeviceBatch(b)
+    want = expect(b, Epp=b["E"])
+    Emax = int(b["E"].max())
+    say(f"  wave mixed n={db.n} Emax={Emax}")
+    ps = db.pack_stream()
+    out = db.filter_wave(ps, Emax, per_pair=True)
+    torch.cuda.synchronize()
+    check("wave mixed", rt.results_numpy(out, db.n), want)
+    # plain kernel on the short pairs only (its rows are held in registers, E <= 31)
+    short = np.nonzero(b["lengths"] < 1000)[0]
+    sb = dict(n=len(short), reads=b["reads"], refs=b["refs"], offsets=b["offsets"][short],
+              lengths=b["lengths"][short], E=b["E"][short])
+    dsb = rt.DeviceBatch(dict(sb))
+    # DeviceBatch copies reads/refs in full; offsets index into them
+    ps2 = dsb.pack_stream()
+    out2 = dsb.filter_plain(ps2, int(sb["E"].max()), per_pair=True)
+    torch.cuda.synchronize()
+    check("plain mixed", rt.results_numpy(out2, dsb.n), expect(sb, Epp=sb["E"]))
+
+
+@pytest.mark.parametrize("m,E", [(1000, 33), (1000, 50), (1000, 100), (3000, 300), (10000, 100)])
+def test_wave_large_E(rt, m, E):
+    rng = np.random.default_rng(E + m)
+    n = 24
+    A = np.frombuffer(b"ACGT", np.uint8)
+    reads = rng.choice(A, size=n * m)
+    refs = reads.copy()
+    rate = np.linspace(0.0, 0.12, n)
+    for p in range(n):
+        seg = slice(p * m, (p + 1) * m)
+        fl = rng.random(m) < rate[p]
+        r = refs[seg].copy()
+        r[fl] = rng.choice(A, size=int(fl.sum()))
+        if p % 3 == 1:      # a few indels: shift a tail by one
+            cut = m // 3
+            r = np.concatenate([r[:cut], r[cut + 1:], rng.choice(A, size=1)])
+        refs[seg] = r
+    b = dict(n=n, reads=reads, refs=refs, offsets=np.arange(n, dtype=np.int64) * m,
+             lengths=np.full(n, m, np.int32), E=None)
+    run_all(rt, b, E, kernels=("wave",))
+
+
+def test_invalid_base_is_reported(rt):
+    import torch
+    b = gen.make(0, n=64)
+    b["refs"] = b["refs"].copy()
+    b["refs"][1234] = ord("N")
+    db = rt.DeviceBatch(b)
+    db.pack_sliced()
+    torch.cuda.synchronize()
+    assert db.bad_bases()
+    db2 = rt.DeviceBatch(b)
+    db2.pack_stream()
+    torch.cuda.synchronize()
+    assert db2.bad_bases()
+
+
+def test_host_api_matches_oracle(rt):
+    import paper_1910_09020_amd as ss
+    b = gen.make(0, n=3000)
+    acc, ed = ss.ss_filter_batch(b["reads"], b["refs"], b["lengths"], 5)
+    check("ss_filter_batch", (acc, ed), expect(b, E=5))
+    b3 = gen.make(3, n=2000, n_long=3)
+    acc, ed = ss.ss_filter_batch_var(b3["reads"], b3["refs"], b3["lengths"], b3["E"])
+    check("ss_filter_batch_var", (acc, ed), expect(b3, Epp=b3["E"]))
+
+
+def test_host_api_errors_leave_outputs(rt):
+    import paper_1910_09020_amd as ss
+    L = ss.lib()
+    b = gen.make(0, n=100)
+    refs = b["refs"].copy()
+    refs[50] = ord("x")
+    acc = np.full(100, 7, np.uint8)
+    ed = np.full(100, -9, np.int32)
+    rc = L.ss_filter_batch(b["reads"].ctypes.data, refs.ctypes.data, b["lengths"].ctypes.data, 100, 5,
+                           acc.ctypes.data, ed.ctypes.data)
+    assert rc == ss.SS_EBASE
+    assert np.all(acc == 7) and np.all(ed == -9)
+    rc = L.ss_filter_batch(b["reads"].ctypes.data, b["refs"].ctypes.data, b["lengths"].ctypes.data, 100, -1,
+                           acc.ctypes.data, ed.ctypes.data)
+    assert rc == ss.SS_EINVAL
+    assert np.all(acc == 7)
+    assert L.ss_filter_batch(None, None, None, 0, 5, None, None) == ss.SS_OK
