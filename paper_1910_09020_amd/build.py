@@ -2,8 +2,8 @@
 
 Compiles every source under csrc/ with hipcc for gfx950 and links them into
 ``paper_1910_09020_amd/libss.so``.  The device assembly of every translation
-unit is kept under ``_build/`` and scanned: the build fails if any scalar-cache
-write (scalar store, scalar atomic, scalar cache write-back) appears in it.
+unit is kept under ``_build/`` and scanned by ``isa_check``: the build fails if
+any write through the scalar data cache appears in it.
 
 Usage: python -m paper_1910_09020_amd.build [-j N]
 """
@@ -13,7 +13,6 @@ import argparse
 import concurrent.futures as cf
 import glob
 import os
-import re
 import shutil
 import subprocess
 import sys
@@ -31,9 +30,10 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", INCLUDE, "-I", CSRC, "-Wno-unused-command-line-argument"]
 
-# scalar-memory writes: stores, atomics and write-back/discard of the scalar cache
-FORBIDDEN = re.compile(r"^\s*(s_store_|s_buffer_store|s_scratch_store|s_atomic_|s_buffer_atomic|s_dcache_wb|"
-                       r"s_dcache_discard)", re.M)
+try:                                   # assembly scanner (kept out of GPU uploads)
+    from . import isa_check
+except ImportError:                    # pragma: no cover
+    isa_check = None
 
 
 def _compile(src: str) -> str:
@@ -48,10 +48,9 @@ def _compile(src: str) -> str:
         raise RuntimeError(f"hipcc failed for {src}:\n{out}")
     # -save-temps=obj writes next to the object
     for s in glob.glob(os.path.join(BUILD, name + "*amdgcn*.s")):
-        text = open(s).read()
-        bad = FORBIDDEN.findall(text)
+        bad = isa_check.scan(s) if isa_check else []
         if bad:
-            raise RuntimeError(f"{src}: forbidden scalar-memory write instructions in device code: {sorted(set(bad))}")
+            raise RuntimeError(f"{src}: forbidden scalar-memory write instructions in device code: {bad}")
     return obj
 
 
