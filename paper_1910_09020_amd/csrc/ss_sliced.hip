@@ -4,6 +4,8 @@
 // group per lane of the sweep kernel).  The encoder transposes 32 pairs at a
 // time with wavefront ballots: one ballot per (plane, position) gives the word
 // of 32 pairs for each half of the wavefront.
+#include <algorithm>
+
 #include "ss_common.h"
 
 namespace ss {
@@ -77,6 +79,106 @@ __global__ __launch_bounds__(64) void k_pack_sliced(const uint8_t* __restrict__ 
     if (bad && err) atomicOr(err, 1u);
 }
 
+// ---------------------------------------------------------------- tiled encoder
+// One 256-thread block encodes GB consecutive groups (32*GB pair slots).
+// Phase 1 copies the slots' bases into LDS as 2-bit codes (one byte per base,
+// rows padded to whole dwords, one pad dword per group so that the phase-2
+// reads of different groups fall in different banks) and validates every
+// byte: a byte b is one of ACGTacgt exactly when (b & 0xDF) equals the letter
+// its code stands for, looked up with a byte permute.  Phase 2: one thread per
+// (group, chunk of four positions) folds the 32 slots' code dwords into the
+// four words of each plane.
+__device__ __forceinline__ uint32_t codes4(uint32_t x, uint32_t& bad)
+{
+    const uint32_t cc = ((x >> 1) ^ (x >> 2)) & 0x03030303u;
+    const uint32_t letter = __builtin_amdgcn_perm(0u, 0x54474341u, cc);   // 'A','C','G','T' by code
+    bad |= (x & 0xDFDFDFDFu) ^ letter;
+    return cc;
+}
+
+__global__ __launch_bounds__(256) void k_pack_tile(const uint8_t* __restrict__ reads,
+                                                   const uint8_t* __restrict__ refs,
+                                                   const int64_t* __restrict__ offsets,
+                                                   const int64_t* __restrict__ index, int64_t n_pairs, int m,
+                                                   int64_t G, int GB, int fast, uint32_t* __restrict__ packed,
+                                                   uint32_t* __restrict__ err)
+{
+    extern __shared__ uint32_t lds[];
+    const int mw = (m + 3) >> 2;              // dwords per slot row
+    const int gs = 32 * mw + 1;               // dwords per group
+    const int nch = mw;
+    const int64_t g0 = (int64_t)blockIdx.x * GB;
+    const int64_t s0 = g0 * 32;
+    const int np = (int)min((int64_t)32 * GB, n_pairs - s0);
+    const int t = threadIdx.x;
+    uint32_t bad = 0;
+    uint4* __restrict__ out4 = reinterpret_cast<uint4*>(packed);
+    for (int side = 0; side < 2; side++) {
+        const uint8_t* __restrict__ src = side ? refs : reads;
+        if (fast) {
+            // slots s0.. are pairs s0.. stored back to back; m % 4 == 0 and the
+            // block's first byte is 16-byte aligned
+            const int ndw = np * mw;
+            const int nq = ndw >> 2;
+            const uint4* __restrict__ s128 = reinterpret_cast<const uint4*>(src + s0 * (int64_t)m);
+            for (int q = t; q < nq; q += 256) {
+                const uint4 v = s128[q];
+                const uint32_t d[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int k = 0; k < 4; k++) {
+                    const int dw = 4 * q + k;
+                    const int p = dw / mw, col = dw - p * mw;
+                    lds[(p >> 5) * gs + (p & 31) * mw + col] = codes4(d[k], bad);
+                }
+            }
+            const uint32_t* __restrict__ s32 = reinterpret_cast<const uint32_t*>(src + s0 * (int64_t)m);
+            for (int dw = 4 * nq + t; dw < ndw; dw += 256) {
+                const int p = dw / mw, col = dw - p * mw;
+                lds[(p >> 5) * gs + (p & 31) * mw + col] = codes4(s32[dw], bad);
+            }
+        } else {
+            uint8_t* lb = reinterpret_cast<uint8_t*>(lds);
+            const int nb = np * m;
+            for (int i = t; i < nb; i += 256) {
+                const int p = i / m, col = i - p * m;
+                const int64_t slot = s0 + p;
+                const int64_t pi = index ? index[slot] : slot;
+                const int64_t off = offsets ? offsets[pi] : pi * (int64_t)m;
+                uint32_t bb = 0;
+                const uint32_t c = codes4((uint32_t)src[off + col] | 0x41414100u, bb);   // pad the other lanes with 'A'
+                bad |= bb;
+                lb[4 * ((p >> 5) * gs + (p & 31) * mw) + col] = (uint8_t)(c & 3u);
+            }
+        }
+        __syncthreads();
+        for (int task = t; task < GB * nch; task += 256) {
+            const int gl = task % GB, c = task / GB;
+            if (g0 + gl >= G) continue;
+            uint32_t lo[4] = {0u, 0u, 0u, 0u}, hi[4] = {0u, 0u, 0u, 0u};
+            const uint32_t* __restrict__ row = lds + gl * gs + c;
+#pragma unroll
+            for (int s = 0; s < 32; s++) {
+                const uint32_t cc = row[s * mw];
+                lo[s >> 3] |= (cc & 0x01010101u) << (s & 7);
+                hi[s >> 3] |= ((cc >> 1) & 0x01010101u) << (s & 7);
+            }
+            uint32_t wl[4], wh[4];
+#pragma unroll
+            for (int tt = 0; tt < 4; tt++) {
+                // word of position 4c+tt: byte q = slots 8q..8q+7
+                const uint32_t sel01 = (uint32_t)tt | ((uint32_t)(tt + 4) << 8) | 0x0C0C0000u;
+                const uint32_t sel23 = 0x00000C0Cu | ((uint32_t)tt << 16) | ((uint32_t)(tt + 4) << 24);
+                wl[tt] = __builtin_amdgcn_perm(lo[1], lo[0], sel01) | __builtin_amdgcn_perm(lo[3], lo[2], sel23);
+                wh[tt] = __builtin_amdgcn_perm(hi[1], hi[0], sel01) | __builtin_amdgcn_perm(hi[3], hi[2], sel23);
+            }
+            out4[((int64_t)(2 * side) * nch + c) * G + g0 + gl] = make_uint4(wl[0], wl[1], wl[2], wl[3]);
+            out4[((int64_t)(2 * side + 1) * nch + c) * G + g0 + gl] = make_uint4(wh[0], wh[1], wh[2], wh[3]);
+        }
+        __syncthreads();
+    }
+    if (bad && err) atomicOr(err, 1u);
+}
+
 }  // namespace
 
 hipError_t launch_sliced_lo(int E, const uint32_t* packed, int64_t n, int32_t m, uint16_t* out, hipStream_t s);
@@ -89,6 +191,20 @@ hipError_t launch_pack_sliced(const uint8_t* reads, const uint8_t* refs, const i
 {
     const int64_t G = cdiv(n_pairs, 32);
     if (G == 0 || m == 0) return hipSuccess;
+    const int64_t mw = cdiv(m, 4);
+    const int64_t group_bytes = (32 * mw + 1) * 4;
+    if (group_bytes <= 65536) {
+        // tiled path: GB groups per block, LDS <= 32 KiB when possible
+        int GB = (int)std::max<int64_t>(1, std::min<int64_t>(8, 32768 / group_bytes));
+        const bool fast = index == nullptr && m % 4 == 0 &&
+                          ((((uintptr_t)reads | (uintptr_t)refs) & 15u) == 0) && (((int64_t)GB * 32 * m) % 16 == 0);
+        // the fast path needs pair i at byte i*m
+        const bool contiguous = offsets == nullptr;
+        const size_t shmem = (size_t)GB * group_bytes;
+        hipLaunchKernelGGL(k_pack_tile, dim3((unsigned)cdiv(G, GB)), dim3(256), shmem, s, reads, refs, offsets, index,
+                           n_pairs, m, G, GB, (fast && contiguous) ? 1 : 0, packed, err);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_pack_sliced, dim3((unsigned)G), dim3(64), 0, s, reads, refs, offsets, index, n_pairs, m,
                        G, packed, err);
     return hipGetLastError();

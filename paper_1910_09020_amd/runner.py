@@ -49,6 +49,9 @@ class DeviceBatch:
         self.E_np = None if E is None else np.ascontiguousarray(E, dtype=np.int32)
         self.E = None if E is None else torch.from_numpy(self.E_np).to(d)
         self.uniform_m = int(self.lengths_np[0]) if self.n and np.all(self.lengths_np == self.lengths_np[0]) else None
+        # pairs stored back to back (pair i at byte i*m): the encoder can stream them
+        self.contiguous = self.uniform_m is not None and bool(
+            np.array_equal(self.offsets_np, np.arange(self.n, dtype=np.int64) * self.uniform_m))
         self.err = torch.zeros(1, dtype=torch.int32, device=d)
 
     # ---- encodings -------------------------------------------------------------
@@ -62,7 +65,8 @@ class DeviceBatch:
         if packed is None:
             packed = torch.empty(words, dtype=torch.int32, device=_dev(self.device))
         assert packed.numel() >= words
-        ss_pack_sliced_async(context(self.device), self.reads, self.refs, self.offsets, index, n, m, packed,
+        offsets = None if (index is None and self.contiguous) else self.offsets
+        ss_pack_sliced_async(context(self.device), self.reads, self.refs, offsets, index, n, m, packed,
                              self.err, stream or torch.cuda.current_stream(self.device))
         return packed
 
