@@ -113,22 +113,40 @@ __global__ __launch_bounds__(256) void k_pack_tile(const uint8_t* __restrict__ r
     const int t = threadIdx.x;
     uint32_t bad = 0;
     uint4* __restrict__ out4 = reinterpret_cast<uint4*>(packed);
+    // fast path: slots s0.. are pairs s0.. stored back to back, m % 4 == 0, the
+    // block's first byte is 16-byte aligned and the block holds at most
+    // 256 * kQ 16-byte loads per side.  Every load of both sides is issued
+    // before any is consumed, to keep enough bytes in flight.
+    constexpr int kQ = 8;
+    const int ndw = np * mw;
+    const int nq = ndw >> 2;
+    uint4 v[2][kQ];
+    if (fast) {
+#pragma unroll
+        for (int sd = 0; sd < 2; sd++) {
+            const uint4* __restrict__ s128 = reinterpret_cast<const uint4*>((sd ? refs : reads) + s0 * (int64_t)m);
+#pragma unroll
+            for (int k = 0; k < kQ; k++) {
+                const int q = t + 256 * k;
+                if (q < nq) v[sd][k] = s128[q];
+            }
+        }
+    }
+#pragma unroll
     for (int side = 0; side < 2; side++) {
         const uint8_t* __restrict__ src = side ? refs : reads;
         if (fast) {
-            // slots s0.. are pairs s0.. stored back to back; m % 4 == 0 and the
-            // block's first byte is 16-byte aligned
-            const int ndw = np * mw;
-            const int nq = ndw >> 2;
-            const uint4* __restrict__ s128 = reinterpret_cast<const uint4*>(src + s0 * (int64_t)m);
-            for (int q = t; q < nq; q += 256) {
-                const uint4 v = s128[q];
-                const uint32_t d[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-                for (int k = 0; k < 4; k++) {
-                    const int dw = 4 * q + k;
-                    const int p = dw / mw, col = dw - p * mw;
-                    lds[(p >> 5) * gs + (p & 31) * mw + col] = codes4(d[k], bad);
+            for (int k = 0; k < kQ; k++) {
+                const int q = t + 256 * k;
+                if (q < nq) {
+                    const uint32_t d[4] = {v[side][k].x, v[side][k].y, v[side][k].z, v[side][k].w};
+#pragma unroll
+                    for (int e = 0; e < 4; e++) {
+                        const int dw = 4 * q + e;
+                        const int p = dw / mw, col = dw - p * mw;
+                        lds[(p >> 5) * gs + (p & 31) * mw + col] = codes4(d[e], bad);
+                    }
                 }
             }
             const uint32_t* __restrict__ s32 = reinterpret_cast<const uint32_t*>(src + s0 * (int64_t)m);
@@ -196,8 +214,9 @@ hipError_t launch_pack_sliced(const uint8_t* reads, const uint8_t* refs, const i
     if (group_bytes <= 65536) {
         // tiled path: GB groups per block, LDS <= 32 KiB when possible
         int GB = (int)std::max<int64_t>(1, std::min<int64_t>(8, 32768 / group_bytes));
-        const bool fast = index == nullptr && m % 4 == 0 &&
-                          ((((uintptr_t)reads | (uintptr_t)refs) & 15u) == 0) && (((int64_t)GB * 32 * m) % 16 == 0);
+        // the streaming path: at most 8 sixteen-byte loads per thread and side
+        const bool fast = index == nullptr && m % 4 == 0 && (int64_t)GB * mw <= 256 &&
+                          ((((uintptr_t)reads | (uintptr_t)refs) & 15u) == 0);
         // the fast path needs pair i at byte i*m
         const bool contiguous = offsets == nullptr;
         const size_t shmem = (size_t)GB * group_bytes;
