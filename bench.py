@@ -124,6 +124,19 @@ def main():
         log(f"plain: encode {ps_ms:.3f} ms filter {pf_ms:.3f} ms identical={plain['identical_outputs']}")
         del ps, pout
 
+    # HBM calibration: a device-to-device copy of 2 GiB (reads and writes 2 GiB each)
+    del db.reads, db.refs
+    torch.cuda.empty_cache()
+    src = torch.empty(2 << 30, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    cp = lambda: dst.copy_(src)
+    cp(); torch.cuda.synchronize()
+    _, (cp_ms,) = timed_loop([cp], 5, torch)
+    copy_gbs = 2 * src.numel() / (cp_ms * 1e-3) / 1e9
+    log(f"device copy: {copy_gbs:.0f} GB/s (read + write)")
+    del src, dst
+
     cpu = None
     if not a.no_cpu:
         threads = min(16, os.cpu_count() or 1)
@@ -165,6 +178,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None},
         "cpu_baseline": cpu,
+        "hbm_copy_calibration_gbs": copy_gbs,
     }
     print(json.dumps(line), flush=True)
 
