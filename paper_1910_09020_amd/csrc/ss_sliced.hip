@@ -120,8 +120,10 @@ __global__ __launch_bounds__(256) void k_pack_tile(const uint8_t* __restrict__ r
     constexpr int kQ = 8;
     const int ndw = np * mw;
     const int nq = ndw >> 2;
-    // dw / mw by multiply-high: exact for dw < 2^16 and mw < 2^16
-    const uint32_t rmw = 0xFFFFFFFFu / (uint32_t)mw + 1u;
+    // dw / mw by multiply-high, exact for dw < 2^16 and 2 <= mw < 2^16 (the
+    // reciprocal of mw = 1 does not fit 32 bits: that case divides by itself)
+    const uint32_t rmw = mw > 1 ? 0xFFFFFFFFu / (uint32_t)mw + 1u : 0u;
+    auto row_of = [&](int dw) { return mw > 1 ? (int)__umulhi((uint32_t)dw, rmw) : dw; };
     uint4 v[2][kQ];
     if (fast) {
 #pragma unroll
@@ -146,14 +148,14 @@ __global__ __launch_bounds__(256) void k_pack_tile(const uint8_t* __restrict__ r
 #pragma unroll
                     for (int e = 0; e < 4; e++) {
                         const int dw = 4 * q + e;
-                        const int p = (int)__umulhi((uint32_t)dw, rmw), col = dw - p * mw;
+                        const int p = row_of(dw), col = dw - p * mw;
                         lds[(p >> 5) * gs + (p & 31) * mw + col] = codes4(d[e], bad);
                     }
                 }
             }
             const uint32_t* __restrict__ s32 = reinterpret_cast<const uint32_t*>(src + s0 * (int64_t)m);
             for (int dw = 4 * nq + t; dw < ndw; dw += 256) {
-                const int p = (int)__umulhi((uint32_t)dw, rmw), col = dw - p * mw;
+                const int p = row_of(dw), col = dw - p * mw;
                 lds[(p >> 5) * gs + (p & 31) * mw + col] = codes4(s32[dw], bad);
             }
         } else {
