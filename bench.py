@@ -50,6 +50,67 @@ def timed_loop(fns, steps, torch):
     return wall, per
 
 
+def mixed_leg(a, torch, ss, gen, runner, oracle):
+    """Mixed-length batch (5 M short pairs of 100/150/250 bp + 20,000 pairs of 10 kbp, per-pair E):
+    one persistent launch from an autotuned plan, replayed from a captured HIP graph, against one
+    unbucketed launch of the wavefront kernel over the batch in input order (every pair laid out for
+    the largest threshold).  Both run on the same bit-stream encoding resident in HBM."""
+    t = time.perf_counter()
+    b = gen.make(3, n=a.mixed_n, threads=min(16, os.cpu_count() or 1))
+    n = b["n"]
+    log(f"mixed: generated {n} pairs ({int((b['lengths'] >= 10000).sum())} long) in {time.perf_counter() - t:.1f}s")
+    db = runner.DeviceBatch(b)
+    ps = db.pack_stream()
+    torch.cuda.synchronize()
+    enc = lambda: db.pack_stream(packed=ps)
+    _, (enc_ms,) = timed_loop([enc], 3, torch)
+    ctx = runner.context()
+    out = db.new_out()
+    cache = os.environ.get("SS_TUNE_CACHE", "/tmp/ss_tune_cache.json")
+    t = time.perf_counter()
+    plan, chosen = ss.ss_plan_create_tuned(ctx, b["lengths"], b["E"], ps, db.total, db.offsets, db.lengths, db.E,
+                                           out, cache)
+    plan_s = time.perf_counter() - t
+    info = ss.ss_plan_info(plan)
+    ss.ss_plan_capture(ctx, plan, ps, db.total, db.offsets, db.lengths, db.E, out)
+    stream = torch.cuda.current_stream()
+    run = lambda: ss.ss_plan_launch(plan, stream)
+    for _ in range(max(1, a.warmup)):
+        run()
+    torch.cuda.synchronize()
+    _, (bat_ms,) = timed_loop([run], max(3, a.steps // 2), torch)
+    acc, ed = runner.results_numpy(out, n)
+    emax = int(b["E"].max())
+    uout = db.new_out()
+    flat = lambda: db.filter_wave(ps, emax, per_pair=True, out=uout)
+    flat(); torch.cuda.synchronize()
+    _, (flat_ms,) = timed_loop([flat], 2, torch)
+    uacc, ued = runner.results_numpy(uout, n)
+    identical = bool(np.array_equal(acc, uacc) and np.array_equal(ed, ued))
+    # sampled oracle check: short pairs and long pairs separately
+    rng = np.random.default_rng(11)
+    long_idx = np.nonzero(b["lengths"] >= 10000)[0]
+    short_idx = np.nonzero(b["lengths"] < 10000)[0]
+    idx = np.sort(np.concatenate([rng.choice(short_idx, size=min(50000, len(short_idx)), replace=False),
+                                  rng.choice(long_idx, size=min(400, len(long_idx)), replace=False)]))
+    w = oracle.batch(b["reads"], b["refs"], b["offsets"][idx], b["lengths"][idx], E_per_pair=b["E"][idx],
+                     threads=min(16, os.cpu_count() or 1))
+    mism = int(np.sum((w["accept"] != acc[idx]) | (w["edits"] != ed[idx])))
+    ss.ss_plan_destroy(plan)
+    res = dict(workload="5M short (100/150/250 bp) + 20k x 10 kbp, per-pair E = ceil(rate x m), rate in "
+                        "{1,2,5,10}%", n_pairs=n, encode_ms=round(enc_ms, 4), batched_ms=round(bat_ms, 4),
+               batched_pairs_per_s=n / (1e-3 * bat_ms), step_pairs_per_s=n / (1e-3 * (bat_ms + enc_ms)),
+               unbucketed_ms=round(flat_ms, 4), unbucketed_pairs_per_s=n / (1e-3 * flat_ms),
+               speedup_vs_unbucketed=flat_ms / bat_ms, identical_outputs=identical, plan_seconds=round(plan_s, 3),
+               plan=info, tuned_slices_per_lane=chosen, oracle_sample_pairs=int(len(idx)),
+               oracle_sample_mismatches=mism)
+    log(f"mixed: batched {bat_ms:.3f} ms, unbucketed {flat_ms:.3f} ms, identical={identical}, "
+        f"oracle mismatches {mism}/{len(idx)}, plan {plan_s:.2f}s {info}")
+    del db, ps, out, uout
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -60,6 +121,8 @@ def main():
     ap.add_argument("--sample", type=int, default=200000, help="pairs checked against the oracle")
     ap.add_argument("--cpu-pairs", type=int, default=12_000_000, help="oracle baseline sample")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--mixed-n", type=int, default=None, help="pairs of the mixed-length batch (default 5.02 M)")
     ap.add_argument("--no-cpu", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1:
@@ -125,7 +188,8 @@ def main():
         del ps, pout
 
     # HBM calibration: a device-to-device copy of 2 GiB (reads and writes 2 GiB each)
-    del db.reads, db.refs
+    del db.reads, db.refs, packed
+    torch.cuda.empty_cache()
     torch.cuda.empty_cache()
     src = torch.empty(2 << 30, dtype=torch.uint8, device="cuda")
     dst = torch.empty_like(src)
@@ -136,6 +200,10 @@ def main():
     copy_gbs = 2 * src.numel() / (cp_ms * 1e-3) / 1e9
     log(f"device copy: {copy_gbs:.0f} GB/s (read + write)")
     del src, dst
+
+    mixed = None
+    if not a.no_mixed:
+        mixed = mixed_leg(a, torch, ss, gen, runner, oracle)
 
     cpu = None
     if not a.no_cpu:
@@ -179,6 +247,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None},
         "cpu_baseline": cpu,
         "hbm_copy_calibration_gbs": copy_gbs,
+        "mixed": mixed,
     }
     print(json.dumps(line), flush=True)
 

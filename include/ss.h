@@ -170,6 +170,54 @@ int ss_filter_wave_async(ss_ctx* ctx, const uint32_t* packed, int64_t total_base
                          const int32_t* E_per_pair, int64_t n_pairs, int32_t E,
                          uint16_t* out, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Batched launch: pairs of uneven lengths with a threshold per pair, all in
+ * one persistent kernel.  Not part of the paper (its GPU design launches one
+ * thread per pair, Section 2.6); it runs the wavefront sweep above on work
+ * items popped from a device queue.
+ *
+ * A plan is built on the host from the pairs' lengths and thresholds (host
+ * arrays, copied; the plan keeps no pointer to them): each pair gets a shape
+ * (lanes per pair, 32-row slices per lane, at most slices_per_lane = 4 or 8)
+ * from its threshold; pairs are sorted by shape and length, cut into work
+ * items of one 256-thread block round, and the items ordered largest
+ * estimated cost first.  The plan owns its device buffers (permutation, item
+ * table, queue counter) and is bound to the device current at creation.
+ * ---------------------------------------------------------------------- */
+typedef struct ss_plan ss_plan;
+int ss_plan_create(ss_ctx* ctx, const int32_t* lengths, const int32_t* E_per_pair, int64_t n_pairs,
+                   int32_t slices_per_lane, ss_plan** out);
+int ss_plan_destroy(ss_plan* plan);
+/* Items in the queue, shape classes, persistent grid size, slices per lane. */
+int ss_plan_info(const ss_plan* plan, int64_t* n_items, int32_t* n_classes, int32_t* grid,
+                 int32_t* slices_per_lane);
+
+/* Run a plan on bit-stream encoded pairs (device arrays as for
+ * ss_filter_wave_async; E_per_pair is required).  Enqueues a counter reset
+ * and the persistent kernel on stream.  One call at a time per plan (the
+ * queue counter is part of the plan). */
+int ss_filter_planned_async(ss_ctx* ctx, const ss_plan* plan, const uint32_t* packed, int64_t total_bases,
+                            const int64_t* offsets, const int32_t* lengths, const int32_t* E_per_pair,
+                            uint16_t* out, void* stream);
+
+/* Capture the planned launch for these device buffers into a HIP graph held
+ * by the plan (replacing any earlier capture); ss_plan_launch replays it on
+ * stream.  The buffers must outlive every replay. */
+int ss_plan_capture(ss_ctx* ctx, ss_plan* plan, const uint32_t* packed, int64_t total_bases,
+                    const int64_t* offsets, const int32_t* lengths, const int32_t* E_per_pair, uint16_t* out);
+int ss_plan_launch(ss_plan* plan, void* stream);
+
+/* Autotuned plan: times the candidate shapes (4 and 8 slices per lane) on
+ * this batch with the given device buffers (out_dev is overwritten), keeps
+ * the fastest and records it in the JSON file cache_path (may be NULL) under
+ * a key made of the device architecture and a coarse signature of the batch;
+ * a later call with a matching key skips the timing.  *chosen_slices (may be
+ * NULL) receives the choice.  Synchronous. */
+int ss_plan_create_tuned(ss_ctx* ctx, const int32_t* lengths, const int32_t* E_per_pair, int64_t n_pairs,
+                         const uint32_t* packed, int64_t total_bases, const int64_t* offsets_dev,
+                         const int32_t* lengths_dev, const int32_t* E_dev, uint16_t* out_dev,
+                         const char* cache_path, ss_plan** out, int32_t* chosen_slices);
+
 /* Expand device result words into accept bytes and int32 counts (device). */
 int ss_unpack_results_async(ss_ctx* ctx, const uint16_t* results, int64_t n_pairs,
                             uint8_t* accept_out, int32_t* edits_out, void* stream);

@@ -60,6 +60,14 @@ def lib():
         "ss_filter_plain_async": ([vp, vp, i64, vp, vp, vp, i64, i32, vp, vp], ctypes.c_int),
         "ss_filter_wave_async": ([vp, vp, i64, vp, vp, vp, i64, i32, vp, vp], ctypes.c_int),
         "ss_unpack_results_async": ([vp, vp, i64, vp, vp, vp], ctypes.c_int),
+        "ss_plan_create": ([vp, vp, vp, i64, i32, ctypes.POINTER(vp)], ctypes.c_int),
+        "ss_plan_destroy": ([vp], ctypes.c_int),
+        "ss_plan_info": ([vp, vp, vp, vp, vp], ctypes.c_int),
+        "ss_filter_planned_async": ([vp, vp, vp, i64, vp, vp, vp, vp, vp], ctypes.c_int),
+        "ss_plan_capture": ([vp, vp, vp, i64, vp, vp, vp, vp], ctypes.c_int),
+        "ss_plan_launch": ([vp, vp], ctypes.c_int),
+        "ss_plan_create_tuned": ([vp, vp, vp, i64, vp, i64, vp, vp, vp, vp, ctypes.c_char_p, ctypes.POINTER(vp),
+                                  vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -73,7 +81,9 @@ def exported_symbols():
     """Names of the C entry points this binding declares."""
     return ["ss_status_str", "ss_filter_batch", "ss_filter_batch_var", "ss_create", "ss_destroy",
             "ss_sliced_bytes", "ss_stream_words", "ss_pack_sliced_async", "ss_filter_sliced_async",
-            "ss_pack_stream_async", "ss_filter_plain_async", "ss_filter_wave_async", "ss_unpack_results_async"]
+            "ss_pack_stream_async", "ss_filter_plain_async", "ss_filter_wave_async", "ss_unpack_results_async",
+            "ss_plan_create", "ss_plan_destroy", "ss_plan_info", "ss_filter_planned_async", "ss_plan_capture",
+            "ss_plan_launch", "ss_plan_create_tuned"]
 
 
 def status_str(status: int) -> str:
@@ -187,6 +197,56 @@ def ss_filter_wave_async(ctx, packed, total_bases, offsets, lengths, E_per_pair,
 def ss_unpack_results_async(ctx, results, n_pairs, accept_out, edits_out, stream=None):
     _check(lib().ss_unpack_results_async(ctx, _ptr(results), int(n_pairs), _ptr(accept_out), _ptr(edits_out),
                                          _stream(stream)), "ss_unpack_results_async")
+
+
+# ---------------------------------------------------------------- batched launch
+def ss_plan_create(ctx, lengths, E_per_pair, slices_per_lane: int = 8) -> int:
+    lengths = np.ascontiguousarray(lengths, dtype=np.int32)
+    Epp = np.ascontiguousarray(E_per_pair, dtype=np.int32)
+    h = ctypes.c_void_p()
+    _check(lib().ss_plan_create(ctx, _ptr(lengths), _ptr(Epp), len(lengths), int(slices_per_lane), ctypes.byref(h)),
+           "ss_plan_create")
+    return h.value
+
+
+def ss_plan_destroy(plan) -> None:
+    _check(lib().ss_plan_destroy(plan), "ss_plan_destroy")
+
+
+def ss_plan_info(plan) -> dict:
+    ni = ctypes.c_int64(0)
+    nc, gr, rs = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
+    _check(lib().ss_plan_info(plan, ctypes.addressof(ni), ctypes.addressof(nc), ctypes.addressof(gr),
+                              ctypes.addressof(rs)), "ss_plan_info")
+    return dict(items=ni.value, classes=nc.value, grid=gr.value, slices_per_lane=rs.value)
+
+
+def ss_filter_planned_async(ctx, plan, packed, total_bases, offsets, lengths, E_per_pair, out, stream=None):
+    _check(lib().ss_filter_planned_async(ctx, plan, _ptr(packed), int(total_bases), _ptr(offsets), _ptr(lengths),
+                                         _ptr(E_per_pair), _ptr(out), _stream(stream)), "ss_filter_planned_async")
+
+
+def ss_plan_capture(ctx, plan, packed, total_bases, offsets, lengths, E_per_pair, out):
+    _check(lib().ss_plan_capture(ctx, plan, _ptr(packed), int(total_bases), _ptr(offsets), _ptr(lengths),
+                                 _ptr(E_per_pair), _ptr(out)), "ss_plan_capture")
+
+
+def ss_plan_launch(plan, stream=None):
+    _check(lib().ss_plan_launch(plan, _stream(stream)), "ss_plan_launch")
+
+
+def ss_plan_create_tuned(ctx, lengths, E_per_pair, packed, total_bases, offsets_dev, lengths_dev, E_dev, out_dev,
+                         cache_path=None):
+    """Returns (plan handle, chosen slices per lane)."""
+    lengths = np.ascontiguousarray(lengths, dtype=np.int32)
+    Epp = np.ascontiguousarray(E_per_pair, dtype=np.int32)
+    h = ctypes.c_void_p()
+    ch = ctypes.c_int32(0)
+    cp = cache_path.encode() if cache_path else None
+    _check(lib().ss_plan_create_tuned(ctx, _ptr(lengths), _ptr(Epp), len(lengths), _ptr(packed), int(total_bases),
+                                      _ptr(offsets_dev), _ptr(lengths_dev), _ptr(E_dev), _ptr(out_dev), cp,
+                                      ctypes.byref(h), ctypes.addressof(ch)), "ss_plan_create_tuned")
+    return h.value, ch.value
 
 
 def decode_results(res: np.ndarray):

@@ -1,0 +1,483 @@
+// Batched launch for pairs of uneven lengths and per-pair thresholds.
+//
+// Planning (host): every pair gets a shape class from its threshold (lanes per
+// pair LP and 32-row slices per lane rs, see wave::shape_for).  Pairs are
+// sorted by class and length, cut into work items of one block-round (four
+// wavefronts of 64 / LP pairs each) and the items are ordered by estimated
+// cost, largest first, so that the long pairs start early and the short ones
+// fill in behind.
+//
+// Launch: one persistent kernel; each 256-thread block pops the next item
+// from a device counter and runs the wavefront sweep of ss_wave.h on it, until
+// the queue is empty.  Every block exits once the counter passes the number
+// of items, so the grid always drains.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <new>
+#include <numeric>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "ss.h"
+#include "ss_common.h"
+#include "ss_wave.h"
+
+namespace ss {
+
+struct PItem {
+    int64_t first;    // first slot in the permutation
+    int32_t count;    // pairs in this item
+    int16_t lp;       // lanes per pair
+    int16_t rs;       // slices per lane
+    int32_t emax;     // row layout threshold (max E over the item's pairs)
+    int32_t pad;
+};
+static_assert(sizeof(PItem) == 24, "PItem layout");
+
+namespace {
+
+__global__ void k_zero_counter(int* c) { if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0; }
+
+template <int RS>
+__global__ __launch_bounds__(256) void k_persist(const PItem* __restrict__ items, int n_items, int* __restrict__ head,
+                                                 const int64_t* __restrict__ perm, const uint32_t* __restrict__ pk,
+                                                 int64_t SW, const int64_t* __restrict__ offsets,
+                                                 const int32_t* __restrict__ lengths,
+                                                 const int32_t* __restrict__ Epp, uint16_t* __restrict__ out)
+{
+    __shared__ int s_item;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(head, 1);
+        __syncthreads();
+        const int it = s_item;
+        __syncthreads();
+        if (it >= n_items) break;
+        const PItem I = items[it];
+        const int LP = I.lp;
+        const int PW = 64 / LP;
+        const int k = wv * PW + lane / LP;
+        const bool ok = k < I.count;
+        const int64_t pi = ok ? perm[I.first + k] : perm[I.first];
+        const int m = ok ? lengths[pi] : 0;
+        const int Ei = ok ? Epp[pi] : 0;
+        const int lip = lane % LP;
+        const int c = wave::sweep_pair<RS, 0>(pk, SW, offsets[pi], m, Ei, ok, LP, lip, I.rs, I.emax);
+        if (ok && lip == 0) out[pi] = wave::result_word(c, Ei);
+    }
+}
+
+}  // namespace
+}  // namespace ss
+
+using namespace ss;
+
+// Tunables chosen per plan.
+struct PlanCfg {
+    int rsmax = 8;          // slices per lane at most (4 or 8)
+};
+
+struct ss_plan {
+    int device = 0;
+    int64_t n = 0;
+    PlanCfg cfg;
+    std::vector<PItem> items;
+    std::vector<int64_t> perm;
+    PItem* d_items = nullptr;
+    int64_t* d_perm = nullptr;
+    int* d_head = nullptr;
+    int grid = 0;
+    double est_cost = 0;
+    int n_classes = 0;
+    // captured launch
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+int map_err(hipError_t e)
+{
+    if (e == hipSuccess) return SS_OK;
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return SS_ENOMEM;
+    return SS_EDEVICE;
+}
+
+int build_plan(ss_plan* P, const int32_t* lengths, const int32_t* E, int64_t n)
+{
+    // shape class per pair
+    std::vector<int32_t> cls((size_t)n);
+    std::map<std::pair<int, int>, int> class_id;
+    std::vector<std::pair<int, int>> shapes;
+    for (int64_t i = 0; i < n; i++) {
+        int lp, rs;
+        wave::shape_for(E[i], P->cfg.rsmax, &lp, &rs);
+        auto key = std::make_pair(lp, rs);
+        auto it = class_id.find(key);
+        int id;
+        if (it == class_id.end()) {
+            id = (int)shapes.size();
+            class_id.emplace(key, id);
+            shapes.push_back(key);
+        } else {
+            id = it->second;
+        }
+        cls[(size_t)i] = id;
+    }
+    P->n_classes = (int)shapes.size();
+    // sort by (class, length desc, E desc): pairs of one wavefront share the column loop
+    P->perm.resize((size_t)n);
+    std::iota(P->perm.begin(), P->perm.end(), (int64_t)0);
+    std::stable_sort(P->perm.begin(), P->perm.end(), [&](int64_t a, int64_t b) {
+        if (cls[(size_t)a] != cls[(size_t)b]) return cls[(size_t)a] < cls[(size_t)b];
+        if (lengths[a] != lengths[b]) return lengths[a] > lengths[b];
+        return E[a] > E[b];
+    });
+    // cut into items of one block-round
+    P->items.clear();
+    std::vector<double> cost;
+    P->est_cost = 0;
+    int64_t i = 0;
+    while (i < n) {
+        const int c = cls[(size_t)P->perm[(size_t)i]];
+        const int lp = shapes[(size_t)c].first, rs = shapes[(size_t)c].second;
+        const int per_item = 4 * (64 / lp);
+        int64_t j = i;
+        int32_t emax = 0;
+        double work = 0;
+        int64_t mmax = 0;
+        while (j < n && j - i < per_item && cls[(size_t)P->perm[(size_t)j]] == c) {
+            const int64_t p = P->perm[(size_t)j];
+            emax = std::max(emax, E[p]);
+            mmax = std::max<int64_t>(mmax, lengths[p]);
+            j++;
+        }
+        // a block-round costs its longest pair's columns times the lanes' slices
+        work = (double)mmax * (double)rs * (double)(4 * 64) / 64.0;
+        PItem it;
+        it.first = i;
+        it.count = (int32_t)(j - i);
+        it.lp = (int16_t)lp;
+        it.rs = (int16_t)rs;
+        it.emax = emax;
+        it.pad = 0;
+        P->items.push_back(it);
+        cost.push_back(work);
+        P->est_cost += work;
+        i = j;
+    }
+    // largest items first
+    std::vector<size_t> order(P->items.size());
+    std::iota(order.begin(), order.end(), (size_t)0);
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
+    std::vector<PItem> sorted;
+    sorted.reserve(order.size());
+    for (size_t k : order) sorted.push_back(P->items[k]);
+    P->items.swap(sorted);
+    return SS_OK;
+}
+
+int upload_plan(ss_plan* P)
+{
+    hipError_t e;
+    const size_t ib = std::max<size_t>(P->items.size(), 1) * sizeof(PItem);
+    const size_t pb = std::max<size_t>(P->perm.size(), 1) * sizeof(int64_t);
+    if ((e = hipMalloc(&P->d_items, ib)) != hipSuccess) return map_err(e);
+    if ((e = hipMalloc(&P->d_perm, pb)) != hipSuccess) return map_err(e);
+    if ((e = hipMalloc(&P->d_head, 256)) != hipSuccess) return map_err(e);
+    if (!P->items.empty() &&
+        (e = hipMemcpy(P->d_items, P->items.data(), P->items.size() * sizeof(PItem), hipMemcpyHostToDevice)) != hipSuccess)
+        return map_err(e);
+    if (!P->perm.empty() &&
+        (e = hipMemcpy(P->d_perm, P->perm.data(), P->perm.size() * sizeof(int64_t), hipMemcpyHostToDevice)) != hipSuccess)
+        return map_err(e);
+    // persistent grid: resident blocks per CU x CUs, no more blocks than items
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    hipDeviceProp_t prop;
+    if ((e = hipGetDeviceProperties(&prop, dev)) != hipSuccess) return map_err(e);
+    int per_cu = 1;
+    if (P->cfg.rsmax <= 4) (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persist<4>, 256, 0);
+    else (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persist<8>, 256, 0);
+    per_cu = std::max(1, per_cu);
+    P->grid = (int)std::min<int64_t>((int64_t)per_cu * prop.multiProcessorCount, std::max<size_t>(P->items.size(), 1));
+    return SS_OK;
+}
+
+void free_plan(ss_plan* P)
+{
+    if (P->exec) (void)hipGraphExecDestroy(P->exec);
+    if (P->graph) (void)hipGraphDestroy(P->graph);
+    if (P->d_items) (void)hipFree(P->d_items);
+    if (P->d_perm) (void)hipFree(P->d_perm);
+    if (P->d_head) (void)hipFree(P->d_head);
+    P->exec = nullptr; P->graph = nullptr; P->d_items = nullptr; P->d_perm = nullptr; P->d_head = nullptr;
+}
+
+hipError_t enqueue(const ss_plan* P, const uint32_t* packed, int64_t total_bases, const int64_t* offsets,
+                   const int32_t* lengths, const int32_t* Epp, uint16_t* out, hipStream_t s)
+{
+    if (P->items.empty()) return hipSuccess;
+    const int64_t SW = cdiv(total_bases, 32) + 2;
+    hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, s, P->d_head);
+    if (P->cfg.rsmax <= 4)
+        hipLaunchKernelGGL(k_persist<4>, dim3(P->grid), dim3(256), 0, s, P->d_items, (int)P->items.size(), P->d_head,
+                           P->d_perm, packed, SW, offsets, lengths, Epp, out);
+    else
+        hipLaunchKernelGGL(k_persist<8>, dim3(P->grid), dim3(256), 0, s, P->d_items, (int)P->items.size(), P->d_head,
+                           P->d_perm, packed, SW, offsets, lengths, Epp, out);
+    return hipGetLastError();
+}
+
+int validate_plan_inputs(const int32_t* lengths, const int32_t* E, int64_t n)
+{
+    if (n < 0) return SS_EINVAL;
+    if (n > 0 && (!lengths || !E)) return SS_EINVAL;
+    for (int64_t i = 0; i < n; i++) {
+        if (lengths[i] < 0 || E[i] < 0) return SS_EINVAL;
+        if (lengths[i] > SS_MAX_LEN || E[i] > SS_MAX_E) return SS_ELEN;
+    }
+    return SS_OK;
+}
+
+int make_plan(const PlanCfg& cfg, const int32_t* lengths, const int32_t* E, int64_t n, ss_plan** out)
+{
+    ss_plan* P = new (std::nothrow) ss_plan();
+    if (!P) return SS_ENOMEM;
+    (void)hipGetDevice(&P->device);
+    P->n = n;
+    P->cfg = cfg;
+    int rc = build_plan(P, lengths, E, n);
+    if (rc == SS_OK) rc = upload_plan(P);
+    if (rc != SS_OK) {
+        free_plan(P);
+        delete P;
+        return rc;
+    }
+    *out = P;
+    return SS_OK;
+}
+
+}  // namespace
+
+extern "C" int ss_plan_create(ss_ctx* ctx, const int32_t* lengths, const int32_t* E_per_pair, int64_t n_pairs,
+                              int32_t slices_per_lane, ss_plan** out)
+{
+    if (!ctx || !out) return SS_EINVAL;
+    if (slices_per_lane != 4 && slices_per_lane != 8) return SS_EINVAL;
+    int rc = validate_plan_inputs(lengths, E_per_pair, n_pairs);
+    if (rc != SS_OK) return rc;
+    PlanCfg cfg;
+    cfg.rsmax = slices_per_lane;
+    try {
+        return make_plan(cfg, lengths, E_per_pair, n_pairs, out);
+    } catch (const std::bad_alloc&) {
+        return SS_ENOMEM;
+    }
+}
+
+extern "C" int ss_plan_destroy(ss_plan* plan)
+{
+    if (!plan) return SS_EINVAL;
+    free_plan(plan);
+    delete plan;
+    return SS_OK;
+}
+
+extern "C" int ss_plan_info(const ss_plan* plan, int64_t* n_items, int32_t* n_classes, int32_t* grid,
+                            int32_t* slices_per_lane)
+{
+    if (!plan) return SS_EINVAL;
+    if (n_items) *n_items = (int64_t)plan->items.size();
+    if (n_classes) *n_classes = plan->n_classes;
+    if (grid) *grid = plan->grid;
+    if (slices_per_lane) *slices_per_lane = plan->cfg.rsmax;
+    return SS_OK;
+}
+
+extern "C" int ss_filter_planned_async(ss_ctx* ctx, const ss_plan* plan, const uint32_t* packed, int64_t total_bases,
+                                       const int64_t* offsets, const int32_t* lengths, const int32_t* E_per_pair,
+                                       uint16_t* out, void* stream)
+{
+    if (!ctx || !plan || total_bases < 0) return SS_EINVAL;
+    if (plan->n == 0) return SS_OK;
+    if (!packed || !offsets || !lengths || !E_per_pair || !out) return SS_EINVAL;
+    return map_err(enqueue(plan, packed, total_bases, offsets, lengths, E_per_pair, out, (hipStream_t)stream));
+}
+
+// Capture the planned launch (counter reset + persistent kernel) into a HIP
+// graph bound to these device buffers; ss_plan_launch replays it.
+extern "C" int ss_plan_capture(ss_ctx* ctx, ss_plan* plan, const uint32_t* packed, int64_t total_bases,
+                               const int64_t* offsets, const int32_t* lengths, const int32_t* E_per_pair,
+                               uint16_t* out)
+{
+    if (!ctx || !plan) return SS_EINVAL;
+    if (plan->n > 0 && (!packed || !offsets || !lengths || !E_per_pair || !out)) return SS_EINVAL;
+    if (plan->exec) { (void)hipGraphExecDestroy(plan->exec); plan->exec = nullptr; }
+    if (plan->graph) { (void)hipGraphDestroy(plan->graph); plan->graph = nullptr; }
+    hipStream_t s = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e != hipSuccess) return map_err(e);
+    e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t e2 = enqueue(plan, packed, total_bases, offsets, lengths, E_per_pair, out, s);
+        e = hipStreamEndCapture(s, &plan->graph);
+        if (e2 != hipSuccess) e = e2;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0);
+    (void)hipStreamDestroy(s);
+    return map_err(e);
+}
+
+extern "C" int ss_plan_launch(ss_plan* plan, void* stream)
+{
+    if (!plan) return SS_EINVAL;
+    if (plan->n == 0) return SS_OK;
+    if (!plan->exec) return SS_EINVAL;
+    return map_err(hipGraphLaunch(plan->exec, (hipStream_t)stream));
+}
+
+// ---------------------------------------------------------------- autotuner
+// Candidate configurations are timed on the batch itself (two launches each,
+// the faster counts); the winner is stored in a JSON cache keyed by device
+// architecture and a coarse signature of the batch (pair count, length and
+// threshold ranges), so later plans for similar batches skip the timing.
+namespace {
+
+std::string signature(const char* arch, const int32_t* lengths, const int32_t* E, int64_t n)
+{
+    int32_t mlo = INT32_MAX, mhi = 0, elo = INT32_MAX, ehi = 0;
+    for (int64_t i = 0; i < n; i++) {
+        mlo = std::min(mlo, lengths[i]); mhi = std::max(mhi, lengths[i]);
+        elo = std::min(elo, E[i]); ehi = std::max(ehi, E[i]);
+    }
+    auto lg = [](int64_t v) { int b = 0; while (v > 1) { v >>= 1; b++; } return b; };
+    std::ostringstream os;
+    os << arch << "|n2^" << lg(n) << "|m2^" << lg(mlo) << "-2^" << lg(mhi) << "|E2^" << lg(elo + 1) << "-2^" << lg(ehi + 1);
+    return os.str();
+}
+
+// Minimal "key": value reader/writer for a flat JSON object of integers.
+std::map<std::string, int> read_cache(const std::string& path)
+{
+    std::map<std::string, int> m;
+    std::ifstream f(path);
+    if (!f) return m;
+    std::stringstream ss;
+    ss << f.rdbuf();
+    const std::string s = ss.str();
+    size_t i = 0;
+    while ((i = s.find('"', i)) != std::string::npos) {
+        const size_t j = s.find('"', i + 1);
+        if (j == std::string::npos) break;
+        const std::string key = s.substr(i + 1, j - i - 1);
+        const size_t c = s.find(':', j);
+        if (c == std::string::npos) break;
+        m[key] = std::atoi(s.c_str() + c + 1);
+        i = s.find_first_of(",}", c);
+        if (i == std::string::npos) break;
+    }
+    return m;
+}
+
+void write_cache(const std::string& path, const std::map<std::string, int>& m)
+{
+    const std::string tmp = path + ".tmp";
+    {
+        std::ofstream f(tmp);
+        f << "{\n";
+        size_t k = 0;
+        for (auto& kv : m) f << "  \"" << kv.first << "\": " << kv.second << (++k < m.size() ? ",\n" : "\n");
+        f << "}\n";
+    }
+    std::rename(tmp.c_str(), path.c_str());
+}
+
+std::mutex g_cache_mu;
+
+}  // namespace
+
+extern "C" int ss_plan_create_tuned(ss_ctx* ctx, const int32_t* lengths, const int32_t* E_per_pair, int64_t n_pairs,
+                                    const uint32_t* packed, int64_t total_bases, const int64_t* offsets_dev,
+                                    const int32_t* lengths_dev, const int32_t* E_dev, uint16_t* out_dev,
+                                    const char* cache_path, ss_plan** out, int32_t* chosen_slices)
+{
+    if (!ctx || !out) return SS_EINVAL;
+    int rc = validate_plan_inputs(lengths, E_per_pair, n_pairs);
+    if (rc != SS_OK) return rc;
+    if (n_pairs > 0 && (!packed || !offsets_dev || !lengths_dev || !E_dev || !out_dev)) return SS_EINVAL;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return SS_EDEVICE;
+    const std::string key = signature(prop.gcnArchName, lengths, E_per_pair, n_pairs);
+    try {
+        if (cache_path && *cache_path) {
+            std::lock_guard<std::mutex> lk(g_cache_mu);
+            auto m = read_cache(cache_path);
+            auto it = m.find(key);
+            if (it != m.end() && (it->second == 4 || it->second == 8)) {
+                PlanCfg cfg;
+                cfg.rsmax = it->second;
+                if (chosen_slices) *chosen_slices = cfg.rsmax;
+                return make_plan(cfg, lengths, E_per_pair, n_pairs, out);
+            }
+        }
+        const int cands[2] = {4, 8};
+        float best_ms = 1e30f;
+        int best = 8;
+        hipStream_t s = nullptr;
+        hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+        if (e != hipSuccess) return map_err(e);
+        hipEvent_t a = nullptr, b = nullptr;
+        (void)hipEventCreate(&a);
+        (void)hipEventCreate(&b);
+        for (int c : cands) {
+            PlanCfg cfg;
+            cfg.rsmax = c;
+            ss_plan* P = nullptr;
+            rc = make_plan(cfg, lengths, E_per_pair, n_pairs, &P);
+            if (rc != SS_OK) break;
+            float ms = 1e30f;
+            for (int rep = 0; rep < 2 && rc == SS_OK; rep++) {
+                (void)hipEventRecord(a, s);
+                e = enqueue(P, packed, total_bases, offsets_dev, lengths_dev, E_dev, out_dev, s);
+                (void)hipEventRecord(b, s);
+                if (e == hipSuccess) e = hipEventSynchronize(b);
+                float t = 0;
+                if (e == hipSuccess) (void)hipEventElapsedTime(&t, a, b);
+                else rc = map_err(e);
+                ms = std::min(ms, t);
+            }
+            free_plan(P);
+            delete P;
+            if (rc != SS_OK) break;
+            if (ms < best_ms) { best_ms = ms; best = c; }
+        }
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        (void)hipStreamDestroy(s);
+        if (rc != SS_OK) return rc;
+        if (cache_path && *cache_path) {
+            std::lock_guard<std::mutex> lk(g_cache_mu);
+            auto m = read_cache(cache_path);
+            m[key] = best;
+            write_cache(cache_path, m);
+        }
+        PlanCfg cfg;
+        cfg.rsmax = best;
+        if (chosen_slices) *chosen_slices = best;
+        return make_plan(cfg, lengths, E_per_pair, n_pairs, out);
+    } catch (const std::bad_alloc&) {
+        return SS_ENOMEM;
+    }
+}

@@ -3,7 +3,7 @@
 // Bit-stream layout: four planes (Q0, Q1, R0, R1) of the concatenated batch;
 // base b is bit b%32 of word b/32 of its plane, code A=0 C=1 G=2 T=3 (plane 0 =
 // low bit).  Every plane carries two zero guard words at its end.
-#include "ss_common.h"
+#include "ss_wave.h"
 
 namespace ss {
 namespace {
@@ -77,26 +77,8 @@ __global__ __launch_bounds__(256) void k_pack_stream(const uint8_t* __restrict__
     if (bad && err) atomicOr(err, 1u);
 }
 
-// 32 bits of a plane starting at absolute stream bit a (zero outside the buffer)
-__device__ __forceinline__ uint32_t bits32(const uint32_t* __restrict__ P, int64_t SW, int64_t a)
-{
-    const int64_t w = a >> 5;                 // arithmetic shift: floor for negative a
-    const uint32_t sh = (uint32_t)(a & 31);
-    const uint32_t lo = (w >= 0 && w < SW) ? P[w] : 0u;
-    const uint32_t hi = (w + 1 >= 0 && w + 1 < SW) ? P[w + 1] : 0u;
-    return __builtin_amdgcn_alignbit(hi, lo, sh);
-}
-
-// bits [lo, hi) of a word set (lo, hi clamped to [0, 32])
-__device__ __forceinline__ uint32_t span_mask(int lo, int hi)
-{
-    lo = lo < 0 ? 0 : (lo > 32 ? 32 : lo);
-    hi = hi < 0 ? 0 : (hi > 32 ? 32 : hi);
-    if (hi <= lo) return 0u;
-    const uint32_t up = hi == 32 ? ~0u : ((1u << hi) - 1u);
-    const uint32_t dn = (1u << lo) - 1u;      // lo < 32 here
-    return up & ~dn;
-}
+using wave::bits32;
+using wave::span_mask;
 
 // --------------------------------------------------------------- one pair per lane
 // Each lane holds one pair.  Word by word (32 columns, the same word for every
@@ -214,12 +196,8 @@ __global__ __launch_bounds__(256) void k_plain(const uint32_t* __restrict__ pk, 
 }
 
 // --------------------------------------------------------------- wavefront-cooperative
-// LP lanes per pair, RS 32-row slices per lane (slice s = lane_in_pair + LP*t
-// holds rows 32s..32s+31 of the 2E+1 rows, row index r = k + E).  Each column
-// is one step of the sweep (see the lane-sliced kernel): every row still free
-// since the checkpoint stays alive if its Equation 1 cell is 0; a wavefront
-// ballot tells whether any row of the pair is alive; if none, the column holds
-// the obstacle closing the longest escape segment: count it and free all rows.
+// Standalone launch of the sweep in ss_wave.h: LP lanes per pair, RS slices per
+// lane, pairs in input order (64 / LP pairs per wavefront).
 template <int LP, int RS>
 __global__ __launch_bounds__(256) void k_wave(const uint32_t* __restrict__ pk, int64_t SW,
                                               const int64_t* __restrict__ offsets,
@@ -229,92 +207,15 @@ __global__ __launch_bounds__(256) void k_wave(const uint32_t* __restrict__ pk, i
 {
     constexpr int PW = 64 / LP;
     const int lane = threadIdx.x & 63;
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t wv = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int grp = lane / LP, lip = lane % LP;
-    const int64_t pi = wave * PW + grp;
+    const int64_t pi = wv * PW + grp;
     const bool pair_ok = pi < n;
     const int64_t pc = pair_ok ? pi : 0;
     const int m = pair_ok ? lengths[pc] : 0;
     const int Ei = Epp ? Epp[pc] : Emax;
-    const int64_t b0 = offsets[pc];
-    const uint32_t* __restrict__ Q0 = pk;
-    const uint32_t* __restrict__ Q1 = pk + SW;
-    const uint32_t* __restrict__ R0 = pk + 2 * SW;
-    const uint32_t* __restrict__ R1 = pk + 3 * SW;
-    const int NR = 2 * Emax + 1;
-
-    uint32_t alive[RS], rmask[RS], q0lo[RS], q0hi[RS], q1lo[RS], q1hi[RS];
-#pragma unroll
-    for (int t = 0; t < RS; t++) {
-        const int s = lip + LP * t;
-        // rows r in [32s, 32s+32) that exist (r < NR) and whose |k| = |r - Emax| <= Ei
-        const int lo = Emax - Ei - 32 * s, hi = Emax + Ei + 1 - 32 * s;
-        rmask[t] = span_mask(lo, hi < NR - 32 * s ? hi : NR - 32 * s);
-        alive[t] = rmask[t];
-    }
-    int count = 0;
-    bool fin = !pair_ok || m == 0;
-    // interior blocks need no query-range mask for any pair of this wave
-    int mmin = fin ? 0x7FFFFFFF : m;
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) mmin = min(mmin, __shfl_xor(mmin, o));
-    int mmax = fin ? 0 : m;
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) mmax = max(mmax, __shfl_xor(mmax, o));
-
-    for (int jb = 0; jb < mmax; jb += 32) {
-        if (__all(fin)) break;
-        // query window of slice s for this block: pair-relative positions jb - Emax + 32 s + [0, 64)
-#pragma unroll
-        for (int t = 0; t < RS; t++) {
-            const int s = lip + LP * t;
-            const int64_t a = b0 + jb - Emax + 32 * (int64_t)s;
-            q0lo[t] = bits32(Q0, SW, a);
-            q0hi[t] = bits32(Q0, SW, a + 32);
-            q1lo[t] = bits32(Q1, SW, a);
-            q1hi[t] = bits32(Q1, SW, a + 32);
-        }
-        const uint32_t rw0 = bits32(R0, SW, b0 + jb), rw1 = bits32(R1, SW, b0 + jb);
-        const bool interior = (jb >= Emax) && (jb + 31 + Emax < mmin);
-        const int jend = min(32, mmax - jb);
-        for (int jj = 0; jj < jend; jj++) {
-            const int j = jb + jj;
-            const uint32_t rb0 = (uint32_t)((int32_t)(rw0 << (31 - jj)) >> 31);   // R bit j broadcast
-            const uint32_t rb1 = (uint32_t)((int32_t)(rw1 << (31 - jj)) >> 31);
-            uint32_t any = 0;
-#pragma unroll
-            for (int t = 0; t < RS; t++) {
-                const uint32_t x0 = __builtin_amdgcn_alignbit(q0hi[t], q0lo[t], jj);
-                const uint32_t x1 = __builtin_amdgcn_alignbit(q1hi[t], q1lo[t], jj);
-                uint32_t a = SS_BITOP3(SS_BITOP3(alive[t], x0, rb0, 0x90), x1, rb1, 0x90);
-                if (!interior) {
-                    const int s = lip + LP * t;
-                    const int base = j - Emax + 32 * s;      // query position of bit 0
-                    a &= span_mask(-base, m - base);
-                }
-                alive[t] = a;
-                any |= a;
-            }
-            bool pany = any != 0u;
-            if (LP > 1) {
-                const uint64_t bal = __ballot(pany);
-                const uint64_t gm = LP == 64 ? bal : (bal >> (grp * LP)) & ((1ull << (LP == 64 ? 0 : LP)) - 1ull);
-                pany = gm != 0ull;
-            }
-            const bool live = !fin && j < m;
-            if (live && !pany) {
-                count++;
-#pragma unroll
-                for (int t = 0; t < RS; t++) alive[t] = rmask[t];
-                if (count > Ei) fin = true;
-            }
-            if (j + 1 >= m) fin = true;
-        }
-    }
-    if (pair_ok && lip == 0) {
-        const int c = count > Ei + 1 ? Ei + 1 : count;
-        out[pi] = (uint16_t)((c <= Ei ? 0x8000u : 0u) | (uint32_t)c);
-    }
+    const int c = wave::sweep_pair<RS, LP>(pk, SW, offsets[pc], m, Ei, pair_ok, LP, lip, RS, Emax);
+    if (pair_ok && lip == 0) out[pi] = wave::result_word(c, Ei);
 }
 
 __global__ __launch_bounds__(256) void k_unpack(const uint16_t* __restrict__ res, int64_t n,
@@ -381,6 +282,7 @@ hipError_t launch_wave_R(int LP, const uint32_t* pk, int64_t SW, const int64_t* 
 
 void wave_shape(int32_t E, int* lanes_per_pair, int* slices_per_lane)
 {
+    // standalone launches use power-of-two slices per lane, up to 16
     const int SL = (int)cdiv(2 * (int64_t)E + 1, 32);
     int RS = 1;
     while (RS < SL && RS < 16) RS <<= 1;

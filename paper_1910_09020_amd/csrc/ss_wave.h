@@ -1,0 +1,161 @@
+// Wavefront-cooperative column sweep: the body shared by the standalone kernel
+// and the persistent batched kernel.
+//
+// LP lanes work on one pair; every lane holds up to RS 32-row slices of the
+// 2E+1 rows (slice s = lane_in_pair + LP * t holds rows 32s..32s+31, row index
+// r = k + Emax for diagonal offset k).  Each column is one step of the greedy
+// walk of Section 2.4 read column-wise: a row still free since the checkpoint
+// stays alive if its Equation 1 cell is 0; a wavefront ballot tells whether
+// any row of the pair is still alive; if none, the column holds the obstacle
+// that closes the longest escape segment: count it, and every row is free
+// again from the next column (the new checkpoint).  A pair stops counting once
+// its count exceeds its threshold (step 4) and reports min(count, E+1).
+#pragma once
+#include "ss_common.h"
+
+namespace ss {
+namespace wave {
+
+// three-input logic (v_bitop3_b32); truth-table index (src0 << 2) | (src1 << 1) | src2
+__device__ __forceinline__ uint32_t and_xnor(uint32_t s, uint32_t a, uint32_t b)
+{
+    return __builtin_amdgcn_bitop3_b32(s, a, b, 0x90);     // s & ~(a ^ b)
+}
+
+// 32 bits of a plane starting at absolute stream bit a (zero outside the buffer)
+__device__ __forceinline__ uint32_t bits32(const uint32_t* __restrict__ P, int64_t SW, int64_t a)
+{
+    const int64_t w = a >> 5;                 // arithmetic shift: floor for negative a
+    const uint32_t sh = (uint32_t)(a & 31);
+    const uint32_t lo = (w >= 0 && w < SW) ? P[w] : 0u;
+    const uint32_t hi = (w + 1 >= 0 && w + 1 < SW) ? P[w + 1] : 0u;
+    return __builtin_amdgcn_alignbit(hi, lo, sh);
+}
+
+// bits [lo, hi) of a word set (lo, hi clamped to [0, 32])
+__device__ __forceinline__ uint32_t span_mask(int lo, int hi)
+{
+    lo = lo < 0 ? 0 : (lo > 32 ? 32 : lo);
+    hi = hi < 0 ? 0 : (hi > 32 ? 32 : hi);
+    if (hi <= lo) return 0u;
+    const uint32_t up = hi == 32 ? ~0u : ((1u << hi) - 1u);
+    const uint32_t dn = (1u << lo) - 1u;      // lo < 32 here
+    return up & ~dn;
+}
+
+// Shape for a maximum threshold E: lanes per pair and slices per lane, with at
+// most RSMAX slices per lane.
+__host__ __device__ inline void shape_for(int32_t E, int RSMAX, int* lp, int* rs)
+{
+    const int SL = (2 * E + 1 + 31) / 32;
+    if (SL <= RSMAX) { *lp = 1; *rs = SL; return; }
+    int L = 1;
+    while ((int64_t)L * RSMAX < SL) L <<= 1;
+    *lp = L;
+    *rs = (SL + L - 1) / L;
+}
+
+// Sweep one pair with the calling lane's share of its rows.  All 64 lanes of
+// the wavefront must call this together (it uses wavefront votes).
+//   b0, m, Ei   : the pair's stream bit offset, length and threshold
+//   pair_ok     : false for lanes without a pair (they still vote)
+//   LP, lip     : lanes per pair and this lane's index in its pair
+//   rs          : slices this lane holds (<= RS); Emax: row layout threshold
+// Returns the count reported by the walk, min(count, Ei+1).
+template <int RS, int LPC>
+__device__ __forceinline__ int sweep_pair(const uint32_t* __restrict__ pk, int64_t SW, int64_t b0, int m, int Ei,
+                                          bool pair_ok, int LP_rt, int lip, int rs, int Emax)
+{
+    const int LP = LPC > 0 ? LPC : LP_rt;
+    const int lane = threadIdx.x & 63;
+    const int grp = lane / LP;
+    const uint32_t* __restrict__ Q0 = pk;
+    const uint32_t* __restrict__ Q1 = pk + SW;
+    const uint32_t* __restrict__ R0 = pk + 2 * SW;
+    const uint32_t* __restrict__ R1 = pk + 3 * SW;
+    const int NR = 2 * Emax + 1;
+
+    uint32_t alive[RS], rmask[RS], q0lo[RS], q0hi[RS], q1lo[RS], q1hi[RS];
+#pragma unroll
+    for (int t = 0; t < RS; t++) {
+        const int s = lip + LP * t;
+        // rows r in [32s, 32s+32) that exist (r < NR, t < rs) and whose |r - Emax| <= Ei
+        const int lo = Emax - Ei - 32 * s, hi = Emax + Ei + 1 - 32 * s;
+        rmask[t] = (t < rs) ? span_mask(lo, hi < NR - 32 * s ? hi : NR - 32 * s) : 0u;
+        alive[t] = rmask[t];
+        q0lo[t] = q0hi[t] = q1lo[t] = q1hi[t] = 0u;
+    }
+    int count = 0;
+    bool fin = !pair_ok || m == 0;
+    // interior blocks of columns need no query-range mask for any pair of the wavefront
+    int mmin = fin ? 0x7FFFFFFF : m;
+    int mmax = fin ? 0 : m;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        mmin = min(mmin, __shfl_xor(mmin, o));
+        mmax = max(mmax, __shfl_xor(mmax, o));
+    }
+
+    for (int jb = 0; jb < mmax; jb += 32) {
+        if (__all(fin)) break;
+        // query window of slice s for this block: pair-relative positions jb - Emax + 32 s + [0, 64)
+#pragma unroll
+        for (int t = 0; t < RS; t++) {
+            if (t < rs) {
+                const int s = lip + LP * t;
+                const int64_t a = b0 + jb - Emax + 32 * (int64_t)s;
+                q0lo[t] = bits32(Q0, SW, a);
+                q0hi[t] = bits32(Q0, SW, a + 32);
+                q1lo[t] = bits32(Q1, SW, a);
+                q1hi[t] = bits32(Q1, SW, a + 32);
+            }
+        }
+        const uint32_t rw0 = bits32(R0, SW, b0 + jb), rw1 = bits32(R1, SW, b0 + jb);
+        const bool interior = (jb >= Emax) && (jb + 31 + Emax < mmin);
+        const int jend = min(32, mmax - jb);
+        for (int jj = 0; jj < jend; jj++) {
+            const int j = jb + jj;
+            const uint32_t rb0 = (uint32_t)((int32_t)(rw0 << (31 - jj)) >> 31);   // reference bit j, broadcast
+            const uint32_t rb1 = (uint32_t)((int32_t)(rw1 << (31 - jj)) >> 31);
+            uint32_t any = 0;
+#pragma unroll
+            for (int t = 0; t < RS; t++) {
+                if (t < rs) {
+                    const uint32_t x0 = __builtin_amdgcn_alignbit(q0hi[t], q0lo[t], jj);
+                    const uint32_t x1 = __builtin_amdgcn_alignbit(q1hi[t], q1lo[t], jj);
+                    uint32_t a = and_xnor(and_xnor(alive[t], x0, rb0), x1, rb1);
+                    if (!interior) {
+                        const int s = lip + LP * t;
+                        const int base = j - Emax + 32 * s;      // query position of bit 0
+                        a &= span_mask(-base, m - base);
+                    }
+                    alive[t] = a;
+                    any |= a;
+                }
+            }
+            bool pany = any != 0u;
+            if (LP > 1) {
+                const uint64_t bal = __ballot(pany);
+                const uint64_t gm = LP >= 64 ? bal : (bal >> (grp * LP)) & ((1ull << (LP & 63)) - 1ull);
+                pany = gm != 0ull;
+            }
+            const bool live = !fin && j < m;
+            if (live && !pany) {
+                count++;
+#pragma unroll
+                for (int t = 0; t < RS; t++) alive[t] = rmask[t];
+                if (count > Ei) fin = true;
+            }
+            if (j + 1 >= m) fin = true;
+        }
+    }
+    return count > Ei + 1 ? Ei + 1 : count;
+}
+
+__device__ __forceinline__ uint16_t result_word(int count, int Ei)
+{
+    return (uint16_t)((count <= Ei ? 0x8000u : 0u) | (uint32_t)count);
+}
+
+}  // namespace wave
+}  // namespace ss

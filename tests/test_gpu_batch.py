@@ -1,0 +1,134 @@
+"""GPU tests of the batched launch (plan + persistent kernel + graph + autotune)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1910_09020_amd import gen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1910_09020_amd as ss
+    from paper_1910_09020_amd import runner
+    ss.lib()
+    return ss, runner, torch
+
+
+def _mixed(n=20000, n_long=40):
+    b = gen.make(3, n=n, n_long=n_long)
+    want = oracle.batch(b["reads"], b["refs"], b["offsets"], b["lengths"], E_per_pair=b["E"], threads=8)
+    return b, (want["accept"], want["edits"])
+
+
+def _check(got, want, what):
+    ga, ge = got
+    wa, we = want
+    bad = np.nonzero((ga != wa) | (ge != we))[0]
+    assert len(bad) == 0, f"{what}: {len(bad)} mismatches, first {bad[:5]}"
+
+
+def test_planned_matches_oracle(env):
+    ss, runner, torch = env
+    b, want = _mixed()
+    db = runner.DeviceBatch(b)
+    ps = db.pack_stream()
+    ctx = runner.context()
+    for spl in (4, 8):
+        print(f"  plan slices_per_lane={spl}", flush=True)
+        plan = ss.ss_plan_create(ctx, b["lengths"], b["E"], spl)
+        info = ss.ss_plan_info(plan)
+        assert info["items"] > 0 and info["slices_per_lane"] == spl
+        out = db.new_out()
+        ss.ss_filter_planned_async(ctx, plan, ps, db.total, db.offsets, db.lengths, db.E, out,
+                                   torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        _check(runner.results_numpy(out, db.n), want, f"planned spl={spl}")
+        ss.ss_plan_destroy(plan)
+
+
+def test_shuffled_mix_equals_per_bucket_launches(env):
+    """The persistent launch on a shuffled mix equals separate launches per (length, E) bucket."""
+    ss, runner, torch = env
+    b, want = _mixed(n=8000, n_long=16)
+    db = runner.DeviceBatch(b)
+    ps = db.pack_stream()
+    plan = ss.ss_plan_create(runner.context(), b["lengths"], b["E"], 8)
+    out = db.new_out()
+    ss.ss_filter_planned_async(runner.context(), plan, ps, db.total, db.offsets, db.lengths, db.E, out)
+    torch.cuda.synchronize()
+    got = runner.results_numpy(out, db.n)
+    keys = sorted(set(zip(b["lengths"].tolist(), b["E"].tolist())))
+    for (m, E) in keys:
+        idx = np.nonzero((b["lengths"] == m) & (b["E"] == E))[0]
+        sub = dict(n=len(idx), reads=b["reads"], refs=b["refs"], offsets=b["offsets"][idx],
+                   lengths=b["lengths"][idx], E=None)
+        ds = runner.DeviceBatch(sub)
+        p2 = ds.pack_stream()
+        o2 = ds.filter_wave(p2, int(E))
+        torch.cuda.synchronize()
+        a2, e2 = runner.results_numpy(o2, ds.n)
+        assert np.array_equal(a2, got[0][idx]) and np.array_equal(e2, got[1][idx]), (m, E)
+    ss.ss_plan_destroy(plan)
+    _check(got, want, "shuffled mix")
+
+
+def test_graph_replays(env):
+    ss, runner, torch = env
+    b, want = _mixed(n=6000, n_long=12)
+    db = runner.DeviceBatch(b)
+    ps = db.pack_stream()
+    torch.cuda.synchronize()
+    ctx = runner.context()
+    plan = ss.ss_plan_create(ctx, b["lengths"], b["E"], 8)
+    out = db.new_out()
+    ss.ss_plan_capture(ctx, plan, ps, db.total, db.offsets, db.lengths, db.E, out)
+    for rep in range(4):
+        out.fill_(-1)                                   # eager work between replays
+        ss.ss_plan_launch(plan, torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        _check(runner.results_numpy(out, db.n), want, f"graph replay {rep}")
+        eager = db.filter_wave(ps, int(b["E"].max()), per_pair=True)   # eager launch in between
+        torch.cuda.synchronize()
+        _check(runner.results_numpy(eager, db.n), want, f"eager after replay {rep}")
+    ss.ss_plan_destroy(plan)
+
+
+def test_autotune_cache(env, tmp_path):
+    ss, runner, torch = env
+    b, want = _mixed(n=6000, n_long=12)
+    db = runner.DeviceBatch(b)
+    ps = db.pack_stream()
+    torch.cuda.synchronize()
+    ctx = runner.context()
+    cache = str(tmp_path / "tune.json")
+    scratch = db.new_out()
+    plan, chosen = ss.ss_plan_create_tuned(ctx, b["lengths"], b["E"], ps, db.total, db.offsets, db.lengths, db.E,
+                                           scratch, cache)
+    assert chosen in (4, 8)
+    entries = json.load(open(cache))
+    assert len(entries) == 1 and list(entries.values())[0] == chosen
+    out = db.new_out()
+    ss.ss_filter_planned_async(ctx, plan, ps, db.total, db.offsets, db.lengths, db.E, out)
+    torch.cuda.synchronize()
+    _check(runner.results_numpy(out, db.n), want, "tuned plan")
+    ss.ss_plan_destroy(plan)
+    plan2, chosen2 = ss.ss_plan_create_tuned(ctx, b["lengths"], b["E"], ps, db.total, db.offsets, db.lengths, db.E,
+                                             scratch, cache)
+    assert chosen2 == chosen
+    ss.ss_plan_destroy(plan2)
+
+
+def test_empty_plan(env):
+    ss, runner, torch = env
+    ctx = runner.context()
+    plan = ss.ss_plan_create(ctx, np.zeros(0, np.int32), np.zeros(0, np.int32), 8)
+    assert ss.ss_plan_info(plan)["items"] == 0
+    ss.ss_plan_destroy(plan)
