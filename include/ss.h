@@ -218,6 +218,54 @@ int ss_plan_create_tuned(ss_ctx* ctx, const int32_t* lengths, const int32_t* E_p
                          const int32_t* lengths_dev, const int32_t* E_dev, uint16_t* out_dev,
                          const char* cache_path, ss_plan** out, int32_t* chosen_slices);
 
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of filter requests on one device (not part of
+ * the paper).  The server owns n_slots slots (stream, device arena, pinned
+ * staging), reused from request to request.  Admission is by HBM budget: the
+ * slots' arenas never total more than hbm_budget_bytes; requests that do not
+ * fit wait in FIFO order until slots and memory free up.  Each admitted
+ * request is encoded, planned (batched launch above) and filtered on its
+ * slot's stream, so requests in different slots overlap on the device.
+ * Threads: a dispatcher and a completion thread per server; the submit / poll
+ * / wait calls are thread-safe.  The server uses the device current at
+ * creation.
+ * ---------------------------------------------------------------------- */
+typedef struct ss_server ss_server;
+typedef uint64_t ss_ticket;
+int ss_server_create(ss_ctx* ctx, size_t hbm_budget_bytes, int32_t n_slots, ss_server** out);
+/* Device bytes a request of n_pairs pairs and total_bases bases needs (its
+ * share of the budget); -1 for negative arguments. */
+int64_t ss_server_footprint(int64_t n_pairs, int64_t total_bases);
+
+/* Submit one request (host arrays, copied before returning; E_per_pair is
+ * required).  accept_out / edits_out (host, n_pairs entries) are written by
+ * the server before the ticket reports done, and must stay valid until then.
+ * SS_EBUDGET if the request alone needs more than the budget.  Validation of
+ * lengths and thresholds happens here; the alphabet is checked on the device
+ * and reported by ss_server_wait (outputs then untouched). */
+int ss_server_submit(ss_server* server, const uint8_t* reads, const uint8_t* refs, const int32_t* lengths,
+                     const int32_t* E_per_pair, int64_t n_pairs, uint8_t* accept_out, int32_t* edits_out,
+                     ss_ticket* ticket);
+/* *done = 1 once the request has finished (or was cancelled). */
+int ss_server_poll(ss_server* server, ss_ticket ticket, int* done);
+/* Wait up to timeout_us (negative: no limit).  Returns the request's status
+ * (SS_OK, SS_EBASE, SS_EDEVICE, ...), SS_ETIMEOUT if still running, or
+ * SS_EAGAIN if it was cancelled.  The request keeps running after a timeout. */
+int ss_server_wait(ss_server* server, ss_ticket ticket, int64_t timeout_us);
+/* Steady-clock nanoseconds of submission, admission and completion (0 = not yet). */
+int ss_server_times(ss_server* server, ss_ticket ticket, int64_t* submit_ns, int64_t* admit_ns, int64_t* done_ns);
+/* Cancel a request that is still queued (SS_EAGAIN once admitted). */
+int ss_server_cancel(ss_server* server, ss_ticket ticket);
+/* Forget a finished ticket (SS_EAGAIN while queued or running). */
+int ss_server_release(ss_server* server, ss_ticket ticket);
+/* Pause (hold != 0) or resume dispatching; paused requests stay queued.  For
+ * tests of the timeout and queueing paths. */
+int ss_server_set_hold(ss_server* server, int hold);
+int ss_server_stats(ss_server* server, int64_t* admitted, int64_t* deferred, int64_t* completed,
+                    int64_t* peak_bytes, int64_t* peak_in_flight);
+/* Cancels queued requests, waits for running ones, frees everything. */
+int ss_server_destroy(ss_server* server);
+
 /* Expand device result words into accept bytes and int32 counts (device). */
 int ss_unpack_results_async(ss_ctx* ctx, const uint16_t* results, int64_t n_pairs,
                             uint8_t* accept_out, int32_t* edits_out, void* stream);

@@ -68,6 +68,17 @@ def lib():
         "ss_plan_launch": ([vp, vp], ctypes.c_int),
         "ss_plan_create_tuned": ([vp, vp, vp, i64, vp, i64, vp, vp, vp, vp, ctypes.c_char_p, ctypes.POINTER(vp),
                                   vp], ctypes.c_int),
+        "ss_server_create": ([vp, ctypes.c_size_t, i32, ctypes.POINTER(vp)], ctypes.c_int),
+        "ss_server_submit": ([vp, vp, vp, vp, vp, i64, vp, vp, ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
+        "ss_server_poll": ([vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+        "ss_server_wait": ([vp, ctypes.c_uint64, i64], ctypes.c_int),
+        "ss_server_times": ([vp, ctypes.c_uint64, vp, vp, vp], ctypes.c_int),
+        "ss_server_cancel": ([vp, ctypes.c_uint64], ctypes.c_int),
+        "ss_server_release": ([vp, ctypes.c_uint64], ctypes.c_int),
+        "ss_server_set_hold": ([vp, ctypes.c_int], ctypes.c_int),
+        "ss_server_stats": ([vp, vp, vp, vp, vp, vp], ctypes.c_int),
+        "ss_server_destroy": ([vp], ctypes.c_int),
+        "ss_server_footprint": ([i64, i64], i64),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -83,7 +94,9 @@ def exported_symbols():
             "ss_sliced_bytes", "ss_stream_words", "ss_pack_sliced_async", "ss_filter_sliced_async",
             "ss_pack_stream_async", "ss_filter_plain_async", "ss_filter_wave_async", "ss_unpack_results_async",
             "ss_plan_create", "ss_plan_destroy", "ss_plan_info", "ss_filter_planned_async", "ss_plan_capture",
-            "ss_plan_launch", "ss_plan_create_tuned"]
+            "ss_plan_launch", "ss_plan_create_tuned", "ss_server_create", "ss_server_submit", "ss_server_poll",
+            "ss_server_wait", "ss_server_times", "ss_server_cancel", "ss_server_release", "ss_server_set_hold",
+            "ss_server_stats", "ss_server_destroy", "ss_server_footprint"]
 
 
 def status_str(status: int) -> str:
@@ -247,6 +260,68 @@ def ss_plan_create_tuned(ctx, lengths, E_per_pair, packed, total_bases, offsets_
                                       _ptr(offsets_dev), _ptr(lengths_dev), _ptr(E_dev), _ptr(out_dev), cp,
                                       ctypes.byref(h), ctypes.addressof(ch)), "ss_plan_create_tuned")
     return h.value, ch.value
+
+
+# ---------------------------------------------------------------- serving
+def ss_server_create(ctx, hbm_budget_bytes: int, n_slots: int = 8) -> int:
+    h = ctypes.c_void_p()
+    _check(lib().ss_server_create(ctx, int(hbm_budget_bytes), int(n_slots), ctypes.byref(h)), "ss_server_create")
+    return h.value
+
+
+def ss_server_submit(server, reads, refs, lengths, E_per_pair, accept_out, edits_out) -> int:
+    """Submit host numpy arrays; accept_out (uint8) and edits_out (int32) must stay alive until done."""
+    n = len(lengths)
+    t = ctypes.c_uint64(0)
+    rc = lib().ss_server_submit(server, _ptr(reads), _ptr(refs), _ptr(lengths), _ptr(E_per_pair), n,
+                                _ptr(accept_out), _ptr(edits_out), ctypes.byref(t))
+    _check(rc, "ss_server_submit")
+    return t.value
+
+
+def ss_server_poll(server, ticket) -> bool:
+    d = ctypes.c_int(0)
+    _check(lib().ss_server_poll(server, ticket, ctypes.byref(d)), "ss_server_poll")
+    return bool(d.value)
+
+
+def ss_server_wait(server, ticket, timeout_us: int = -1) -> int:
+    """Returns the status code (does not raise)."""
+    return int(lib().ss_server_wait(server, ticket, int(timeout_us)))
+
+
+def ss_server_times(server, ticket):
+    a, b, c = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
+    _check(lib().ss_server_times(server, ticket, ctypes.addressof(a), ctypes.addressof(b), ctypes.addressof(c)),
+           "ss_server_times")
+    return a.value, b.value, c.value
+
+
+def ss_server_cancel(server, ticket) -> int:
+    return int(lib().ss_server_cancel(server, ticket))
+
+
+def ss_server_release(server, ticket) -> int:
+    return int(lib().ss_server_release(server, ticket))
+
+
+def ss_server_set_hold(server, hold: bool) -> None:
+    _check(lib().ss_server_set_hold(server, 1 if hold else 0), "ss_server_set_hold")
+
+
+def ss_server_stats(server) -> dict:
+    v = [ctypes.c_int64(0) for _ in range(5)]
+    _check(lib().ss_server_stats(server, *[ctypes.addressof(x) for x in v]), "ss_server_stats")
+    return dict(admitted=v[0].value, deferred=v[1].value, completed=v[2].value, peak_bytes=v[3].value,
+                peak_in_flight=v[4].value)
+
+
+def ss_server_footprint(n_pairs: int, total_bases: int) -> int:
+    return int(lib().ss_server_footprint(int(n_pairs), int(total_bases)))
+
+
+def ss_server_destroy(server) -> None:
+    _check(lib().ss_server_destroy(server), "ss_server_destroy")
 
 
 def decode_results(res: np.ndarray):

@@ -33,16 +33,6 @@
 
 namespace ss {
 
-struct PItem {
-    int64_t first;    // first slot in the permutation
-    int32_t count;    // pairs in this item
-    int16_t lp;       // lanes per pair
-    int16_t rs;       // slices per lane
-    int32_t emax;     // row layout threshold (max E over the item's pairs)
-    int32_t pad;
-};
-static_assert(sizeof(PItem) == 24, "PItem layout");
-
 namespace {
 
 __global__ void k_zero_counter(int* c) { if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0; }
@@ -77,6 +67,105 @@ __global__ __launch_bounds__(256) void k_persist(const PItem* __restrict__ items
 }
 
 }  // namespace
+
+void plan_items(const int32_t* lengths, const int32_t* E, int64_t n, int rsmax, std::vector<PItem>& items,
+                std::vector<int64_t>& perm, int* n_classes, double* est_cost)
+{
+    // shape class per pair
+    std::vector<int32_t> cls((size_t)n);
+    std::map<std::pair<int, int>, int> class_id;
+    std::vector<std::pair<int, int>> shapes;
+    for (int64_t i = 0; i < n; i++) {
+        int lp, rs;
+        wave::shape_for(E[i], rsmax, &lp, &rs);
+        auto key = std::make_pair(lp, rs);
+        auto it = class_id.find(key);
+        int id;
+        if (it == class_id.end()) {
+            id = (int)shapes.size();
+            class_id.emplace(key, id);
+            shapes.push_back(key);
+        } else {
+            id = it->second;
+        }
+        cls[(size_t)i] = id;
+    }
+    *n_classes = (int)shapes.size();
+    // sort by (class, length desc, E desc): pairs of one wavefront share the column loop
+    perm.resize((size_t)n);
+    std::iota(perm.begin(), perm.end(), (int64_t)0);
+    std::stable_sort(perm.begin(), perm.end(), [&](int64_t a, int64_t b) {
+        if (cls[(size_t)a] != cls[(size_t)b]) return cls[(size_t)a] < cls[(size_t)b];
+        if (lengths[a] != lengths[b]) return lengths[a] > lengths[b];
+        return E[a] > E[b];
+    });
+    // cut into items of one block-round
+    items.clear();
+    std::vector<double> cost;
+    *est_cost = 0;
+    int64_t i = 0;
+    while (i < n) {
+        const int c = cls[(size_t)perm[(size_t)i]];
+        const int lp = shapes[(size_t)c].first, rs = shapes[(size_t)c].second;
+        const int per_item = 4 * (64 / lp);
+        int64_t j = i;
+        int32_t emax = 0;
+        double work = 0;
+        int64_t mmax = 0;
+        while (j < n && j - i < per_item && cls[(size_t)perm[(size_t)j]] == c) {
+            const int64_t p = perm[(size_t)j];
+            emax = std::max(emax, E[p]);
+            mmax = std::max<int64_t>(mmax, lengths[p]);
+            j++;
+        }
+        // a block-round costs its longest pair's columns times the lanes' slices
+        work = (double)mmax * (double)rs * (double)(4 * 64) / 64.0;
+        PItem it;
+        it.first = i;
+        it.count = (int32_t)(j - i);
+        it.lp = (int16_t)lp;
+        it.rs = (int16_t)rs;
+        it.emax = emax;
+        it.pad = 0;
+        items.push_back(it);
+        cost.push_back(work);
+        *est_cost += work;
+        i = j;
+    }
+    // largest items first
+    std::vector<size_t> order(items.size());
+    std::iota(order.begin(), order.end(), (size_t)0);
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
+    std::vector<PItem> sorted;
+    sorted.reserve(order.size());
+    for (size_t k : order) sorted.push_back(items[k]);
+    items.swap(sorted);
+}
+
+int persist_blocks_per_cu(int rsmax)
+{
+    int per_cu = 1;
+    if (rsmax <= 4) (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persist<4>, 256, 0);
+    else (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persist<8>, 256, 0);
+    return per_cu < 1 ? 1 : per_cu;
+}
+
+hipError_t launch_persist(int rsmax, int grid, const PItem* d_items, int n_items, int* d_head, const int64_t* d_perm,
+                          const uint32_t* packed, int64_t total_bases, const int64_t* offsets, const int32_t* lengths,
+                          const int32_t* Epp, uint16_t* out, hipStream_t s)
+{
+    if (n_items == 0) return hipSuccess;
+    const int64_t SW = cdiv(total_bases, 32) + 2;
+    hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, s, d_head);
+    if (rsmax <= 4)
+        hipLaunchKernelGGL(k_persist<4>, dim3(grid), dim3(256), 0, s, d_items, n_items, d_head, d_perm, packed, SW,
+                           offsets, lengths, Epp, out);
+    else
+        hipLaunchKernelGGL(k_persist<8>, dim3(grid), dim3(256), 0, s, d_items, n_items, d_head, d_perm, packed, SW,
+                           offsets, lengths, Epp, out);
+    return hipGetLastError();
+}
+
 }  // namespace ss
 
 using namespace ss;
@@ -114,75 +203,7 @@ int map_err(hipError_t e)
 
 int build_plan(ss_plan* P, const int32_t* lengths, const int32_t* E, int64_t n)
 {
-    // shape class per pair
-    std::vector<int32_t> cls((size_t)n);
-    std::map<std::pair<int, int>, int> class_id;
-    std::vector<std::pair<int, int>> shapes;
-    for (int64_t i = 0; i < n; i++) {
-        int lp, rs;
-        wave::shape_for(E[i], P->cfg.rsmax, &lp, &rs);
-        auto key = std::make_pair(lp, rs);
-        auto it = class_id.find(key);
-        int id;
-        if (it == class_id.end()) {
-            id = (int)shapes.size();
-            class_id.emplace(key, id);
-            shapes.push_back(key);
-        } else {
-            id = it->second;
-        }
-        cls[(size_t)i] = id;
-    }
-    P->n_classes = (int)shapes.size();
-    // sort by (class, length desc, E desc): pairs of one wavefront share the column loop
-    P->perm.resize((size_t)n);
-    std::iota(P->perm.begin(), P->perm.end(), (int64_t)0);
-    std::stable_sort(P->perm.begin(), P->perm.end(), [&](int64_t a, int64_t b) {
-        if (cls[(size_t)a] != cls[(size_t)b]) return cls[(size_t)a] < cls[(size_t)b];
-        if (lengths[a] != lengths[b]) return lengths[a] > lengths[b];
-        return E[a] > E[b];
-    });
-    // cut into items of one block-round
-    P->items.clear();
-    std::vector<double> cost;
-    P->est_cost = 0;
-    int64_t i = 0;
-    while (i < n) {
-        const int c = cls[(size_t)P->perm[(size_t)i]];
-        const int lp = shapes[(size_t)c].first, rs = shapes[(size_t)c].second;
-        const int per_item = 4 * (64 / lp);
-        int64_t j = i;
-        int32_t emax = 0;
-        double work = 0;
-        int64_t mmax = 0;
-        while (j < n && j - i < per_item && cls[(size_t)P->perm[(size_t)j]] == c) {
-            const int64_t p = P->perm[(size_t)j];
-            emax = std::max(emax, E[p]);
-            mmax = std::max<int64_t>(mmax, lengths[p]);
-            j++;
-        }
-        // a block-round costs its longest pair's columns times the lanes' slices
-        work = (double)mmax * (double)rs * (double)(4 * 64) / 64.0;
-        PItem it;
-        it.first = i;
-        it.count = (int32_t)(j - i);
-        it.lp = (int16_t)lp;
-        it.rs = (int16_t)rs;
-        it.emax = emax;
-        it.pad = 0;
-        P->items.push_back(it);
-        cost.push_back(work);
-        P->est_cost += work;
-        i = j;
-    }
-    // largest items first
-    std::vector<size_t> order(P->items.size());
-    std::iota(order.begin(), order.end(), (size_t)0);
-    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
-    std::vector<PItem> sorted;
-    sorted.reserve(order.size());
-    for (size_t k : order) sorted.push_back(P->items[k]);
-    P->items.swap(sorted);
+    plan_items(lengths, E, n, P->cfg.rsmax, P->items, P->perm, &P->n_classes, &P->est_cost);
     return SS_OK;
 }
 
@@ -205,10 +226,7 @@ int upload_plan(ss_plan* P)
     (void)hipGetDevice(&dev);
     hipDeviceProp_t prop;
     if ((e = hipGetDeviceProperties(&prop, dev)) != hipSuccess) return map_err(e);
-    int per_cu = 1;
-    if (P->cfg.rsmax <= 4) (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persist<4>, 256, 0);
-    else (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persist<8>, 256, 0);
-    per_cu = std::max(1, per_cu);
+    const int per_cu = persist_blocks_per_cu(P->cfg.rsmax);
     P->grid = (int)std::min<int64_t>((int64_t)per_cu * prop.multiProcessorCount, std::max<size_t>(P->items.size(), 1));
     return SS_OK;
 }
@@ -226,16 +244,8 @@ void free_plan(ss_plan* P)
 hipError_t enqueue(const ss_plan* P, const uint32_t* packed, int64_t total_bases, const int64_t* offsets,
                    const int32_t* lengths, const int32_t* Epp, uint16_t* out, hipStream_t s)
 {
-    if (P->items.empty()) return hipSuccess;
-    const int64_t SW = cdiv(total_bases, 32) + 2;
-    hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, s, P->d_head);
-    if (P->cfg.rsmax <= 4)
-        hipLaunchKernelGGL(k_persist<4>, dim3(P->grid), dim3(256), 0, s, P->d_items, (int)P->items.size(), P->d_head,
-                           P->d_perm, packed, SW, offsets, lengths, Epp, out);
-    else
-        hipLaunchKernelGGL(k_persist<8>, dim3(P->grid), dim3(256), 0, s, P->d_items, (int)P->items.size(), P->d_head,
-                           P->d_perm, packed, SW, offsets, lengths, Epp, out);
-    return hipGetLastError();
+    return launch_persist(P->cfg.rsmax, P->grid, P->d_items, (int)P->items.size(), P->d_head, P->d_perm, packed,
+                          total_bases, offsets, lengths, Epp, out, s);
 }
 
 int validate_plan_inputs(const int32_t* lengths, const int32_t* E, int64_t n)

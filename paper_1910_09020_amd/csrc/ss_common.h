@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace ss {
 
 constexpr int kChunk = 4;              // positions per chunk in the lane-sliced layout
@@ -30,5 +32,26 @@ hipError_t launch_unpack(const uint16_t* res, int64_t n, uint8_t* accept, int32_
 // Lanes per pair and row slices per lane chosen by the wavefront kernel for a
 // given maximum threshold (rows 2E+1 are split in 32-row slices).
 void wave_shape(int32_t E, int* lanes_per_pair, int* slices_per_lane);
+
+// ---- batched launch (work items of the persistent kernel) ----
+struct PItem {
+    int64_t first;    // first slot in the permutation
+    int32_t count;    // pairs in this item
+    int16_t lp;       // lanes per pair
+    int16_t rs;       // slices per lane
+    int32_t emax;     // row layout threshold (max E over the item's pairs)
+    int32_t pad;
+};
+static_assert(sizeof(PItem) == 24, "PItem layout");
+
+// Host planner: shape classes, sort, items ordered largest estimated cost first.
+void plan_items(const int32_t* lengths, const int32_t* E, int64_t n, int rsmax, std::vector<PItem>& items,
+                std::vector<int64_t>& perm, int* n_classes, double* est_cost);
+// Resident blocks per CU of the persistent kernel for this slice width.
+int persist_blocks_per_cu(int rsmax);
+// Counter reset + persistent kernel on stream s.
+hipError_t launch_persist(int rsmax, int grid, const PItem* d_items, int n_items, int* d_head, const int64_t* d_perm,
+                          const uint32_t* packed, int64_t total_bases, const int64_t* offsets, const int32_t* lengths,
+                          const int32_t* Epp, uint16_t* out, hipStream_t s);
 
 }  // namespace ss

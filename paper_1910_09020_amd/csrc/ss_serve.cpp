@@ -1,0 +1,517 @@
+// Serving loop: continuous batching of filter requests on one device.
+//
+// A request is a batch of pairs (ASCII, lengths, per-pair thresholds) with host
+// output arrays.  The server owns a fixed number of slots; each slot has its
+// own HIP stream, a device arena and pinned staging that stay allocated and
+// are reused from request to request.  Admission is by HBM budget: the sum of
+// the slots' arenas never exceeds the budget given at creation; a request that
+// does not fit waits in a FIFO queue until slots and memory free up (idle
+// arenas are released to make room).  An admitted request is enqueued on its
+// slot's stream: copies in, bit-stream encoding, a per-request plan of the
+// batched launch (ss_batch.hip), the persistent filter kernel, copies out.
+// Requests in different slots run concurrently on the device, and requests
+// that arrive while others are running are admitted as soon as a slot and
+// memory are free.  A completion thread polls the slots' events, writes the
+// results to the caller's arrays and timestamps the completion.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "ss.h"
+#include "ss_common.h"
+
+using namespace ss;
+
+namespace {
+
+int64_t now_ns()
+{
+    return std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+int map_err(hipError_t e)
+{
+    if (e == hipSuccess) return SS_OK;
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return SS_ENOMEM;
+    return SS_EDEVICE;
+}
+
+size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Byte offsets of one request's buffers inside a slot arena.
+struct Layout {
+    size_t reads, refs, packed, offsets, lengths, E, items, perm, head, results, err, total;
+    size_t in_bytes;     // staged host -> device (reads .. perm)
+    int64_t SW;
+    Layout(int64_t n, int64_t T, int64_t n_items)
+    {
+        SW = cdiv(T, 32) + 2;
+        size_t o = 0;
+        reads = o; o += al((size_t)T + 16);
+        refs = o; o += al((size_t)T + 16);
+        offsets = o; o += al((size_t)n * 8);
+        lengths = o; o += al((size_t)n * 4);
+        E = o; o += al((size_t)n * 4);
+        items = o; o += al((size_t)n_items * sizeof(PItem));
+        perm = o; o += al((size_t)n * 8);
+        in_bytes = o;
+        packed = o; o += al((size_t)SW * 16);
+        head = o; o += 256;
+        results = o; o += al((size_t)n * 2);
+        err = o; o += 256;
+        total = o;
+    }
+};
+
+enum State { QUEUED = 0, RUNNING = 1, DONE = 2, CANCELLED = 3 };
+
+struct Request {
+    uint64_t id = 0;
+    int64_t n = 0, total = 0;
+    std::vector<uint8_t> reads, refs;
+    std::vector<int32_t> lengths, E;
+    std::vector<int64_t> offsets;
+    std::vector<PItem> items;
+    std::vector<int64_t> perm;
+    uint8_t* accept_out = nullptr;
+    int32_t* edits_out = nullptr;
+    size_t footprint = 0;
+    int64_t t_submit = 0, t_admit = 0, t_done = 0;
+    int status = SS_OK;
+    State state = QUEUED;
+    int slot = -1;
+};
+
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    void* arena = nullptr;
+    size_t arena_cap = 0;
+    void* pinned = nullptr;
+    size_t pinned_cap = 0;
+    Request* cur = nullptr;
+};
+
+}  // namespace
+
+struct ss_server {
+    ss_ctx* ctx = nullptr;
+    int device = 0;
+    size_t budget = 0;
+    size_t used = 0;                 // sum of slot arena capacities
+    int rsmax = 8;
+    int grid_cap = 1;
+    std::vector<Slot> slots;
+    std::deque<Request*> queue;
+    std::unordered_map<uint64_t, Request*> reqs;
+    uint64_t next_id = 1;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::thread dispatcher, completer;
+    bool stop = false;
+    bool hold = false;
+    int running = 0;
+    // statistics
+    int64_t admitted = 0, deferred = 0, completed = 0, peak_used = 0, peak_running = 0;
+};
+
+namespace {
+
+size_t footprint_of(int64_t n, int64_t T)
+{
+    // items <= n (one pair per item at worst)
+    return Layout(n, T, n).total;
+}
+
+// Enqueue the whole request on its slot's stream.  Called without the lock.
+int launch_request(ss_server* S, Slot& sl, Request* r)
+{
+    const Layout L(r->n, r->total, (int64_t)r->items.size());
+    // pinned staging: inputs, then results and the error word
+    const size_t pin_need = L.in_bytes + al((size_t)r->n * 2) + 256;
+    if (sl.pinned_cap < pin_need) {
+        if (sl.pinned) (void)hipHostFree(sl.pinned);
+        sl.pinned = nullptr;
+        sl.pinned_cap = 0;
+        const size_t want = std::max(pin_need, (size_t)1 << 20);
+        hipError_t e = hipHostMalloc(&sl.pinned, want, hipHostMallocDefault);
+        if (e != hipSuccess) return map_err(e);
+        sl.pinned_cap = want;
+    }
+    uint8_t* h = (uint8_t*)sl.pinned;
+    if (r->total) {
+        std::memcpy(h + L.reads, r->reads.data(), (size_t)r->total);
+        std::memcpy(h + L.refs, r->refs.data(), (size_t)r->total);
+    }
+    std::memcpy(h + L.offsets, r->offsets.data(), (size_t)r->n * 8);
+    std::memcpy(h + L.lengths, r->lengths.data(), (size_t)r->n * 4);
+    std::memcpy(h + L.E, r->E.data(), (size_t)r->n * 4);
+    if (!r->items.empty()) std::memcpy(h + L.items, r->items.data(), r->items.size() * sizeof(PItem));
+    std::memcpy(h + L.perm, r->perm.data(), (size_t)r->n * 8);
+    uint8_t* d = (uint8_t*)sl.arena;
+    hipStream_t s = sl.stream;
+    hipError_t e = hipMemcpyAsync(d, h, L.in_bytes, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemsetAsync(d + L.err, 0, 4, s);
+    if (e == hipSuccess)
+        e = launch_pack_stream(d + L.reads, d + L.refs, r->total, (uint32_t*)(d + L.packed), (uint32_t*)(d + L.err), s);
+    if (e == hipSuccess) {
+        const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)r->items.size(), S->grid_cap));
+        e = launch_persist(S->rsmax, grid, (const PItem*)(d + L.items), (int)r->items.size(), (int*)(d + L.head),
+                           (const int64_t*)(d + L.perm), (const uint32_t*)(d + L.packed), r->total,
+                           (const int64_t*)(d + L.offsets), (const int32_t*)(d + L.lengths),
+                           (const int32_t*)(d + L.E), (uint16_t*)(d + L.results), s);
+    }
+    const size_t hres = L.in_bytes, herr = L.in_bytes + al((size_t)r->n * 2);
+    if (e == hipSuccess && r->n)
+        e = hipMemcpyAsync(h + hres, d + L.results, (size_t)r->n * 2, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(h + herr, d + L.err, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipEventRecord(sl.done, s);
+    return map_err(e);
+}
+
+// Pick a free slot for the head request, growing its arena within the budget
+// (releasing idle arenas when needed).  Returns the slot index or -1.  Lock held.
+int admit_slot(ss_server* S, Request* r)
+{
+    int best = -1;
+    for (int i = 0; i < (int)S->slots.size(); i++) {
+        Slot& sl = S->slots[(size_t)i];
+        if (sl.cur) continue;
+        if (sl.arena_cap >= r->footprint) return i;            // fits in an existing arena
+        if (best < 0 || sl.arena_cap > S->slots[(size_t)best].arena_cap) best = i;
+    }
+    if (best < 0) return -1;
+    Slot& sl = S->slots[(size_t)best];
+    size_t need = r->footprint - sl.arena_cap;
+    if (S->used + need > S->budget) {
+        // release idle arenas (other than the chosen one) until the request fits
+        for (auto& o : S->slots) {
+            if (&o == &sl || o.cur || !o.arena) continue;
+            (void)hipFree(o.arena);
+            S->used -= o.arena_cap;
+            o.arena = nullptr;
+            o.arena_cap = 0;
+            if (S->used + need <= S->budget) break;
+        }
+    }
+    if (S->used + need > S->budget) return -1;
+    if (sl.arena) { (void)hipFree(sl.arena); S->used -= sl.arena_cap; sl.arena = nullptr; sl.arena_cap = 0; }
+    void* p = nullptr;
+    if (hipMalloc(&p, r->footprint) != hipSuccess) return -1;
+    sl.arena = p;
+    sl.arena_cap = r->footprint;
+    S->used += r->footprint;
+    S->peak_used = std::max<int64_t>(S->peak_used, (int64_t)S->used);
+    return best;
+}
+
+void finish(ss_server* S, Request* r, int status)
+{
+    // lock held
+    r->status = status;
+    r->state = DONE;
+    r->t_done = now_ns();
+    r->reads.clear(); r->reads.shrink_to_fit();
+    r->refs.clear(); r->refs.shrink_to_fit();
+    S->completed++;
+    S->cv_done.notify_all();
+}
+
+void dispatcher_main(ss_server* S)
+{
+    (void)hipSetDevice(S->device);
+    std::unique_lock<std::mutex> lk(S->mu);
+    for (;;) {
+        S->cv_work.wait(lk, [&] { return S->stop || (!S->hold && !S->queue.empty()); });
+        if (S->stop) return;
+        Request* r = S->queue.front();
+        const int si = admit_slot(S, r);
+        if (si < 0) {
+            S->deferred++;
+            // wait for a completion (or new state) and try again
+            S->cv_work.wait_for(lk, std::chrono::milliseconds(5));
+            continue;
+        }
+        S->queue.pop_front();
+        Slot& sl = S->slots[(size_t)si];
+        sl.cur = r;
+        r->slot = si;
+        r->state = RUNNING;
+        r->t_admit = now_ns();
+        S->admitted++;
+        S->running++;
+        S->peak_running = std::max<int64_t>(S->peak_running, S->running);
+        lk.unlock();
+        const int rc = launch_request(S, sl, r);
+        lk.lock();
+        if (rc != SS_OK) {
+            // the stream may hold part of the work: wait for it before reusing the slot
+            (void)hipStreamSynchronize(sl.stream);
+            sl.cur = nullptr;
+            S->running--;
+            finish(S, r, rc);
+        }
+        S->cv_work.notify_all();     // wake the completion thread
+    }
+}
+
+void completer_main(ss_server* S)
+{
+    (void)hipSetDevice(S->device);
+    for (;;) {
+        std::vector<int> busy;
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            if (S->stop && S->running == 0) return;
+            for (int i = 0; i < (int)S->slots.size(); i++)
+                if (S->slots[(size_t)i].cur) busy.push_back(i);
+            if (busy.empty()) {
+                S->cv_work.wait_for(lk, std::chrono::milliseconds(2));
+                continue;
+            }
+        }
+        bool any = false;
+        for (int i : busy) {
+            Slot& sl = S->slots[(size_t)i];
+            const hipError_t q = hipEventQuery(sl.done);
+            if (q == hipErrorNotReady) continue;
+            Request* r = sl.cur;
+            int status = map_err(q);
+            if (status == SS_OK) {
+                const Layout L(r->n, r->total, (int64_t)r->items.size());
+                const uint8_t* h = (const uint8_t*)sl.pinned;
+                const uint16_t* res = (const uint16_t*)(h + L.in_bytes);
+                uint32_t err = 0;
+                std::memcpy(&err, h + L.in_bytes + al((size_t)r->n * 2), 4);
+                if (err) {
+                    status = SS_EBASE;                 // outputs untouched
+                } else {
+                    for (int64_t k = 0; k < r->n; k++) {
+                        r->accept_out[k] = (uint8_t)(res[k] >> 15);
+                        r->edits_out[k] = (int32_t)(res[k] & SS_RESULT_COUNT);
+                    }
+                }
+            }
+            std::lock_guard<std::mutex> lk(S->mu);
+            sl.cur = nullptr;
+            S->running--;
+            finish(S, r, status);
+            S->cv_work.notify_all();
+            any = true;
+        }
+        if (!any) std::this_thread::sleep_for(std::chrono::microseconds(20));
+    }
+}
+
+}  // namespace
+
+extern "C" int64_t ss_server_footprint(int64_t n_pairs, int64_t total_bases)
+{
+    if (n_pairs < 0 || total_bases < 0) return -1;
+    return (int64_t)footprint_of(n_pairs, total_bases);
+}
+
+extern "C" int ss_server_create(ss_ctx* ctx, size_t hbm_budget_bytes, int32_t n_slots, ss_server** out)
+{
+    if (!ctx || !out || n_slots < 1 || n_slots > 64 || hbm_budget_bytes < 4096) return SS_EINVAL;
+    ss_server* S = new (std::nothrow) ss_server();
+    if (!S) return SS_ENOMEM;
+    S->ctx = ctx;
+    (void)hipGetDevice(&S->device);
+    S->budget = hbm_budget_bytes;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, S->device) != hipSuccess) { delete S; return SS_EDEVICE; }
+    S->grid_cap = persist_blocks_per_cu(S->rsmax) * prop.multiProcessorCount;
+    S->slots.resize((size_t)n_slots);
+    for (auto& sl : S->slots) {
+        hipError_t e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            for (auto& o : S->slots) {
+                if (o.done) (void)hipEventDestroy(o.done);
+                if (o.stream) (void)hipStreamDestroy(o.stream);
+            }
+            delete S;
+            return map_err(e);
+        }
+    }
+    S->dispatcher = std::thread(dispatcher_main, S);
+    S->completer = std::thread(completer_main, S);
+    *out = S;
+    return SS_OK;
+}
+
+extern "C" int ss_server_submit(ss_server* S, const uint8_t* reads, const uint8_t* refs, const int32_t* lengths,
+                                const int32_t* E_per_pair, int64_t n_pairs, uint8_t* accept_out, int32_t* edits_out,
+                                ss_ticket* ticket)
+{
+    if (!S || !ticket || n_pairs < 0) return SS_EINVAL;
+    if (n_pairs > 0 && (!reads || !refs || !lengths || !E_per_pair || !accept_out || !edits_out)) return SS_EINVAL;
+    int64_t T = 0;
+    for (int64_t i = 0; i < n_pairs; i++) {
+        if (lengths[i] < 0 || E_per_pair[i] < 0) return SS_EINVAL;
+        if (lengths[i] > SS_MAX_LEN || E_per_pair[i] > SS_MAX_E) return SS_ELEN;
+        T += lengths[i];
+    }
+    Request* r = nullptr;
+    try {
+        r = new Request();
+        r->n = n_pairs;
+        r->total = T;
+        r->footprint = footprint_of(n_pairs, T);
+        if (r->footprint > S->budget) {
+            delete r;
+            return SS_EBUDGET;
+        }
+        r->reads.assign(reads, reads + T);
+        r->refs.assign(refs, refs + T);
+        r->lengths.assign(lengths, lengths + n_pairs);
+        r->E.assign(E_per_pair, E_per_pair + n_pairs);
+        r->offsets.resize((size_t)n_pairs);
+        int64_t o = 0;
+        for (int64_t i = 0; i < n_pairs; i++) { r->offsets[(size_t)i] = o; o += lengths[i]; }
+        int nc = 0;
+        double cost = 0;
+        plan_items(r->lengths.data(), r->E.data(), n_pairs, S->rsmax, r->items, r->perm, &nc, &cost);
+    } catch (const std::bad_alloc&) {
+        delete r;
+        return SS_ENOMEM;
+    }
+    r->accept_out = accept_out;
+    r->edits_out = edits_out;
+    r->t_submit = now_ns();
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->stop) { delete r; return SS_EINVAL; }
+    r->id = S->next_id++;
+    S->reqs[r->id] = r;
+    *ticket = r->id;
+    if (n_pairs == 0) {
+        finish(S, r, SS_OK);
+        return SS_OK;
+    }
+    S->queue.push_back(r);
+    S->cv_work.notify_all();
+    return SS_OK;
+}
+
+extern "C" int ss_server_poll(ss_server* S, ss_ticket t, int* done)
+{
+    if (!S || !done) return SS_EINVAL;
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->reqs.find(t);
+    if (it == S->reqs.end()) return SS_EINVAL;
+    *done = it->second->state == DONE || it->second->state == CANCELLED;
+    return SS_OK;
+}
+
+extern "C" int ss_server_wait(ss_server* S, ss_ticket t, int64_t timeout_us)
+{
+    if (!S) return SS_EINVAL;
+    std::unique_lock<std::mutex> lk(S->mu);
+    auto it = S->reqs.find(t);
+    if (it == S->reqs.end()) return SS_EINVAL;
+    Request* r = it->second;
+    auto pred = [&] { return r->state == DONE || r->state == CANCELLED; };
+    if (timeout_us < 0) S->cv_done.wait(lk, pred);
+    else if (!S->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), pred)) return SS_ETIMEOUT;
+    return r->state == CANCELLED ? SS_EAGAIN : r->status;
+}
+
+extern "C" int ss_server_times(ss_server* S, ss_ticket t, int64_t* submit_ns, int64_t* admit_ns, int64_t* done_ns)
+{
+    if (!S) return SS_EINVAL;
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->reqs.find(t);
+    if (it == S->reqs.end()) return SS_EINVAL;
+    if (submit_ns) *submit_ns = it->second->t_submit;
+    if (admit_ns) *admit_ns = it->second->t_admit;
+    if (done_ns) *done_ns = it->second->t_done;
+    return SS_OK;
+}
+
+extern "C" int ss_server_cancel(ss_server* S, ss_ticket t)
+{
+    if (!S) return SS_EINVAL;
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->reqs.find(t);
+    if (it == S->reqs.end()) return SS_EINVAL;
+    Request* r = it->second;
+    if (r->state != QUEUED) return SS_EAGAIN;
+    S->queue.erase(std::remove(S->queue.begin(), S->queue.end(), r), S->queue.end());
+    r->state = CANCELLED;
+    r->t_done = now_ns();
+    S->cv_done.notify_all();
+    return SS_OK;
+}
+
+extern "C" int ss_server_release(ss_server* S, ss_ticket t)
+{
+    if (!S) return SS_EINVAL;
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->reqs.find(t);
+    if (it == S->reqs.end()) return SS_EINVAL;
+    if (it->second->state == QUEUED || it->second->state == RUNNING) return SS_EAGAIN;
+    delete it->second;
+    S->reqs.erase(it);
+    return SS_OK;
+}
+
+extern "C" int ss_server_set_hold(ss_server* S, int hold)
+{
+    if (!S) return SS_EINVAL;
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->hold = hold != 0;
+    S->cv_work.notify_all();
+    return SS_OK;
+}
+
+extern "C" int ss_server_stats(ss_server* S, int64_t* admitted, int64_t* deferred, int64_t* completed,
+                               int64_t* peak_bytes, int64_t* peak_in_flight)
+{
+    if (!S) return SS_EINVAL;
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (admitted) *admitted = S->admitted;
+    if (deferred) *deferred = S->deferred;
+    if (completed) *completed = S->completed;
+    if (peak_bytes) *peak_bytes = S->peak_used;
+    if (peak_in_flight) *peak_in_flight = S->peak_running;
+    return SS_OK;
+}
+
+extern "C" int ss_server_destroy(ss_server* S)
+{
+    if (!S) return SS_EINVAL;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        // queued requests are cancelled; running ones finish
+        for (Request* r : S->queue) { r->state = CANCELLED; r->t_done = now_ns(); }
+        S->queue.clear();
+        S->hold = false;
+        S->stop = true;
+        S->cv_work.notify_all();
+        S->cv_done.notify_all();
+    }
+    S->dispatcher.join();
+    S->completer.join();
+    for (auto& sl : S->slots) {
+        if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+        if (sl.arena) (void)hipFree(sl.arena);
+        if (sl.pinned) (void)hipHostFree(sl.pinned);
+        if (sl.done) (void)hipEventDestroy(sl.done);
+        if (sl.stream) (void)hipStreamDestroy(sl.stream);
+    }
+    for (auto& kv : S->reqs) delete kv.second;
+    delete S;
+    return SS_OK;
+}
