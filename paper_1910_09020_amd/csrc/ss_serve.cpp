@@ -101,6 +101,7 @@ struct Slot {
     void* pinned = nullptr;
     size_t pinned_cap = 0;
     Request* cur = nullptr;
+    bool launched = false;     // cur's work (and the completion event) is enqueued
 };
 
 }  // namespace
@@ -261,6 +262,8 @@ void dispatcher_main(ss_server* S)
             sl.cur = nullptr;
             S->running--;
             finish(S, r, rc);
+        } else {
+            sl.launched = true;      // only now may the completion thread poll the event
         }
         S->cv_work.notify_all();     // wake the completion thread
     }
@@ -275,7 +278,7 @@ void completer_main(ss_server* S)
             std::unique_lock<std::mutex> lk(S->mu);
             if (S->stop && S->running == 0) return;
             for (int i = 0; i < (int)S->slots.size(); i++)
-                if (S->slots[(size_t)i].cur) busy.push_back(i);
+                if (S->slots[(size_t)i].cur && S->slots[(size_t)i].launched) busy.push_back(i);
             if (busy.empty()) {
                 S->cv_work.wait_for(lk, std::chrono::milliseconds(2));
                 continue;
@@ -305,6 +308,7 @@ void completer_main(ss_server* S)
             }
             std::lock_guard<std::mutex> lk(S->mu);
             sl.cur = nullptr;
+            sl.launched = false;
             S->running--;
             finish(S, r, status);
             S->cv_work.notify_all();
