@@ -111,6 +111,72 @@ def mixed_leg(a, torch, ss, gen, runner, oracle):
     return res
 
 
+def serving_leg(a, ss, gen, runner, oracle):
+    """Continuous batching: Poisson arrivals, requests of 1..4096 pairs of 100..10,000 bp (log-uniform)
+    with one threshold rate per request, submitted at their scheduled times to one server; latency is
+    completion time minus scheduled arrival time."""
+    import concurrent.futures as cf
+    seed = 1910090204
+    arr = gen.arrivals(seed, a.serve_rate, a.serve_seconds)
+    nreq = len(arr)
+    ctx = runner.context()
+    srv = ss.ss_server_create(ctx, 32 << 30, a.serve_slots)
+    pool = cf.ThreadPoolExecutor(max_workers=min(12, os.cpu_count() or 1))
+    ahead = 0.25                                      # generate requests up to this far ahead
+    futs = {}
+    nxt = 0
+    tickets = []
+    keep = []
+    t0 = time.perf_counter_ns() + 300_000_000      # schedule starts 0.3 s from now
+    for i in range(nreq):
+        while nxt < nreq and arr[nxt] < arr[i] + ahead:
+            futs[nxt] = pool.submit(gen.request, seed, nxt)
+            nxt += 1
+        r = futs.pop(i).result()
+        due = t0 + int(arr[i] * 1e9)
+        now = time.perf_counter_ns()
+        if due > now:
+            time.sleep((due - now) / 1e9)
+        acc = np.empty(r["n"], np.uint8)
+        ed = np.empty(r["n"], np.int32)
+        t = ss.ss_server_submit(srv, r["reads"], r["refs"], r["lengths"], r["E"], acc, ed)
+        tickets.append(t)
+        keep.append((r["n"], int(len(r["reads"])), acc, ed, due))
+    pool.shutdown()
+    for t in tickets:
+        rc = ss.ss_server_wait(srv, t, -1)
+        assert rc == ss.SS_OK, rc
+    # steady-clock ns of the server vs perf_counter_ns of this process: both CLOCK_MONOTONIC on Linux
+    lat = []
+    done_last = 0
+    for t, (n, bases, acc, ed, due) in zip(tickets, keep):
+        _, _, done = ss.ss_server_times(srv, t)
+        lat.append((done - due) / 1e6)
+        done_last = max(done_last, done)
+    lat = np.array(lat)
+    pairs = int(sum(k[0] for k in keep))
+    bases = int(sum(k[1] for k in keep))
+    st = ss.ss_server_stats(srv)
+    span = (done_last - t0) / 1e9
+    # exactness: a sample of requests against the oracle
+    rng = np.random.default_rng(5)
+    chk = rng.choice(nreq, size=min(40, nreq), replace=False)
+    mism = 0
+    for i in chk:
+        r = gen.request(seed, int(i))
+        w = oracle.batch(r["reads"], r["refs"], r["offsets"], r["lengths"], E_per_pair=r["E"],
+                         threads=min(16, os.cpu_count() or 1))
+        mism += int(np.sum((w["accept"] != keep[i][2]) | (w["edits"] != keep[i][3])))
+    ss.ss_server_destroy(srv)
+    res = dict(arrival_rate=a.serve_rate, seconds=a.serve_seconds, requests=nreq, pairs=pairs, bases=bases,
+               pairs_per_s=pairs / span, p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
+               max_ms=float(lat.max()), slots=a.serve_slots, hbm_budget_bytes=32 << 30, stats=st,
+               oracle_checked_requests=int(len(chk)), oracle_mismatches=mism)
+    log(f"serving: {nreq} requests, {pairs} pairs in {span:.2f}s, p50 {res['p50_ms']:.3f} ms, "
+        f"p99 {res['p99_ms']:.3f} ms, stats {st}, oracle mismatches {mism}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -123,6 +189,10 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--mixed-n", type=int, default=None, help="pairs of the mixed-length batch (default 5.02 M)")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=10.0, help="serving schedule length (60 s in full)")
+    ap.add_argument("--serve-rate", type=float, default=2000.0, help="Poisson arrival rate, requests/s")
+    ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--no-cpu", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1:
@@ -205,6 +275,10 @@ def main():
     if not a.no_mixed:
         mixed = mixed_leg(a, torch, ss, gen, runner, oracle)
 
+    serving = None
+    if not a.no_serve:
+        serving = serving_leg(a, ss, gen, runner, oracle)
+
     cpu = None
     if not a.no_cpu:
         threads = min(16, os.cpu_count() or 1)
@@ -248,6 +322,7 @@ def main():
         "cpu_baseline": cpu,
         "hbm_copy_calibration_gbs": copy_gbs,
         "mixed": mixed,
+        "serving": serving,
     }
     print(json.dumps(line), flush=True)
 
