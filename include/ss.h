@@ -178,7 +178,9 @@ int ss_filter_wave_async(ss_ctx* ctx, const uint32_t* packed, int64_t total_base
  *
  * A plan is built on the host from the pairs' lengths and thresholds (host
  * arrays, copied; the plan keeps no pointer to them): each pair gets a shape
- * (lanes per pair, 32-row slices per lane, at most slices_per_lane = 4 or 8)
+ * (lanes per pair, 32-row slices per lane, at most slices_per_lane = 1, 2, 4
+ * or 8: fewer slices per lane spread a pair over more lanes, for lower
+ * latency per pair at some cost in total work)
  * from its threshold; pairs are sorted by shape and length, cut into work
  * items of one 256-thread block round, and the items ordered largest
  * estimated cost first.  The plan owns its device buffers (permutation, item
@@ -207,7 +209,7 @@ int ss_plan_capture(ss_ctx* ctx, ss_plan* plan, const uint32_t* packed, int64_t 
                     const int64_t* offsets, const int32_t* lengths, const int32_t* E_per_pair, uint16_t* out);
 int ss_plan_launch(ss_plan* plan, void* stream);
 
-/* Autotuned plan: times the candidate shapes (4 and 8 slices per lane) on
+/* Autotuned plan: times the candidate shapes (1, 2, 4, 8 slices per lane) on
  * this batch with the given device buffers (out_dev is overwritten), keeps
  * the fastest and records it in the JSON file cache_path (may be NULL) under
  * a key made of the device architecture and a coarse signature of the batch;
@@ -261,6 +263,11 @@ int ss_server_release(ss_server* server, ss_ticket ticket);
 /* Pause (hold != 0) or resume dispatching; paused requests stay queued.  For
  * tests of the timeout and queueing paths. */
 int ss_server_set_hold(ss_server* server, int hold);
+/* Slice width (1, 2, 4 or 8 32-row slices per lane, default 2) used to plan
+ * requests submitted from now on: fewer slices spread each pair over more
+ * lanes and shorten the longest pair's sweep, which bounds a request's
+ * latency. */
+int ss_server_set_slices(ss_server* server, int32_t slices_per_lane);
 int ss_server_stats(ss_server* server, int64_t* admitted, int64_t* deferred, int64_t* completed,
                     int64_t* peak_bytes, int64_t* peak_in_flight);
 /* Cancels queued requests, waits for running ones, frees everything. */

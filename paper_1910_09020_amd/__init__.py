@@ -79,6 +79,7 @@ def lib():
         "ss_server_stats": ([vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "ss_server_destroy": ([vp], ctypes.c_int),
         "ss_server_footprint": ([i64, i64], i64),
+        "ss_server_set_slices": ([vp, i32], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -96,7 +97,7 @@ def exported_symbols():
             "ss_plan_create", "ss_plan_destroy", "ss_plan_info", "ss_filter_planned_async", "ss_plan_capture",
             "ss_plan_launch", "ss_plan_create_tuned", "ss_server_create", "ss_server_submit", "ss_server_poll",
             "ss_server_wait", "ss_server_times", "ss_server_cancel", "ss_server_release", "ss_server_set_hold",
-            "ss_server_stats", "ss_server_destroy", "ss_server_footprint"]
+            "ss_server_stats", "ss_server_destroy", "ss_server_footprint", "ss_server_set_slices"]
 
 
 def status_str(status: int) -> str:
@@ -314,6 +315,10 @@ def ss_server_stats(server) -> dict:
     _check(lib().ss_server_stats(server, *[ctypes.addressof(x) for x in v]), "ss_server_stats")
     return dict(admitted=v[0].value, deferred=v[1].value, completed=v[2].value, peak_bytes=v[3].value,
                 peak_in_flight=v[4].value)
+
+
+def ss_server_set_slices(server, slices_per_lane: int) -> None:
+    _check(lib().ss_server_set_slices(server, int(slices_per_lane)), "ss_server_set_slices")
 
 
 def ss_server_footprint(n_pairs: int, total_bases: int) -> int:

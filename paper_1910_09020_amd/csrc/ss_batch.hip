@@ -145,8 +145,12 @@ void plan_items(const int32_t* lengths, const int32_t* E, int64_t n, int rsmax, 
 int persist_blocks_per_cu(int rsmax)
 {
     int per_cu = 1;
-    if (rsmax <= 4) (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persist<4>, 256, 0);
-    else (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persist<8>, 256, 0);
+    switch (rsmax) {
+    case 1: (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persist<1>, 256, 0); break;
+    case 2: (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persist<2>, 256, 0); break;
+    case 4: (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persist<4>, 256, 0); break;
+    default: (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persist<8>, 256, 0); break;
+    }
     return per_cu < 1 ? 1 : per_cu;
 }
 
@@ -157,12 +161,16 @@ hipError_t launch_persist(int rsmax, int grid, const PItem* d_items, int n_items
     if (n_items == 0) return hipSuccess;
     const int64_t SW = cdiv(total_bases, 32) + 2;
     hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, s, d_head);
-    if (rsmax <= 4)
-        hipLaunchKernelGGL(k_persist<4>, dim3(grid), dim3(256), 0, s, d_items, n_items, d_head, d_perm, packed, SW,
-                           offsets, lengths, Epp, out);
-    else
-        hipLaunchKernelGGL(k_persist<8>, dim3(grid), dim3(256), 0, s, d_items, n_items, d_head, d_perm, packed, SW,
-                           offsets, lengths, Epp, out);
+#define SS_PERSIST(RS)                                                                                     \
+    hipLaunchKernelGGL(k_persist<RS>, dim3(grid), dim3(256), 0, s, d_items, n_items, d_head, d_perm, packed, SW, \
+                       offsets, lengths, Epp, out)
+    switch (rsmax) {
+    case 1: SS_PERSIST(1); break;
+    case 2: SS_PERSIST(2); break;
+    case 4: SS_PERSIST(4); break;
+    default: SS_PERSIST(8); break;
+    }
+#undef SS_PERSIST
     return hipGetLastError();
 }
 
@@ -172,7 +180,7 @@ using namespace ss;
 
 // Tunables chosen per plan.
 struct PlanCfg {
-    int rsmax = 8;          // slices per lane at most (4 or 8)
+    int rsmax = 8;          // slices per lane at most (1, 2, 4 or 8)
 };
 
 struct ss_plan {
@@ -283,7 +291,7 @@ extern "C" int ss_plan_create(ss_ctx* ctx, const int32_t* lengths, const int32_t
                               int32_t slices_per_lane, ss_plan** out)
 {
     if (!ctx || !out) return SS_EINVAL;
-    if (slices_per_lane != 4 && slices_per_lane != 8) return SS_EINVAL;
+    if (slices_per_lane != 1 && slices_per_lane != 2 && slices_per_lane != 4 && slices_per_lane != 8) return SS_EINVAL;
     int rc = validate_plan_inputs(lengths, E_per_pair, n_pairs);
     if (rc != SS_OK) return rc;
     PlanCfg cfg;
@@ -435,14 +443,14 @@ extern "C" int ss_plan_create_tuned(ss_ctx* ctx, const int32_t* lengths, const i
             std::lock_guard<std::mutex> lk(g_cache_mu);
             auto m = read_cache(cache_path);
             auto it = m.find(key);
-            if (it != m.end() && (it->second == 4 || it->second == 8)) {
+            if (it != m.end() && (it->second == 1 || it->second == 2 || it->second == 4 || it->second == 8)) {
                 PlanCfg cfg;
                 cfg.rsmax = it->second;
                 if (chosen_slices) *chosen_slices = cfg.rsmax;
                 return make_plan(cfg, lengths, E_per_pair, n_pairs, out);
             }
         }
-        const int cands[2] = {4, 8};
+        const int cands[4] = {1, 2, 4, 8};
         float best_ms = 1e30f;
         int best = 8;
         hipStream_t s = nullptr;

@@ -79,11 +79,15 @@ enum State { QUEUED = 0, RUNNING = 1, DONE = 2, CANCELLED = 3 };
 struct Request {
     uint64_t id = 0;
     int64_t n = 0, total = 0;
-    std::vector<uint8_t> reads, refs;
-    std::vector<int32_t> lengths, E;
-    std::vector<int64_t> offsets;
-    std::vector<PItem> items;
-    std::vector<int64_t> perm;
+    int64_t n_items = 0;
+    int rsmax = 2;                 // slice width the plan was made for
+    // staging in the device layout (inputs, then results and the error word):
+    // a pooled pinned block when available, else pageable memory copied into
+    // the slot's pinned buffer at launch
+    void* pin = nullptr;
+    size_t pin_cls = 0;
+    std::vector<uint8_t> page;
+    uint8_t* stage = nullptr;      // where results come back (set at launch)
     uint8_t* accept_out = nullptr;
     int32_t* edits_out = nullptr;
     size_t footprint = 0;
@@ -106,13 +110,60 @@ struct Slot {
 
 }  // namespace
 
+// Pinned host blocks in power-of-two size classes, reused across requests.
+struct PinnedPool {
+    std::mutex mu;
+    std::unordered_map<size_t, std::vector<void*>> free_blocks;
+    size_t total = 0;
+    size_t cap = (size_t)4 << 30;
+    void* get(size_t need, size_t* cls)
+    {
+        size_t c = (size_t)1 << 20;
+        while (c < need) c <<= 1;
+        *cls = c;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            auto& v = free_blocks[c];
+            if (!v.empty()) {
+                void* p = v.back();
+                v.pop_back();
+                return p;
+            }
+            if (total + c > cap) return nullptr;
+            total += c;
+        }
+        void* p = nullptr;
+        if (hipHostMalloc(&p, c, hipHostMallocDefault) != hipSuccess) {
+            std::lock_guard<std::mutex> lk(mu);
+            total -= c;
+            return nullptr;
+        }
+        return p;
+    }
+    void put(void* p, size_t cls)
+    {
+        if (!p) return;
+        std::lock_guard<std::mutex> lk(mu);
+        free_blocks[cls].push_back(p);
+    }
+    void release_all()
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        for (auto& kv : free_blocks)
+            for (void* p : kv.second) (void)hipHostFree(p);
+        free_blocks.clear();
+        total = 0;
+    }
+};
+
 struct ss_server {
     ss_ctx* ctx = nullptr;
+    PinnedPool pool;
     int device = 0;
     size_t budget = 0;
     size_t used = 0;                 // sum of slot arena capacities
-    int rsmax = 8;
-    int grid_cap = 1;
+    int rsmax = 2;                   // slices per lane for new requests
+    int grid_cap[9] = {0};
     std::vector<Slot> slots;
     std::deque<Request*> queue;
     std::unordered_map<uint64_t, Request*> reqs;
@@ -135,31 +186,30 @@ size_t footprint_of(int64_t n, int64_t T)
     return Layout(n, T, n).total;
 }
 
+// Bytes of a request's staging: the device layout's inputs, results, error word.
+size_t stage_bytes(const Layout& L, int64_t n) { return L.in_bytes + al((size_t)n * 2) + 256; }
+
 // Enqueue the whole request on its slot's stream.  Called without the lock.
 int launch_request(ss_server* S, Slot& sl, Request* r)
 {
-    const Layout L(r->n, r->total, (int64_t)r->items.size());
-    // pinned staging: inputs, then results and the error word
-    const size_t pin_need = L.in_bytes + al((size_t)r->n * 2) + 256;
-    if (sl.pinned_cap < pin_need) {
-        if (sl.pinned) (void)hipHostFree(sl.pinned);
-        sl.pinned = nullptr;
-        sl.pinned_cap = 0;
-        const size_t want = std::max(pin_need, (size_t)1 << 20);
-        hipError_t e = hipHostMalloc(&sl.pinned, want, hipHostMallocDefault);
-        if (e != hipSuccess) return map_err(e);
-        sl.pinned_cap = want;
+    const Layout L(r->n, r->total, r->n_items);
+    uint8_t* h = (uint8_t*)r->pin;
+    if (!h) {
+        // pageable staging: copy into the slot's own pinned buffer first
+        const size_t need = stage_bytes(L, r->n);
+        if (sl.pinned_cap < need) {
+            if (sl.pinned) (void)hipHostFree(sl.pinned);
+            sl.pinned = nullptr;
+            sl.pinned_cap = 0;
+            const size_t want = std::max(need, (size_t)1 << 20);
+            hipError_t e = hipHostMalloc(&sl.pinned, want, hipHostMallocDefault);
+            if (e != hipSuccess) return map_err(e);
+            sl.pinned_cap = want;
+        }
+        h = (uint8_t*)sl.pinned;
+        std::memcpy(h, r->page.data(), L.in_bytes);
     }
-    uint8_t* h = (uint8_t*)sl.pinned;
-    if (r->total) {
-        std::memcpy(h + L.reads, r->reads.data(), (size_t)r->total);
-        std::memcpy(h + L.refs, r->refs.data(), (size_t)r->total);
-    }
-    std::memcpy(h + L.offsets, r->offsets.data(), (size_t)r->n * 8);
-    std::memcpy(h + L.lengths, r->lengths.data(), (size_t)r->n * 4);
-    std::memcpy(h + L.E, r->E.data(), (size_t)r->n * 4);
-    if (!r->items.empty()) std::memcpy(h + L.items, r->items.data(), r->items.size() * sizeof(PItem));
-    std::memcpy(h + L.perm, r->perm.data(), (size_t)r->n * 8);
+    r->stage = h;
     uint8_t* d = (uint8_t*)sl.arena;
     hipStream_t s = sl.stream;
     hipError_t e = hipMemcpyAsync(d, h, L.in_bytes, hipMemcpyHostToDevice, s);
@@ -167,8 +217,9 @@ int launch_request(ss_server* S, Slot& sl, Request* r)
     if (e == hipSuccess)
         e = launch_pack_stream(d + L.reads, d + L.refs, r->total, (uint32_t*)(d + L.packed), (uint32_t*)(d + L.err), s);
     if (e == hipSuccess) {
-        const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)r->items.size(), S->grid_cap));
-        e = launch_persist(S->rsmax, grid, (const PItem*)(d + L.items), (int)r->items.size(), (int*)(d + L.head),
+        const int cap = S->grid_cap[r->rsmax] > 0 ? S->grid_cap[r->rsmax] : 1;
+        const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(r->n_items, cap));
+        e = launch_persist(r->rsmax, grid, (const PItem*)(d + L.items), (int)r->n_items, (int*)(d + L.head),
                            (const int64_t*)(d + L.perm), (const uint32_t*)(d + L.packed), r->total,
                            (const int64_t*)(d + L.offsets), (const int32_t*)(d + L.lengths),
                            (const int32_t*)(d + L.E), (uint16_t*)(d + L.results), s);
@@ -223,8 +274,10 @@ void finish(ss_server* S, Request* r, int status)
     r->status = status;
     r->state = DONE;
     r->t_done = now_ns();
-    r->reads.clear(); r->reads.shrink_to_fit();
-    r->refs.clear(); r->refs.shrink_to_fit();
+    if (r->pin) { S->pool.put(r->pin, r->pin_cls); r->pin = nullptr; }
+    r->page.clear();
+    r->page.shrink_to_fit();
+    r->stage = nullptr;
     S->completed++;
     S->cv_done.notify_all();
 }
@@ -292,8 +345,8 @@ void completer_main(ss_server* S)
             Request* r = sl.cur;
             int status = map_err(q);
             if (status == SS_OK) {
-                const Layout L(r->n, r->total, (int64_t)r->items.size());
-                const uint8_t* h = (const uint8_t*)sl.pinned;
+                const Layout L(r->n, r->total, r->n_items);
+                const uint8_t* h = r->stage;
                 const uint16_t* res = (const uint16_t*)(h + L.in_bytes);
                 uint32_t err = 0;
                 std::memcpy(&err, h + L.in_bytes + al((size_t)r->n * 2), 4);
@@ -336,7 +389,7 @@ extern "C" int ss_server_create(ss_ctx* ctx, size_t hbm_budget_bytes, int32_t n_
     S->budget = hbm_budget_bytes;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, S->device) != hipSuccess) { delete S; return SS_EDEVICE; }
-    S->grid_cap = persist_blocks_per_cu(S->rsmax) * prop.multiProcessorCount;
+    for (int w : {1, 2, 4, 8}) S->grid_cap[w] = persist_blocks_per_cu(w) * prop.multiProcessorCount;
     S->slots.resize((size_t)n_slots);
     for (auto& sl : S->slots) {
         hipError_t e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
@@ -378,17 +431,38 @@ extern "C" int ss_server_submit(ss_server* S, const uint8_t* reads, const uint8_
             delete r;
             return SS_EBUDGET;
         }
-        r->reads.assign(reads, reads + T);
-        r->refs.assign(refs, refs + T);
-        r->lengths.assign(lengths, lengths + n_pairs);
-        r->E.assign(E_per_pair, E_per_pair + n_pairs);
-        r->offsets.resize((size_t)n_pairs);
-        int64_t o = 0;
-        for (int64_t i = 0; i < n_pairs; i++) { r->offsets[(size_t)i] = o; o += lengths[i]; }
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            r->rsmax = S->rsmax;
+        }
+        std::vector<PItem> items;
+        std::vector<int64_t> perm;
         int nc = 0;
         double cost = 0;
-        plan_items(r->lengths.data(), r->E.data(), n_pairs, S->rsmax, r->items, r->perm, &nc, &cost);
+        plan_items(lengths, E_per_pair, n_pairs, r->rsmax, items, perm, &nc, &cost);
+        r->n_items = (int64_t)items.size();
+        const Layout L(n_pairs, T, r->n_items);
+        const size_t need = stage_bytes(L, n_pairs);
+        uint8_t* h = (uint8_t*)S->pool.get(need, &r->pin_cls);
+        if (h) {
+            r->pin = h;
+        } else {
+            r->page.resize(need);
+            h = r->page.data();
+        }
+        if (T) {
+            std::memcpy(h + L.reads, reads, (size_t)T);
+            std::memcpy(h + L.refs, refs, (size_t)T);
+        }
+        int64_t* off = (int64_t*)(h + L.offsets);
+        int64_t o = 0;
+        for (int64_t i = 0; i < n_pairs; i++) { off[i] = o; o += lengths[i]; }
+        std::memcpy(h + L.lengths, lengths, (size_t)n_pairs * 4);
+        std::memcpy(h + L.E, E_per_pair, (size_t)n_pairs * 4);
+        if (!items.empty()) std::memcpy(h + L.items, items.data(), items.size() * sizeof(PItem));
+        std::memcpy(h + L.perm, perm.data(), (size_t)n_pairs * 8);
     } catch (const std::bad_alloc&) {
+        if (r && r->pin) S->pool.put(r->pin, r->pin_cls);
         delete r;
         return SS_ENOMEM;
     }
@@ -396,7 +470,11 @@ extern "C" int ss_server_submit(ss_server* S, const uint8_t* reads, const uint8_
     r->edits_out = edits_out;
     r->t_submit = now_ns();
     std::lock_guard<std::mutex> lk(S->mu);
-    if (S->stop) { delete r; return SS_EINVAL; }
+    if (S->stop) {
+        if (r->pin) S->pool.put(r->pin, r->pin_cls);
+        delete r;
+        return SS_EINVAL;
+    }
     r->id = S->next_id++;
     S->reqs[r->id] = r;
     *ticket = r->id;
@@ -455,6 +533,8 @@ extern "C" int ss_server_cancel(ss_server* S, ss_ticket t)
     S->queue.erase(std::remove(S->queue.begin(), S->queue.end(), r), S->queue.end());
     r->state = CANCELLED;
     r->t_done = now_ns();
+    if (r->pin) { S->pool.put(r->pin, r->pin_cls); r->pin = nullptr; }
+    r->page.clear();
     S->cv_done.notify_all();
     return SS_OK;
 }
@@ -480,6 +560,15 @@ extern "C" int ss_server_set_hold(ss_server* S, int hold)
     return SS_OK;
 }
 
+extern "C" int ss_server_set_slices(ss_server* S, int32_t slices_per_lane)
+{
+    if (!S) return SS_EINVAL;
+    if (slices_per_lane != 1 && slices_per_lane != 2 && slices_per_lane != 4 && slices_per_lane != 8) return SS_EINVAL;
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->rsmax = slices_per_lane;
+    return SS_OK;
+}
+
 extern "C" int ss_server_stats(ss_server* S, int64_t* admitted, int64_t* deferred, int64_t* completed,
                                int64_t* peak_bytes, int64_t* peak_in_flight)
 {
@@ -499,7 +588,11 @@ extern "C" int ss_server_destroy(ss_server* S)
     {
         std::lock_guard<std::mutex> lk(S->mu);
         // queued requests are cancelled; running ones finish
-        for (Request* r : S->queue) { r->state = CANCELLED; r->t_done = now_ns(); }
+        for (Request* r : S->queue) {
+            r->state = CANCELLED;
+            r->t_done = now_ns();
+            if (r->pin) { S->pool.put(r->pin, r->pin_cls); r->pin = nullptr; }
+        }
         S->queue.clear();
         S->hold = false;
         S->stop = true;
@@ -516,6 +609,7 @@ extern "C" int ss_server_destroy(ss_server* S)
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
     }
     for (auto& kv : S->reqs) delete kv.second;
+    S->pool.release_all();
     delete S;
     return SS_OK;
 }

@@ -57,6 +57,12 @@ def test_alone_and_in_mix_are_identical(env):
         assert np.array_equal(subs[11][1], acc) and np.array_equal(subs[11][2], ed)
         st = ss.ss_server_stats(srv)
         assert st["completed"] == 26 and st["peak_in_flight"] >= 1
+        # every slice width gives the same results
+        for spl in (1, 4, 8):
+            ss.ss_server_set_slices(srv, spl)
+            t3, a3, e3 = submit(ss, srv, x)
+            assert ss.ss_server_wait(srv, t3, 60_000_000) == ss.SS_OK
+            assert np.array_equal(a3, acc) and np.array_equal(e3, ed), spl
     finally:
         ss.ss_server_destroy(srv)
 
