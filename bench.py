@@ -147,13 +147,17 @@ def serving_leg(a, ss, gen, runner, oracle):
         rc = ss.ss_server_wait(srv, t, -1)
         assert rc == ss.SS_OK, rc
     # steady-clock ns of the server vs perf_counter_ns of this process: both CLOCK_MONOTONIC on Linux
-    lat = []
+    lat, svc, wait, lag = [], [], [], []
     done_last = 0
     for t, (n, bases, acc, ed, due) in zip(tickets, keep):
-        _, _, done = ss.ss_server_times(srv, t)
+        sub, adm, done = ss.ss_server_times(srv, t)
         lat.append((done - due) / 1e6)
+        svc.append((done - adm) / 1e6)
+        wait.append((adm - sub) / 1e6)
+        lag.append((sub - due) / 1e6)
         done_last = max(done_last, done)
     lat = np.array(lat)
+    pct = lambda v, q: float(np.percentile(np.array(v), q))
     pairs = int(sum(k[0] for k in keep))
     bases = int(sum(k[1] for k in keep))
     st = ss.ss_server_stats(srv)
@@ -170,10 +174,14 @@ def serving_leg(a, ss, gen, runner, oracle):
     ss.ss_server_destroy(srv)
     res = dict(arrival_rate=a.serve_rate, seconds=a.serve_seconds, requests=nreq, pairs=pairs, bases=bases,
                pairs_per_s=pairs / span, p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
-               max_ms=float(lat.max()), slots=a.serve_slots, hbm_budget_bytes=32 << 30, stats=st,
+               max_ms=float(lat.max()), service_p50_ms=pct(svc, 50), service_p99_ms=pct(svc, 99),
+               queue_p50_ms=pct(wait, 50), queue_p99_ms=pct(wait, 99), submit_lag_p50_ms=pct(lag, 50),
+               submit_lag_p99_ms=pct(lag, 99), slots=a.serve_slots, hbm_budget_bytes=32 << 30, stats=st,
                oracle_checked_requests=int(len(chk)), oracle_mismatches=mism)
     log(f"serving: {nreq} requests, {pairs} pairs in {span:.2f}s, p50 {res['p50_ms']:.3f} ms, "
-        f"p99 {res['p99_ms']:.3f} ms, stats {st}, oracle mismatches {mism}")
+        f"p99 {res['p99_ms']:.3f} ms, service p50/p99 {res['service_p50_ms']:.3f}/{res['service_p99_ms']:.3f} ms, "
+        f"queue p50/p99 {res['queue_p50_ms']:.3f}/{res['queue_p99_ms']:.3f} ms, submit lag p50/p99 "
+        f"{res['submit_lag_p50_ms']:.3f}/{res['submit_lag_p99_ms']:.3f} ms, stats {st}, oracle mismatches {mism}")
     return res
 
 
@@ -193,6 +201,7 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="serving schedule length (60 s in full)")
     ap.add_argument("--serve-rate", type=float, default=2000.0, help="Poisson arrival rate, requests/s")
     ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-only", action="store_true", help="run only the serving leg (diagnostics)")
     ap.add_argument("--no-cpu", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1:
@@ -206,6 +215,10 @@ def main():
 
     ss.lib()
     torch.cuda.set_device(0)
+    if a.serve_only:
+        import oracle
+        print(json.dumps(serving_leg(a, ss, gen, runner, oracle)), flush=True)
+        return
     E = a.E
     n = a.n or gen.default_pairs(1)
     t = time.perf_counter()
