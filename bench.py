@@ -113,44 +113,25 @@ def mixed_leg(a, torch, ss, gen, runner, oracle):
 
 def serving_leg(a, ss, gen, runner, oracle):
     """Continuous batching: Poisson arrivals, requests of 1..4096 pairs of 100..10,000 bp (log-uniform)
-    with one threshold rate per request, submitted at their scheduled times to one server; latency is
-    completion time minus scheduled arrival time."""
-    import concurrent.futures as cf
+    with one threshold rate per request, generated by native worker threads just ahead of their arrival
+    and submitted at their scheduled times to one server; latency = completion - scheduled arrival."""
+    import ctypes
     seed = 1910090204
     arr = gen.arrivals(seed, a.serve_rate, a.serve_seconds)
     nreq = len(arr)
     ctx = runner.context()
     srv = ss.ss_server_create(ctx, 32 << 30, a.serve_slots)
-    pool = cf.ThreadPoolExecutor(max_workers=min(12, os.cpu_count() or 1))
-    ahead = 0.25                                      # generate requests up to this far ahead
-    futs = {}
-    nxt = 0
-    tickets = []
-    keep = []
-    t0 = time.perf_counter_ns() + 300_000_000      # schedule starts 0.3 s from now
-    for i in range(nreq):
-        while nxt < nreq and arr[nxt] < arr[i] + ahead:
-            futs[nxt] = pool.submit(gen.request, seed, nxt)
-            nxt += 1
-        r = futs.pop(i).result()
-        due = t0 + int(arr[i] * 1e9)
-        now = time.perf_counter_ns()
-        if due > now:
-            time.sleep((due - now) / 1e9)
-        acc = np.empty(r["n"], np.uint8)
-        ed = np.empty(r["n"], np.int32)
-        t = ss.ss_server_submit(srv, r["reads"], r["refs"], r["lengths"], r["E"], acc, ed)
-        tickets.append(t)
-        keep.append((r["n"], int(len(r["reads"])), acc, ed, due))
-    pool.shutdown()
-    for t in tickets:
-        rc = ss.ss_server_wait(srv, t, -1)
+    submit_ptr = ctypes.cast(ss.lib().ss_server_submit, ctypes.c_void_p).value
+    D = gen.drive(seed, arr, submit_ptr, srv, threads=min(12, os.cpu_count() or 1), window=1024)
+    assert D.submitted == nreq, f"submission failed: {D.submitted}"
+    for t in D.tickets:
+        rc = ss.ss_server_wait(srv, int(t), -1)
         assert rc == ss.SS_OK, rc
-    # steady-clock ns of the server vs perf_counter_ns of this process: both CLOCK_MONOTONIC on Linux
     lat, svc, wait, lag = [], [], [], []
     done_last = 0
-    for t, (n, bases, acc, ed, due) in zip(tickets, keep):
-        sub, adm, done = ss.ss_server_times(srv, t)
+    for i in range(nreq):
+        sub, adm, done = ss.ss_server_times(srv, int(D.tickets[i]))
+        due = int(D.due_ns[i])
         lat.append((done - due) / 1e6)
         svc.append((done - adm) / 1e6)
         wait.append((adm - sub) / 1e6)
@@ -158,25 +139,28 @@ def serving_leg(a, ss, gen, runner, oracle):
         done_last = max(done_last, done)
     lat = np.array(lat)
     pct = lambda v, q: float(np.percentile(np.array(v), q))
-    pairs = int(sum(k[0] for k in keep))
-    bases = int(sum(k[1] for k in keep))
+    pairs = int(D.pairs.sum())
+    bases = int(D.bases.sum())
     st = ss.ss_server_stats(srv)
-    span = (done_last - t0) / 1e9
+    span = (done_last - int(D.due_ns[0]) + int(arr[0] * 1e9)) / 1e9
     # exactness: a sample of requests against the oracle
     rng = np.random.default_rng(5)
     chk = rng.choice(nreq, size=min(40, nreq), replace=False)
     mism = 0
     for i in chk:
         r = gen.request(seed, int(i))
+        acc, ed = D.outputs(int(i))
         w = oracle.batch(r["reads"], r["refs"], r["offsets"], r["lengths"], E_per_pair=r["E"],
                          threads=min(16, os.cpu_count() or 1))
-        mism += int(np.sum((w["accept"] != keep[i][2]) | (w["edits"] != keep[i][3])))
+        mism += int(np.sum((w["accept"] != acc) | (w["edits"] != ed)))
+    D.free()
     ss.ss_server_destroy(srv)
     res = dict(arrival_rate=a.serve_rate, seconds=a.serve_seconds, requests=nreq, pairs=pairs, bases=bases,
                pairs_per_s=pairs / span, p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
                max_ms=float(lat.max()), service_p50_ms=pct(svc, 50), service_p99_ms=pct(svc, 99),
                queue_p50_ms=pct(wait, 50), queue_p99_ms=pct(wait, 99), submit_lag_p50_ms=pct(lag, 50),
                submit_lag_p99_ms=pct(lag, 99), slots=a.serve_slots, hbm_budget_bytes=32 << 30, stats=st,
+               hw_queues=os.environ.get("GPU_MAX_HW_QUEUES", "default"),
                oracle_checked_requests=int(len(chk)), oracle_mismatches=mism)
     log(f"serving: {nreq} requests, {pairs} pairs in {span:.2f}s, p50 {res['p50_ms']:.3f} ms, "
         f"p99 {res['p99_ms']:.3f} ms, service p50/p99 {res['service_p50_ms']:.3f}/{res['service_p99_ms']:.3f} ms, "

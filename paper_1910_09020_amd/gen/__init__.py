@@ -62,6 +62,11 @@ def _load():
     lib.ssgen_request_plan.restype = ctypes.c_int64
     lib.ssgen_request_fill.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32, vp, vp, vp, vp]
     lib.ssgen_request_fill.restype = ctypes.c_int
+    lib.ssgen_drive.argtypes = [ctypes.c_uint64, vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                vp, vp, ctypes.c_int, ctypes.c_int64, ctypes.c_int64, vp, vp, vp, vp, vp, vp]
+    lib.ssgen_drive.restype = ctypes.c_int64
+    lib.ssgen_drive_free.argtypes = [ctypes.c_int64, vp, vp]
+    lib.ssgen_drive_free.restype = None
     _lib = lib
     return lib
 
@@ -124,6 +129,47 @@ def request(seed: int, req: int, max_pairs: int = 4096, min_len: int = 100, max_
     refs = np.empty(total, dtype=np.uint8)
     lib.ssgen_request_fill(seed, req, n, _p(offsets), _p(lengths), _p(reads), _p(refs))
     return dict(n=n, reads=reads, refs=refs, offsets=offsets, lengths=lengths, E=E)
+
+
+class Drive:
+    """Result of a native serving-schedule run (see ssgen_drive): tickets, scheduled times and the
+    per-request output buffers, which stay owned by the generator library until free()."""
+
+    def __init__(self, n):
+        self.n = n
+        self.tickets = np.zeros(n, np.uint64)
+        self.due_ns = np.zeros(n, np.int64)
+        self.pairs = np.zeros(n, np.int32)
+        self.bases = np.zeros(n, np.int64)
+        self._acc = (ctypes.c_void_p * max(n, 1))()
+        self._ed = (ctypes.c_void_p * max(n, 1))()
+        self.submitted = 0
+
+    def outputs(self, i):
+        n = int(self.pairs[i])
+        a = np.ctypeslib.as_array((ctypes.c_uint8 * n).from_address(self._acc[i])).copy() if n else np.zeros(0, np.uint8)
+        e = np.ctypeslib.as_array((ctypes.c_int32 * n).from_address(self._ed[i])).copy() if n else np.zeros(0, np.int32)
+        return a, e
+
+    def free(self):
+        if self.n:
+            _load().ssgen_drive_free(self.n, ctypes.cast(self._acc, ctypes.c_void_p), ctypes.cast(self._ed, ctypes.c_void_p))
+            self.n = 0
+
+
+def drive(seed: int, arrivals_s: np.ndarray, submit_fn_ptr: int, server: int, threads: int = 8, window: int = 512,
+          t0_ns: int = 0, max_pairs: int = 4096, min_len: int = 100, max_len: int = 10000) -> Drive:
+    """Generate and submit the requests of a schedule natively (submit_fn_ptr: address of a function with
+    the signature of ss_server_submit; server: its first argument)."""
+    lib = _load()
+    arr = np.ascontiguousarray(arrivals_s, dtype=np.float64)
+    n = len(arr)
+    D = Drive(n)
+    got = lib.ssgen_drive(seed, _p(arr), n, max_pairs, min_len, max_len, ctypes.c_void_p(submit_fn_ptr),
+                          ctypes.c_void_p(server), threads, window, t0_ns, _p(D.tickets), _p(D.due_ns), _p(D.pairs),
+                          _p(D.bases), ctypes.cast(D._acc, ctypes.c_void_p), ctypes.cast(D._ed, ctypes.c_void_p))
+    D.submitted = int(got)
+    return D
 
 
 def concat(pairs) -> dict:
