@@ -352,19 +352,14 @@ typedef int (*ssgen_submit_fn)(void* server, const uint8_t* reads, const uint8_t
                                uint64_t* ticket);
 
 typedef struct {
-    int32_t n;
-    int64_t total;
-    uint8_t* reads; uint8_t* refs;
-    int32_t* lengths; int32_t* E; int64_t* offsets;
-    _Atomic int ready;
-} drive_req;
-
-typedef struct {
     uint64_t seed; int64_t n_req; int32_t max_pairs, min_len, max_len;
-    drive_req* reqs;
-    _Atomic int64_t next_gen;
-    _Atomic int64_t submitted;   /* requests handed to the server so far */
-    int64_t window;
+    const double* arrivals; int64_t t0_ns;
+    ssgen_submit_fn submit; void* server;
+    uint64_t* tickets; int64_t* due_ns; int32_t* pairs; int64_t* bases;
+    uint8_t** accept_out; int32_t** edits_out;
+    _Atomic int64_t next;
+    _Atomic int failed;          /* first failing status, 0 if none */
+    _Atomic int64_t submitted;
 } drive_ctx;
 
 static int64_t mono_ns(void)
@@ -374,98 +369,87 @@ static int64_t mono_ns(void)
     return (int64_t)ts.tv_sec * 1000000000LL + ts.tv_nsec;
 }
 
+static void sleep_until(int64_t due)
+{
+    for (;;) {
+        const int64_t now = mono_ns();
+        if (now >= due) return;
+        const int64_t left = due - now;
+        if (left > 200000) {
+            struct timespec ts = {(time_t)((left - 100000) / 1000000000LL), (long)((left - 100000) % 1000000000LL)};
+            nanosleep(&ts, NULL);
+        }
+    }
+}
+
+/* Each worker takes the next request index, generates it (ahead of its due
+ * time, since workers run ahead of the clock), sleeps until it is due and
+ * submits it itself, so the submit-time copies run on all workers. */
 static void* drive_worker(void* arg)
 {
     drive_ctx* D = (drive_ctx*)arg;
     for (;;) {
-        int64_t i = atomic_fetch_add(&D->next_gen, 1);
-        if (i >= D->n_req) break;
-        while (i - atomic_load(&D->submitted) > D->window) {   /* stay within the window */
-            struct timespec ts = {0, 200000};
-            nanosleep(&ts, NULL);
-        }
-        drive_req* r = &D->reqs[i];
-        int32_t n = ssgen_request_pairs(D->seed, i, D->max_pairs);
-        r->n = n;
-        r->lengths = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
-        r->E = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
-        r->offsets = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
-        r->total = ssgen_request_plan(D->seed, i, n, D->min_len, D->max_len, r->lengths, r->E);
+        const int64_t i = atomic_fetch_add(&D->next, 1);
+        if (i >= D->n_req || atomic_load(&D->failed)) break;
+        const int32_t n = ssgen_request_pairs(D->seed, i, D->max_pairs);
+        const size_t nn = (size_t)(n > 0 ? n : 1);
+        int32_t* lengths = (int32_t*)malloc(sizeof(int32_t) * nn);
+        int32_t* E = (int32_t*)malloc(sizeof(int32_t) * nn);
+        int64_t* offsets = (int64_t*)malloc(sizeof(int64_t) * nn);
+        const int64_t total = ssgen_request_plan(D->seed, i, n, D->min_len, D->max_len, lengths, E);
         int64_t o = 0;
-        for (int32_t k = 0; k < n; k++) { r->offsets[k] = o; o += r->lengths[k]; }
-        r->reads = (uint8_t*)malloc((size_t)(r->total > 0 ? r->total : 1));
-        r->refs = (uint8_t*)malloc((size_t)(r->total > 0 ? r->total : 1));
-        ssgen_request_fill(D->seed, i, n, r->offsets, r->lengths, r->reads, r->refs);
-        atomic_store(&r->ready, 1);
+        for (int32_t k = 0; k < n; k++) { offsets[k] = o; o += lengths[k]; }
+        uint8_t* reads = (uint8_t*)malloc((size_t)(total > 0 ? total : 1));
+        uint8_t* refs = (uint8_t*)malloc((size_t)(total > 0 ? total : 1));
+        ssgen_request_fill(D->seed, i, n, offsets, lengths, reads, refs);
+        const int64_t due = D->t0_ns + (int64_t)(D->arrivals[i] * 1e9);
+        D->accept_out[i] = (uint8_t*)malloc(nn);
+        D->edits_out[i] = (int32_t*)malloc(sizeof(int32_t) * nn);
+        D->due_ns[i] = due;
+        D->pairs[i] = n;
+        D->bases[i] = total;
+        sleep_until(due);
+        const int rc = D->submit(D->server, reads, refs, lengths, E, n, D->accept_out[i], D->edits_out[i],
+                                 &D->tickets[i]);
+        free(reads); free(refs); free(lengths); free(E); free(offsets);
+        if (rc != 0) {
+            int zero = 0;
+            atomic_compare_exchange_strong(&D->failed, &zero, rc);
+            break;
+        }
+        atomic_fetch_add(&D->submitted, 1);
     }
     return NULL;
 }
 
-/* Runs the whole schedule; returns the number of requests submitted, or -1 -
- * status of the first failed submission.  Per request (n_req entries):
- * tickets, due_ns (scheduled time), pairs, bases, and owned output buffers
- * (accept_out[i], edits_out[i]; freed by ssgen_drive_free).  t0_ns: the
- * schedule's time zero on CLOCK_MONOTONIC (0 = now + 100 ms). */
+/* Runs the whole schedule on `threads` workers; returns the number of
+ * requests submitted, or -1 + (status of a failed submission).  Per request
+ * (n_req entries, indexed by schedule position): ticket, due time
+ * (CLOCK_MONOTONIC ns), pairs, bases, and output buffers owned here until
+ * ssgen_drive_free.  t0_ns: schedule time zero (0 = now + 100 ms). */
 int64_t ssgen_drive(uint64_t seed, const double* arrivals, int64_t n_req, int32_t max_pairs, int32_t min_len,
                     int32_t max_len, ssgen_submit_fn submit, void* server, int threads, int64_t window,
                     int64_t t0_ns, uint64_t* tickets, int64_t* due_ns, int32_t* pairs, int64_t* bases,
                     uint8_t** accept_out, int32_t** edits_out)
 {
+    (void)window;
     if (threads < 1) threads = 1;
     if (threads > 64) threads = 64;
     drive_ctx D;
     D.seed = seed; D.n_req = n_req; D.max_pairs = max_pairs; D.min_len = min_len; D.max_len = max_len;
-    D.window = window > 0 ? window : 256;
-    D.reqs = (drive_req*)calloc((size_t)(n_req > 0 ? n_req : 1), sizeof(drive_req));
-    atomic_store(&D.next_gen, 0);
+    D.arrivals = arrivals; D.submit = submit; D.server = server;
+    D.tickets = tickets; D.due_ns = due_ns; D.pairs = pairs; D.bases = bases;
+    D.accept_out = accept_out; D.edits_out = edits_out;
+    for (int64_t i = 0; i < n_req; i++) { accept_out[i] = NULL; edits_out[i] = NULL; }
+    D.t0_ns = t0_ns ? t0_ns : mono_ns() + 100000000LL;
+    atomic_store(&D.next, 0);
+    atomic_store(&D.failed, 0);
     atomic_store(&D.submitted, 0);
     pthread_t tid[64];
     for (int t = 0; t < threads; t++) pthread_create(&tid[t], NULL, drive_worker, &D);
-    if (t0_ns == 0) t0_ns = mono_ns() + 100000000LL;
-    int64_t fail_at = -1;
-    int rc_fail = 0;
-    for (int64_t i = 0; i < n_req; i++) {
-        drive_req* r = &D.reqs[i];
-        while (!atomic_load(&r->ready)) {
-            struct timespec ts = {0, 20000};
-            nanosleep(&ts, NULL);
-        }
-        const int64_t due = t0_ns + (int64_t)(arrivals[i] * 1e9);
-        for (;;) {
-            const int64_t now = mono_ns();
-            if (now >= due) break;
-            const int64_t left = due - now;
-            if (left > 200000) {
-                struct timespec ts = {0, (long)(left - 100000)};
-                nanosleep(&ts, NULL);
-            }
-        }
-        accept_out[i] = (uint8_t*)malloc((size_t)(r->n > 0 ? r->n : 1));
-        edits_out[i] = (int32_t*)malloc(sizeof(int32_t) * (size_t)(r->n > 0 ? r->n : 1));
-        due_ns[i] = due;
-        pairs[i] = r->n;
-        bases[i] = r->total;
-        const int rc = submit(server, r->reads, r->refs, r->lengths, r->E, r->n, accept_out[i], edits_out[i],
-                              &tickets[i]);
-        free(r->reads); free(r->refs); free(r->lengths); free(r->E); free(r->offsets);
-        atomic_fetch_add(&D.submitted, 1);
-        if (rc != 0) { fail_at = i; rc_fail = rc; break; }
-    }
-    if (fail_at >= 0) {
-        atomic_store(&D.next_gen, n_req);                 /* no new work for the generators */
-        atomic_store(&D.submitted, n_req + D.window);     /* and none of them waits */
-    }
     for (int t = 0; t < threads; t++) pthread_join(tid[t], NULL);
-    if (fail_at >= 0) {
-        for (int64_t i = fail_at + 1; i < n_req; i++) {
-            drive_req* r = &D.reqs[i];
-            if (atomic_load(&r->ready)) { free(r->reads); free(r->refs); free(r->lengths); free(r->E); free(r->offsets); }
-            accept_out[i] = NULL;
-            edits_out[i] = NULL;
-        }
-    }
-    free(D.reqs);
-    return fail_at >= 0 ? (int64_t)(-1 + rc_fail) : n_req;
+    const int f = atomic_load(&D.failed);
+    return f ? (int64_t)(-1 + f) : atomic_load(&D.submitted);
 }
 
 void ssgen_drive_free(int64_t n_req, uint8_t** accept_out, int32_t** edits_out)
