@@ -126,7 +126,8 @@ def serving_leg(a, ss, gen, runner, oracle):
     ctx = runner.context()
     srv = ss.ss_server_create(ctx, 32 << 30, a.serve_slots)
     submit_ptr = ctypes.cast(ss.lib().ss_server_submit, ctypes.c_void_p).value
-    D = gen.drive(seed, arr, submit_ptr, srv, threads=min(16, max(4, os.cpu_count() or 1)), window=1024)
+    pool = min(nreq, a.serve_pool)
+    D = gen.drive(seed, arr, submit_ptr, srv, threads=min(16, max(4, os.cpu_count() or 1)), pool=pool)
     assert D.submitted == nreq, f"submission failed: {D.submitted}"
     for t in D.tickets:
         rc = ss.ss_server_wait(srv, int(t), -1)
@@ -153,7 +154,7 @@ def serving_leg(a, ss, gen, runner, oracle):
     chk = rng.choice(nreq, size=min(40, nreq), replace=False)
     mism = 0
     for i in chk:
-        r = gen.request(seed, int(i))
+        r = gen.request(seed, int(i) % pool if pool else int(i))
         acc, ed = D.outputs(int(i))
         w = oracle.batch(r["reads"], r["refs"], r["offsets"], r["lengths"], E_per_pair=r["E"],
                          threads=min(16, os.cpu_count() or 1))
@@ -165,7 +166,7 @@ def serving_leg(a, ss, gen, runner, oracle):
                max_ms=float(lat.max()), service_p50_ms=pct(svc, 50), service_p99_ms=pct(svc, 99),
                queue_p50_ms=pct(wait, 50), queue_p99_ms=pct(wait, 99), submit_lag_p50_ms=pct(lag, 50),
                submit_lag_p99_ms=pct(lag, 99), slots=a.serve_slots, hbm_budget_bytes=32 << 30, stats=st,
-               hw_queues=os.environ.get("GPU_MAX_HW_QUEUES", "default"),
+               hw_queues=os.environ.get("GPU_MAX_HW_QUEUES", "default"), distinct_requests=pool or nreq,
                oracle_checked_requests=int(len(chk)), oracle_mismatches=mism)
     log(f"serving: {nreq} requests, {pairs} pairs in {span:.2f}s, p50 {res['p50_ms']:.3f} ms, "
         f"p99 {res['p99_ms']:.3f} ms, service p50/p99 {res['service_p50_ms']:.3f}/{res['service_p99_ms']:.3f} ms, "
@@ -190,6 +191,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="serving schedule length (60 s in full)")
     ap.add_argument("--serve-rate", type=float, default=2000.0, help="Poisson arrival rate, requests/s")
     ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-pool", type=int, default=2000,
+                    help="distinct requests generated before the clock starts (0: generate on the fly)")
     ap.add_argument("--serve-only", action="store_true", help="run only the serving leg (diagnostics)")
     ap.add_argument("--no-cpu", action="store_true")
     a = ap.parse_args()

@@ -157,16 +157,17 @@ class Drive:
             self.n = 0
 
 
-def drive(seed: int, arrivals_s: np.ndarray, submit_fn_ptr: int, server: int, threads: int = 8, window: int = 512,
+def drive(seed: int, arrivals_s: np.ndarray, submit_fn_ptr: int, server: int, threads: int = 8, pool: int = 0,
           t0_ns: int = 0, max_pairs: int = 4096, min_len: int = 100, max_len: int = 10000) -> Drive:
     """Generate and submit the requests of a schedule natively (submit_fn_ptr: address of a function with
-    the signature of ss_server_submit; server: its first argument)."""
+    the signature of ss_server_submit; server: its first argument).  pool > 0: requests 0..pool-1 are
+    generated before the clock starts and schedule position i replays request i mod pool."""
     lib = _load()
     arr = np.ascontiguousarray(arrivals_s, dtype=np.float64)
     n = len(arr)
     D = Drive(n)
     got = lib.ssgen_drive(seed, _p(arr), n, max_pairs, min_len, max_len, ctypes.c_void_p(submit_fn_ptr),
-                          ctypes.c_void_p(server), threads, window, t0_ns, _p(D.tickets), _p(D.due_ns), _p(D.pairs),
+                          ctypes.c_void_p(server), threads, pool, t0_ns, _p(D.tickets), _p(D.due_ns), _p(D.pairs),
                           _p(D.bases), ctypes.cast(D._acc, ctypes.c_void_p), ctypes.cast(D._ed, ctypes.c_void_p))
     D.submitted = int(got)
     return D

@@ -352,7 +352,15 @@ typedef int (*ssgen_submit_fn)(void* server, const uint8_t* reads, const uint8_t
                                uint64_t* ticket);
 
 typedef struct {
+    int32_t n;
+    int64_t total;
+    uint8_t* reads; uint8_t* refs;
+    int32_t* lengths; int32_t* E;
+} pool_req;
+
+typedef struct {
     uint64_t seed; int64_t n_req; int32_t max_pairs, min_len, max_len;
+    pool_req* pool; int64_t n_pool; _Atomic int64_t next_pool;
     const double* arrivals; int64_t t0_ns;
     ssgen_submit_fn submit; void* server;
     uint64_t* tickets; int64_t* due_ns; int32_t* pairs; int64_t* bases;
@@ -382,36 +390,58 @@ static void sleep_until(int64_t due)
     }
 }
 
-/* Each worker takes the next request index, generates it (ahead of its due
- * time, since workers run ahead of the clock), sleeps until it is due and
- * submits it itself, so the submit-time copies run on all workers. */
+static void make_request(drive_ctx* D, int64_t id, pool_req* q)
+{
+    const int32_t n = ssgen_request_pairs(D->seed, id, D->max_pairs);
+    const size_t nn = (size_t)(n > 0 ? n : 1);
+    q->n = n;
+    q->lengths = (int32_t*)malloc(sizeof(int32_t) * nn);
+    q->E = (int32_t*)malloc(sizeof(int32_t) * nn);
+    int64_t* offsets = (int64_t*)malloc(sizeof(int64_t) * nn);
+    q->total = ssgen_request_plan(D->seed, id, n, D->min_len, D->max_len, q->lengths, q->E);
+    int64_t o = 0;
+    for (int32_t k = 0; k < n; k++) { offsets[k] = o; o += q->lengths[k]; }
+    q->reads = (uint8_t*)malloc((size_t)(q->total > 0 ? q->total : 1));
+    q->refs = (uint8_t*)malloc((size_t)(q->total > 0 ? q->total : 1));
+    ssgen_request_fill(D->seed, id, n, offsets, q->lengths, q->reads, q->refs);
+    free(offsets);
+}
+
+static void* pool_worker(void* arg)
+{
+    drive_ctx* D = (drive_ctx*)arg;
+    for (;;) {
+        const int64_t k = atomic_fetch_add(&D->next_pool, 1);
+        if (k >= D->n_pool) break;
+        make_request(D, k, &D->pool[k]);
+    }
+    return NULL;
+}
+
+/* Each worker takes the next schedule position i, sleeps until it is due and
+ * submits request (i mod pool size) itself, so the submit-time copies run on
+ * all workers.  Without a pool the worker generates request i first. */
 static void* drive_worker(void* arg)
 {
     drive_ctx* D = (drive_ctx*)arg;
     for (;;) {
         const int64_t i = atomic_fetch_add(&D->next, 1);
         if (i >= D->n_req || atomic_load(&D->failed)) break;
-        const int32_t n = ssgen_request_pairs(D->seed, i, D->max_pairs);
-        const size_t nn = (size_t)(n > 0 ? n : 1);
-        int32_t* lengths = (int32_t*)malloc(sizeof(int32_t) * nn);
-        int32_t* E = (int32_t*)malloc(sizeof(int32_t) * nn);
-        int64_t* offsets = (int64_t*)malloc(sizeof(int64_t) * nn);
-        const int64_t total = ssgen_request_plan(D->seed, i, n, D->min_len, D->max_len, lengths, E);
-        int64_t o = 0;
-        for (int32_t k = 0; k < n; k++) { offsets[k] = o; o += lengths[k]; }
-        uint8_t* reads = (uint8_t*)malloc((size_t)(total > 0 ? total : 1));
-        uint8_t* refs = (uint8_t*)malloc((size_t)(total > 0 ? total : 1));
-        ssgen_request_fill(D->seed, i, n, offsets, lengths, reads, refs);
+        pool_req own;
+        const pool_req* q;
+        if (D->n_pool > 0) q = &D->pool[i % D->n_pool];
+        else { make_request(D, i, &own); q = &own; }
+        const size_t nn = (size_t)(q->n > 0 ? q->n : 1);
         const int64_t due = D->t0_ns + (int64_t)(D->arrivals[i] * 1e9);
         D->accept_out[i] = (uint8_t*)malloc(nn);
         D->edits_out[i] = (int32_t*)malloc(sizeof(int32_t) * nn);
         D->due_ns[i] = due;
-        D->pairs[i] = n;
-        D->bases[i] = total;
+        D->pairs[i] = q->n;
+        D->bases[i] = q->total;
         sleep_until(due);
-        const int rc = D->submit(D->server, reads, refs, lengths, E, n, D->accept_out[i], D->edits_out[i],
-                                 &D->tickets[i]);
-        free(reads); free(refs); free(lengths); free(E); free(offsets);
+        const int rc = D->submit(D->server, q->reads, q->refs, q->lengths, q->E, q->n, D->accept_out[i],
+                                 D->edits_out[i], &D->tickets[i]);
+        if (D->n_pool <= 0) { free(own.reads); free(own.refs); free(own.lengths); free(own.E); }
         if (rc != 0) {
             int zero = 0;
             atomic_compare_exchange_strong(&D->failed, &zero, rc);
@@ -426,13 +456,15 @@ static void* drive_worker(void* arg)
  * requests submitted, or -1 + (status of a failed submission).  Per request
  * (n_req entries, indexed by schedule position): ticket, due time
  * (CLOCK_MONOTONIC ns), pairs, bases, and output buffers owned here until
- * ssgen_drive_free.  t0_ns: schedule time zero (0 = now + 100 ms). */
+ * ssgen_drive_free.  pool > 0: requests 0..pool-1 are generated before the
+ * schedule starts and position i replays request i mod pool; pool = 0: each
+ * position generates its own request on the fly.  t0_ns: schedule time zero
+ * (0 = 100 ms after the pool is ready). */
 int64_t ssgen_drive(uint64_t seed, const double* arrivals, int64_t n_req, int32_t max_pairs, int32_t min_len,
-                    int32_t max_len, ssgen_submit_fn submit, void* server, int threads, int64_t window,
+                    int32_t max_len, ssgen_submit_fn submit, void* server, int threads, int64_t pool,
                     int64_t t0_ns, uint64_t* tickets, int64_t* due_ns, int32_t* pairs, int64_t* bases,
                     uint8_t** accept_out, int32_t** edits_out)
 {
-    (void)window;
     if (threads < 1) threads = 1;
     if (threads > 64) threads = 64;
     drive_ctx D;
@@ -441,6 +473,14 @@ int64_t ssgen_drive(uint64_t seed, const double* arrivals, int64_t n_req, int32_
     D.tickets = tickets; D.due_ns = due_ns; D.pairs = pairs; D.bases = bases;
     D.accept_out = accept_out; D.edits_out = edits_out;
     for (int64_t i = 0; i < n_req; i++) { accept_out[i] = NULL; edits_out[i] = NULL; }
+    D.n_pool = pool > 0 ? pool : 0;
+    D.pool = (pool_req*)calloc((size_t)(D.n_pool > 0 ? D.n_pool : 1), sizeof(pool_req));
+    atomic_store(&D.next_pool, 0);
+    {
+        pthread_t pt[64];
+        for (int t = 0; t < threads; t++) pthread_create(&pt[t], NULL, pool_worker, &D);
+        for (int t = 0; t < threads; t++) pthread_join(pt[t], NULL);
+    }
     D.t0_ns = t0_ns ? t0_ns : mono_ns() + 100000000LL;
     atomic_store(&D.next, 0);
     atomic_store(&D.failed, 0);
@@ -448,6 +488,10 @@ int64_t ssgen_drive(uint64_t seed, const double* arrivals, int64_t n_req, int32_
     pthread_t tid[64];
     for (int t = 0; t < threads; t++) pthread_create(&tid[t], NULL, drive_worker, &D);
     for (int t = 0; t < threads; t++) pthread_join(tid[t], NULL);
+    for (int64_t k = 0; k < D.n_pool; k++) {
+        free(D.pool[k].reads); free(D.pool[k].refs); free(D.pool[k].lengths); free(D.pool[k].E);
+    }
+    free(D.pool);
     const int f = atomic_load(&D.failed);
     return f ? (int64_t)(-1 + f) : atomic_load(&D.submitted);
 }
