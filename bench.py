@@ -125,6 +125,7 @@ def serving_leg(a, ss, gen, runner, oracle):
     nreq = len(arr)
     ctx = runner.context()
     srv = ss.ss_server_create(ctx, 32 << 30, a.serve_slots)
+    ss.ss_server_set_slices(srv, a.serve_slices)
     submit_ptr = ctypes.cast(ss.lib().ss_server_submit, ctypes.c_void_p).value
     pool = min(nreq, a.serve_pool)
     D = gen.drive(seed, arr, submit_ptr, srv, threads=min(16, max(4, os.cpu_count() or 1)), pool=pool)
@@ -167,6 +168,7 @@ def serving_leg(a, ss, gen, runner, oracle):
                queue_p50_ms=pct(wait, 50), queue_p99_ms=pct(wait, 99), submit_lag_p50_ms=pct(lag, 50),
                submit_lag_p99_ms=pct(lag, 99), slots=a.serve_slots, hbm_budget_bytes=32 << 30, stats=st,
                hw_queues=os.environ.get("GPU_MAX_HW_QUEUES", "default"), distinct_requests=pool or nreq,
+               slices_per_lane=a.serve_slices,
                oracle_checked_requests=int(len(chk)), oracle_mismatches=mism)
     log(f"serving: {nreq} requests, {pairs} pairs in {span:.2f}s, p50 {res['p50_ms']:.3f} ms, "
         f"p99 {res['p99_ms']:.3f} ms, service p50/p99 {res['service_p50_ms']:.3f}/{res['service_p99_ms']:.3f} ms, "
@@ -191,6 +193,7 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="serving schedule length (60 s in full)")
     ap.add_argument("--serve-rate", type=float, default=2000.0, help="Poisson arrival rate, requests/s")
     ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-slices", type=int, default=2, help="32-row slices per lane for served requests")
     ap.add_argument("--serve-pool", type=int, default=2000,
                     help="distinct requests generated before the clock starts (0: generate on the fly)")
     ap.add_argument("--serve-only", action="store_true", help="run only the serving leg (diagnostics)")

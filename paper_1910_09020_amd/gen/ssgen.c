@@ -337,10 +337,9 @@ int ssgen_request_fill(uint64_t seed, int64_t req, int32_t n, const int64_t* off
  * Native load driver for serving benchmarks.
  *
  * Generates the requests of a Poisson schedule on worker threads (each request
- * from its own stream, at most `window` requests ahead of the submitter) and
- * submits them at their scheduled times (CLOCK_MONOTONIC) through a caller
- * supplied submit function with the signature of the filter server's submit
- * entry point.  Output buffers are allocated here and kept until
+ * from its own stream) and submits them at their scheduled times
+ * (CLOCK_MONOTONIC) through a caller supplied submit function with the
+ * signature of the filter server's submit entry point.  Output buffers are allocated here and kept until
  * ssgen_drive_free.  This keeps the client's cost per request to a few
  * memcpys, so the measured latency is the server's.
  * ------------------------------------------------------------------------- */
