@@ -22,7 +22,7 @@ import time
 
 # more hardware queues than HIP's default 4, so that the serving leg's per-slot
 # streams run side by side (must be set before the HIP runtime starts)
-os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
+os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
 
 import numpy as np
 
@@ -192,8 +192,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="serving schedule length (60 s in full)")
     ap.add_argument("--serve-rate", type=float, default=2000.0, help="Poisson arrival rate, requests/s")
-    ap.add_argument("--serve-slots", type=int, default=8)
-    ap.add_argument("--serve-slices", type=int, default=2, help="32-row slices per lane for served requests")
+    ap.add_argument("--serve-slots", type=int, default=16)
+    ap.add_argument("--serve-slices", type=int, default=1, help="32-row slices per lane for served requests")
     ap.add_argument("--serve-pool", type=int, default=2000,
                     help="distinct requests generated before the clock starts (0: generate on the fly)")
     ap.add_argument("--serve-only", action="store_true", help="run only the serving leg (diagnostics)")

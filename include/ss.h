@@ -222,15 +222,16 @@ int ss_plan_create_tuned(ss_ctx* ctx, const int32_t* lengths, const int32_t* E_p
 
 /* ------------------------------------------------------------------------
  * Serving: continuous batching of filter requests on one device (not part of
- * the paper).  The server owns n_slots slots (stream, device arena, pinned
- * staging), reused from request to request.  Admission is by HBM budget: the
- * slots' arenas never total more than hbm_budget_bytes; requests that do not
- * fit wait in FIFO order until slots and memory free up.  Each admitted
- * request is encoded, planned (batched launch above) and filtered on its
- * slot's stream, so requests in different slots overlap on the device.
- * Threads: a dispatcher and a completion thread per server; the submit / poll
- * / wait calls are thread-safe.  The server uses the device current at
- * creation.
+ * the paper).  The server owns n_slots slots (a stream each); inputs are
+ * staged in pooled pinned host blocks at submission, device memory comes from
+ * the stream-ordered pool and is kept resident between requests.  Admission is
+ * by HBM budget: the device footprints (ss_server_footprint) of the requests
+ * in flight never total more than hbm_budget_bytes; requests that do not fit
+ * wait in FIFO order until slots and memory free up.  Each admitted request is
+ * encoded, planned (batched launch above) and filtered on its slot's stream,
+ * so requests in different slots overlap on the device.  Threads: a
+ * dispatcher and a completion thread per server; submit / poll / wait are
+ * thread-safe.  The server uses the device current at creation.
  * ---------------------------------------------------------------------- */
 typedef struct ss_server ss_server;
 typedef uint64_t ss_ticket;
@@ -263,7 +264,7 @@ int ss_server_release(ss_server* server, ss_ticket ticket);
 /* Pause (hold != 0) or resume dispatching; paused requests stay queued.  For
  * tests of the timeout and queueing paths. */
 int ss_server_set_hold(ss_server* server, int hold);
-/* Slice width (1, 2, 4 or 8 32-row slices per lane, default 2) used to plan
+/* Slice width (1, 2, 4 or 8 32-row slices per lane, default 1) used to plan
  * requests submitted from now on: fewer slices spread each pair over more
  * lanes and shorten the longest pair's sweep, which bounds a request's
  * latency. */

@@ -1,13 +1,15 @@
 // Serving loop: continuous batching of filter requests on one device.
 //
 // A request is a batch of pairs (ASCII, lengths, per-pair thresholds) with host
-// output arrays.  The server owns a fixed number of slots; each slot has its
-// own HIP stream, a device arena and pinned staging that stay allocated and
-// are reused from request to request.  Admission is by HBM budget: the sum of
-// the slots' arenas never exceeds the budget given at creation; a request that
-// does not fit waits in a FIFO queue until slots and memory free up (idle
-// arenas are released to make room).  An admitted request is enqueued on its
-// slot's stream: copies in, bit-stream encoding, a per-request plan of the
+// output arrays.  The server owns a fixed number of slots, each with its own
+// HIP stream.  Admission is by HBM budget: the device footprints of the
+// requests in flight never total more than the budget given at creation; a
+// request that does not fit waits in a FIFO queue until slots and memory free
+// up.  Device memory comes from the stream-ordered pool (hipMallocAsync on the
+// slot's stream, hipFreeAsync after the last copy), kept resident between
+// requests, so dispatching never synchronises the device.  Inputs are staged
+// in pooled pinned blocks at submission.  An admitted request is enqueued on
+// its slot's stream: copies in, bit-stream encoding, a per-request plan of the
 // batched launch (ss_batch.hip), the persistent filter kernel, copies out.
 // Requests in different slots run concurrently on the device, and requests
 // that arrive while others are running are admitted as soon as a slot and
@@ -100,7 +102,7 @@ struct Request {
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
-    void* arena = nullptr;
+    void* arena = nullptr;           // the running request's device memory (stream-ordered)
     size_t arena_cap = 0;
     void* pinned = nullptr;
     size_t pinned_cap = 0;
@@ -161,8 +163,8 @@ struct ss_server {
     PinnedPool pool;
     int device = 0;
     size_t budget = 0;
-    size_t used = 0;                 // sum of slot arena capacities
-    int rsmax = 2;                   // slices per lane for new requests
+    size_t used = 0;                 // sum of the footprints of requests in flight
+    int rsmax = 1;                   // slices per lane for new requests
     int grid_cap[9] = {0};
     std::vector<Slot> slots;
     std::deque<Request*> queue;
@@ -210,9 +212,14 @@ int launch_request(ss_server* S, Slot& sl, Request* r)
         std::memcpy(h, r->page.data(), L.in_bytes);
     }
     r->stage = h;
-    uint8_t* d = (uint8_t*)sl.arena;
     hipStream_t s = sl.stream;
-    hipError_t e = hipMemcpyAsync(d, h, L.in_bytes, hipMemcpyHostToDevice, s);
+    void* arena = nullptr;
+    hipError_t e = hipMallocAsync(&arena, r->footprint, s);
+    if (e != hipSuccess) return map_err(e);
+    sl.arena = arena;
+    sl.arena_cap = r->footprint;
+    uint8_t* d = (uint8_t*)arena;
+    e = hipMemcpyAsync(d, h, L.in_bytes, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemsetAsync(d + L.err, 0, 4, s);
     if (e == hipSuccess)
         e = launch_pack_stream(d + L.reads, d + L.refs, r->total, (uint32_t*)(d + L.packed), (uint32_t*)(d + L.err), s);
@@ -228,49 +235,33 @@ int launch_request(ss_server* S, Slot& sl, Request* r)
     if (e == hipSuccess && r->n)
         e = hipMemcpyAsync(h + hres, d + L.results, (size_t)r->n * 2, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipMemcpyAsync(h + herr, d + L.err, 4, hipMemcpyDeviceToHost, s);
+    // the memory returns to the pool once the stream has passed this point
+    const hipError_t ef = hipFreeAsync(arena, s);
+    if (e == hipSuccess) e = ef;
+    sl.arena = nullptr;
+    sl.arena_cap = 0;
     if (e == hipSuccess) e = hipEventRecord(sl.done, s);
     return map_err(e);
 }
 
-// Pick a free slot for the head request, growing its arena within the budget
-// (releasing idle arenas when needed).  Returns the slot index or -1.  Lock held.
+// Pick a free slot for the head request if its footprint fits the budget next
+// to the requests in flight.  Returns the slot index or -1.  Lock held.
 int admit_slot(ss_server* S, Request* r)
 {
-    int best = -1;
+    if (S->used + r->footprint > S->budget) return -1;
     for (int i = 0; i < (int)S->slots.size(); i++) {
-        Slot& sl = S->slots[(size_t)i];
-        if (sl.cur) continue;
-        if (sl.arena_cap >= r->footprint) return i;            // fits in an existing arena
-        if (best < 0 || sl.arena_cap > S->slots[(size_t)best].arena_cap) best = i;
+        if (S->slots[(size_t)i].cur) continue;
+        S->used += r->footprint;
+        S->peak_used = std::max<int64_t>(S->peak_used, (int64_t)S->used);
+        return i;
     }
-    if (best < 0) return -1;
-    Slot& sl = S->slots[(size_t)best];
-    size_t need = r->footprint - sl.arena_cap;
-    if (S->used + need > S->budget) {
-        // release idle arenas (other than the chosen one) until the request fits
-        for (auto& o : S->slots) {
-            if (&o == &sl || o.cur || !o.arena) continue;
-            (void)hipFree(o.arena);
-            S->used -= o.arena_cap;
-            o.arena = nullptr;
-            o.arena_cap = 0;
-            if (S->used + need <= S->budget) break;
-        }
-    }
-    if (S->used + need > S->budget) return -1;
-    if (sl.arena) { (void)hipFree(sl.arena); S->used -= sl.arena_cap; sl.arena = nullptr; sl.arena_cap = 0; }
-    void* p = nullptr;
-    if (hipMalloc(&p, r->footprint) != hipSuccess) return -1;
-    sl.arena = p;
-    sl.arena_cap = r->footprint;
-    S->used += r->footprint;
-    S->peak_used = std::max<int64_t>(S->peak_used, (int64_t)S->used);
-    return best;
+    return -1;
 }
 
 void finish(ss_server* S, Request* r, int status)
 {
     // lock held
+    if (r->state == RUNNING) S->used -= r->footprint;
     r->status = status;
     r->state = DONE;
     r->t_done = now_ns();
@@ -390,6 +381,14 @@ extern "C" int ss_server_create(ss_ctx* ctx, size_t hbm_budget_bytes, int32_t n_
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, S->device) != hipSuccess) { delete S; return SS_EDEVICE; }
     for (int w : {1, 2, 4, 8}) S->grid_cap[w] = persist_blocks_per_cu(w) * prop.multiProcessorCount;
+    {
+        // keep freed request memory in the device's stream-ordered pool
+        hipMemPool_t pool = nullptr;
+        if (hipDeviceGetDefaultMemPool(&pool, S->device) == hipSuccess && pool) {
+            uint64_t keep = (uint64_t)hbm_budget_bytes;
+            (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+        }
+    }
     S->slots.resize((size_t)n_slots);
     for (auto& sl : S->slots) {
         hipError_t e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
@@ -603,7 +602,6 @@ extern "C" int ss_server_destroy(ss_server* S)
     S->completer.join();
     for (auto& sl : S->slots) {
         if (sl.stream) (void)hipStreamSynchronize(sl.stream);
-        if (sl.arena) (void)hipFree(sl.arena);
         if (sl.pinned) (void)hipHostFree(sl.pinned);
         if (sl.done) (void)hipEventDestroy(sl.done);
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
