@@ -277,6 +277,11 @@ def main():
     _, (cp_ms,) = timed_loop([cp], 5, torch)
     copy_gbs = 2 * src.numel() / (cp_ms * 1e-3) / 1e9
     log(f"device copy: {copy_gbs:.0f} GB/s (read + write)")
+    # read-only kernel of known size (2 GiB summed as int32): calibrates the fetch counter
+    rd = lambda: src.view(torch.int32).sum()
+    rd(); torch.cuda.synchronize()
+    _, (rd_ms,) = timed_loop([rd], 3, torch)
+    log(f"device read: {src.numel() / (rd_ms * 1e-3) / 1e9:.0f} GB/s")
     del src, dst
 
     mixed = None
