@@ -33,6 +33,28 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 VALU_PEAK_TOPS = 39.3          # 256 CU x 64 lanes x 2.4 GHz, 32-bit lane ops / s (1e12)
 
 
+def measured_traffic(name):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 PMC summary, or None when the
+    kernel's source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "encode_sweep_100bp_E5_pmc_traffic.md")
+    try:
+        text = open(path).read()
+    except OSError:
+        return None
+    for line in text.splitlines():
+        f = line.split()
+        if len(f) == 5 and f[0] == "traffic" and f[1] == name:
+            kv = dict(x.split("=", 1) for x in f[2:])
+            src = os.path.join(ROOT, kv["source"])
+            try:
+                sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+            except OSError:
+                return None
+            return float(kv["bytes"]) if sha == kv["sha256_16"] else None
+    return None
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -307,8 +329,10 @@ def main():
     filt_bytes = n * (m / 2 + 2)             # read 2-bit planes, write one result word
     if pack_ms >= filt_ms:
         dom, bytes_, ms = "encode (lane-sliced)", enc_bytes, pack_ms
+        traffic = measured_traffic("k_pack_tile") if n == 30_000_000 else None
     else:
         dom, bytes_, ms = "column sweep E=%d" % E, filt_bytes, filt_ms
+        traffic = measured_traffic("k_sliced_E%d" % E) if n == 30_000_000 else None
     achieved = bytes_ / (ms * 1e-3) / 1e9
     line = {
         "metric": "filtered pairs/sec at 1 GPU (100bp E=5)",
@@ -331,7 +355,8 @@ def main():
         "oracle_sample_pairs": int(len(idx)),
         "plain": plain,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "algorithmic_bytes": bytes_},
         "cpu_baseline": cpu,
         "hbm_copy_calibration_gbs": copy_gbs,
         "mixed": mixed,
