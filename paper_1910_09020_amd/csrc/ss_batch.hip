@@ -37,7 +37,7 @@ namespace {
 
 __global__ void k_zero_counter(int* c) { if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0; }
 
-template <int RS>
+template <int RSMAX>
 __global__ __launch_bounds__(256) void k_persist(const PItem* __restrict__ items, int n_items, int* __restrict__ head,
                                                  const int64_t* __restrict__ perm, const uint32_t* __restrict__ pk,
                                                  int64_t SW, const int64_t* __restrict__ offsets,
@@ -49,19 +49,34 @@ __global__ __launch_bounds__(256) void k_persist(const PItem* __restrict__ items
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(head, 1);
         __syncthreads();
-        const int it = s_item;
+        const int it = __builtin_amdgcn_readfirstlane(s_item);
         __syncthreads();
         if (it >= n_items) break;
-        const PItem I = items[it];
-        const int LP = I.lp;
+        // the item is the same for the whole block: keep its fields in scalar registers
+        const int64_t first = items[it].first;
+        const int count = __builtin_amdgcn_readfirstlane(items[it].count);
+        const int LP = __builtin_amdgcn_readfirstlane(items[it].lp);
+        const int rs = __builtin_amdgcn_readfirstlane(items[it].rs);
+        const int emax = __builtin_amdgcn_readfirstlane(items[it].emax);
         const int PW = 64 / LP;
         const int k = wv * PW + lane / LP;
-        const bool ok = k < I.count;
-        const int64_t pi = ok ? perm[I.first + k] : perm[I.first];
+        const bool ok = k < count;
+        const int64_t pi = perm[first + (ok ? k : 0)];
         const int m = ok ? lengths[pi] : 0;
         const int Ei = ok ? Epp[pi] : 0;
         const int lip = lane % LP;
-        const int c = wave::sweep_pair<RS, 0>(pk, SW, offsets[pi], m, Ei, ok, LP, lip, I.rs, I.emax);
+        const int64_t b0 = offsets[pi];
+        int c = 0;
+        switch (rs) {
+        case 1: c = wave::sweep_pair<1, 0>(pk, SW, b0, m, Ei, ok, LP, lip, emax); break;
+        case 2: if (RSMAX >= 2) c = wave::sweep_pair<(RSMAX >= 2 ? 2 : 1), 0>(pk, SW, b0, m, Ei, ok, LP, lip, emax); break;
+        case 3: if (RSMAX >= 3) c = wave::sweep_pair<(RSMAX >= 3 ? 3 : 1), 0>(pk, SW, b0, m, Ei, ok, LP, lip, emax); break;
+        case 4: if (RSMAX >= 4) c = wave::sweep_pair<(RSMAX >= 4 ? 4 : 1), 0>(pk, SW, b0, m, Ei, ok, LP, lip, emax); break;
+        case 5: if (RSMAX >= 5) c = wave::sweep_pair<(RSMAX >= 5 ? 5 : 1), 0>(pk, SW, b0, m, Ei, ok, LP, lip, emax); break;
+        case 6: if (RSMAX >= 6) c = wave::sweep_pair<(RSMAX >= 6 ? 6 : 1), 0>(pk, SW, b0, m, Ei, ok, LP, lip, emax); break;
+        case 7: if (RSMAX >= 7) c = wave::sweep_pair<(RSMAX >= 7 ? 7 : 1), 0>(pk, SW, b0, m, Ei, ok, LP, lip, emax); break;
+        default: if (RSMAX >= 8) c = wave::sweep_pair<(RSMAX >= 8 ? 8 : 1), 0>(pk, SW, b0, m, Ei, ok, LP, lip, emax); break;
+        }
         if (ok && lip == 0) out[pi] = wave::result_word(c, Ei);
     }
 }

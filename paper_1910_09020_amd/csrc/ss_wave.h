@@ -55,16 +55,57 @@ __host__ __device__ inline void shape_for(int32_t E, int RSMAX, int* lp, int* rs
     *rs = (SL + L - 1) / L;
 }
 
+// One 32-column block of the sweep for the calling lane's RS slices.
+// MASK: apply the query-range mask (columns whose rows may index outside [0, m)).
+template <int RS, bool MASK>
+__device__ __forceinline__ void sweep_block(uint32_t (&alive)[RS], const uint32_t (&rmask)[RS],
+                                            const uint32_t (&q0lo)[RS], const uint32_t (&q0hi)[RS],
+                                            const uint32_t (&q1lo)[RS], const uint32_t (&q1hi)[RS], uint32_t rw0,
+                                            uint32_t rw1, int jb, int jend, int m, int Ei, int Emax, int LP,
+                                            int lip, int grp, int& count, bool& fin)
+{
+    for (int jj = 0; jj < jend; jj++) {
+        const int j = jb + jj;
+        const uint32_t rb0 = (uint32_t)__builtin_amdgcn_sbfe((int)rw0, jj, 1);   // reference bit j, broadcast
+        const uint32_t rb1 = (uint32_t)__builtin_amdgcn_sbfe((int)rw1, jj, 1);
+        uint32_t any = 0;
+#pragma unroll
+        for (int t = 0; t < RS; t++) {
+            const uint32_t x0 = __builtin_amdgcn_alignbit(q0hi[t], q0lo[t], jj);
+            const uint32_t x1 = __builtin_amdgcn_alignbit(q1hi[t], q1lo[t], jj);
+            uint32_t a = and_xnor(and_xnor(alive[t], x0, rb0), x1, rb1);
+            if (MASK) {
+                const int base = j - Emax + 32 * (lip + LP * t);      // query position of bit 0
+                a &= span_mask(-base, m - base);
+            }
+            alive[t] = a;
+            any |= a;
+        }
+        bool pany = any != 0u;
+        if (LP > 1) {
+            const uint64_t bal = __ballot(pany);
+            const uint64_t gm = LP >= 64 ? bal : (bal >> (grp * LP)) & ((1ull << (LP & 63)) - 1ull);
+            pany = gm != 0ull;
+        }
+        const bool dead = !fin && j < m && !pany;
+        count += dead ? 1 : 0;
+#pragma unroll
+        for (int t = 0; t < RS; t++) alive[t] = dead ? rmask[t] : alive[t];
+        fin = fin || (dead && count > Ei) || (j + 1 >= m);
+    }
+}
+
 // Sweep one pair with the calling lane's share of its rows.  All 64 lanes of
-// the wavefront must call this together (it uses wavefront votes).
+// the wavefront must call this together (it uses wavefront votes), with the
+// same LP.
 //   b0, m, Ei   : the pair's stream bit offset, length and threshold
 //   pair_ok     : false for lanes without a pair (they still vote)
 //   LP, lip     : lanes per pair and this lane's index in its pair
-//   rs          : slices this lane holds (<= RS); Emax: row layout threshold
+//   RS          : slices this lane holds; Emax: row layout threshold
 // Returns the count reported by the walk, min(count, Ei+1).
 template <int RS, int LPC>
 __device__ __forceinline__ int sweep_pair(const uint32_t* __restrict__ pk, int64_t SW, int64_t b0, int m, int Ei,
-                                          bool pair_ok, int LP_rt, int lip, int rs, int Emax)
+                                          bool pair_ok, int LP_rt, int lip, int Emax)
 {
     const int LP = LPC > 0 ? LPC : LP_rt;
     const int lane = threadIdx.x & 63;
@@ -75,15 +116,15 @@ __device__ __forceinline__ int sweep_pair(const uint32_t* __restrict__ pk, int64
     const uint32_t* __restrict__ R1 = pk + 3 * SW;
     const int NR = 2 * Emax + 1;
 
-    uint32_t alive[RS], rmask[RS], q0lo[RS], q0hi[RS], q1lo[RS], q1hi[RS];
+    uint32_t alive[RS], rmask[RS], q0lo[RS], q0hi[RS], q1lo[RS], q1hi[RS], n0[RS], n1[RS];
 #pragma unroll
     for (int t = 0; t < RS; t++) {
         const int s = lip + LP * t;
-        // rows r in [32s, 32s+32) that exist (r < NR, t < rs) and whose |r - Emax| <= Ei
+        // rows r in [32s, 32s+32) that exist (r < NR) and whose |r - Emax| <= Ei
         const int lo = Emax - Ei - 32 * s, hi = Emax + Ei + 1 - 32 * s;
-        rmask[t] = (t < rs) ? span_mask(lo, hi < NR - 32 * s ? hi : NR - 32 * s) : 0u;
+        rmask[t] = span_mask(lo, hi < NR - 32 * s ? hi : NR - 32 * s);
         alive[t] = rmask[t];
-        q0lo[t] = q0hi[t] = q1lo[t] = q1hi[t] = 0u;
+        q0lo[t] = q0hi[t] = q1lo[t] = q1hi[t] = n0[t] = n1[t] = 0u;
     }
     int count = 0;
     bool fin = !pair_ok || m == 0;
@@ -96,58 +137,44 @@ __device__ __forceinline__ int sweep_pair(const uint32_t* __restrict__ pk, int64
         mmax = max(mmax, __shfl_xor(mmax, o));
     }
 
-    for (int jb = 0; jb < mmax; jb += 32) {
-        if (__all(fin)) break;
-        // query window of slice s for this block: pair-relative positions jb - Emax + 32 s + [0, 64)
+    // Query window of slice s for block jb: pair-relative positions jb - Emax + 32 s + [0, 64).
+    // The window moves by one word per block, so each block loads only the
+    // next high word (and the next reference word), one block ahead.
+    if (!fin) {
 #pragma unroll
         for (int t = 0; t < RS; t++) {
-            if (t < rs) {
-                const int s = lip + LP * t;
-                const int64_t a = b0 + jb - Emax + 32 * (int64_t)s;
-                q0lo[t] = bits32(Q0, SW, a);
-                q0hi[t] = bits32(Q0, SW, a + 32);
-                q1lo[t] = bits32(Q1, SW, a);
-                q1hi[t] = bits32(Q1, SW, a + 32);
-            }
+            const int64_t a = b0 - Emax + 32 * (int64_t)(lip + LP * t);
+            q0lo[t] = bits32(Q0, SW, a);
+            q1lo[t] = bits32(Q1, SW, a);
+            n0[t] = bits32(Q0, SW, a + 32);
+            n1[t] = bits32(Q1, SW, a + 32);
         }
-        const uint32_t rw0 = bits32(R0, SW, b0 + jb), rw1 = bits32(R1, SW, b0 + jb);
-        const bool interior = (jb >= Emax) && (jb + 31 + Emax < mmin);
-        const int jend = min(32, mmax - jb);
-        for (int jj = 0; jj < jend; jj++) {
-            const int j = jb + jj;
-            const uint32_t rb0 = (uint32_t)((int32_t)(rw0 << (31 - jj)) >> 31);   // reference bit j, broadcast
-            const uint32_t rb1 = (uint32_t)((int32_t)(rw1 << (31 - jj)) >> 31);
-            uint32_t any = 0;
+    }
+    uint32_t nr0 = fin ? 0u : bits32(R0, SW, b0), nr1 = fin ? 0u : bits32(R1, SW, b0);
+    for (int jb = 0; jb < mmax; jb += 32) {
+        if (__all(fin)) break;
+#pragma unroll
+        for (int t = 0; t < RS; t++) { q0hi[t] = n0[t]; q1hi[t] = n1[t]; }
+        const uint32_t rw0 = nr0, rw1 = nr1;
+        if (jb + 32 < mmax && !fin) {
 #pragma unroll
             for (int t = 0; t < RS; t++) {
-                if (t < rs) {
-                    const uint32_t x0 = __builtin_amdgcn_alignbit(q0hi[t], q0lo[t], jj);
-                    const uint32_t x1 = __builtin_amdgcn_alignbit(q1hi[t], q1lo[t], jj);
-                    uint32_t a = and_xnor(and_xnor(alive[t], x0, rb0), x1, rb1);
-                    if (!interior) {
-                        const int s = lip + LP * t;
-                        const int base = j - Emax + 32 * s;      // query position of bit 0
-                        a &= span_mask(-base, m - base);
-                    }
-                    alive[t] = a;
-                    any |= a;
-                }
+                const int64_t a = b0 + jb + 64 - Emax + 32 * (int64_t)(lip + LP * t);
+                n0[t] = bits32(Q0, SW, a);
+                n1[t] = bits32(Q1, SW, a);
             }
-            bool pany = any != 0u;
-            if (LP > 1) {
-                const uint64_t bal = __ballot(pany);
-                const uint64_t gm = LP >= 64 ? bal : (bal >> (grp * LP)) & ((1ull << (LP & 63)) - 1ull);
-                pany = gm != 0ull;
-            }
-            const bool live = !fin && j < m;
-            if (live && !pany) {
-                count++;
-#pragma unroll
-                for (int t = 0; t < RS; t++) alive[t] = rmask[t];
-                if (count > Ei) fin = true;
-            }
-            if (j + 1 >= m) fin = true;
+            nr0 = bits32(R0, SW, b0 + jb + 32);
+            nr1 = bits32(R1, SW, b0 + jb + 32);
         }
+        const int jend = min(32, mmax - jb);
+        if ((jb >= Emax) && (jb + 31 + Emax < mmin))
+            sweep_block<RS, false>(alive, rmask, q0lo, q0hi, q1lo, q1hi, rw0, rw1, jb, jend, m, Ei, Emax, LP, lip,
+                                   grp, count, fin);
+        else
+            sweep_block<RS, true>(alive, rmask, q0lo, q0hi, q1lo, q1hi, rw0, rw1, jb, jend, m, Ei, Emax, LP, lip,
+                                  grp, count, fin);
+#pragma unroll
+        for (int t = 0; t < RS; t++) { q0lo[t] = q0hi[t]; q1lo[t] = q1hi[t]; }
     }
     return count > Ei + 1 ? Ei + 1 : count;
 }
