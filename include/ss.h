@@ -62,6 +62,7 @@ const char* ss_status_str(int status);
 #define SS_MAX_E_PLAIN    31      /* one-pair-per-lane kernel: 0 <= E <= 31 */
 #define SS_MAX_E          16383   /* any path: counts must fit 14 bits */
 #define SS_MAX_LEN        (1 << 24)
+#define SS_MAX_LEN_FUSED  2048    /* fused encode-and-filter kernel: m <= 2048 */
 
 /* Device result word, one per pair: bit 15 = accept, bits 0..14 = obstacle
  * count reported by the walk (min(count, E+1)). */
@@ -132,6 +133,32 @@ int ss_pack_sliced_async(ss_ctx* ctx, const uint8_t* reads, const uint8_t* refs,
  * since the checkpoint"). */
 int ss_filter_sliced_async(ss_ctx* ctx, const uint32_t* packed, int64_t n_pairs, int32_t m,
                            int32_t E, uint16_t* out, void* stream);
+
+/* Encode and filter in one call, for pairs of one length m stored back to
+ * back (pair i at byte i*m of reads and of refs; device pointers).  The
+ * results are identical to ss_pack_sliced_async followed by
+ * ss_filter_sliced_async (Equation 1 operands, Section 2.4 walk); the schedule
+ * depends on E:
+ *   E <= 5 : one fused kernel.  Each workgroup encodes tile_groups groups of
+ *            32 pairs into on-chip memory and sweeps them there, so the packed
+ *            encoding never reaches device memory.
+ *   E > 5  : the two kernels over chunks of about 400 MB of packed data, kept
+ *            in a buffer owned by ctx (allocated on first use, grown when a
+ *            longer m needs it): calls with E > 5 on one context must be
+ *            ordered (one stream), or use one context per stream.
+ *   n_pairs >= 0; 0 <= m <= SS_MAX_LEN_FUSED; 0 <= E <= SS_MAX_E_SLICED
+ *   tile_groups : groups per workgroup of the fused kernel, 1..256, or 0 for
+ *                 the automatic choice (the largest tile that keeps two
+ *                 workgroups per CU); SS_EINVAL when the tile does not fit
+ *                 on-chip memory
+ *   out         : n_pairs result words (see SS_RESULT_*), 16-byte aligned
+ *   err         : one device uint32; bit 0 is OR-ed in when a byte outside
+ *                 ACGTacgt is seen (the caller zeroes it beforehand); the
+ *                 results are then unspecified.
+ * Asynchronous on stream; the caller keeps every buffer alive until the
+ * stream has passed this call. */
+int ss_filter_ascii_async(ss_ctx* ctx, const uint8_t* reads, const uint8_t* refs, int64_t n_pairs, int32_t m,
+                          int32_t E, int32_t tile_groups, uint16_t* out, uint32_t* err, void* stream);
 
 /* ------------------------------------------------------------------------
  * Bit-stream layout (any lengths).

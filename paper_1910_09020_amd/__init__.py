@@ -24,6 +24,7 @@ SS_OK, SS_EINVAL, SS_EBASE, SS_ELEN, SS_ENOMEM, SS_EBUDGET, SS_EDEVICE, SS_EAGAI
 SS_MAX_E_SLICED = 32
 SS_MAX_E_PLAIN = 31
 SS_MAX_E = 16383
+SS_MAX_LEN_FUSED = 2048
 SS_RESULT_ACCEPT = 0x8000
 SS_RESULT_COUNT = 0x7FFF
 
@@ -56,6 +57,7 @@ def lib():
         "ss_stream_words": ([i64], i64),
         "ss_pack_sliced_async": ([vp, vp, vp, vp, vp, i64, i32, vp, vp, vp], ctypes.c_int),
         "ss_filter_sliced_async": ([vp, vp, i64, i32, i32, vp, vp], ctypes.c_int),
+        "ss_filter_ascii_async": ([vp, vp, vp, i64, i32, i32, i32, vp, vp, vp], ctypes.c_int),
         "ss_pack_stream_async": ([vp, vp, vp, i64, vp, vp, vp], ctypes.c_int),
         "ss_filter_plain_async": ([vp, vp, i64, vp, vp, vp, i64, i32, vp, vp], ctypes.c_int),
         "ss_filter_wave_async": ([vp, vp, i64, vp, vp, vp, i64, i32, vp, vp], ctypes.c_int),
@@ -93,7 +95,8 @@ def exported_symbols():
     """Names of the C entry points this binding declares."""
     return ["ss_status_str", "ss_filter_batch", "ss_filter_batch_var", "ss_create", "ss_destroy",
             "ss_sliced_bytes", "ss_stream_words", "ss_pack_sliced_async", "ss_filter_sliced_async",
-            "ss_pack_stream_async", "ss_filter_plain_async", "ss_filter_wave_async", "ss_unpack_results_async",
+            "ss_filter_ascii_async", "ss_pack_stream_async", "ss_filter_plain_async", "ss_filter_wave_async",
+            "ss_unpack_results_async",
             "ss_plan_create", "ss_plan_destroy", "ss_plan_info", "ss_filter_planned_async", "ss_plan_capture",
             "ss_plan_launch", "ss_plan_create_tuned", "ss_server_create", "ss_server_submit", "ss_server_poll",
             "ss_server_wait", "ss_server_times", "ss_server_cancel", "ss_server_release", "ss_server_set_hold",
@@ -189,6 +192,12 @@ def ss_pack_sliced_async(ctx, reads, refs, offsets, index, n_pairs, m, packed, e
 def ss_filter_sliced_async(ctx, packed, n_pairs, m, E, out, stream=None):
     _check(lib().ss_filter_sliced_async(ctx, _ptr(packed), int(n_pairs), int(m), int(E), _ptr(out),
                                         _stream(stream)), "ss_filter_sliced_async")
+
+
+def ss_filter_ascii_async(ctx, reads, refs, n_pairs, m, E, tile_groups, out, err, stream=None):
+    _check(lib().ss_filter_ascii_async(ctx, _ptr(reads), _ptr(refs), int(n_pairs), int(m), int(E),
+                                       int(tile_groups), _ptr(out), _ptr(err), _stream(stream)),
+           "ss_filter_ascii_async")
 
 
 def ss_pack_stream_async(ctx, reads, refs, total_bases, packed, err, stream=None):

@@ -57,6 +57,7 @@ struct ss_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     DevBuf reads, refs, offsets, lengths, epp, packed, results, err;
+    DevBuf chunk;      // lane-sliced chunk of ss_filter_ascii_async's two-kernel schedule
 };
 
 extern "C" const char* ss_status_str(int status)
@@ -108,7 +109,7 @@ extern "C" int ss_destroy(ss_ctx* ctx)
     (void)hipSetDevice(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     for (DevBuf* b : {&ctx->reads, &ctx->refs, &ctx->offsets, &ctx->lengths, &ctx->epp, &ctx->packed,
-                      &ctx->results, &ctx->err})
+                      &ctx->results, &ctx->err, &ctx->chunk})
         b->release();
     if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
     (void)hipSetDevice(prev);
@@ -152,6 +153,40 @@ extern "C" int ss_filter_sliced_async(ss_ctx* ctx, const uint32_t* packed, int64
     if (!out || (m > 0 && !packed)) return SS_EINVAL;
     if ((((uintptr_t)packed | (uintptr_t)out) & 15u) != 0) return SS_EINVAL;
     return map_err(launch_sliced(packed, n_pairs, m, E, out, (hipStream_t)stream));
+}
+
+// Thresholds up to this run the fused kernel; above it, where the sweep's
+// registers leave the fused kernel too few waves, encode and sweep run as two
+// kernels over chunks whose packed form (about 400 MB) stays in the device's
+// cache between the two.
+constexpr int32_t kFusedMaxE = 5;
+constexpr int64_t kChunkPackedBytes = 400ll << 20;
+
+extern "C" int ss_filter_ascii_async(ss_ctx* ctx, const uint8_t* reads, const uint8_t* refs, int64_t n_pairs,
+                                     int32_t m, int32_t E, int32_t tile_groups, uint16_t* out, uint32_t* err,
+                                     void* stream)
+{
+    if (!ctx || n_pairs < 0 || m < 0 || E < 0 || tile_groups < 0 || tile_groups > 256) return SS_EINVAL;
+    if (E > SS_MAX_E_SLICED || m > SS_MAX_LEN_FUSED) return SS_ELEN;
+    if (n_pairs == 0) return SS_OK;
+    if (!out || (m > 0 && (!reads || !refs))) return SS_EINVAL;
+    if (((uintptr_t)out & 15u) != 0) return SS_EINVAL;
+    int T = 0, GB = 0;
+    if (fused_shape(m, tile_groups, &T, &GB) == 0) return SS_EINVAL;
+    const hipStream_t s = (hipStream_t)stream;
+    if (E <= kFusedMaxE || m == 0)
+        return map_err(launch_fused(reads, refs, n_pairs, m, E, tile_groups, out, err, s));
+    // chunks of whole groups; slot offsets keep the encoder's and the sweep's alignment
+    const int64_t per_pair = std::max<int64_t>(1, ss_sliced_bytes(32, m) / 32);
+    const int64_t chunk = std::min<int64_t>(n_pairs, std::max<int64_t>(32, (kChunkPackedBytes / per_pair) / 32 * 32));
+    SS_TRY(ctx->chunk.ensure((size_t)ss_sliced_bytes(chunk, m)));
+    for (int64_t s0 = 0; s0 < n_pairs; s0 += chunk) {
+        const int64_t k = std::min(chunk, n_pairs - s0);
+        SS_TRY(launch_pack_sliced(reads + s0 * m, refs + s0 * m, nullptr, nullptr, k, m, (uint32_t*)ctx->chunk.p,
+                                  err, s));
+        SS_TRY(launch_sliced((const uint32_t*)ctx->chunk.p, k, m, E, out + s0, s));
+    }
+    return SS_OK;
 }
 
 extern "C" int ss_pack_stream_async(ss_ctx* ctx, const uint8_t* reads, const uint8_t* refs, int64_t total_bases,
@@ -261,7 +296,12 @@ int filter_host(const uint8_t* reads, const uint8_t* refs, const int32_t* length
     SS_TRY(hipMemsetAsync(d_err, 0, 4, s));
 
     const bool sliced = uniform && !E_per_pair && E <= SS_MAX_E_SLICED;
-    if (sliced) {
+    if (sliced && lengths[0] <= SS_MAX_LEN_FUSED) {
+        // encode and filter in one call; the alphabet check is read before any output is written
+        rc = ss_filter_ascii_async(ctx, (const uint8_t*)ctx->reads.p, (const uint8_t*)ctx->refs.p, n, lengths[0],
+                                   E, 0, d_res, d_err, s);
+        if (rc != SS_OK) return rc;
+    } else if (sliced) {
         const int32_t m = lengths[0];
         SS_TRY(ctx->packed.ensure((size_t)std::max<int64_t>(ss_sliced_bytes(n, m), 16)));
         rc = ss_pack_sliced_async(ctx, (const uint8_t*)ctx->reads.p, (const uint8_t*)ctx->refs.p, nullptr, nullptr,
@@ -286,7 +326,9 @@ int filter_host(const uint8_t* reads, const uint8_t* refs, const int32_t* length
     SS_TRY(hipStreamSynchronize(s));
     if (h_err) return SS_EBASE;
 
-    if (sliced) {
+    if (sliced && lengths[0] <= SS_MAX_LEN_FUSED) {
+        rc = SS_OK;     // filtered above
+    } else if (sliced) {
         rc = ss_filter_sliced_async(ctx, (const uint32_t*)ctx->packed.p, n, lengths[0], E, d_res, s);
     } else {
         rc = ss_filter_wave_async(ctx, (const uint32_t*)ctx->packed.p, total, (const int64_t*)ctx->offsets.p,

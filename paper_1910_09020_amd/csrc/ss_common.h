@@ -10,6 +10,7 @@ namespace ss {
 constexpr int kChunk = 4;              // positions per chunk in the lane-sliced layout
 constexpr int kMaxESliced = 32;
 constexpr int kMaxEPlain = 31;
+constexpr int64_t kMaxFusedLds = 160 * 1024;   // LDS per workgroup on gfx950
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
@@ -19,6 +20,11 @@ hipError_t launch_pack_sliced(const uint8_t* reads, const uint8_t* refs, const i
                               uint32_t* err, hipStream_t s);
 hipError_t launch_sliced(const uint32_t* packed, int64_t n_pairs, int32_t m, int32_t E, uint16_t* out,
                          hipStream_t s);
+// Fused encode + sweep of pairs stored back to back (pair i at byte i*m).
+// tile_groups: groups of 32 pairs per block (0: automatic).
+hipError_t launch_fused(const uint8_t* reads, const uint8_t* refs, int64_t n_pairs, int32_t m, int32_t E,
+                        int tile_groups, uint16_t* out, uint32_t* err, hipStream_t s);
+size_t fused_shape(int32_t m, int tile_groups, int* T, int* GB);
 hipError_t launch_pack_stream(const uint8_t* reads, const uint8_t* refs, int64_t total_bases,
                               uint32_t* packed, uint32_t* err, hipStream_t s);
 hipError_t launch_plain(const uint32_t* packed, int64_t stream_words, const int64_t* offsets,

@@ -7,6 +7,7 @@
 #include <algorithm>
 
 #include "ss_common.h"
+#include "ss_tile.h"
 
 namespace ss {
 namespace {
@@ -80,22 +81,7 @@ __global__ __launch_bounds__(64) void k_pack_sliced(const uint8_t* __restrict__ 
 }
 
 // ---------------------------------------------------------------- tiled encoder
-// One 256-thread block encodes GB consecutive groups (32*GB pair slots).
-// Phase 1 copies the slots' bases into LDS as 2-bit codes (one byte per base,
-// rows padded to whole dwords, one pad dword per group so that the phase-2
-// reads of different groups fall in different banks) and validates every
-// byte: a byte b is one of ACGTacgt exactly when (b & 0xDF) equals the letter
-// its code stands for, looked up with a byte permute.  Phase 2: one thread per
-// (group, chunk of four positions) folds the 32 slots' code dwords into the
-// four words of each plane.
-__device__ __forceinline__ uint32_t codes4(uint32_t x, uint32_t& bad)
-{
-    const uint32_t cc = ((x >> 1) ^ (x >> 2)) & 0x03030303u;
-    const uint32_t letter = __builtin_amdgcn_perm(0u, 0x54474341u, cc);   // 'A','C','G','T' by code
-    bad |= (x & 0xDFDFDFDFu) ^ letter;
-    return cc;
-}
-
+// One 256-thread block encodes GB consecutive groups into the packed buffer.
 __global__ __launch_bounds__(256) void k_pack_tile(const uint8_t* __restrict__ reads,
                                                    const uint8_t* __restrict__ refs,
                                                    const int64_t* __restrict__ offsets,
@@ -104,100 +90,10 @@ __global__ __launch_bounds__(256) void k_pack_tile(const uint8_t* __restrict__ r
                                                    uint32_t* __restrict__ err)
 {
     extern __shared__ uint32_t lds[];
-    const int mw = (m + 3) >> 2;              // dwords per slot row
-    const int gs = 32 * mw + 1;               // dwords per group
-    const int nch = mw;
     const int64_t g0 = (int64_t)blockIdx.x * GB;
-    const int64_t s0 = g0 * 32;
-    const int np = (int)min((int64_t)32 * GB, n_pairs - s0);
-    const int t = threadIdx.x;
     uint32_t bad = 0;
-    uint4* __restrict__ out4 = reinterpret_cast<uint4*>(packed);
-    // fast path: slots s0.. are pairs s0.. stored back to back, m % 4 == 0, the
-    // block's first byte is 16-byte aligned and the block holds at most
-    // 256 * kQ 16-byte loads per side.  Every load of both sides is issued
-    // before any is consumed, to keep enough bytes in flight.
-    constexpr int kQ = 8;
-    const int ndw = np * mw;
-    const int nq = ndw >> 2;
-    // dw / mw by multiply-high, exact for dw < 2^16 and 2 <= mw < 2^16 (the
-    // reciprocal of mw = 1 does not fit 32 bits: that case divides by itself)
-    const uint32_t rmw = mw > 1 ? 0xFFFFFFFFu / (uint32_t)mw + 1u : 0u;
-    auto row_of = [&](int dw) { return mw > 1 ? (int)__umulhi((uint32_t)dw, rmw) : dw; };
-    uint4 v[2][kQ];
-    if (fast) {
-#pragma unroll
-        for (int sd = 0; sd < 2; sd++) {
-            const uint4* __restrict__ s128 = reinterpret_cast<const uint4*>((sd ? refs : reads) + s0 * (int64_t)m);
-#pragma unroll
-            for (int k = 0; k < kQ; k++) {
-                const int q = t + 256 * k;
-                if (q < nq) v[sd][k] = s128[q];
-            }
-        }
-    }
-#pragma unroll
-    for (int side = 0; side < 2; side++) {
-        const uint8_t* __restrict__ src = side ? refs : reads;
-        if (fast) {
-#pragma unroll
-            for (int k = 0; k < kQ; k++) {
-                const int q = t + 256 * k;
-                if (q < nq) {
-                    const uint32_t d[4] = {v[side][k].x, v[side][k].y, v[side][k].z, v[side][k].w};
-#pragma unroll
-                    for (int e = 0; e < 4; e++) {
-                        const int dw = 4 * q + e;
-                        const int p = row_of(dw), col = dw - p * mw;
-                        lds[(p >> 5) * gs + (p & 31) * mw + col] = codes4(d[e], bad);
-                    }
-                }
-            }
-            const uint32_t* __restrict__ s32 = reinterpret_cast<const uint32_t*>(src + s0 * (int64_t)m);
-            for (int dw = 4 * nq + t; dw < ndw; dw += 256) {
-                const int p = row_of(dw), col = dw - p * mw;
-                lds[(p >> 5) * gs + (p & 31) * mw + col] = codes4(s32[dw], bad);
-            }
-        } else {
-            uint8_t* lb = reinterpret_cast<uint8_t*>(lds);
-            const int nb = np * m;
-            for (int i = t; i < nb; i += 256) {
-                const int p = i / m, col = i - p * m;
-                const int64_t slot = s0 + p;
-                const int64_t pi = index ? index[slot] : slot;
-                const int64_t off = offsets ? offsets[pi] : pi * (int64_t)m;
-                uint32_t bb = 0;
-                const uint32_t c = codes4((uint32_t)src[off + col] | 0x41414100u, bb);   // pad the other lanes with 'A'
-                bad |= bb;
-                lb[4 * ((p >> 5) * gs + (p & 31) * mw) + col] = (uint8_t)(c & 3u);
-            }
-        }
-        __syncthreads();
-        for (int task = t; task < GB * nch; task += 256) {
-            const int gl = task % GB, c = task / GB;
-            if (g0 + gl >= G) continue;
-            uint32_t lo[4] = {0u, 0u, 0u, 0u}, hi[4] = {0u, 0u, 0u, 0u};
-            const uint32_t* __restrict__ row = lds + gl * gs + c;
-#pragma unroll
-            for (int s = 0; s < 32; s++) {
-                const uint32_t cc = row[s * mw];
-                lo[s >> 3] |= (cc & 0x01010101u) << (s & 7);
-                hi[s >> 3] |= ((cc >> 1) & 0x01010101u) << (s & 7);
-            }
-            uint32_t wl[4], wh[4];
-#pragma unroll
-            for (int tt = 0; tt < 4; tt++) {
-                // word of position 4c+tt: byte q = slots 8q..8q+7
-                const uint32_t sel01 = (uint32_t)tt | ((uint32_t)(tt + 4) << 8) | 0x0C0C0000u;
-                const uint32_t sel23 = 0x00000C0Cu | ((uint32_t)tt << 16) | ((uint32_t)(tt + 4) << 24);
-                wl[tt] = __builtin_amdgcn_perm(lo[1], lo[0], sel01) | __builtin_amdgcn_perm(lo[3], lo[2], sel23);
-                wh[tt] = __builtin_amdgcn_perm(hi[1], hi[0], sel01) | __builtin_amdgcn_perm(hi[3], hi[2], sel23);
-            }
-            out4[((int64_t)(2 * side) * nch + c) * G + g0 + gl] = make_uint4(wl[0], wl[1], wl[2], wl[3]);
-            out4[((int64_t)(2 * side + 1) * nch + c) * G + g0 + gl] = make_uint4(wh[0], wh[1], wh[2], wh[3]);
-        }
-        __syncthreads();
-    }
+    tile::load_encode_groups(reads, refs, offsets, index, n_pairs, m, g0, GB, fast, lds,
+                             reinterpret_cast<uint4*>(packed), G, g0, bad);
     if (bad && err) atomicOr(err, 1u);
 }
 
@@ -206,6 +102,12 @@ __global__ __launch_bounds__(256) void k_pack_tile(const uint8_t* __restrict__ r
 hipError_t launch_sliced_lo(int E, const uint32_t* packed, int64_t n, int32_t m, uint16_t* out, hipStream_t s);
 hipError_t launch_sliced_mid(int E, const uint32_t* packed, int64_t n, int32_t m, uint16_t* out, hipStream_t s);
 hipError_t launch_sliced_hi(int E, const uint32_t* packed, int64_t n, int32_t m, uint16_t* out, hipStream_t s);
+hipError_t launch_fused_lo(int E, const uint8_t* reads, const uint8_t* refs, int64_t n, int32_t m, int T, int GB,
+                          int fast, size_t shmem, uint16_t* out, uint32_t* err, hipStream_t s);
+hipError_t launch_fused_mid(int E, const uint8_t* reads, const uint8_t* refs, int64_t n, int32_t m, int T, int GB,
+                           int fast, size_t shmem, uint16_t* out, uint32_t* err, hipStream_t s);
+hipError_t launch_fused_hi(int E, const uint8_t* reads, const uint8_t* refs, int64_t n, int32_t m, int T, int GB,
+                          int fast, size_t shmem, uint16_t* out, uint32_t* err, hipStream_t s);
 
 hipError_t launch_pack_sliced(const uint8_t* reads, const uint8_t* refs, const int64_t* offsets,
                               const int64_t* index, int64_t n_pairs, int32_t m, uint32_t* packed,
@@ -214,10 +116,11 @@ hipError_t launch_pack_sliced(const uint8_t* reads, const uint8_t* refs, const i
     const int64_t G = cdiv(n_pairs, 32);
     if (G == 0 || m == 0) return hipSuccess;
     const int64_t mw = cdiv(m, 4);
-    const int64_t group_bytes = (32 * mw + 1) * 4;
+    const int64_t group_bytes = (int64_t)tile::stage_dwords(m) * 4;
     if (group_bytes <= 65536) {
         // tiled path: GB groups per block, LDS <= 32 KiB when possible
-        int GB = (int)std::max<int64_t>(1, std::min<int64_t>(8, 32768 / group_bytes));
+        int GB = 8;
+        while (GB > 1 && GB * group_bytes > 32768) GB >>= 1;
         // the streaming path: at most 8 sixteen-byte loads per thread and side
         const bool fast = index == nullptr && m % 4 == 0 && (int64_t)GB * mw <= 256 &&
                           ((((uintptr_t)reads | (uintptr_t)refs) & 15u) == 0);
@@ -241,6 +144,50 @@ hipError_t launch_sliced(const uint32_t* packed, int64_t n_pairs, int32_t m, int
     if (E <= 10) return launch_sliced_lo(E, packed, n_pairs, m, out, s);
     if (E <= 20) return launch_sliced_mid(E, packed, n_pairs, m, out, s);
     return launch_sliced_hi(E, packed, n_pairs, m, out, s);
+}
+
+// Tile shape of the fused kernel: T groups per block, staged GB at a time.
+// Returns the LDS bytes per block, or 0 when no shape fits.
+size_t fused_shape(int32_t m, int tile_groups, int* T_out, int* GB_out)
+{
+    const int64_t mw = cdiv(m, 4);
+    const int64_t stage_b = (int64_t)tile::stage_dwords(m) * 4;
+    const int64_t pk_b = 16 * 4 * mw;                     // four planes of 16-byte chunks per group
+    auto lds_for = [&](int64_t T, int64_t GB) { return ((GB * stage_b + 15) & ~(int64_t)15) + T * pk_b; };
+    int GB = 8;
+    while (GB > 1 && GB * stage_b > 32768) GB >>= 1;
+    int T = tile_groups;
+    if (T <= 0) {
+        // largest multiple of GB that keeps two blocks per CU
+        T = 0;
+        for (int t = GB; t <= 256; t += GB)
+            if (2 * lds_for(t, GB) <= kMaxFusedLds) T = t;
+        if (T == 0) T = GB;
+    } else {
+        if (T > 256) return 0;
+        while (GB > 1 && T % GB != 0) GB >>= 1;
+    }
+    const int64_t lds = lds_for(T, GB);
+    if (lds > kMaxFusedLds) return 0;
+    *T_out = T;
+    *GB_out = GB;
+    return (size_t)lds;
+}
+
+hipError_t launch_fused(const uint8_t* reads, const uint8_t* refs, int64_t n_pairs, int32_t m, int32_t E,
+                        int tile_groups, uint16_t* out, uint32_t* err, hipStream_t s)
+{
+    if (n_pairs == 0) return hipSuccess;
+    if (E < 0 || E > kMaxESliced) return hipErrorInvalidValue;
+    int T = 0, GB = 0;
+    const size_t shmem = fused_shape(m, tile_groups, &T, &GB);
+    if (shmem == 0) return hipErrorInvalidValue;
+    const int64_t mw = cdiv(m, 4);
+    const int fast = (m % 4 == 0 && (int64_t)GB * mw <= 256 &&
+                      ((((uintptr_t)reads | (uintptr_t)refs) & 15u) == 0)) ? 1 : 0;
+    if (E <= 10) return launch_fused_lo(E, reads, refs, n_pairs, m, T, GB, fast, shmem, out, err, s);
+    if (E <= 20) return launch_fused_mid(E, reads, refs, n_pairs, m, T, GB, fast, shmem, out, err, s);
+    return launch_fused_hi(E, reads, refs, n_pairs, m, T, GB, fast, shmem, out, err, s);
 }
 
 }  // namespace ss

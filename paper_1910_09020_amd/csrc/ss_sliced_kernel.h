@@ -19,7 +19,9 @@
 // saturating thermometer (t_l = count >= l, l = 1..E+1), which reproduces the
 // stop of step 4 (count = E+1 for rejected pairs) without any early exit.
 #pragma once
+#include <algorithm>
 #include "ss_common.h"
+#include "ss_tile.h"
 
 namespace ss {
 namespace sliced {
@@ -91,30 +93,22 @@ __device__ __forceinline__ constexpr int floordiv(int a, int b) { return a >= 0 
 // Interior chunk loop variants.
 enum { MAIN_CIRC = 0, MAIN_SHIFT4 = 1 };
 
-// Column-sweep kernel.  Chunks whose columns see a query index outside [0, m)
-// (the first EC and the last few) run through a checked path; interior chunks
-// run unchecked with the query window held in registers:
+// Column sweep of group g (pairs 32g .. 32g+31); writes the group's results.
+// ld(plane, c) returns the four words of chunk c of a plane (Q0, Q1, R0, R1)
+// of this group.  Chunks whose columns see a query index outside [0, m) (the
+// first EC and the last few) run through a checked path; interior chunks run
+// unchecked with the query window held in registers:
 //   MAIN_CIRC  : slot = chunk mod W with the loop unrolled W chunks, so every
 //                register index is static and the window never moves;
 //   MAIN_SHIFT4: four chunks per step, the window shifts by four chunks.
-template <int E, int MODE>
-__global__ __launch_bounds__(256) void k_sliced(const uint32_t* __restrict__ pk, int64_t G, int m,
-                                                int64_t n_pairs, uint16_t* __restrict__ out)
+template <int E, int MODE, class LD>
+__device__ __forceinline__ void sweep_group(LD&& ld, int m, int64_t g, int64_t n_pairs,
+                                            uint16_t* __restrict__ out)
 {
-    constexpr int NR = 2 * E + 1;
     constexpr int B = kChunk;
     constexpr int EC = (E + B - 1) / B;
     constexpr int W = 2 * EC + 1;
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= G) return;
     const int nch = (m + B - 1) / B;
-    const int64_t cstride = G * B;
-    const int64_t pstride = (int64_t)nch * cstride;
-    const uint32_t* __restrict__ base = pk + g * B;
-
-    auto ld = [&](int plane, int c) -> uint4 {
-        return *reinterpret_cast<const uint4*>(base + plane * pstride + (int64_t)c * cstride);
-    };
     auto put = [](uint32_t (&d)[B], const uint4& v) { d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w; };
     auto zero = [](uint32_t (&d)[B]) { d[0] = 0; d[1] = 0; d[2] = 0; d[3] = 0; };
 
@@ -254,6 +248,108 @@ __global__ __launch_bounds__(256) void k_sliced(const uint32_t* __restrict__ pk,
     }
 }
 
+template <int E, int MODE>
+__global__ __launch_bounds__(256) void k_sliced(const uint32_t* __restrict__ pk, int64_t G, int m,
+                                                int64_t n_pairs, uint16_t* __restrict__ out)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= G) return;
+    const int nch = (m + kChunk - 1) / kChunk;
+    const int64_t cstride = G * kChunk;
+    const int64_t pstride = (int64_t)nch * cstride;
+    const uint32_t* __restrict__ base = pk + g * kChunk;
+    sweep_group<E, MODE>(
+        [&](int plane, int c) -> uint4 {
+            return *reinterpret_cast<const uint4*>(base + plane * pstride + (int64_t)c * cstride);
+        },
+        m, g, n_pairs, out);
+}
+
+// Fused encode and sweep.  Tiles of T consecutive groups are dealt to the
+// blocks round-robin (persistent blocks).  A block encodes a tile GB groups at
+// a time from the ASCII pairs (stored back to back, pair i at byte i*m) into an
+// LDS copy of the lane-sliced layout; then lanes 0..T-1 sweep one group each
+// from LDS.  The packed encoding never reaches HBM.  Two register buffers take
+// turns: the loads of the next GB groups (possibly of the block's next tile)
+// are in flight while the current ones are encoded and while the tile is
+// swept.  LDS: GB * stage_dwords(m) dwords of staging, then 4 * nch * T words.
+// No barrier is needed around the sweep: encode_groups ends with one (the
+// tile is complete) and the next encode writes the tile only after its own
+// first barrier.
+template <int E, int MODE>
+__global__ __launch_bounds__(256) void k_fused(const uint8_t* __restrict__ reads, const uint8_t* __restrict__ refs,
+                                               int64_t n_pairs, int m, int T, int GB, int fast,
+                                               uint16_t* __restrict__ out, uint32_t* __restrict__ err)
+{
+    extern __shared__ uint32_t lds[];
+    const int nch = (m + kChunk - 1) / kChunk;
+    const int64_t G = (n_pairs + 31) / 32;
+    const int64_t ntiles = (G + T - 1) / T;
+    const int stage_w = (GB * tile::stage_dwords(m) + 3) & ~3;
+    uint4* __restrict__ pk4 = reinterpret_cast<uint4*>(lds + stage_w);
+    uint32_t bad = 0;
+    int64_t tl = blockIdx.x;               // current tile and group offset in it
+    int sb = 0;
+    if (tl >= ntiles) return;
+    auto tile_groups = [&](int64_t t) { return (int)min<int64_t>(T, G - t * T); };
+    auto advance = [&](int64_t& t, int& b) {
+        b += GB;
+        if (b >= tile_groups(t)) { t += gridDim.x; b = 0; }
+    };
+    // one step: encode the current GB groups from cur while the next groups'
+    // loads (possibly of the block's next tile) run; after a tile's last
+    // groups, sweep it; false when the block is done
+    auto step = [&](const uint4 (&cur)[2][tile::kQ], uint4 (&nxt)[2][tile::kQ]) -> bool {
+        int64_t tn = tl;
+        int bn = sb;
+        advance(tn, bn);
+        tile::load_groups(reads, refs, n_pairs, m, tn * T + bn, GB, fast && tn < ntiles, nxt);
+        tile::encode_groups(reads, refs, nullptr, nullptr, n_pairs, m, tl * T + sb, GB, fast, cur, lds, pk4, T, sb,
+                            bad);
+        if (tn != tl) {
+            const int gl = threadIdx.x;
+            if (gl < tile_groups(tl)) {
+                sweep_group<E, MODE>([&](int plane, int c) -> uint4 { return pk4[(plane * nch + c) * T + gl]; }, m,
+                                     tl * T + gl, n_pairs, out);
+            }
+        }
+        tl = tn;
+        sb = bn;
+        return tl < ntiles;
+    };
+    if constexpr (MODE == MAIN_CIRC) {
+        uint4 va[2][tile::kQ], vb[2][tile::kQ];
+        tile::load_groups(reads, refs, n_pairs, m, tl * T, GB, fast != 0, va);
+        for (;;) {
+            if (!step(va, vb)) break;
+            if (!step(vb, va)) break;
+        }
+    } else {
+        // larger thresholds: the sweep's window already takes most registers,
+        // so one load buffer (no loads in flight across a step)
+        for (;;) {
+            uint4 v[2][tile::kQ];
+            tile::load_groups(reads, refs, n_pairs, m, tl * T + sb, GB, fast != 0, v);
+            tile::encode_groups(reads, refs, nullptr, nullptr, n_pairs, m, tl * T + sb, GB, fast, v, lds, pk4, T,
+                                sb, bad);
+            int64_t tn = tl;
+            int bn = sb;
+            advance(tn, bn);
+            if (tn != tl) {
+                const int gl = threadIdx.x;
+                if (gl < tile_groups(tl)) {
+                    sweep_group<E, MODE>([&](int plane, int c) -> uint4 { return pk4[(plane * nch + c) * T + gl]; },
+                                         m, tl * T + gl, n_pairs, out);
+                }
+            }
+            tl = tn;
+            sb = bn;
+            if (tl >= ntiles) break;
+        }
+    }
+    if (bad && err) atomicOr(err, 1u);
+}
+
 template <int E>
 hipError_t launch_sliced_E(const uint32_t* packed, int64_t n_pairs, int32_t m, uint16_t* out, hipStream_t s)
 {
@@ -264,6 +360,42 @@ hipError_t launch_sliced_E(const uint32_t* packed, int64_t n_pairs, int32_t m, u
     hipLaunchKernelGGL((k_sliced<E, mode>), dim3((unsigned)blocks), dim3(threads), 0, s, packed, G, m, n_pairs, out);
     return hipGetLastError();
 }
+
+template <int E>
+hipError_t launch_fused_E(const uint8_t* reads, const uint8_t* refs, int64_t n_pairs, int32_t m, int T, int GB,
+                          int fast, size_t shmem, uint16_t* out, uint32_t* err, hipStream_t s)
+{
+    const int64_t G = cdiv(n_pairs, 32);
+    constexpr int mode = E <= 10 ? MAIN_CIRC : MAIN_SHIFT4;
+    if (shmem > 65536) {
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fused<E, mode>),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+        if (e != hipSuccess) return e;
+    }
+    // persistent blocks: as many as are resident at once (LDS and registers), at most one per tile
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, reinterpret_cast<const void*>(&k_fused<E, mode>), 256, shmem);
+    if (e != hipSuccess) return e;
+    int dev = 0, cus = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+    const int64_t grid = std::min<int64_t>(cdiv(G, T), (int64_t)std::max(1, per_cu) * cus);
+    hipLaunchKernelGGL((k_fused<E, mode>), dim3((unsigned)grid), dim3(256), shmem, s, reads, refs, n_pairs, m, T,
+                       GB, fast, out, err);
+    return hipGetLastError();
+}
+
+template <int... Es>
+struct FusedTable {
+    static hipError_t run(int E, const uint8_t* reads, const uint8_t* refs, int64_t n, int32_t m, int T, int GB,
+                          int fast, size_t shmem, uint16_t* out, uint32_t* err, hipStream_t s)
+    {
+        hipError_t r = hipErrorInvalidValue;
+        ((E == Es ? (r = launch_fused_E<Es>(reads, refs, n, m, T, GB, fast, shmem, out, err, s), 0) : 0), ...);
+        return r;
+    }
+};
 
 template <int... Es>
 struct SlicedTable {

@@ -1,0 +1,166 @@
+// Tiled encoder body shared by the standalone encoder and the fused
+// encode-and-sweep kernel.
+//
+// A 256-thread block encodes GB consecutive groups of 32 pair slots into the
+// lane-sliced layout (bit s of a word belongs to slot 32*g + s).  Phase 1
+// copies the slots' bases into LDS staging as 2-bit codes (one byte per base,
+// rows padded to whole dwords, four pad dwords per group: 16-byte stores stay
+// aligned, and the 32 phase-2 reads of a half-wave, 8 groups x 4 chunks, fall
+// in 32 different banks) and validates every
+// byte: a byte b is one of ACGTacgt exactly when (b & 0xDF) equals the letter
+// its code stands for, looked up with a byte permute.  Phase 2: one thread per
+// (group, chunk of four positions) folds the 32 slots' code dwords into the
+// four words of each plane.
+#pragma once
+#include "ss_common.h"
+
+namespace ss {
+namespace tile {
+
+// dwords of LDS staging per group of 32 slots of length m
+__host__ __device__ inline int stage_dwords(int m) { return 32 * ((m + 3) >> 2) + 4; }
+
+__device__ __forceinline__ uint32_t codes4(uint32_t x, uint32_t& bad)
+{
+    const uint32_t cc = ((x >> 1) ^ (x >> 2)) & 0x03030303u;
+    const uint32_t letter = __builtin_amdgcn_perm(0u, 0x54474341u, cc);   // 'A','C','G','T' by code
+    bad |= (x & 0xDFDFDFDFu) ^ letter;
+    return cc;
+}
+
+constexpr int kQ = 8;      // 16-byte loads per thread and side on the fast path
+
+// Fast path: the block's 16-byte loads of groups g0 .. g0+GB-1, both sides
+// (thread t takes loads t, t + 256, ...).  Raw buffer loads over exactly the
+// groups' bytes: the hardware range check returns zero for a load past the
+// end instead of touching memory, so every load is issued unconditionally
+// (straight-line code keeps all of them in flight together, and a caller can
+// issue the next groups' loads before consuming these).  present == false
+// issues loads over an empty range (nothing is read).
+__device__ __forceinline__ void load_groups(const uint8_t* __restrict__ reads, const uint8_t* __restrict__ refs,
+                                            int64_t n_pairs, int m, int64_t g0, int GB, bool present,
+                                            uint4 (&v)[2][kQ])
+{
+    const int64_t s0 = g0 * 32;
+    const int np = present ? (int)min((int64_t)32 * GB, n_pairs - s0) : 0;
+    const int nbytes = np > 0 ? np * m : 0;
+#pragma unroll
+    for (int sd = 0; sd < 2; sd++) {
+        const uint8_t* base = (sd ? refs : reads) + (present ? s0 * (int64_t)m : 0);
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(base), (short)0, nbytes, 0x00020000);
+#pragma unroll
+        for (int k = 0; k < kQ; k++)
+            v[sd][k] = __builtin_bit_cast(
+                uint4, __builtin_amdgcn_raw_buffer_load_b128(rs, 16 * (threadIdx.x + 256 * k), 0, 0));
+    }
+}
+
+// Encode groups g0 .. g0+GB-1 (those that hold a slot below n_pairs); GB is a
+// power of two.  Slot i reads pair index[i] (or i) at offsets[pair] (or
+// pair * m).  The words of (plane p, chunk c, local group gl) go to
+// out4[(p * nch + c) * ostride + obase + gl] (out4 may point to global memory
+// or to LDS).  stage: GB * stage_dwords(m) dwords of LDS, 16-byte aligned.
+// fast: slots are pairs stored back to back from a 16-byte aligned byte
+// (index and offsets null), m % 4 == 0 and GB * m / 4 <= 256; v then holds
+// load_groups' loads of these groups.  Every thread of the block must call
+// this (it synchronises the block).
+__device__ __forceinline__ void encode_groups(const uint8_t* __restrict__ reads, const uint8_t* __restrict__ refs,
+                                              const int64_t* __restrict__ offsets,
+                                              const int64_t* __restrict__ index, int64_t n_pairs, int m,
+                                              int64_t g0, int GB, int fast, const uint4 (&v)[2][kQ],
+                                              uint32_t* __restrict__ stage, uint4* __restrict__ out4,
+                                              int64_t ostride, int64_t obase, uint32_t& bad)
+{
+    const int mw = (m + 3) >> 2;              // dwords per slot row
+    const int gs = 32 * mw + 4;               // dwords per group
+    const int nch = mw;
+    const int64_t s0 = g0 * 32;
+    const int np = (int)min((int64_t)32 * GB, n_pairs - s0);
+    const int lgb = 31 - __builtin_clz((unsigned)GB);
+    const int t = threadIdx.x;
+    const int ndw = np * mw;
+    const int nq = ndw >> 2;
+    // Staging index of source dword dw (slot p = dw / mw, column dw % mw):
+    // (p / 32) * gs + (p % 32) * mw + dw % mw = dw + 4 * (dw / (32 * mw)).  The
+    // four dwords of a 16-byte load share their group (32 * mw is a multiple
+    // of 4), so one quotient q / (8 * mw) serves all four and they go out as
+    // one aligned 16-byte store.  Quotients by multiply-high with
+    // ceil(2^32 / d): exact while x * d < 2^32 (here x < 2^13 and d <= 2^13
+    // on the fast path, x < 2^11 for q).
+    const uint32_t d16 = 8u * (uint32_t)(mw > 0 ? mw : 1), d4 = 4u * d16;
+    const uint32_t r16 = 0xFFFFFFFFu / d16 + 1u, r4 = 0xFFFFFFFFu / d4 + 1u;
+#pragma unroll
+    for (int side = 0; side < 2; side++) {
+        const uint8_t* __restrict__ src = side ? refs : reads;
+        if (fast) {
+#pragma unroll
+            for (int k = 0; k < kQ; k++) {
+                const int q = t + 256 * k;
+                if (q < nq) {
+                    uint4* __restrict__ dst = reinterpret_cast<uint4*>(stage) + q + (int)__umulhi((uint32_t)q, r16);
+                    *dst = make_uint4(codes4(v[side][k].x, bad), codes4(v[side][k].y, bad),
+                                      codes4(v[side][k].z, bad), codes4(v[side][k].w, bad));
+                }
+            }
+            const uint32_t* __restrict__ s32 = reinterpret_cast<const uint32_t*>(src + s0 * (int64_t)m);
+            for (int dw = 4 * nq + t; dw < ndw; dw += 256)
+                stage[dw + 4 * (int)__umulhi((uint32_t)dw, r4)] = codes4(s32[dw], bad);
+        } else {
+            uint8_t* lb = reinterpret_cast<uint8_t*>(stage);
+            const int nb = np * m;
+            for (int i = t; i < nb; i += 256) {
+                const int p = i / m, col = i - p * m;
+                const int64_t slot = s0 + p;
+                const int64_t pi = index ? index[slot] : slot;
+                const int64_t off = offsets ? offsets[pi] : pi * (int64_t)m;
+                uint32_t bb = 0;
+                const uint32_t c = codes4((uint32_t)src[off + col] | 0x41414100u, bb);   // pad the other lanes with 'A'
+                bad |= bb;
+                lb[4 * ((p >> 5) * gs + (p & 31) * mw) + col] = (uint8_t)(c & 3u);
+            }
+        }
+        __syncthreads();
+        for (int task = t; task < GB * nch; task += 256) {
+            const int gl = task & (GB - 1), c = task >> lgb;
+            if (32 * gl >= np) continue;
+            uint32_t lo[4] = {0u, 0u, 0u, 0u}, hi[4] = {0u, 0u, 0u, 0u};
+            const uint32_t* __restrict__ row = stage + gl * gs + c;
+#pragma unroll
+            for (int s = 0; s < 32; s++) {
+                const uint32_t cc = row[s * mw];
+                lo[s >> 3] |= (cc & 0x01010101u) << (s & 7);
+                hi[s >> 3] |= ((cc >> 1) & 0x01010101u) << (s & 7);
+            }
+            uint32_t wl[4], wh[4];
+#pragma unroll
+            for (int tt = 0; tt < 4; tt++) {
+                // word of position 4c+tt: byte q = slots 8q..8q+7
+                const uint32_t sel01 = (uint32_t)tt | ((uint32_t)(tt + 4) << 8) | 0x0C0C0000u;
+                const uint32_t sel23 = 0x00000C0Cu | ((uint32_t)tt << 16) | ((uint32_t)(tt + 4) << 24);
+                wl[tt] = __builtin_amdgcn_perm(lo[1], lo[0], sel01) | __builtin_amdgcn_perm(lo[3], lo[2], sel23);
+                wh[tt] = __builtin_amdgcn_perm(hi[1], hi[0], sel01) | __builtin_amdgcn_perm(hi[3], hi[2], sel23);
+            }
+            out4[((int64_t)(2 * side) * nch + c) * ostride + obase + gl] = make_uint4(wl[0], wl[1], wl[2], wl[3]);
+            out4[((int64_t)(2 * side + 1) * nch + c) * ostride + obase + gl] = make_uint4(wh[0], wh[1], wh[2], wh[3]);
+        }
+        __syncthreads();
+    }
+}
+
+// load_groups + encode_groups
+__device__ __forceinline__ void load_encode_groups(const uint8_t* __restrict__ reads,
+                                                   const uint8_t* __restrict__ refs,
+                                                   const int64_t* __restrict__ offsets,
+                                                   const int64_t* __restrict__ index, int64_t n_pairs, int m,
+                                                   int64_t g0, int GB, int fast, uint32_t* __restrict__ stage,
+                                                   uint4* __restrict__ out4, int64_t ostride, int64_t obase,
+                                                   uint32_t& bad)
+{
+    uint4 v[2][kQ];
+    load_groups(reads, refs, n_pairs, m, g0, GB, fast != 0, v);
+    encode_groups(reads, refs, offsets, index, n_pairs, m, g0, GB, fast, v, stage, out4, ostride, obase, bad);
+}
+
+}  // namespace tile
+}  // namespace ss

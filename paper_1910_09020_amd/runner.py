@@ -8,7 +8,7 @@ from __future__ import annotations
 import numpy as np
 import torch
 
-from . import (ss_create, ss_filter_plain_async, ss_filter_sliced_async, ss_filter_wave_async,
+from . import (ss_create, ss_filter_ascii_async, ss_filter_plain_async, ss_filter_sliced_async, ss_filter_wave_async,
                ss_pack_sliced_async, ss_pack_stream_async, ss_sliced_bytes, ss_stream_words)
 
 _ctx = {}
@@ -92,6 +92,15 @@ class DeviceBatch:
         out = self.new_out(n) if out is None else out
         ss_filter_sliced_async(context(self.device), packed, n, m, E, out,
                                stream or torch.cuda.current_stream(self.device))
+        return out
+
+    def filter_fused(self, E: int, out=None, tile_groups: int = 0, stream=None) -> torch.Tensor:
+        """Encode and filter in one call (pairs of one length stored back to back): fused kernel or chunks."""
+        if not self.contiguous:
+            raise ValueError("the fused kernel needs pairs of one length stored back to back")
+        out = self.new_out() if out is None else out
+        ss_filter_ascii_async(context(self.device), self.reads, self.refs, self.n, self.uniform_m, E, tile_groups,
+                              out, self.err, stream or torch.cuda.current_stream(self.device))
         return out
 
     def filter_plain(self, packed, E: int, per_pair: bool = False, out=None, stream=None) -> torch.Tensor:

@@ -1,8 +1,8 @@
 """Parity at the full workload sizes, in the launch configuration the benchmark times.
 
 The oracle checks a random sample pair by pair; every pair is checked by
-properties that hold at any size: the lane-sliced sweep and the one-pair-per-
-lane walk agree on all pairs, the accept decision is monotone in E, a reported
+properties that hold at any size: the lane-sliced sweep, the one-call path
+(fused or chunked) and the one-pair-per-lane walk agree on all pairs, the accept decision is monotone in E, a reported
 count never exceeds E+1 and the decision is exactly count <= E.
 """
 import os
@@ -49,6 +49,15 @@ def _run(rt, b, Es, plain_E, sample):
         res[E] = runner.results_numpy(out, db.n)
     assert not db.bad_bases()
     del pk
+    # the one-call path (fused kernel for small E, chunked two-kernel schedule
+    # above) must give the same words for every pair
+    for E in Es:
+        print(f"  one-call n={db.n} E={E}", flush=True)
+        f = db.filter_fused(E)
+        torch.cuda.synchronize()
+        fa, fe = runner.results_numpy(f, db.n)
+        assert np.array_equal(fa, res[E][0]) and np.array_equal(fe, res[E][1]), f"one-call E={E}"
+        del f
     ps = db.pack_stream()
     print(f"  plain E={plain_E}", flush=True)
     pout = db.filter_plain(ps, plain_E)

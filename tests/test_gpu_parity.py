@@ -47,7 +47,7 @@ def check(name, got, want):
     assert len(bad) == 0, f"{name}: {len(bad)} mismatches, first {bad[:5]} got {ge[bad[:5]]} want {we[bad[:5]]}"
 
 
-def run_all(rt, b, E, kernels=("sliced", "plain", "wave")):
+def run_all(rt, b, E, kernels=("sliced", "fused", "plain", "wave")):
     import torch
     db = rt.DeviceBatch(b)
     want = expect(b, E=E)
@@ -58,6 +58,12 @@ def run_all(rt, b, E, kernels=("sliced", "plain", "wave")):
         torch.cuda.synchronize()
         assert not db.bad_bases()
         check(f"sliced E={E}", rt.results_numpy(out, db.n), want)
+    if "fused" in kernels and db.contiguous and db.uniform_m <= 2048 and E <= 32:
+        say(f"  fused n={db.n} m={db.uniform_m} E={E}")
+        out = db.filter_fused(E)
+        torch.cuda.synchronize()
+        assert not db.bad_bases()
+        check(f"fused E={E}", rt.results_numpy(out, db.n), want)
     ps = None
     if "plain" in kernels and E <= 31:
         say(f"  plain n={db.n} E={E}")
@@ -120,7 +126,7 @@ def test_degenerate_pairs(rt):
     for m in (1, 4, 8, 40):
         sub = gen.concat([p for p in pairs if len(p[0]) == m])
         for E in (0, 1, 3, 10, 32):
-            run_all(rt, sub, E, kernels=("sliced",))
+            run_all(rt, sub, E, kernels=("sliced", "fused"))
 
 
 def test_mixed_lengths_per_pair_E(rt):
