@@ -2,13 +2,15 @@
 """Benchmark: filtered pairs/s on one MI355X for 100 bp pairs at E = 5.
 
 One step is one pass of the whole hot path over one batch: the 30 M pairs of
-100 bp (ASCII, already resident in HBM) are encoded into the lane-sliced 2-bit
-layout and filtered at E = 5 (Equation 1 maze + greedy walk, accept bit and
-obstacle count written per pair).  Reported alongside: the filter launch alone
-on the resident encoding (the per-E cost of a threshold sweep), the
-one-pair-per-lane kernel on the same batch, a sampled bit-exact check against
-the CPU oracle, the oracle's own throughput on the host cores, and the
-roofline of the dominant kernel.
+100 bp (ASCII, already resident in HBM) are encoded into 2-bit planes and
+filtered at E = 5 (Equation 1 maze + greedy walk, accept bit and obstacle
+count written per pair) by one call of ss_filter_ascii_async (at E = 5 one
+fused kernel: each workgroup encodes its tile on chip and sweeps it there).
+Reported alongside: the two-kernel path (encode to HBM, then the sweep) and
+the sweep alone on the resident encoding (the per-E cost of a threshold
+sweep), the one-pair-per-lane kernel on the same batch, a sampled bit-exact
+check against the CPU oracle, the oracle's own throughput on the host cores,
+the roofline of the step's kernel, the mixed-length batch and the serving loop.
 
 Prints one JSON line.  Only one GPU is used; --gpus above 1 is refused.
 """
@@ -33,25 +35,26 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 VALU_PEAK_TOPS = 39.3          # 256 CU x 64 lanes x 2.4 GHz, 32-bit lane ops / s (1e12)
 
 
-def measured_traffic(name):
-    """HBM bytes per launch of a kernel from the committed rocprofv3 PMC summary, or None when the
-    kernel's source has changed since the counters were taken."""
+def measured_traffic(name, profile="fused_encode_sweep_100bp_E5_pmc_traffic.md"):
+    """HBM bytes per launch of a kernel from a committed rocprofv3 PMC summary, or None when one of
+    the kernel's source files has changed since the counters were taken (the summary line carries a
+    hash of those files, concatenated in the order listed)."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "encode_sweep_100bp_E5_pmc_traffic.md")
     try:
-        text = open(path).read()
+        text = open(os.path.join(ROOT, "profiles", profile)).read()
     except OSError:
         return None
     for line in text.splitlines():
         f = line.split()
         if len(f) == 5 and f[0] == "traffic" and f[1] == name:
             kv = dict(x.split("=", 1) for x in f[2:])
-            src = os.path.join(ROOT, kv["source"])
+            h = hashlib.sha256()
             try:
-                sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+                for src in kv["source"].split(","):
+                    h.update(open(os.path.join(ROOT, src), "rb").read())
             except OSError:
                 return None
-            return float(kv["bytes"]) if sha == kv["sha256_16"] else None
+            return float(kv["bytes"]) if h.hexdigest()[:16] == kv["sha256_16"] else None
     return None
 
 
@@ -207,7 +210,7 @@ def main():
     ap.add_argument("--E", type=int, default=5)
     ap.add_argument("--n", type=int, default=None, help="pairs (default: 30 M, the 100 bp workload)")
     ap.add_argument("--sample", type=int, default=200000, help="pairs checked against the oracle")
-    ap.add_argument("--cpu-pairs", type=int, default=12_000_000, help="oracle baseline sample")
+    ap.add_argument("--cpu-pairs", type=int, default=None, help="oracle baseline sample (default: all pairs)")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--mixed-n", type=int, default=None, help="pairs of the mixed-length batch (default 5.02 M)")
@@ -244,22 +247,31 @@ def main():
     m = 100
     db = runner.DeviceBatch(b)
     torch.cuda.synchronize()
-    packed = torch.empty(max(4, ss.ss_sliced_bytes(n, m) // 4), dtype=torch.int32, device="cuda")
     out = torch.empty(n, dtype=torch.int16, device="cuda")
-    pack = lambda: db.pack_sliced(packed=packed)
-    filt = lambda: db.filter_sliced(packed, E, out=out)
+    step = lambda: db.filter_fused(E, out=out)          # one call: encode + filter
     for _ in range(a.warmup):
-        pack(); filt()
+        step()
     torch.cuda.synchronize()
     assert not db.bad_bases()
-    wall, (pack_ms, filt_ms) = timed_loop([pack, filt], a.steps, torch)
+    wall, (step_ms,) = timed_loop([step], a.steps, torch)
     ms_per_step = 1e3 * wall / a.steps
     value = n / (ms_per_step / 1e3)
-    log(f"step {ms_per_step:.3f} ms  (encode {pack_ms:.3f} ms, filter {filt_ms:.3f} ms)  {value / 1e9:.2f} G pairs/s")
+    log(f"step {ms_per_step:.3f} ms (one call, {step_ms:.3f} ms on the stream)  {value / 1e9:.2f} G pairs/s")
 
-    # filter alone on the resident encoding (per-E cost of a sweep)
-    fwall, (f_only_ms,) = timed_loop([filt], a.steps, torch)
+    # two-kernel path: encode to HBM, then the sweep (what a threshold sweep reuses)
+    packed = torch.empty(max(4, ss.ss_sliced_bytes(n, m) // 4), dtype=torch.int32, device="cuda")
+    out2 = torch.empty(n, dtype=torch.int16, device="cuda")
+    pack = lambda: db.pack_sliced(packed=packed)
+    filt = lambda: db.filter_sliced(packed, E, out=out2)
+    pack(); filt(); torch.cuda.synchronize()
+    _, (pack_ms, filt_ms) = timed_loop([pack, filt], a.steps, torch)
+    _, (f_only_ms,) = timed_loop([filt], a.steps, torch)
     filter_only = n / (1e-3 * f_only_ms)
+    two_kernel = dict(encode_ms=round(pack_ms, 4), filter_ms=round(filt_ms, 4),
+                      pairs_per_s=n / (1e-3 * (pack_ms + filt_ms)), filter_only_pairs_per_s=filter_only,
+                      identical_outputs=bool(torch.equal(out, out2)))
+    log(f"two kernels: encode {pack_ms:.3f} ms, filter {filt_ms:.3f} ms, identical={two_kernel['identical_outputs']}")
+    del packed, out2
 
     # sampled bit-exact check against the oracle
     import oracle
@@ -288,7 +300,7 @@ def main():
         del ps, pout
 
     # HBM calibration: a device-to-device copy of 2 GiB (reads and writes 2 GiB each)
-    del db.reads, db.refs, packed
+    del db.reads, db.refs
     torch.cuda.empty_cache()
     torch.cuda.empty_cache()
     src = torch.empty(2 << 30, dtype=torch.uint8, device="cuda")
@@ -299,11 +311,12 @@ def main():
     _, (cp_ms,) = timed_loop([cp], 5, torch)
     copy_gbs = 2 * src.numel() / (cp_ms * 1e-3) / 1e9
     log(f"device copy: {copy_gbs:.0f} GB/s (read + write)")
-    # read-only kernel of known size (2 GiB summed as int32): calibrates the fetch counter
-    rd = lambda: src.view(torch.int32).sum()
+    # read-only kernel of known size (2 GiB summed as int64): calibrates the fetch counter
+    rd = lambda: src.view(torch.int64).sum()
     rd(); torch.cuda.synchronize()
     _, (rd_ms,) = timed_loop([rd], 3, torch)
-    log(f"device read: {src.numel() / (rd_ms * 1e-3) / 1e9:.0f} GB/s")
+    read_gbs = src.numel() / (rd_ms * 1e-3) / 1e9
+    log(f"device read: {read_gbs:.0f} GB/s")
     del src, dst
 
     mixed = None
@@ -317,23 +330,25 @@ def main():
     cpu = None
     if not a.no_cpu:
         threads = min(16, os.cpu_count() or 1)
-        k = min(a.cpu_pairs, n)
+        k = min(a.cpu_pairs or n, n)
         r = oracle.batch(b["reads"], b["refs"], b["offsets"][:k], b["lengths"][:k], E=E, threads=threads)
+        what = "all" if k == n else f"the first {k} of the"
         cpu = dict(value=k / r["seconds"], unit="pairs/s", cores=threads, kind="oracle",
-                   sample=f"first {k} pairs of the 100 bp workload at E={E}, {threads} threads "
-                          f"({r['seconds']:.2f} s wall)")
+                   sample=f"{what} {n} pairs of the 100 bp workload at E={E}, {threads} threads "
+                          f"({r['seconds']:.2f} s wall, {r['seconds'] * threads:.1f} CPU-seconds at most)")
         log(f"oracle: {cpu['value'] / 1e6:.2f} M pairs/s on {threads} threads")
 
-    # roofline of the dominant kernel (algorithmic bytes per launch / mean launch time)
-    enc_bytes = n * (2 * m + m / 2)          # read two ASCII sequences, write 2-bit planes
-    filt_bytes = n * (m / 2 + 2)             # read 2-bit planes, write one result word
-    if pack_ms >= filt_ms:
-        dom, bytes_, ms = "encode (lane-sliced)", enc_bytes, pack_ms
-        traffic = measured_traffic("k_pack_tile") if n == 30_000_000 else None
+    # roofline of the step's kernel (algorithmic bytes per launch / mean launch time on its stream)
+    fused = E <= 5          # the one-call path runs the fused kernel up to E = 5
+    if fused:
+        dom = "fused encode + column sweep (k_fused<%d>)" % E
+        bytes_ = n * (2 * m + 2)                 # read two ASCII sequences, write one result word
+        traffic = measured_traffic("k_fused_E%d" % E) if n == 30_000_000 else None
     else:
-        dom, bytes_, ms = "column sweep E=%d" % E, filt_bytes, filt_ms
-        traffic = measured_traffic("k_sliced_E%d" % E) if n == 30_000_000 else None
-    achieved = bytes_ / (ms * 1e-3) / 1e9
+        dom = "encode + column sweep in chunks"
+        bytes_ = n * (2 * m + 2)
+        traffic = None
+    achieved = bytes_ / (step_ms * 1e-3) / 1e9
     line = {
         "metric": "filtered pairs/sec at 1 GPU (100bp E=5)",
         "value": value,
@@ -347,9 +362,11 @@ def main():
         "vs_baseline": None,
         "dtype": "u32 bitwise",
         "data": "synthetic (seeded generator; stands in for the paper's 100bp datasets)",
-        "config": {"workload": "100 bp pairs, 30M, 40% k~U{0..3} / 40% k~U{4..15} / 20% unrelated, E=5",
-                   "n_pairs": n, "m": m, "E": E, "kernel": "lane-sliced column sweep"},
-        "step_breakdown_ms": {"encode": round(pack_ms, 4), "filter": round(filt_ms, 4)},
+        "config": {"workload": f"100 bp pairs, 30M, 40% k~U{{0..3}} / 40% k~U{{4..15}} / 20% unrelated, E={E}",
+                   "n_pairs": n, "m": m, "E": E,
+                   "kernel": "fused encode + lane-sliced column sweep" if fused else "chunked encode + sweep"},
+        "step_kernel_ms": round(step_ms, 4),
+        "two_kernel": two_kernel,
         "filter_only_pairs_per_s": filter_only,
         "oracle_sample_mismatches": mism,
         "oracle_sample_pairs": int(len(idx)),
@@ -359,6 +376,7 @@ def main():
                      "algorithmic_bytes": bytes_},
         "cpu_baseline": cpu,
         "hbm_copy_calibration_gbs": copy_gbs,
+        "hbm_read_calibration_gbs": read_gbs,
         "mixed": mixed,
         "serving": serving,
     }
