@@ -79,6 +79,87 @@ def timed_loop(fns, steps, torch):
     return wall, per
 
 
+def sweep_leg(torch, ss, gen, runner, config, Es, steps, batch=None):
+    """Threshold sweep on one resident batch: the two-kernel path encodes once and sweeps each E;
+    the one-call path (fused up to E = 5, chunked above) runs per E.  Mean ms per launch."""
+    b = batch if batch is not None else gen.make(config, threads=min(16, os.cpu_count() or 1))
+    db = runner.DeviceBatch(b)
+    n, m = db.n, db.uniform_m
+    packed = torch.empty(max(4, ss.ss_sliced_bytes(n, m) // 4), dtype=torch.int32, device="cuda")
+    out = torch.empty(n, dtype=torch.int16, device="cuda")
+    out1 = torch.empty(n, dtype=torch.int16, device="cuda")
+    db.pack_sliced(packed=packed)
+    torch.cuda.synchronize()
+    _, (enc_ms,) = timed_loop([lambda: db.pack_sliced(packed=packed)], steps, torch)
+    per_E = {}
+    same = True
+    for E in Es:
+        db.filter_sliced(packed, E, out=out)
+        db.filter_fused(E, out=out1)
+        torch.cuda.synchronize()
+        same = same and bool(torch.equal(out, out1))
+        _, (sw_ms, one_ms) = timed_loop([lambda: db.filter_sliced(packed, E, out=out),
+                                         lambda: db.filter_fused(E, out=out1)], steps, torch)
+        per_E[E] = dict(sweep_ms=round(sw_ms, 4), one_call_ms=round(one_ms, 4))
+    assert not db.bad_bases()
+    total_sweep = enc_ms + sum(v["sweep_ms"] for v in per_E.values())
+    log(f"sweep config {config} ({n} x {m} bp): encode {enc_ms:.3f} ms, E={Es[0]}..{Es[-1]} "
+        f"sweeps {sum(v['sweep_ms'] for v in per_E.values()):.3f} ms, identical={same}")
+    res = dict(n_pairs=n, m=m, encode_ms=round(enc_ms, 4), per_E=per_E,
+               whole_sweep_ms=round(total_sweep, 4),
+               whole_sweep_pair_thresholds_per_s=n * len(Es) / (1e-3 * total_sweep),
+               one_call_equals_two_kernel=same)
+    del db, packed, out, out1
+    torch.cuda.empty_cache()
+    return res
+
+
+def latency_leg(torch, ss, gen, runner, E=5, reps=200):
+    """Single-call latency on the small 10,000-pair batch: eager calls, and the same call
+    captured once in a HIP graph and replayed (each replay checked against the eager result)."""
+    b = gen.make(0)
+    db = runner.DeviceBatch(b)
+    out = torch.empty(db.n, dtype=torch.int16, device="cuda")
+    db.filter_fused(E, out=out)
+    torch.cuda.synchronize()
+    ref = out.clone()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        db.filter_fused(E, out=out)
+    torch.cuda.synchronize()
+    eager_us = 1e6 * (time.perf_counter() - t0) / reps
+    _, (eager_dev_ms,) = timed_loop([lambda: db.filter_fused(E, out=out)], reps, torch)
+    g = torch.cuda.CUDAGraph()
+    gout = torch.empty_like(out)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        db.filter_fused(E, out=gout, stream=s)          # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=s):
+        db.filter_fused(E, out=gout, stream=s)
+    ok = True
+    for _ in range(3):
+        gout.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        ok = ok and bool(torch.equal(gout, ref))
+        db.filter_fused(E, out=out)                       # eager work between replays
+        torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g.replay()
+    torch.cuda.synchronize()
+    graph_us = 1e6 * (time.perf_counter() - t0) / reps
+    log(f"latency (10,000 pairs, E={E}): eager {eager_us:.1f} us/call, graph {graph_us:.1f} us/replay, "
+        f"replays identical={ok}")
+    res = dict(n_pairs=db.n, E=E, eager_us_per_call=eager_us, eager_kernel_us=1e3 * eager_dev_ms,
+               graph_us_per_replay=graph_us, graph_replays_identical=ok)
+    del g, db
+    return res
+
+
 def mixed_leg(a, torch, ss, gen, runner, oracle):
     """Mixed-length batch (5 M short pairs of 100/150/250 bp + 20,000 pairs of 10 kbp, per-pair E):
     one persistent launch from an autotuned plan, replayed from a captured HIP graph, against one
@@ -223,6 +304,7 @@ def main():
                     help="distinct requests generated before the clock starts (0: generate on the fly)")
     ap.add_argument("--serve-only", action="store_true", help="run only the serving leg (diagnostics)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the threshold sweeps and the latency leg")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported (pairs shard independently "
@@ -319,6 +401,11 @@ def main():
     log(f"device read: {read_gbs:.0f} GB/s")
     del src, dst
 
+    sweeps = None
+    if not a.no_sweep:
+        sweeps = {"100bp_30M_E0-10": sweep_leg(torch, ss, gen, runner, 1, list(range(0, 11)), 5, batch=b),
+                  "250bp_10M_E0-25": sweep_leg(torch, ss, gen, runner, 2, list(range(0, 26)), 3)}
+
     mixed = None
     if not a.no_mixed:
         mixed = mixed_leg(a, torch, ss, gen, runner, oracle)
@@ -326,6 +413,14 @@ def main():
     serving = None
     if not a.no_serve:
         serving = serving_leg(a, ss, gen, runner, oracle)
+
+    latency = None
+    if not a.no_sweep:
+        try:
+            latency = latency_leg(torch, ss, gen, runner)
+        except Exception as e:          # reported, not fatal: the headline is already measured
+            latency = {"error": repr(e)}
+            log(f"latency leg failed: {e!r}")
 
     cpu = None
     if not a.no_cpu:
@@ -377,6 +472,8 @@ def main():
         "cpu_baseline": cpu,
         "hbm_copy_calibration_gbs": copy_gbs,
         "hbm_read_calibration_gbs": read_gbs,
+        "threshold_sweeps": sweeps,
+        "latency_10k": latency,
         "mixed": mixed,
         "serving": serving,
     }
