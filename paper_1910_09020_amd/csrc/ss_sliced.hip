@@ -121,14 +121,12 @@ hipError_t launch_pack_sliced(const uint8_t* reads, const uint8_t* refs, const i
         // tiled path: GB groups per block, LDS <= 32 KiB when possible
         int GB = 8;
         while (GB > 1 && GB * group_bytes > 32768) GB >>= 1;
-        // the streaming path: at most 8 sixteen-byte loads per thread and side
-        const bool fast = index == nullptr && m % 4 == 0 && (int64_t)GB * mw <= 256 &&
-                          ((((uintptr_t)reads | (uintptr_t)refs) & 15u) == 0);
-        // the fast path needs pair i at byte i*m
-        const bool contiguous = offsets == nullptr;
+        // the streaming paths need pair i at byte i*m from 16-byte aligned bases
+        const bool contiguous = index == nullptr && offsets == nullptr &&
+                                ((((uintptr_t)reads | (uintptr_t)refs) & 15u) == 0);
         const size_t shmem = (size_t)GB * group_bytes;
         hipLaunchKernelGGL(k_pack_tile, dim3((unsigned)cdiv(G, GB)), dim3(256), shmem, s, reads, refs, offsets, index,
-                           n_pairs, m, G, GB, (fast && contiguous) ? 1 : 0, packed, err);
+                           n_pairs, m, G, GB, tile::fast_mode(m, GB, contiguous), packed, err);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_pack_sliced, dim3((unsigned)G), dim3(64), 0, s, reads, refs, offsets, index, n_pairs, m,
@@ -182,9 +180,7 @@ hipError_t launch_fused(const uint8_t* reads, const uint8_t* refs, int64_t n_pai
     int T = 0, GB = 0;
     const size_t shmem = fused_shape(m, tile_groups, &T, &GB);
     if (shmem == 0) return hipErrorInvalidValue;
-    const int64_t mw = cdiv(m, 4);
-    const int fast = (m % 4 == 0 && (int64_t)GB * mw <= 256 &&
-                      ((((uintptr_t)reads | (uintptr_t)refs) & 15u) == 0)) ? 1 : 0;
+    const int fast = tile::fast_mode(m, GB, (((uintptr_t)reads | (uintptr_t)refs) & 15u) == 0);
     if (E <= 10) return launch_fused_lo(E, reads, refs, n_pairs, m, T, GB, fast, shmem, out, err, s);
     if (E <= 20) return launch_fused_mid(E, reads, refs, n_pairs, m, T, GB, fast, shmem, out, err, s);
     return launch_fused_hi(E, reads, refs, n_pairs, m, T, GB, fast, shmem, out, err, s);

@@ -30,6 +30,18 @@ __device__ __forceinline__ uint32_t codes4(uint32_t x, uint32_t& bad)
 
 constexpr int kQ = 8;      // 16-byte loads per thread and side on the fast path
 
+// Encoder mode for GB groups of pairs of length m stored back to back from
+// 16-byte aligned bases (contiguous), else 0: 1 when m % 4 == 0 and each side
+// of the GB groups fits 256 * kQ sixteen-byte loads, 2 when m % 4 != 0 and the
+// raw bytes fit them as well.
+__host__ __device__ inline int fast_mode(int m, int GB, bool contiguous)
+{
+    if (!contiguous || m <= 0) return 0;
+    const int64_t bytes = 32ll * GB * (m % 4 == 0 ? m : 4 * ((m + 3) / 4));
+    if (bytes > 256ll * kQ * 16) return 0;
+    return m % 4 == 0 ? 1 : 2;
+}
+
 // Fast path: the block's 16-byte loads of groups g0 .. g0+GB-1, both sides
 // (thread t takes loads t, t + 256, ...).  Raw buffer loads over exactly the
 // groups' bytes: the hardware range check returns zero for a load past the
@@ -61,10 +73,12 @@ __device__ __forceinline__ void load_groups(const uint8_t* __restrict__ reads, c
 // pair * m).  The words of (plane p, chunk c, local group gl) go to
 // out4[(p * nch + c) * ostride + obase + gl] (out4 may point to global memory
 // or to LDS).  stage: GB * stage_dwords(m) dwords of LDS, 16-byte aligned.
-// fast: slots are pairs stored back to back from a 16-byte aligned byte
-// (index and offsets null), m % 4 == 0 and GB * m / 4 <= 256; v then holds
-// load_groups' loads of these groups.  Every thread of the block must call
-// this (it synchronises the block).
+// fast (see fast_mode): 0 = any slots, byte loads; 1 or 2 = slots are pairs
+// stored back to back from a 16-byte aligned byte (index and offsets null)
+// and v holds load_groups' loads of these groups; 1 when m % 4 == 0 (codes
+// staged per slot row), 2 otherwise (raw bytes staged in source order, read
+// back per slot and chunk with a byte-align).  Every thread of the block must
+// call this (it synchronises the block).
 __device__ __forceinline__ void encode_groups(const uint8_t* __restrict__ reads, const uint8_t* __restrict__ refs,
                                               const int64_t* __restrict__ offsets,
                                               const int64_t* __restrict__ index, int64_t n_pairs, int m,
@@ -93,7 +107,17 @@ __device__ __forceinline__ void encode_groups(const uint8_t* __restrict__ reads,
 #pragma unroll
     for (int side = 0; side < 2; side++) {
         const uint8_t* __restrict__ src = side ? refs : reads;
-        if (fast) {
+        if (fast == 2) {
+            // raw bytes in source order; the bytes past the last whole 16 one at a time
+            const int nb = np * m, nq16 = nb >> 4;
+#pragma unroll
+            for (int k = 0; k < kQ; k++) {
+                const int q = t + 256 * k;
+                if (q < nq16) reinterpret_cast<uint4*>(stage)[q] = v[side][k];
+            }
+            const uint8_t* __restrict__ sb = src + s0 * (int64_t)m;
+            for (int i = 16 * nq16 + t; i < nb; i += 256) reinterpret_cast<uint8_t*>(stage)[i] = sb[i];
+        } else if (fast) {
 #pragma unroll
             for (int k = 0; k < kQ; k++) {
                 const int q = t + 256 * k;
@@ -125,12 +149,30 @@ __device__ __forceinline__ void encode_groups(const uint8_t* __restrict__ reads,
             const int gl = task & (GB - 1), c = task >> lgb;
             if (32 * gl >= np) continue;
             uint32_t lo[4] = {0u, 0u, 0u, 0u}, hi[4] = {0u, 0u, 0u, 0u};
-            const uint32_t* __restrict__ row = stage + gl * gs + c;
+            if (fast == 2) {
+                // positions 4c..4c+3 of slot p start at byte p*m + 4c; bytes past m
+                // and slots past the batch read as 'A' (validated and coded once, here)
+                const int keepb = m - 4 * c;
+                const uint32_t keep = keepb >= 4 ? 0xFFFFFFFFu : ((1u << (8 * keepb)) - 1u);
+                int off = 32 * gl * m + 4 * c;
 #pragma unroll
-            for (int s = 0; s < 32; s++) {
-                const uint32_t cc = row[s * mw];
-                lo[s >> 3] |= (cc & 0x01010101u) << (s & 7);
-                hi[s >> 3] |= ((cc >> 1) & 0x01010101u) << (s & 7);
+                for (int s = 0; s < 32; s++) {
+                    const uint32_t w0 = stage[off >> 2], w1 = stage[(off >> 2) + 1];
+                    uint32_t x = __builtin_amdgcn_alignbyte(w1, w0, (uint32_t)(off & 3));
+                    x = (32 * gl + s < np) ? ((x & keep) | (0x41414141u & ~keep)) : 0x41414141u;
+                    const uint32_t cc = codes4(x, bad);
+                    lo[s >> 3] |= (cc & 0x01010101u) << (s & 7);
+                    hi[s >> 3] |= ((cc >> 1) & 0x01010101u) << (s & 7);
+                    off += m;
+                }
+            } else {
+                const uint32_t* __restrict__ row = stage + gl * gs + c;
+#pragma unroll
+                for (int s = 0; s < 32; s++) {
+                    const uint32_t cc = row[s * mw];
+                    lo[s >> 3] |= (cc & 0x01010101u) << (s & 7);
+                    hi[s >> 3] |= ((cc >> 1) & 0x01010101u) << (s & 7);
+                }
             }
             uint32_t wl[4], wh[4];
 #pragma unroll
