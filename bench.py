@@ -114,6 +114,46 @@ def sweep_leg(torch, ss, gen, runner, config, Es, steps, batch=None):
     return res
 
 
+def long_leg(torch, ss, gen, runner, oracle, n=2000, m=100_000, E=5000, steps=3):
+    """Pairs of 100 kbp at E = 5000 (5% of the length; 2E+1 = 10,001 rows per column), edit rates
+    3-7%: one standalone wavefront launch and one planned persistent launch (8 slices per lane),
+    with a sample checked against the oracle."""
+    b = gen.long_pairs(n, m, 300, 700)
+    db = runner.DeviceBatch(b)
+    ps = db.pack_stream()
+    out = db.new_out()
+    db.filter_wave(ps, E, out=out)
+    torch.cuda.synchronize()
+    _, (wave_ms,) = timed_loop([lambda: db.filter_wave(ps, E, out=out)], steps, torch)
+    Es = np.full(n, E, dtype=np.int32)
+    dE = torch.from_numpy(Es).to("cuda")
+    plan = ss.ss_plan_create(runner.context(), b["lengths"], Es, 8)
+    pout = db.new_out()
+    run = lambda: ss.ss_filter_planned_async(runner.context(), plan, ps, db.total, db.offsets, db.lengths, dE,
+                                             pout, torch.cuda.current_stream())
+    run()
+    torch.cuda.synchronize()
+    _, (plan_ms,) = timed_loop([run], steps, torch)
+    acc, ed = runner.results_numpy(out, n)
+    pacc, ped = runner.results_numpy(pout, n)
+    k = 16
+    w = oracle.batch(b["reads"], b["refs"], b["offsets"][:k], b["lengths"][:k], E=E,
+                     threads=min(16, os.cpu_count() or 1))
+    mism = int(np.sum((w["accept"] != acc[:k]) | (w["edits"] != ed[:k])))
+    same = bool(np.array_equal(acc, pacc) and np.array_equal(ed, ped))
+    ss.ss_plan_destroy(plan)
+    log(f"100 kbp: {n} pairs at E={E}: wave {wave_ms:.2f} ms, planned {plan_ms:.2f} ms, identical={same}, "
+        f"accepted {int(acc.sum())}, oracle mismatches {mism}/{k}")
+    res = dict(workload=f"{n} pairs of {m} bp, edit rate U[3%,7%], E={E}", n_pairs=n, m=m, E=E,
+               wave_ms=round(wave_ms, 3), planned_ms=round(plan_ms, 3),
+               pairs_per_s=n / (1e-3 * min(wave_ms, plan_ms)),
+               cells_per_s=n * m * (2 * E + 1) / (1e-3 * min(wave_ms, plan_ms)),
+               accepted=int(acc.sum()), identical_outputs=same, oracle_sample_pairs=k, oracle_sample_mismatches=mism)
+    del db, ps, out, pout
+    torch.cuda.empty_cache()
+    return res
+
+
 def latency_leg(torch, ss, gen, runner, E=5, reps=200):
     """Single-call latency on the small 10,000-pair batch: eager calls, and the same call
     captured once in a HIP graph and replayed (each replay checked against the eager result)."""
@@ -405,6 +445,7 @@ def main():
     if not a.no_sweep:
         sweeps = {"100bp_30M_E0-10": sweep_leg(torch, ss, gen, runner, 1, list(range(0, 11)), 5, batch=b),
                   "250bp_10M_E0-25": sweep_leg(torch, ss, gen, runner, 2, list(range(0, 26)), 3)}
+    long_pairs = None if a.no_sweep else long_leg(torch, ss, gen, runner, oracle)
 
     mixed = None
     if not a.no_mixed:
@@ -474,6 +515,7 @@ def main():
         "hbm_read_calibration_gbs": read_gbs,
         "threshold_sweeps": sweeps,
         "latency_10k": latency,
+        "long_100kbp": long_pairs,
         "mixed": mixed,
         "serving": serving,
     }

@@ -61,6 +61,7 @@ const char* ss_status_str(int status);
 #define SS_MAX_E_SLICED   32      /* lane-sliced kernel: 0 <= E <= 32 */
 #define SS_MAX_E_PLAIN    31      /* one-pair-per-lane kernel: 0 <= E <= 31 */
 #define SS_MAX_E          16383   /* any path: counts must fit 14 bits */
+#define SS_MAX_E_PLANNED  8191    /* batched launch and serving: 2E+1 rows in 64 lanes x 8 slices */
 #define SS_MAX_LEN        (1 << 24)
 #define SS_MAX_LEN_FUSED  2048    /* fused encode-and-filter kernel: m <= 2048 */
 
@@ -212,6 +213,11 @@ int ss_filter_wave_async(ss_ctx* ctx, const uint32_t* packed, int64_t total_base
  * items of one 256-thread block round, and the items ordered largest
  * estimated cost first.  The plan owns its device buffers (permutation, item
  * table, queue counter) and is bound to the device current at creation.
+ * A pair's 2E+1 rows must fit one wavefront (64 lanes x slices_per_lane x 32
+ * rows): slices_per_lane is raised to the smallest width that holds the
+ * largest threshold (ss_plan_info reports the width used), and thresholds
+ * above SS_MAX_E_PLANNED return SS_ELEN (the standalone wavefront kernel,
+ * ss_filter_wave_async, covers them up to SS_MAX_E).
  * ---------------------------------------------------------------------- */
 typedef struct ss_plan ss_plan;
 int ss_plan_create(ss_ctx* ctx, const int32_t* lengths, const int32_t* E_per_pair, int64_t n_pairs,
@@ -270,9 +276,10 @@ int64_t ss_server_footprint(int64_t n_pairs, int64_t total_bases);
 /* Submit one request (host arrays, copied before returning; E_per_pair is
  * required).  accept_out / edits_out (host, n_pairs entries) are written by
  * the server before the ticket reports done, and must stay valid until then.
- * SS_EBUDGET if the request alone needs more than the budget.  Validation of
- * lengths and thresholds happens here; the alphabet is checked on the device
- * and reported by ss_server_wait (outputs then untouched). */
+ * SS_EBUDGET if the request alone needs more than the budget; SS_ELEN for a
+ * threshold above SS_MAX_E_PLANNED.  Validation of lengths and thresholds
+ * happens here; the alphabet is checked on the device and reported by
+ * ss_server_wait (outputs then untouched). */
 int ss_server_submit(ss_server* server, const uint8_t* reads, const uint8_t* refs, const int32_t* lengths,
                      const int32_t* E_per_pair, int64_t n_pairs, uint8_t* accept_out, int32_t* edits_out,
                      ss_ticket* ticket);
@@ -294,7 +301,7 @@ int ss_server_set_hold(ss_server* server, int hold);
 /* Slice width (1, 2, 4 or 8 32-row slices per lane, default 1) used to plan
  * requests submitted from now on: fewer slices spread each pair over more
  * lanes and shorten the longest pair's sweep, which bounds a request's
- * latency. */
+ * latency.  A request whose largest threshold needs a wider slice gets it. */
 int ss_server_set_slices(ss_server* server, int32_t slices_per_lane);
 int ss_server_stats(ss_server* server, int64_t* admitted, int64_t* deferred, int64_t* completed,
                     int64_t* peak_bytes, int64_t* peak_in_flight);

@@ -24,6 +24,7 @@ SS_OK, SS_EINVAL, SS_EBASE, SS_ELEN, SS_ENOMEM, SS_EBUDGET, SS_EDEVICE, SS_EAGAI
 SS_MAX_E_SLICED = 32
 SS_MAX_E_PLAIN = 31
 SS_MAX_E = 16383
+SS_MAX_E_PLANNED = 8191
 SS_MAX_LEN_FUSED = 2048
 SS_RESULT_ACCEPT = 0x8000
 SS_RESULT_COUNT = 0x7FFF

@@ -83,9 +83,23 @@ __global__ __launch_bounds__(256) void k_persist(const PItem* __restrict__ items
 
 }  // namespace
 
-void plan_items(const int32_t* lengths, const int32_t* E, int64_t n, int rsmax, std::vector<PItem>& items,
+int plan_min_slices(const int32_t* E, int64_t n)
+{
+    int32_t emax = 0;
+    for (int64_t i = 0; i < n; i++) emax = std::max(emax, E[i]);
+    const int64_t slices = cdiv(2 * (int64_t)emax + 1, 32);
+    for (int rs = 1; rs <= 8; rs <<= 1)
+        if (64 * (int64_t)rs >= slices) return rs;
+    return 0;
+}
+
+bool plan_items(const int32_t* lengths, const int32_t* E, int64_t n, int rsmax, std::vector<PItem>& items,
                 std::vector<int64_t>& perm, int* n_classes, double* est_cost)
 {
+    items.clear();
+    perm.clear();
+    *n_classes = 0;
+    *est_cost = 0;
     // shape class per pair
     std::vector<int32_t> cls((size_t)n);
     std::map<std::pair<int, int>, int> class_id;
@@ -93,6 +107,7 @@ void plan_items(const int32_t* lengths, const int32_t* E, int64_t n, int rsmax, 
     for (int64_t i = 0; i < n; i++) {
         int lp, rs;
         wave::shape_for(E[i], rsmax, &lp, &rs);
+        if (lp > 64) return false;          // more rows than a wavefront holds at this width
         auto key = std::make_pair(lp, rs);
         auto it = class_id.find(key);
         int id;
@@ -155,6 +170,7 @@ void plan_items(const int32_t* lengths, const int32_t* E, int64_t n, int rsmax, 
     sorted.reserve(order.size());
     for (size_t k : order) sorted.push_back(items[k]);
     items.swap(sorted);
+    return true;
 }
 
 int persist_blocks_per_cu(int rsmax)
@@ -226,8 +242,8 @@ int map_err(hipError_t e)
 
 int build_plan(ss_plan* P, const int32_t* lengths, const int32_t* E, int64_t n)
 {
-    plan_items(lengths, E, n, P->cfg.rsmax, P->items, P->perm, &P->n_classes, &P->est_cost);
-    return SS_OK;
+    return plan_items(lengths, E, n, P->cfg.rsmax, P->items, P->perm, &P->n_classes, &P->est_cost) ? SS_OK
+                                                                                                     : SS_ELEN;
 }
 
 int upload_plan(ss_plan* P)
@@ -309,8 +325,10 @@ extern "C" int ss_plan_create(ss_ctx* ctx, const int32_t* lengths, const int32_t
     if (slices_per_lane != 1 && slices_per_lane != 2 && slices_per_lane != 4 && slices_per_lane != 8) return SS_EINVAL;
     int rc = validate_plan_inputs(lengths, E_per_pair, n_pairs);
     if (rc != SS_OK) return rc;
+    const int rsmin = plan_min_slices(E_per_pair, n_pairs);
+    if (rsmin == 0) return SS_ELEN;
     PlanCfg cfg;
-    cfg.rsmax = slices_per_lane;
+    cfg.rsmax = std::max<int>(slices_per_lane, rsmin);
     try {
         return make_plan(cfg, lengths, E_per_pair, n_pairs, out);
     } catch (const std::bad_alloc&) {
@@ -448,6 +466,8 @@ extern "C" int ss_plan_create_tuned(ss_ctx* ctx, const int32_t* lengths, const i
     int rc = validate_plan_inputs(lengths, E_per_pair, n_pairs);
     if (rc != SS_OK) return rc;
     if (n_pairs > 0 && (!packed || !offsets_dev || !lengths_dev || !E_dev || !out_dev)) return SS_EINVAL;
+    const int rsmin = plan_min_slices(E_per_pair, n_pairs);
+    if (rsmin == 0) return SS_ELEN;
     int dev = 0;
     (void)hipGetDevice(&dev);
     hipDeviceProp_t prop;
@@ -460,7 +480,7 @@ extern "C" int ss_plan_create_tuned(ss_ctx* ctx, const int32_t* lengths, const i
             auto it = m.find(key);
             if (it != m.end() && (it->second == 1 || it->second == 2 || it->second == 4 || it->second == 8)) {
                 PlanCfg cfg;
-                cfg.rsmax = it->second;
+                cfg.rsmax = std::max<int>(it->second, rsmin);
                 if (chosen_slices) *chosen_slices = cfg.rsmax;
                 return make_plan(cfg, lengths, E_per_pair, n_pairs, out);
             }
@@ -475,6 +495,7 @@ extern "C" int ss_plan_create_tuned(ss_ctx* ctx, const int32_t* lengths, const i
         (void)hipEventCreate(&a);
         (void)hipEventCreate(&b);
         for (int c : cands) {
+            if (c < rsmin) continue;        // too narrow for the largest threshold
             PlanCfg cfg;
             cfg.rsmax = c;
             ss_plan* P = nullptr;

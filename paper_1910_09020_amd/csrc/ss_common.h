@@ -51,8 +51,12 @@ struct PItem {
 static_assert(sizeof(PItem) == 24, "PItem layout");
 
 // Host planner: shape classes, sort, items ordered largest estimated cost first.
-void plan_items(const int32_t* lengths, const int32_t* E, int64_t n, int rsmax, std::vector<PItem>& items,
+// false (and no items) when some pair's rows do not fit 64 lanes x rsmax slices.
+bool plan_items(const int32_t* lengths, const int32_t* E, int64_t n, int rsmax, std::vector<PItem>& items,
                 std::vector<int64_t>& perm, int* n_classes, double* est_cost);
+// Smallest slice width (1, 2, 4 or 8) whose 64 lanes hold the 2E+1 rows of
+// every pair, or 0 when some E needs more than 8 (E > 8191).
+int plan_min_slices(const int32_t* E, int64_t n);
 // Resident blocks per CU of the persistent kernel for this slice width.
 int persist_blocks_per_cu(int rsmax);
 // Counter reset + persistent kernel on stream s.

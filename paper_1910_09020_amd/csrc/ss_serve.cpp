@@ -430,15 +430,23 @@ extern "C" int ss_server_submit(ss_server* S, const uint8_t* reads, const uint8_
             delete r;
             return SS_EBUDGET;
         }
+        const int rsmin = plan_min_slices(E_per_pair, n_pairs);
+        if (rsmin == 0) {
+            delete r;
+            return SS_ELEN;
+        }
         {
             std::lock_guard<std::mutex> lk(S->mu);
-            r->rsmax = S->rsmax;
+            r->rsmax = std::max(S->rsmax, rsmin);
         }
         std::vector<PItem> items;
         std::vector<int64_t> perm;
         int nc = 0;
         double cost = 0;
-        plan_items(lengths, E_per_pair, n_pairs, r->rsmax, items, perm, &nc, &cost);
+        if (!plan_items(lengths, E_per_pair, n_pairs, r->rsmax, items, perm, &nc, &cost)) {
+            delete r;
+            return SS_ELEN;
+        }
         r->n_items = (int64_t)items.size();
         const Layout L(n_pairs, T, r->n_items);
         const size_t need = stage_bytes(L, n_pairs);

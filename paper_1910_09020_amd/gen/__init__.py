@@ -55,6 +55,9 @@ def _load():
     lib.ssgen_fill.restype = ctypes.c_int
     lib.ssgen_arrivals.argtypes = [ctypes.c_uint64, ctypes.c_double, ctypes.c_double, vp, ctypes.c_int64]
     lib.ssgen_arrivals.restype = ctypes.c_int64
+    lib.ssgen_long_fill.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                    vp, vp]
+    lib.ssgen_long_fill.restype = ctypes.c_int
     lib.ssgen_request_pairs.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32]
     lib.ssgen_request_pairs.restype = ctypes.c_int32
     lib.ssgen_request_plan.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
@@ -113,6 +116,19 @@ def arrivals(seed: int, rate: float, duration: float) -> np.ndarray:
     t = np.empty(cnt, dtype=np.float64)
     lib.ssgen_arrivals(seed, rate, duration, _p(t), cnt)
     return t
+
+
+def long_pairs(n: int, m: int, bp_lo: int, bp_hi: int, seed: int = 1910090205) -> dict:
+    """n pairs of length m (back to back) at per-pair edit rates ~U[bp_lo, bp_hi] basis points
+    (the long-pair model at any length)."""
+    lib = _load()
+    reads = np.empty(n * m, dtype=np.uint8)
+    refs = np.empty(n * m, dtype=np.uint8)
+    rc = lib.ssgen_long_fill(seed, n, m, bp_lo, bp_hi, _p(reads), _p(refs))
+    if rc != 0:
+        raise ValueError("ssgen_long_fill: bad arguments")
+    return dict(n=n, reads=reads, refs=refs, offsets=np.arange(n, dtype=np.int64) * m,
+                lengths=np.full(n, m, np.int32), E=None)
 
 
 def request(seed: int, req: int, max_pairs: int = 4096, min_len: int = 100, max_len: int = 10000) -> dict:

@@ -333,6 +333,38 @@ int ssgen_request_fill(uint64_t seed, int64_t req, int32_t n, const int64_t* off
     return 0;
 }
 
+/* n long pairs of length m (pair i at byte i*m): per pair an edit rate
+ * ~U[bp_lo, bp_hi] basis points, round(rate*m/1e4) events, half substitutions,
+ * half indels of Geometric(1/2) length (the long-pair model of configuration 3
+ * at any length and rate range).  Pair i draws from stream i of the seed. */
+int ssgen_long_fill(uint64_t seed, int64_t n, int32_t m, int32_t bp_lo, int32_t bp_hi, uint8_t* reads,
+                    uint8_t* refs)
+{
+    if (n < 0 || m < 0 || bp_lo < 0 || bp_hi < bp_lo) return -1;
+    int evcap = m + 1;
+    edit_ev* ev = (edit_ev*)malloc(sizeof(edit_ev) * (size_t)evcap);
+    if (!ev) return -1;
+    for (int64_t i = 0; i < n; i++) {
+        rng_t r = rng_stream(seed ^ 0x10C4B9ULL, (uint64_t)i);
+        uint8_t* Q = reads + i * (int64_t)m;
+        uint8_t* R = refs + i * (int64_t)m;
+        rand_bases(&r, Q, m);
+        const int bp = bp_lo + (int)rng_below(&r, (uint64_t)(bp_hi - bp_lo + 1));
+        int k = (int)(((int64_t)bp * m + 5000) / 10000);
+        if (k > evcap) k = evcap;
+        for (int e = 0; e < k; e++) {
+            edit_ev* v = &ev[e];
+            v->ord = e; v->len = 1;
+            if (rng_below(&r, 2) == 0) v->type = EV_SUB;
+            else { v->type = rng_below(&r, 2) == 0 ? EV_INS : EV_DEL; v->len = rng_geom_half(&r); }
+            v->pos = (int)rng_below(&r, (uint64_t)(v->type == EV_INS ? m + 1 : m));
+        }
+        apply_events(&r, Q, m, ev, k, R);
+    }
+    free(ev);
+    return 0;
+}
+
 /* ---------------------------------------------------------------------------
  * Native load driver for serving benchmarks.
  *

@@ -132,3 +132,52 @@ def test_empty_plan(env):
     plan = ss.ss_plan_create(ctx, np.zeros(0, np.int32), np.zeros(0, np.int32), 8)
     assert ss.ss_plan_info(plan)["items"] == 0
     ss.ss_plan_destroy(plan)
+
+
+@pytest.mark.parametrize("E", [1000, 5000])
+def test_100kbp_pairs(env, E):
+    """Pairs of 100 kbp with thresholds up to 5% of the length (2E+1 = 10,001 rows at E = 5000: one
+    wavefront per pair, 64 lanes x 5 slices): the wavefront kernel and the planned persistent launch
+    against the oracle."""
+    ss, runner, torch = env
+    b = gen.long_pairs(8, 100_000, 300, 700)
+    b["E"] = np.array([E, E // 2, E, E // 5, E, E, E // 10, E], dtype=np.int32)
+    want = oracle.batch(b["reads"], b["refs"], b["offsets"], b["lengths"], E_per_pair=b["E"], threads=8)
+    assert 0 < int(want["accept"].sum()) < 8 or E == 1000     # both decisions occur at E = 5000
+    db = runner.DeviceBatch(b)
+    ps = db.pack_stream()
+    print(f"  wave m=100000 Emax={E}", flush=True)
+    out = db.filter_wave(ps, E, per_pair=True)
+    torch.cuda.synchronize()
+    _check(runner.results_numpy(out, db.n), (want["accept"], want["edits"]), f"wave E={E}")
+    for spl in (4, 8):
+        print(f"  planned m=100000 Emax={E} slices_per_lane={spl}", flush=True)
+        plan = ss.ss_plan_create(runner.context(), b["lengths"], b["E"], spl)
+        out = db.new_out()
+        ss.ss_filter_planned_async(runner.context(), plan, ps, db.total, db.offsets, db.lengths, db.E, out)
+        torch.cuda.synchronize()
+        _check(runner.results_numpy(out, db.n), (want["accept"], want["edits"]), f"planned E={E} spl={spl}")
+        ss.ss_plan_destroy(plan)
+
+
+def test_plan_width_raised_and_limit(env):
+    """A plan raises its slice width to hold the largest threshold's rows in one wavefront and
+    refuses thresholds beyond 64 lanes x 8 slices (SS_ELEN, nothing launched); so does the server."""
+    ss, runner, torch = env
+    ctx = runner.context()
+    lengths = np.array([1000, 2000], dtype=np.int32)
+    for E, want in ((31, 1), (2047, 2), (2048, 4), (5000, 8), (8191, 8)):
+        plan = ss.ss_plan_create(ctx, lengths, np.array([E, 3], dtype=np.int32), 1)
+        assert ss.ss_plan_info(plan)["slices_per_lane"] == want, E
+        ss.ss_plan_destroy(plan)
+    with pytest.raises(ss.SSError) as ei:
+        ss.ss_plan_create(ctx, lengths, np.array([8192, 3], dtype=np.int32), 8)
+    assert ei.value.status == ss.SS_ELEN
+    srv = ss.ss_server_create(ctx, 1 << 30, 2)
+    b = gen.concat([("ACGT" * 10, "ACGT" * 10)])
+    acc = np.zeros(1, np.uint8)
+    ed = np.zeros(1, np.int32)
+    with pytest.raises(ss.SSError) as ei:
+        ss.ss_server_submit(srv, b["reads"], b["refs"], b["lengths"], np.array([9000], np.int32), acc, ed)
+    assert ei.value.status == ss.SS_ELEN
+    ss.ss_server_destroy(srv)
