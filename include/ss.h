@@ -64,6 +64,7 @@ const char* ss_status_str(int status);
 #define SS_MAX_E_PLANNED  8191    /* batched launch and serving: 2E+1 rows in 64 lanes x 8 slices */
 #define SS_MAX_LEN        (1 << 24)
 #define SS_MAX_LEN_FUSED  2048    /* fused encode-and-filter kernel: m <= 2048 */
+#define SS_MAX_LEN_VERIFY 256     /* verification kernel: m <= 256 */
 
 /* Device result word, one per pair: bit 15 = accept, bits 0..14 = obstacle
  * count reported by the walk (min(count, E+1)). */
@@ -197,6 +198,33 @@ int ss_filter_wave_async(ss_ctx* ctx, const uint32_t* packed, int64_t total_base
                          const int64_t* offsets, const int32_t* lengths,
                          const int32_t* E_per_pair, int64_t n_pairs, int32_t E,
                          uint16_t* out, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Verification (not part of SneakySnake): the step a pre-alignment filter
+ * exists to shorten (Section 1: only accepted pairs go on to alignment;
+ * Section 3 measures the filter's false accept rate against the exact edit
+ * distance).  These compute the exact edit distance (unit-cost Levenshtein
+ * distance) of the pairs a filter accepted, on the GPU, so that a batch can
+ * be filtered and verified without leaving the device.
+ * ---------------------------------------------------------------------- */
+
+/* Exact edit distance of n pairs in the bit-stream layout (device arrays as
+ * for ss_filter_wave_async).  index: optional n pair indices (entry k
+ * verifies pair index[k]; NULL: pairs 0..n-1).  max_len >= every listed
+ * pair's length, <= SS_MAX_LEN_VERIFY (SS_ELEN beyond).  ed_out[k] (device,
+ * int32) = edit distance of the k-th listed pair.  One pair per lane, Myers'
+ * bit-vector algorithm (J. ACM 1999) in its global-distance form.
+ * Asynchronous on stream. */
+int ss_verify_async(ss_ctx* ctx, const uint32_t* packed, int64_t total_bases, const int64_t* offsets,
+                    const int32_t* lengths, const int64_t* index, int64_t n, int32_t max_len, int32_t* ed_out,
+                    void* stream);
+
+/* Indices of the accepted pairs of n result words (bit 15 set), written to
+ * index_out (device, room for n entries) in no particular order; their number
+ * to *count_out (device int64, cleared by this call with a kernel, not a
+ * memset).  Asynchronous on stream. */
+int ss_select_accepted_async(ss_ctx* ctx, const uint16_t* results, int64_t n, int64_t* index_out,
+                             int64_t* count_out, void* stream);
 
 /* ------------------------------------------------------------------------
  * Batched launch: pairs of uneven lengths with a threshold per pair, all in

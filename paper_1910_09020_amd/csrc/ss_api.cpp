@@ -189,6 +189,27 @@ extern "C" int ss_filter_ascii_async(ss_ctx* ctx, const uint8_t* reads, const ui
     return SS_OK;
 }
 
+extern "C" int ss_verify_async(ss_ctx* ctx, const uint32_t* packed, int64_t total_bases, const int64_t* offsets,
+                               const int32_t* lengths, const int64_t* index, int64_t n, int32_t max_len,
+                               int32_t* ed_out, void* stream)
+{
+    if (!ctx || n < 0 || total_bases < 0 || max_len < 0) return SS_EINVAL;
+    if (max_len > SS_MAX_LEN_VERIFY) return SS_ELEN;
+    if (n == 0) return SS_OK;
+    if (!packed || !offsets || !lengths || !ed_out) return SS_EINVAL;
+    return map_err(launch_verify(packed, ss_stream_words(total_bases), offsets, lengths, index, n, max_len, ed_out,
+                                 (hipStream_t)stream));
+}
+
+extern "C" int ss_select_accepted_async(ss_ctx* ctx, const uint16_t* results, int64_t n, int64_t* index_out,
+                                        int64_t* count_out, void* stream)
+{
+    if (!ctx || n < 0 || !count_out) return SS_EINVAL;
+    if (n > 0 && (!results || !index_out)) return SS_EINVAL;
+    return map_err(launch_select(results, n, index_out, reinterpret_cast<unsigned long long*>(count_out),
+                                 (hipStream_t)stream));
+}
+
 extern "C" int ss_pack_stream_async(ss_ctx* ctx, const uint8_t* reads, const uint8_t* refs, int64_t total_bases,
                                     uint32_t* packed, uint32_t* err, void* stream)
 {

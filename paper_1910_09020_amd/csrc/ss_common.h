@@ -33,6 +33,12 @@ hipError_t launch_plain(const uint32_t* packed, int64_t stream_words, const int6
 hipError_t launch_wave(const uint32_t* packed, int64_t stream_words, const int64_t* offsets,
                        const int32_t* lengths, const int32_t* Epp, int64_t n, int32_t E, uint16_t* out,
                        hipStream_t s);
+// Verification: exact edit distance of the listed pairs (bit-stream layout, m <= 256), and the
+// compaction of accepted pairs' indices.
+hipError_t launch_verify(const uint32_t* packed, int64_t stream_words, const int64_t* offsets, const int32_t* lengths,
+                         const int64_t* index, int64_t n, int32_t max_len, int32_t* ed_out, hipStream_t s);
+hipError_t launch_select(const uint16_t* results, int64_t n, int64_t* index_out, unsigned long long* count,
+                         hipStream_t s);
 hipError_t launch_unpack(const uint16_t* res, int64_t n, uint8_t* accept, int32_t* edits, hipStream_t s);
 
 // Lanes per pair and row slices per lane chosen by the wavefront kernel for a

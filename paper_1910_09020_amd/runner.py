@@ -8,7 +8,7 @@ from __future__ import annotations
 import numpy as np
 import torch
 
-from . import (ss_create, ss_filter_ascii_async, ss_filter_plain_async, ss_filter_sliced_async, ss_filter_wave_async,
+from . import (ss_create, ss_filter_ascii_async, ss_select_accepted_async, ss_verify_async, ss_filter_plain_async, ss_filter_sliced_async, ss_filter_wave_async,
                ss_pack_sliced_async, ss_pack_stream_async, ss_sliced_bytes, ss_stream_words)
 
 _ctx = {}
@@ -116,6 +116,26 @@ class DeviceBatch:
                              self.E if per_pair else None, self.n, E, out,
                              stream or torch.cuda.current_stream(self.device))
         return out
+
+
+    # ---- verification -----------------------------------------------------------
+    def verify(self, packed, index=None, n=None, max_len=None, out=None, stream=None) -> torch.Tensor:
+        """Exact edit distance of the listed pairs (all pairs when index is None), int32 per entry."""
+        n = (self.n if index is None else int(index.numel())) if n is None else n
+        max_len = int(self.lengths_np.max()) if max_len is None and self.n else (max_len or 0)
+        out = torch.empty(max(1, n), dtype=torch.int32, device=_dev(self.device)) if out is None else out
+        ss_verify_async(context(self.device), packed, self.total, self.offsets, self.lengths, index, n, max_len, out,
+                        stream or torch.cuda.current_stream(self.device))
+        return out
+
+    def select_accepted(self, results, index_out=None, count=None, stream=None):
+        """(index tensor, count tensor) of the pairs whose result word has the accept bit."""
+        d = _dev(self.device)
+        index_out = torch.empty(max(1, self.n), dtype=torch.int64, device=d) if index_out is None else index_out
+        count = torch.empty(1, dtype=torch.int64, device=d) if count is None else count
+        ss_select_accepted_async(context(self.device), results, self.n, index_out, count,
+                                 stream or torch.cuda.current_stream(self.device))
+        return index_out, count
 
 
 def results_numpy(out: torch.Tensor, n: int):
