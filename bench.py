@@ -79,6 +79,39 @@ def timed_loop(fns, steps, torch):
     return wall, per
 
 
+def verify_leg(torch, runner, db, out, n, E, steps):
+    """Filter then verify: exact edit distance (GPU) of every pair, the filter's false accept rate
+    against it, and the pipeline filter -> compact accepted -> verify accepted, against verifying
+    every pair (what the filter saves the aligner)."""
+    ps = db.pack_stream()
+    ed = db.verify(ps, max_len=db.uniform_m)
+    torch.cuda.synchronize()
+    _, (all_ms,) = timed_loop([lambda: db.verify(ps, max_len=db.uniform_m, out=ed)], steps, torch)
+    res = out
+    idx, cnt = db.select_accepted(res)
+    torch.cuda.synchronize()
+    k = int(cnt.item())
+    ved = torch.empty(max(1, k), dtype=torch.int32, device="cuda")
+    fused = lambda: db.filter_fused(E, out=res)
+    sel = lambda: db.select_accepted(res, index_out=idx, count=cnt)
+    ver = lambda: db.verify(ps, index=idx[:k], n=k, max_len=db.uniform_m, out=ved)
+    _, (f_ms, s_ms, v_ms) = timed_loop([fused, sel, ver], steps, torch)
+    acc = (res[:n].view(torch.int16).to(torch.int32) & 0x8000) != 0
+    far_num = int((acc & (ed[:n] > E)).sum().item())
+    far_den = int((ed[:n] > E).sum().item())
+    missed = int(((~acc) & (ed[:n] <= E)).sum().item())
+    pipe_ms = f_ms + s_ms + v_ms
+    log(f"verify: all {all_ms:.3f} ms; filter {f_ms:.3f} + select {s_ms:.3f} + verify {k} accepted {v_ms:.3f} ms; "
+        f"FAR {far_num}/{far_den}; false rejects {missed}")
+    r = dict(verify_all_ms=round(all_ms, 4), filter_ms=round(f_ms, 4), select_ms=round(s_ms, 4),
+             verify_accepted_ms=round(v_ms, 4), accepted=k, pipeline_ms=round(pipe_ms, 4),
+             speedup_vs_verify_all=all_ms / pipe_ms,
+             false_accept_rate=far_num / far_den if far_den else None, false_accepts=far_num,
+             pairs_over_E=far_den, false_rejects=missed)
+    del ps, ed, ved, idx, cnt
+    return r
+
+
 def sweep_leg(torch, ss, gen, runner, config, Es, steps, batch=None):
     """Threshold sweep on one resident batch: the two-kernel path encodes once and sweeps each E;
     the one-call path (fused up to E = 5, chunked above) runs per E.  Mean ms per launch."""
@@ -421,6 +454,8 @@ def main():
         log(f"plain: encode {ps_ms:.3f} ms filter {pf_ms:.3f} ms identical={plain['identical_outputs']}")
         del ps, pout
 
+    verify = None if a.no_sweep else verify_leg(torch, runner, db, out, n, E, max(3, a.steps // 2))
+
     # HBM calibration: a device-to-device copy of 2 GiB (reads and writes 2 GiB each)
     del db.reads, db.refs
     torch.cuda.empty_cache()
@@ -513,6 +548,7 @@ def main():
         "cpu_baseline": cpu,
         "hbm_copy_calibration_gbs": copy_gbs,
         "hbm_read_calibration_gbs": read_gbs,
+        "filter_then_verify": verify,
         "threshold_sweeps": sweeps,
         "latency_10k": latency,
         "long_100kbp": long_pairs,

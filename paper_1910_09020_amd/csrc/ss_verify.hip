@@ -77,18 +77,47 @@ __global__ __launch_bounds__(256) void k_verify(const uint32_t* __restrict__ pk,
 
 __global__ void k_zero_count(unsigned long long* count) { *count = 0ull; }
 
-// Indices of accepted pairs (result bit 15 set), in no particular order.
+// Indices of accepted pairs (result bit 15 set).  A block takes 4096 results
+// (16 per thread, in order), counts them with wavefront ballots and one LDS
+// scan over its four waves, takes its output range with a single atomic and
+// writes the indices in order; the blocks' ranges come in arrival order.
+constexpr int kSelPer = 16;
 __global__ __launch_bounds__(256) void k_select(const uint16_t* __restrict__ res, int64_t n,
                                                 int64_t* __restrict__ idx, unsigned long long* __restrict__ count)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool acc = i < n && (res[i] & 0x8000u);
-    const uint64_t bal = __ballot(acc);
-    const int lane = threadIdx.x & 63;
-    unsigned long long base = 0;
-    if (lane == 0 && bal) base = atomicAdd(count, (unsigned long long)__popcll(bal));
-    base = __shfl(base, 0);
-    if (acc) idx[base + __popcll(bal & ((1ull << lane) - 1ull))] = i;
+    __shared__ unsigned long long s_base;
+    __shared__ int s_wave[4];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int64_t i0 = ((int64_t)blockIdx.x * 256 + t) * kSelPer;
+    uint32_t bits = 0;
+#pragma unroll
+    for (int e = 0; e < kSelPer; e++) {
+        const int64_t i = i0 + e;
+        if (i < n && (res[i] & 0x8000u)) bits |= 1u << e;
+    }
+    const int mine = __popc(bits);
+    // inclusive scan of mine over the wavefront
+    int x = mine;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) s_wave[wv] = x;
+    __syncthreads();
+    if (t == 0) {
+        const int tot = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
+        s_base = tot ? atomicAdd(count, (unsigned long long)tot) : 0ull;
+    }
+    __syncthreads();
+    int before = x - mine;
+    for (int w = 0; w < wv; w++) before += s_wave[w];
+    unsigned long long o = s_base + (unsigned long long)before;
+    while (bits) {
+        const int e = __builtin_ctz(bits);
+        bits &= bits - 1u;
+        idx[o++] = i0 + e;
+    }
 }
 
 }  // namespace
@@ -118,7 +147,8 @@ hipError_t launch_select(const uint16_t* results, int64_t n, int64_t* index_out,
     // the counter is cleared by a kernel (no memset node if the caller captures the stream)
     hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, s, count);
     if (n > 0)
-        hipLaunchKernelGGL(k_select, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, s, results, n, index_out, count);
+        hipLaunchKernelGGL(k_select, dim3((unsigned)cdiv(n, 256 * kSelPer)), dim3(256), 0, s, results, n, index_out,
+                           count);
     return hipGetLastError();
 }
 
