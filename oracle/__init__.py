@@ -2,7 +2,8 @@
 
 Thin ctypes wrapper over ``oracle/ss_oracle.c``: the plain, per-cell CPU
 implementation of the chip maze (Equation 1, Section 2.3) and the greedy walk
-(Section 2.4), plus the two checkers that pin it (minimum-obstacle search over
+(Section 2.4), Snake-on-Chip's sub-maze decomposition of it (Section 2.5), plus
+the two checkers that pin it (minimum-obstacle search over
 all signal nets, Theorem 2; Levenshtein DP, the quantity the filter bounds from
 below, Sections 1 and 2.1).
 
@@ -60,6 +61,11 @@ def _load():
     lib.ss_oracle_min_obstacles_batch.restype = None
     lib.ss_oracle_levenshtein_batch.argtypes = [u8p, u8p, i64p, i32p, ctypes.c_int64, i32p]
     lib.ss_oracle_levenshtein_batch.restype = None
+    lib.ss_oracle_submaze.argtypes = [u8p, u8p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, i32p]
+    lib.ss_oracle_submaze.restype = ctypes.c_int
+    lib.ss_oracle_submaze_batch.argtypes = [u8p, u8p, i64p, i32p, ctypes.c_int64, ctypes.c_int, ctypes.c_int, u8p,
+                                            i32p]
+    lib.ss_oracle_submaze_batch.restype = None
     _lib = lib
     return lib
 
@@ -167,6 +173,28 @@ def min_obstacles_batch(reads, refs, offsets, lengths, E=0, E_per_pair=None) -> 
     _load().ss_oracle_min_obstacles_batch(_u8(np.ascontiguousarray(reads)), _u8(np.ascontiguousarray(refs)),
                                           _i64(offsets), _i32(lengths), n, _i32(E_per_pair), int(E), _i32(out))
     return out
+
+
+def submaze(R, Q, E: int, t: int, stop_early: bool = True):
+    """Snake-on-Chip decomposition (Section 2.5): sum of the greedy walk's counts over sub-mazes of
+    t columns.  Returns (accept, count)."""
+    r, q = _bytes(R), _bytes(Q)
+    assert len(r) == len(q)
+    n = ctypes.c_int32(0)
+    acc = _load().ss_oracle_submaze(_u8(r), _u8(q), len(r), int(E), int(t), 1 if stop_early else 0,
+                                    ctypes.byref(n))
+    return int(acc), int(n.value)
+
+
+def submaze_batch(reads, refs, offsets, lengths, E: int, t: int) -> dict:
+    n = len(lengths)
+    acc = np.zeros(n, dtype=np.uint8)
+    ed = np.zeros(n, dtype=np.int32)
+    lengths = np.ascontiguousarray(lengths, dtype=np.int32)
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    _load().ss_oracle_submaze_batch(_u8(np.ascontiguousarray(reads)), _u8(np.ascontiguousarray(refs)),
+                                    _i64(offsets), _i32(lengths), n, int(E), int(t), _u8(acc), _i32(ed))
+    return dict(accept=acc, edits=ed)
 
 
 def levenshtein_batch(reads, refs, offsets, lengths) -> np.ndarray:

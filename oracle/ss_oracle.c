@@ -13,6 +13,8 @@
  *   - the greedy SneakySnake walk of Section 2.4, steps (1)-(5), evaluating the
  *     maze implicitly: a row is examined from the checkpoint only up to its
  *     first obstacle (the "implicit chip maze" paragraph of Section 2.4);
+ *   - Snake-on-Chip's decomposition (Section 2.5): the same walk run on
+ *     non-overlapping sub-mazes of t columns, the counts summed;
  *   - two checkers used to pin the walk:
  *       * the minimum number of obstacles over every legal signal net, by an
  *         exhaustive dynamic programme over checkpoints (the quantity that
@@ -124,6 +126,55 @@ int ss_oracle_pair_ex(const uint8_t* R, const uint8_t* Q, int m, int E, int stop
 int ss_oracle_pair(const uint8_t* R, const uint8_t* Q, int m, int E, int32_t* edits, ss_oracle_stats* st)
 {
     return ss_oracle_pair_ex(R, Q, m, E, 1, edits, st, NULL, NULL, 0, NULL);
+}
+
+/* Snake-on-Chip's decomposition (Section 2.5): the maze is cut into
+ * non-overlapping sub-mazes of t consecutive columns (the last one may be
+ * narrower) and 2E+1 rows; each is solved on its own by the greedy walk of
+ * Section 2.4, whose first checkpoint is the sub-maze's first column and whose
+ * destination is its last column (a run reaching it counts no obstacle).
+ * Cells keep their Equation 1 values at their global positions.  The count is
+ * the sum over the sub-mazes; with stop_early the walk stops once the sum
+ * exceeds E (rejected pairs report E+1).  The paper's per-module limit (y
+ * instances per sub-maze) is a hardware parameter described in its missing
+ * supplement and is not modelled: every sub-maze is solved completely.
+ * Returns 1 for accept (sum <= E). */
+static int run_within(const uint8_t* R, const uint8_t* Q, int m, int E, int i, int c, int last)
+{
+    int L = 0;
+    while (c + L <= last && ss_oracle_cell(R, Q, m, E, i, c + L) == 0) L++;
+    return L;
+}
+
+int ss_oracle_submaze(const uint8_t* R, const uint8_t* Q, int m, int E, int t, int stop_early, int32_t* edits)
+{
+    int n = 0;
+    if (t < 1) t = 1;
+    for (int first = 1; first <= m && !(stop_early && n > E); first += t) {
+        const int last = first + t - 1 < m ? first + t - 1 : m;
+        int c = first;                                     /* the sub-maze's first checkpoint */
+        while (c <= last) {
+            int best = -1;
+            for (int i = 1; i <= 2 * E + 1; i++) {
+                int L = run_within(R, Q, m, E, i, c, last);
+                if (L > best) best = L;
+            }
+            int end = c + best;
+            if (end <= last) n++;                          /* the segment's obstacle */
+            c = end + 1;
+            if (stop_early && n > E) break;
+        }
+    }
+    if (edits) *edits = n;
+    return n <= E;
+}
+
+/* ss_oracle_submaze over a batch (pair i: reads/refs at offsets[i], lengths[i]). */
+void ss_oracle_submaze_batch(const uint8_t* reads, const uint8_t* refs, const int64_t* offsets, const int32_t* lengths,
+                             int64_t n, int E, int t, uint8_t* accept, int32_t* edits)
+{
+    for (int64_t i = 0; i < n; i++)
+        accept[i] = (uint8_t)ss_oracle_submaze(refs + offsets[i], reads + offsets[i], lengths[i], E, t, 1, &edits[i]);
 }
 
 /* Minimum number of obstacles over all legal signal nets (Section 2.2 rules on
