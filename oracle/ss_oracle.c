@@ -162,7 +162,7 @@ int ss_oracle_submaze(const uint8_t* R, const uint8_t* Q, int m, int E, int t, i
             int end = c + best;
             if (end <= last) n++;                          /* the segment's obstacle */
             c = end + 1;
-            if (stop_early && n > E) break;
+            if (stop_early && E < n) break;    /* the sum exceeds E */
         }
     }
     if (edits) *edits = n;
