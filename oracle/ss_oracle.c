@@ -148,9 +148,9 @@ static int run_within(const uint8_t* R, const uint8_t* Q, int m, int E, int i, i
 
 int ss_oracle_submaze(const uint8_t* R, const uint8_t* Q, int m, int E, int t, int stop_early, int32_t* edits)
 {
-    int n = 0;
+    int sum = 0;                                           /* obstacles over all sub-mazes */
     if (t < 1) t = 1;
-    for (int first = 1; first <= m && !(stop_early && n > E); first += t) {
+    for (int first = 1; first <= m && !(stop_early && sum > E); first += t) {
         const int last = first + t - 1 < m ? first + t - 1 : m;
         int c = first;                                     /* the sub-maze's first checkpoint */
         while (c <= last) {
@@ -160,13 +160,13 @@ int ss_oracle_submaze(const uint8_t* R, const uint8_t* Q, int m, int E, int t, i
                 if (L > best) best = L;
             }
             int end = c + best;
-            if (end <= last) n++;                          /* the segment's obstacle */
+            if (end <= last) sum++;                        /* the segment's obstacle */
             c = end + 1;
-            if (stop_early && E < n) break;    /* the sum exceeds E */
+            if (stop_early && E < sum) break;             /* the sum exceeds E */
         }
     }
-    if (edits) *edits = n;
-    return n <= E;
+    if (edits) *edits = sum;
+    return sum <= E;
 }
 
 /* ss_oracle_submaze over a batch (pair i: reads/refs at offsets[i], lengths[i]). */
