@@ -136,6 +136,18 @@ int ss_pack_sliced_async(ss_ctx* ctx, const uint8_t* reads, const uint8_t* refs,
 int ss_filter_sliced_async(ss_ctx* ctx, const uint32_t* packed, int64_t n_pairs, int32_t m,
                            int32_t E, uint16_t* out, void* stream);
 
+/* Snake-on-Chip's decomposition (Section 2.5) over a lane-sliced buffer: the
+ * maze is cut into non-overlapping sub-mazes of sub_width columns (>= 1; the
+ * last may be narrower) solved independently by the same walk, each starting
+ * at its own first column, and the obstacle counts are summed.  The sum never
+ * exceeds the whole-maze count (it underestimates; sub_width >= m gives
+ * ss_filter_sliced_async's result).  Result words as ss_filter_sliced_async
+ * (count saturated at E+1, accept iff sum <= E).  The paper's per-module
+ * limit of its FPGA design (y instances per sub-maze) is not modelled: every
+ * sub-maze is solved completely.  Asynchronous on stream. */
+int ss_filter_submaze_async(ss_ctx* ctx, const uint32_t* packed, int64_t n_pairs, int32_t m, int32_t E,
+                            int32_t sub_width, uint16_t* out, void* stream);
+
 /* Encode and filter in one call, for pairs of one length m stored back to
  * back (pair i at byte i*m of reads and of refs; device pointers).  The
  * results are identical to ss_pack_sliced_async followed by

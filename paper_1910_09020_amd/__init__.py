@@ -61,6 +61,7 @@ def lib():
         "ss_filter_sliced_async": ([vp, vp, i64, i32, i32, vp, vp], ctypes.c_int),
         "ss_filter_ascii_async": ([vp, vp, vp, i64, i32, i32, i32, vp, vp, vp], ctypes.c_int),
         "ss_verify_async": ([vp, vp, i64, vp, vp, vp, i64, i32, vp, vp], ctypes.c_int),
+        "ss_filter_submaze_async": ([vp, vp, i64, i32, i32, i32, vp, vp], ctypes.c_int),
         "ss_select_accepted_async": ([vp, vp, i64, vp, vp, vp], ctypes.c_int),
         "ss_pack_stream_async": ([vp, vp, vp, i64, vp, vp, vp], ctypes.c_int),
         "ss_filter_plain_async": ([vp, vp, i64, vp, vp, vp, i64, i32, vp, vp], ctypes.c_int),
@@ -100,7 +101,7 @@ def exported_symbols():
     return ["ss_status_str", "ss_filter_batch", "ss_filter_batch_var", "ss_create", "ss_destroy",
             "ss_sliced_bytes", "ss_stream_words", "ss_pack_sliced_async", "ss_filter_sliced_async",
             "ss_filter_ascii_async", "ss_pack_stream_async", "ss_filter_plain_async", "ss_filter_wave_async",
-            "ss_unpack_results_async", "ss_verify_async", "ss_select_accepted_async",
+            "ss_unpack_results_async", "ss_verify_async", "ss_select_accepted_async", "ss_filter_submaze_async",
             "ss_plan_create", "ss_plan_destroy", "ss_plan_info", "ss_filter_planned_async", "ss_plan_capture",
             "ss_plan_launch", "ss_plan_create_tuned", "ss_server_create", "ss_server_submit", "ss_server_poll",
             "ss_server_wait", "ss_server_times", "ss_server_cancel", "ss_server_release", "ss_server_set_hold",
@@ -202,6 +203,11 @@ def ss_filter_ascii_async(ctx, reads, refs, n_pairs, m, E, tile_groups, out, err
     _check(lib().ss_filter_ascii_async(ctx, _ptr(reads), _ptr(refs), int(n_pairs), int(m), int(E),
                                        int(tile_groups), _ptr(out), _ptr(err), _stream(stream)),
            "ss_filter_ascii_async")
+
+
+def ss_filter_submaze_async(ctx, packed, n_pairs, m, E, sub_width, out, stream=None):
+    _check(lib().ss_filter_submaze_async(ctx, _ptr(packed), int(n_pairs), int(m), int(E), int(sub_width), _ptr(out),
+                                         _stream(stream)), "ss_filter_submaze_async")
 
 
 def ss_verify_async(ctx, packed, total_bases, offsets, lengths, index, n, max_len, ed_out, stream=None):

@@ -210,6 +210,17 @@ extern "C" int ss_select_accepted_async(ss_ctx* ctx, const uint16_t* results, in
                                  (hipStream_t)stream));
 }
 
+extern "C" int ss_filter_submaze_async(ss_ctx* ctx, const uint32_t* packed, int64_t n_pairs, int32_t m, int32_t E,
+                                       int32_t sub_width, uint16_t* out, void* stream)
+{
+    if (!ctx || n_pairs < 0 || m < 0 || E < 0 || sub_width < 1) return SS_EINVAL;
+    if (E > SS_MAX_E_SLICED || m > SS_MAX_LEN) return SS_ELEN;
+    if (n_pairs == 0) return SS_OK;
+    if (!out || (m > 0 && !packed)) return SS_EINVAL;
+    if ((((uintptr_t)packed | (uintptr_t)out) & 15u) != 0) return SS_EINVAL;
+    return map_err(launch_sliced(packed, n_pairs, m, E, out, (hipStream_t)stream, sub_width));
+}
+
 extern "C" int ss_pack_stream_async(ss_ctx* ctx, const uint8_t* reads, const uint8_t* refs, int64_t total_bases,
                                     uint32_t* packed, uint32_t* err, void* stream)
 {

@@ -18,8 +18,9 @@ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 hipError_t launch_pack_sliced(const uint8_t* reads, const uint8_t* refs, const int64_t* offsets,
                               const int64_t* index, int64_t n_pairs, int32_t m, uint32_t* packed,
                               uint32_t* err, hipStream_t s);
+// sub_width > 0: Snake-on-Chip sub-mazes of that many columns (Section 2.5)
 hipError_t launch_sliced(const uint32_t* packed, int64_t n_pairs, int32_t m, int32_t E, uint16_t* out,
-                         hipStream_t s);
+                         hipStream_t s, int sub_width = 0);
 // Fused encode + sweep of pairs stored back to back (pair i at byte i*m).
 // tile_groups: groups of 32 pairs per block (0: automatic).
 hipError_t launch_fused(const uint8_t* reads, const uint8_t* refs, int64_t n_pairs, int32_t m, int32_t E,

@@ -99,9 +99,12 @@ __global__ __launch_bounds__(256) void k_pack_tile(const uint8_t* __restrict__ r
 
 }  // namespace
 
-hipError_t launch_sliced_lo(int E, const uint32_t* packed, int64_t n, int32_t m, uint16_t* out, hipStream_t s);
-hipError_t launch_sliced_mid(int E, const uint32_t* packed, int64_t n, int32_t m, uint16_t* out, hipStream_t s);
-hipError_t launch_sliced_hi(int E, const uint32_t* packed, int64_t n, int32_t m, uint16_t* out, hipStream_t s);
+hipError_t launch_sliced_lo(int E, const uint32_t* packed, int64_t n, int32_t m, int sub_width, uint16_t* out,
+                           hipStream_t s);
+hipError_t launch_sliced_mid(int E, const uint32_t* packed, int64_t n, int32_t m, int sub_width, uint16_t* out,
+                           hipStream_t s);
+hipError_t launch_sliced_hi(int E, const uint32_t* packed, int64_t n, int32_t m, int sub_width, uint16_t* out,
+                           hipStream_t s);
 hipError_t launch_fused_lo(int E, const uint8_t* reads, const uint8_t* refs, int64_t n, int32_t m, int T, int GB,
                           int fast, size_t shmem, uint16_t* out, uint32_t* err, hipStream_t s);
 hipError_t launch_fused_mid(int E, const uint8_t* reads, const uint8_t* refs, int64_t n, int32_t m, int T, int GB,
@@ -135,13 +138,13 @@ hipError_t launch_pack_sliced(const uint8_t* reads, const uint8_t* refs, const i
 }
 
 hipError_t launch_sliced(const uint32_t* packed, int64_t n_pairs, int32_t m, int32_t E, uint16_t* out,
-                         hipStream_t s)
+                         hipStream_t s, int sub_width)
 {
     if (n_pairs == 0) return hipSuccess;
     if (E < 0 || E > kMaxESliced) return hipErrorInvalidValue;
-    if (E <= 10) return launch_sliced_lo(E, packed, n_pairs, m, out, s);
-    if (E <= 20) return launch_sliced_mid(E, packed, n_pairs, m, out, s);
-    return launch_sliced_hi(E, packed, n_pairs, m, out, s);
+    if (E <= 10) return launch_sliced_lo(E, packed, n_pairs, m, sub_width, out, s);
+    if (E <= 20) return launch_sliced_mid(E, packed, n_pairs, m, sub_width, out, s);
+    return launch_sliced_hi(E, packed, n_pairs, m, sub_width, out, s);
 }
 
 // Tile shape of the fused kernel: T groups per block, staged GB at a time.

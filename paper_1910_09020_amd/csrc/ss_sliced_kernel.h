@@ -56,6 +56,13 @@ struct SweepState {
         for (int l = 0; l <= E; l++) T[l] = 0u;
     }
 
+    // a new checkpoint without an obstacle: every row free again (a sub-maze boundary)
+    __device__ __forceinline__ void restart()
+    {
+#pragma unroll
+        for (int r = 0; r < NR; r++) S[r] = ~0u;
+    }
+
     // S[r] holds a_r for the column just processed; any = OR of them.
     __device__ __forceinline__ void close_column(uint32_t any)
     {
@@ -101,10 +108,14 @@ enum { MAIN_CIRC = 0, MAIN_SHIFT4 = 1 };
 //   MAIN_CIRC  : slot = chunk mod W with the loop unrolled W chunks, so every
 //                register index is static and the window never moves;
 //   MAIN_SHIFT4: four chunks per step, the window shifts by four chunks.
-template <int E, int MODE, class LD>
+template <int E, int MODE, bool SUB = false, class LD>
 __device__ __forceinline__ void sweep_group(LD&& ld, int m, int64_t g, int64_t n_pairs,
-                                            uint16_t* __restrict__ out)
+                                            uint16_t* __restrict__ out, int sub_width = 0)
 {
+    // SUB: Snake-on-Chip's decomposition (Section 2.5): at every multiple of
+    // sub_width the walk restarts from a new checkpoint, so each sub-maze of
+    // sub_width columns is solved on its own and the counts add up
+    int next_sub = SUB ? sub_width : 0x7FFFFFFF;
     constexpr int B = kChunk;
     constexpr int EC = (E + B - 1) / B;
     constexpr int W = 2 * EC + 1;
@@ -134,6 +145,7 @@ __device__ __forceinline__ void sweep_group(LD&& ld, int m, int64_t g, int64_t n
             for (int t = 0; t < B; t++) {
                 const int j = B * c0 + t;
                 if (j >= m) break;
+                if (SUB && j == next_sub) { st.restart(); next_sub += sub_width; }
                 st.column(comp(rr0, t), comp(rr1, t),
                           [&](int r) { const int o = t + r - E, d = floordiv(o, B); return w0[EC + d][o - d * B]; },
                           [&](int r) { const int o = t + r - E, d = floordiv(o, B); return w1[EC + d][o - d * B]; },
@@ -167,6 +179,7 @@ __device__ __forceinline__ void sweep_group(LD&& ld, int m, int64_t g, int64_t n
                         const uint4 rr0 = ld(2, c0), rr1 = ld(3, c0);
 #pragma unroll
                         for (int t = 0; t < B; t++) {
+                            if (SUB && B * c0 + t == next_sub) { st.restart(); next_sub += sub_width; }
                             st.column(comp(rr0, t), comp(rr1, t),
                                       [&](int r) { const int o = t + r - E, d = floordiv(o, B); return q0w[(u + d + 2 * W) % W][o - d * B]; },
                                       [&](int r) { const int o = t + r - E, d = floordiv(o, B); return q1w[(u + d + 2 * W) % W][o - d * B]; },
@@ -194,6 +207,7 @@ __device__ __forceinline__ void sweep_group(LD&& ld, int m, int64_t g, int64_t n
                     if (cb + u < ct) {
 #pragma unroll
                         for (int t = 0; t < B; t++) {
+                            if (SUB && B * (cb + u) + t == next_sub) { st.restart(); next_sub += sub_width; }
                             st.column(comp(rr0[u], t), comp(rr1[u], t),
                                       [&](int r) { const int o = t + r - E, d = floordiv(o, B); return q0w[EC + u + d][o - d * B]; },
                                       [&](int r) { const int o = t + r - E, d = floordiv(o, B); return q1w[EC + u + d][o - d * B]; },
@@ -248,9 +262,9 @@ __device__ __forceinline__ void sweep_group(LD&& ld, int m, int64_t g, int64_t n
     }
 }
 
-template <int E, int MODE>
+template <int E, int MODE, bool SUB>
 __global__ __launch_bounds__(256) void k_sliced(const uint32_t* __restrict__ pk, int64_t G, int m,
-                                                int64_t n_pairs, uint16_t* __restrict__ out)
+                                                int64_t n_pairs, uint16_t* __restrict__ out, int sub_width)
 {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= G) return;
@@ -258,11 +272,11 @@ __global__ __launch_bounds__(256) void k_sliced(const uint32_t* __restrict__ pk,
     const int64_t cstride = G * kChunk;
     const int64_t pstride = (int64_t)nch * cstride;
     const uint32_t* __restrict__ base = pk + g * kChunk;
-    sweep_group<E, MODE>(
+    sweep_group<E, MODE, SUB>(
         [&](int plane, int c) -> uint4 {
             return *reinterpret_cast<const uint4*>(base + plane * pstride + (int64_t)c * cstride);
         },
-        m, g, n_pairs, out);
+        m, g, n_pairs, out, sub_width);
 }
 
 // Fused encode and sweep.  Tiles of T consecutive groups are dealt to the
@@ -351,13 +365,19 @@ __global__ __launch_bounds__(256) void k_fused(const uint8_t* __restrict__ reads
 }
 
 template <int E>
-hipError_t launch_sliced_E(const uint32_t* packed, int64_t n_pairs, int32_t m, uint16_t* out, hipStream_t s)
+hipError_t launch_sliced_E(const uint32_t* packed, int64_t n_pairs, int32_t m, int sub_width, uint16_t* out,
+                           hipStream_t s)
 {
     const int64_t G = cdiv(n_pairs, 32);
     const int threads = 256;
     const int64_t blocks = cdiv(G, threads);
     constexpr int mode = E <= 10 ? MAIN_CIRC : MAIN_SHIFT4;
-    hipLaunchKernelGGL((k_sliced<E, mode>), dim3((unsigned)blocks), dim3(threads), 0, s, packed, G, m, n_pairs, out);
+    if (sub_width > 0 && sub_width < m)
+        hipLaunchKernelGGL((k_sliced<E, mode, true>), dim3((unsigned)blocks), dim3(threads), 0, s, packed, G, m,
+                           n_pairs, out, sub_width);
+    else
+        hipLaunchKernelGGL((k_sliced<E, mode, false>), dim3((unsigned)blocks), dim3(threads), 0, s, packed, G, m,
+                           n_pairs, out, 0);
     return hipGetLastError();
 }
 
@@ -399,10 +419,11 @@ struct FusedTable {
 
 template <int... Es>
 struct SlicedTable {
-    static hipError_t run(int E, const uint32_t* packed, int64_t n, int32_t m, uint16_t* out, hipStream_t s)
+    static hipError_t run(int E, const uint32_t* packed, int64_t n, int32_t m, int sub_width, uint16_t* out,
+                          hipStream_t s)
     {
         hipError_t r = hipErrorInvalidValue;
-        ((E == Es ? (r = launch_sliced_E<Es>(packed, n, m, out, s), 0) : 0), ...);
+        ((E == Es ? (r = launch_sliced_E<Es>(packed, n, m, sub_width, out, s), 0) : 0), ...);
         return r;
     }
 };

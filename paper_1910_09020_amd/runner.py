@@ -8,7 +8,7 @@ from __future__ import annotations
 import numpy as np
 import torch
 
-from . import (ss_create, ss_filter_ascii_async, ss_select_accepted_async, ss_verify_async, ss_filter_plain_async, ss_filter_sliced_async, ss_filter_wave_async,
+from . import (ss_create, ss_filter_ascii_async, ss_filter_submaze_async, ss_select_accepted_async, ss_verify_async, ss_filter_plain_async, ss_filter_sliced_async, ss_filter_wave_async,
                ss_pack_sliced_async, ss_pack_stream_async, ss_sliced_bytes, ss_stream_words)
 
 _ctx = {}
@@ -92,6 +92,13 @@ class DeviceBatch:
         out = self.new_out(n) if out is None else out
         ss_filter_sliced_async(context(self.device), packed, n, m, E, out,
                                stream or torch.cuda.current_stream(self.device))
+        return out
+
+    def filter_submaze(self, packed, E: int, sub_width: int, out=None, stream=None) -> torch.Tensor:
+        """Snake-on-Chip sub-mazes of sub_width columns over the lane-sliced encoding."""
+        out = self.new_out() if out is None else out
+        ss_filter_submaze_async(context(self.device), packed, self.n, self.uniform_m, E, sub_width, out,
+                                stream or torch.cuda.current_stream(self.device))
         return out
 
     def filter_fused(self, E: int, out=None, tile_groups: int = 0, stream=None) -> torch.Tensor:
