@@ -155,11 +155,10 @@ extern "C" int ss_filter_sliced_async(ss_ctx* ctx, const uint32_t* packed, int64
     return map_err(launch_sliced(packed, n_pairs, m, E, out, (hipStream_t)stream));
 }
 
-// Thresholds up to this run the fused kernel; above it, where the sweep's
-// registers leave the fused kernel too few waves, encode and sweep run as two
-// kernels over chunks whose packed form (about 400 MB) stays in the device's
-// cache between the two.
-constexpr int32_t kFusedMaxE = 5;
+// Thresholds up to kMaxEFused run the fused kernel; above it, where the
+// sweep's registers leave the fused kernel too few waves, encode and sweep run
+// as two kernels over chunks whose packed form (about 400 MB) stays in the
+// device's cache between the two.
 constexpr int64_t kChunkPackedBytes = 400ll << 20;
 
 extern "C" int ss_filter_ascii_async(ss_ctx* ctx, const uint8_t* reads, const uint8_t* refs, int64_t n_pairs,
@@ -174,7 +173,7 @@ extern "C" int ss_filter_ascii_async(ss_ctx* ctx, const uint8_t* reads, const ui
     int T = 0, GB = 0;
     if (fused_shape(m, tile_groups, &T, &GB) == 0) return SS_EINVAL;
     const hipStream_t s = (hipStream_t)stream;
-    if (E <= kFusedMaxE || m == 0)
+    if (E <= kMaxEFused)
         return map_err(launch_fused(reads, refs, n_pairs, m, E, tile_groups, out, err, s));
     // chunks of whole groups; slot offsets keep the encoder's and the sweep's alignment
     const int64_t per_pair = std::max<int64_t>(1, ss_sliced_bytes(32, m) / 32);

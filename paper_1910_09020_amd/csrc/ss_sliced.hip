@@ -107,10 +107,6 @@ hipError_t launch_sliced_hi(int E, const uint32_t* packed, int64_t n, int32_t m,
                            hipStream_t s);
 hipError_t launch_fused_lo(int E, const uint8_t* reads, const uint8_t* refs, int64_t n, int32_t m, int T, int GB,
                           int fast, size_t shmem, uint16_t* out, uint32_t* err, hipStream_t s);
-hipError_t launch_fused_mid(int E, const uint8_t* reads, const uint8_t* refs, int64_t n, int32_t m, int T, int GB,
-                           int fast, size_t shmem, uint16_t* out, uint32_t* err, hipStream_t s);
-hipError_t launch_fused_hi(int E, const uint8_t* reads, const uint8_t* refs, int64_t n, int32_t m, int T, int GB,
-                          int fast, size_t shmem, uint16_t* out, uint32_t* err, hipStream_t s);
 
 hipError_t launch_pack_sliced(const uint8_t* reads, const uint8_t* refs, const int64_t* offsets,
                               const int64_t* index, int64_t n_pairs, int32_t m, uint32_t* packed,
@@ -155,14 +151,17 @@ size_t fused_shape(int32_t m, int tile_groups, int* T_out, int* GB_out)
     const int64_t stage_b = (int64_t)tile::stage_dwords(m) * 4;
     const int64_t pk_b = 16 * 4 * mw;                     // four planes of 16-byte chunks per group
     auto lds_for = [&](int64_t T, int64_t GB) { return ((GB * stage_b + 15) & ~(int64_t)15) + T * pk_b; };
+    // staging groups: the most whose bytes the fused kernel's loads cover (so the streaming path
+    // applies), and whose staging fits 32 KiB
     int GB = 8;
-    while (GB > 1 && GB * stage_b > 32768) GB >>= 1;
+    while (GB > 1 && (GB * stage_b > 32768 || tile::fast_mode(m, GB, true, tile::kFusedQ) == 0)) GB >>= 1;
     int T = tile_groups;
     if (T <= 0) {
-        // largest multiple of GB that keeps two blocks per CU
+        // largest multiple of GB that keeps two blocks per CU, else one
         T = 0;
-        for (int t = GB; t <= 256; t += GB)
-            if (2 * lds_for(t, GB) <= kMaxFusedLds) T = t;
+        for (int blocks = 2; blocks >= 1 && T == 0; blocks--)
+            for (int t = GB; t <= 256; t += GB)
+                if (blocks * lds_for(t, GB) <= kMaxFusedLds) T = t;
         if (T == 0) T = GB;
     } else {
         if (T > 256) return 0;
@@ -179,14 +178,12 @@ hipError_t launch_fused(const uint8_t* reads, const uint8_t* refs, int64_t n_pai
                         int tile_groups, uint16_t* out, uint32_t* err, hipStream_t s)
 {
     if (n_pairs == 0) return hipSuccess;
-    if (E < 0 || E > kMaxESliced) return hipErrorInvalidValue;
+    if (E < 0 || E > kMaxEFused) return hipErrorInvalidValue;
     int T = 0, GB = 0;
     const size_t shmem = fused_shape(m, tile_groups, &T, &GB);
     if (shmem == 0) return hipErrorInvalidValue;
-    const int fast = tile::fast_mode(m, GB, (((uintptr_t)reads | (uintptr_t)refs) & 15u) == 0);
-    if (E <= 10) return launch_fused_lo(E, reads, refs, n_pairs, m, T, GB, fast, shmem, out, err, s);
-    if (E <= 20) return launch_fused_mid(E, reads, refs, n_pairs, m, T, GB, fast, shmem, out, err, s);
-    return launch_fused_hi(E, reads, refs, n_pairs, m, T, GB, fast, shmem, out, err, s);
+    const int fast = tile::fast_mode(m, GB, (((uintptr_t)reads | (uintptr_t)refs) & 15u) == 0, tile::kFusedQ);
+    return launch_fused_lo(E, reads, refs, n_pairs, m, T, GB, fast, shmem, out, err, s);
 }
 
 }  // namespace ss

@@ -1,4 +1,4 @@
-// Column-sweep and fused encode-and-sweep kernels for thresholds E = 21..32.
+// Column-sweep kernels for thresholds E = 21..32.
 #include "ss_sliced_kernel.h"
 
 namespace ss {
@@ -7,13 +7,6 @@ hipError_t launch_sliced_hi(int E, const uint32_t* packed, int64_t n, int32_t m,
                            hipStream_t s)
 {
     return sliced::SlicedTable<21, 22, 23, 24, 25, 26, 27, 28, 29, 30, 31, 32>::run(E, packed, n, m, sub_width, out, s);
-}
-
-hipError_t launch_fused_hi(int E, const uint8_t* reads, const uint8_t* refs, int64_t n, int32_t m, int T, int GB,
-                          int fast, size_t shmem, uint16_t* out, uint32_t* err, hipStream_t s)
-{
-    return sliced::FusedTable<21, 22, 23, 24, 25, 26, 27, 28, 29, 30, 31, 32>::run(E, reads, refs, n, m, T, GB, fast,
-                                                                                     shmem, out, err, s);
 }
 
 }  // namespace ss

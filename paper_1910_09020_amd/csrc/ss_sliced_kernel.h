@@ -313,12 +313,12 @@ __global__ __launch_bounds__(256) void k_fused(const uint8_t* __restrict__ reads
     // one step: encode the current GB groups from cur while the next groups'
     // loads (possibly of the block's next tile) run; after a tile's last
     // groups, sweep it; false when the block is done
-    auto step = [&](const uint4 (&cur)[2][tile::kQ], uint4 (&nxt)[2][tile::kQ]) -> bool {
+    auto step = [&](const uint4 (&cur)[2][tile::kFusedQ], uint4 (&nxt)[2][tile::kFusedQ]) -> bool {
         int64_t tn = tl;
         int bn = sb;
         advance(tn, bn);
-        tile::load_groups(reads, refs, n_pairs, m, tn * T + bn, GB, fast && tn < ntiles, nxt);
-        tile::encode_groups(reads, refs, nullptr, nullptr, n_pairs, m, tl * T + sb, GB, fast, cur, lds, pk4, T, sb,
+        tile::load_groups<tile::kFusedQ>(reads, refs, n_pairs, m, tn * T + bn, GB, fast && tn < ntiles, nxt);
+        tile::encode_groups<tile::kFusedQ>(reads, refs, nullptr, nullptr, n_pairs, m, tl * T + sb, GB, fast, cur, lds, pk4, T, sb,
                             bad);
         if (tn != tl) {
             const int gl = threadIdx.x;
@@ -332,8 +332,8 @@ __global__ __launch_bounds__(256) void k_fused(const uint8_t* __restrict__ reads
         return tl < ntiles;
     };
     if constexpr (MODE == MAIN_CIRC) {
-        uint4 va[2][tile::kQ], vb[2][tile::kQ];
-        tile::load_groups(reads, refs, n_pairs, m, tl * T, GB, fast != 0, va);
+        uint4 va[2][tile::kFusedQ], vb[2][tile::kFusedQ];
+        tile::load_groups<tile::kFusedQ>(reads, refs, n_pairs, m, tl * T, GB, fast != 0, va);
         for (;;) {
             if (!step(va, vb)) break;
             if (!step(vb, va)) break;
@@ -342,9 +342,9 @@ __global__ __launch_bounds__(256) void k_fused(const uint8_t* __restrict__ reads
         // larger thresholds: the sweep's window already takes most registers,
         // so one load buffer (no loads in flight across a step)
         for (;;) {
-            uint4 v[2][tile::kQ];
-            tile::load_groups(reads, refs, n_pairs, m, tl * T + sb, GB, fast != 0, v);
-            tile::encode_groups(reads, refs, nullptr, nullptr, n_pairs, m, tl * T + sb, GB, fast, v, lds, pk4, T,
+            uint4 v[2][tile::kFusedQ];
+            tile::load_groups<tile::kFusedQ>(reads, refs, n_pairs, m, tl * T + sb, GB, fast != 0, v);
+            tile::encode_groups<tile::kFusedQ>(reads, refs, nullptr, nullptr, n_pairs, m, tl * T + sb, GB, fast, v, lds, pk4, T,
                                 sb, bad);
             int64_t tn = tl;
             int bn = sb;

@@ -1,4 +1,4 @@
-// Column-sweep and fused encode-and-sweep kernels for thresholds E = 11..20.
+// Column-sweep kernels for thresholds E = 11..20.
 #include "ss_sliced_kernel.h"
 
 namespace ss {
@@ -7,12 +7,6 @@ hipError_t launch_sliced_mid(int E, const uint32_t* packed, int64_t n, int32_t m
                            hipStream_t s)
 {
     return sliced::SlicedTable<11, 12, 13, 14, 15, 16, 17, 18, 19, 20>::run(E, packed, n, m, sub_width, out, s);
-}
-
-hipError_t launch_fused_mid(int E, const uint8_t* reads, const uint8_t* refs, int64_t n, int32_t m, int T, int GB,
-                          int fast, size_t shmem, uint16_t* out, uint32_t* err, hipStream_t s)
-{
-    return sliced::FusedTable<11, 12, 13, 14, 15, 16, 17, 18, 19, 20>::run(E, reads, refs, n, m, T, GB, fast, shmem, out, err, s);
 }
 
 }  // namespace ss

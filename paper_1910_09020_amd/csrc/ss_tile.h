@@ -28,17 +28,18 @@ __device__ __forceinline__ uint32_t codes4(uint32_t x, uint32_t& bad)
     return cc;
 }
 
-constexpr int kQ = 8;      // 16-byte loads per thread and side on the fast path
+constexpr int kQ = 8;      // 16-byte loads per thread and side on the standalone encoder's fast path
+constexpr int kFusedQ = 8; // the same in the fused kernel (4 loads and three blocks per CU measured slower)
 
 // Encoder mode for GB groups of pairs of length m stored back to back from
 // 16-byte aligned bases (contiguous), else 0: 1 when m % 4 == 0 and each side
 // of the GB groups fits 256 * kQ sixteen-byte loads, 2 when m % 4 != 0 and the
 // raw bytes fit them as well.
-__host__ __device__ inline int fast_mode(int m, int GB, bool contiguous)
+__host__ __device__ inline int fast_mode(int m, int GB, bool contiguous, int kq = kQ)
 {
     if (!contiguous || m <= 0) return 0;
     const int64_t bytes = 32ll * GB * (m % 4 == 0 ? m : 4 * ((m + 3) / 4));
-    if (bytes > 256ll * kQ * 16) return 0;
+    if (bytes > 256ll * kq * 16) return 0;
     return m % 4 == 0 ? 1 : 2;
 }
 
@@ -49,9 +50,10 @@ __host__ __device__ inline int fast_mode(int m, int GB, bool contiguous)
 // (straight-line code keeps all of them in flight together, and a caller can
 // issue the next groups' loads before consuming these).  present == false
 // issues loads over an empty range (nothing is read).
+template <int KQ = kQ>
 __device__ __forceinline__ void load_groups(const uint8_t* __restrict__ reads, const uint8_t* __restrict__ refs,
                                             int64_t n_pairs, int m, int64_t g0, int GB, bool present,
-                                            uint4 (&v)[2][kQ])
+                                            uint4 (&v)[2][KQ])
 {
     const int64_t s0 = g0 * 32;
     const int np = present ? (int)min((int64_t)32 * GB, n_pairs - s0) : 0;
@@ -62,7 +64,7 @@ __device__ __forceinline__ void load_groups(const uint8_t* __restrict__ reads, c
         const __amdgpu_buffer_rsrc_t rs =
             __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(base), (short)0, nbytes, 0x00020000);
 #pragma unroll
-        for (int k = 0; k < kQ; k++)
+        for (int k = 0; k < KQ; k++)
             v[sd][k] = __builtin_bit_cast(
                 uint4, __builtin_amdgcn_raw_buffer_load_b128(rs, 16 * (threadIdx.x + 256 * k), 0, 0));
     }
@@ -79,10 +81,11 @@ __device__ __forceinline__ void load_groups(const uint8_t* __restrict__ reads, c
 // staged per slot row), 2 otherwise (raw bytes staged in source order, read
 // back per slot and chunk with a byte-align).  Every thread of the block must
 // call this (it synchronises the block).
+template <int KQ = kQ>
 __device__ __forceinline__ void encode_groups(const uint8_t* __restrict__ reads, const uint8_t* __restrict__ refs,
                                               const int64_t* __restrict__ offsets,
                                               const int64_t* __restrict__ index, int64_t n_pairs, int m,
-                                              int64_t g0, int GB, int fast, const uint4 (&v)[2][kQ],
+                                              int64_t g0, int GB, int fast, const uint4 (&v)[2][KQ],
                                               uint32_t* __restrict__ stage, uint4* __restrict__ out4,
                                               int64_t ostride, int64_t obase, uint32_t& bad)
 {
@@ -111,7 +114,7 @@ __device__ __forceinline__ void encode_groups(const uint8_t* __restrict__ reads,
             // raw bytes in source order; the bytes past the last whole 16 one at a time
             const int nb = np * m, nq16 = nb >> 4;
 #pragma unroll
-            for (int k = 0; k < kQ; k++) {
+            for (int k = 0; k < KQ; k++) {
                 const int q = t + 256 * k;
                 if (q < nq16) reinterpret_cast<uint4*>(stage)[q] = v[side][k];
             }
@@ -119,7 +122,7 @@ __device__ __forceinline__ void encode_groups(const uint8_t* __restrict__ reads,
             for (int i = 16 * nq16 + t; i < nb; i += 256) reinterpret_cast<uint8_t*>(stage)[i] = sb[i];
         } else if (fast) {
 #pragma unroll
-            for (int k = 0; k < kQ; k++) {
+            for (int k = 0; k < KQ; k++) {
                 const int q = t + 256 * k;
                 if (q < nq) {
                     uint4* __restrict__ dst = reinterpret_cast<uint4*>(stage) + q + (int)__umulhi((uint32_t)q, r16);
