@@ -81,10 +81,10 @@ def test_ragged_batch_sizes(rt, n):
         check(f"n={n} E={E}", rt.results_numpy(out, n), want(b, E))
 
 
-@pytest.mark.parametrize("m", [1, 2, 3, 5, 36, 100, 128, 132, 250, 1000, 2048])
+@pytest.mark.parametrize("m", [0, 1, 2, 3, 5, 36, 100, 128, 132, 250, 1000, 2048])
 def test_lengths_and_thresholds(rt, m):
     import torch
-    n = max(40, min(2000, 200000 // m))
+    n = max(40, min(2000, 200000 // max(m, 1)))
     b = uniform(m, n, seed=m)
     db = rt.DeviceBatch(b)
     for E in (0, 3, 10, 25, 32):
@@ -137,3 +137,24 @@ def test_argument_errors(rt):
     assert call(10, 100, 5, 200) == ss.SS_EINVAL          # 200 groups of 100 bp do not fit on chip
     assert call(10, 100, 5, 0, off=2) == ss.SS_EINVAL     # misaligned output
     torch.cuda.synchronize()
+
+
+def test_unaligned_bases_take_the_byte_path(rt):
+    """Inputs that start 1 byte past a 16-byte boundary cannot use the vector-load path; the result
+    must not change (fused schedule at E <= 5, chunked above)."""
+    import torch
+    import paper_1910_09020_amd as ss
+    b = gen.make(1, n=5000 + 3)
+    n, m = b["n"], 100
+    d = torch.device("cuda")
+    rd = torch.empty(n * m + 64, dtype=torch.uint8, device=d)
+    rf = torch.empty(n * m + 64, dtype=torch.uint8, device=d)
+    rd[1:1 + n * m].copy_(torch.from_numpy(b["reads"]))
+    rf[1:1 + n * m].copy_(torch.from_numpy(b["refs"]))
+    err = torch.zeros(1, dtype=torch.int32, device=d)
+    for E in (0, 5, 6, 12):
+        out = torch.empty(n + 8, dtype=torch.int16, device=d)
+        ss.ss_filter_ascii_async(rt.context(0), rd[1:], rf[1:], n, m, E, 0, out, err)
+        torch.cuda.synchronize()
+        assert int(err.item()) == 0
+        check(f"unaligned E={E}", rt.results_numpy(out, n), want(b, E))
