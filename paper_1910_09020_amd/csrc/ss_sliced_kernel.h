@@ -318,8 +318,8 @@ __global__ __launch_bounds__(256) void k_fused(const uint8_t* __restrict__ reads
         int bn = sb;
         advance(tn, bn);
         tile::load_groups<tile::kFusedQ>(reads, refs, n_pairs, m, tn * T + bn, GB, fast && tn < ntiles, nxt);
-        tile::encode_groups<tile::kFusedQ>(reads, refs, nullptr, nullptr, n_pairs, m, tl * T + sb, GB, fast, cur, lds, pk4, T, sb,
-                            bad);
+        tile::encode_groups<tile::kFusedQ>(reads, refs, nullptr, nullptr, n_pairs, m, tl * T + sb, GB, fast, cur,
+                                           lds, pk4, T, sb, bad);
         if (tn != tl) {
             const int gl = threadIdx.x;
             if (gl < tile_groups(tl)) {
@@ -331,35 +331,12 @@ __global__ __launch_bounds__(256) void k_fused(const uint8_t* __restrict__ reads
         sb = bn;
         return tl < ntiles;
     };
-    if constexpr (MODE == MAIN_CIRC) {
-        uint4 va[2][tile::kFusedQ], vb[2][tile::kFusedQ];
-        tile::load_groups<tile::kFusedQ>(reads, refs, n_pairs, m, tl * T, GB, fast != 0, va);
-        for (;;) {
-            if (!step(va, vb)) break;
-            if (!step(vb, va)) break;
-        }
-    } else {
-        // larger thresholds: the sweep's window already takes most registers,
-        // so one load buffer (no loads in flight across a step)
-        for (;;) {
-            uint4 v[2][tile::kFusedQ];
-            tile::load_groups<tile::kFusedQ>(reads, refs, n_pairs, m, tl * T + sb, GB, fast != 0, v);
-            tile::encode_groups<tile::kFusedQ>(reads, refs, nullptr, nullptr, n_pairs, m, tl * T + sb, GB, fast, v, lds, pk4, T,
-                                sb, bad);
-            int64_t tn = tl;
-            int bn = sb;
-            advance(tn, bn);
-            if (tn != tl) {
-                const int gl = threadIdx.x;
-                if (gl < tile_groups(tl)) {
-                    sweep_group<E, MODE>([&](int plane, int c) -> uint4 { return pk4[(plane * nch + c) * T + gl]; },
-                                         m, tl * T + gl, n_pairs, out);
-                }
-            }
-            tl = tn;
-            sb = bn;
-            if (tl >= ntiles) break;
-        }
+    static_assert(MODE == MAIN_CIRC, "the fused kernel is instantiated for small thresholds only");
+    uint4 va[2][tile::kFusedQ], vb[2][tile::kFusedQ];
+    tile::load_groups<tile::kFusedQ>(reads, refs, n_pairs, m, tl * T, GB, fast != 0, va);
+    for (;;) {
+        if (!step(va, vb)) break;
+        if (!step(vb, va)) break;
     }
     if (bad && err) atomicOr(err, 1u);
 }
