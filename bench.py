@@ -521,6 +521,12 @@ def main():
                    sample=f"{what} {n} pairs of the 100 bp workload at E={E}, {threads} threads "
                           f"({r['seconds']:.2f} s wall, {r['seconds'] * threads:.1f} CPU-seconds at most)")
         log(f"oracle: {cpu['value'] / 1e6:.2f} M pairs/s on {threads} threads")
+        # the same oracle on one thread, over a fixed prefix of the batch
+        k1 = min(2_000_000, n)
+        r1 = oracle.batch(b["reads"], b["refs"], b["offsets"][:k1], b["lengths"][:k1], E=E, threads=1)
+        cpu["one_thread"] = dict(value=k1 / r1["seconds"], unit="pairs/s", cores=1,
+                                 sample=f"first {k1} pairs at E={E} ({r1['seconds']:.2f} s)")
+        log(f"oracle, one thread: {cpu['one_thread']['value'] / 1e6:.2f} M pairs/s")
 
     # roofline of the step's kernel (algorithmic bytes per launch / mean launch time on its stream)
     fused = E <= 5          # the one-call path runs the fused kernel up to E = 5
