@@ -37,6 +37,46 @@ namespace {
 
 __global__ void k_zero_counter(int* c) { if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0; }
 
+// The sweep with the item's shape as template arguments, so that the vote over
+// a pair's lanes compiles to straight-line code.  Shapes from wave::shape_for:
+// one lane with 1..RSMAX slices, or several lanes with more than RSMAX/2 slices
+// each; any other shape takes the generic form (lanes per pair at run time).
+template <int RS, int RSMAX>
+__device__ __forceinline__ int sweep_lanes(int lp, const uint32_t* __restrict__ pk, int64_t SW, int64_t b0, int m,
+                                           int Ei, bool ok, int lip, int emax)
+{
+    constexpr bool multi = 2 * RS > RSMAX;          // shapes with several lanes per pair
+    switch (lp) {
+    case 1: return wave::sweep_pair<RS, 1>(pk, SW, b0, m, Ei, ok, 1, lip, emax);
+    case 2: if constexpr (multi) return wave::sweep_pair<RS, 2>(pk, SW, b0, m, Ei, ok, 2, lip, emax); break;
+    case 4: if constexpr (multi) return wave::sweep_pair<RS, 4>(pk, SW, b0, m, Ei, ok, 4, lip, emax); break;
+    case 8: if constexpr (multi) return wave::sweep_pair<RS, 8>(pk, SW, b0, m, Ei, ok, 8, lip, emax); break;
+    case 16: if constexpr (multi) return wave::sweep_pair<RS, 16>(pk, SW, b0, m, Ei, ok, 16, lip, emax); break;
+    case 32: if constexpr (multi) return wave::sweep_pair<RS, 32>(pk, SW, b0, m, Ei, ok, 32, lip, emax); break;
+    case 64: if constexpr (multi) return wave::sweep_pair<RS, 64>(pk, SW, b0, m, Ei, ok, 64, lip, emax); break;
+    default: break;
+    }
+    return wave::sweep_pair<RS, 0>(pk, SW, b0, m, Ei, ok, lp, lip, emax);
+}
+
+template <int RSMAX>
+__device__ __forceinline__ int sweep_shape(int rs, int lp, const uint32_t* __restrict__ pk, int64_t SW, int64_t b0,
+                                           int m, int Ei, bool ok, int lip, int emax)
+{
+    switch (rs) {
+    case 1: return sweep_lanes<1, RSMAX>(lp, pk, SW, b0, m, Ei, ok, lip, emax);
+    case 2: if constexpr (RSMAX >= 2) return sweep_lanes<2, RSMAX>(lp, pk, SW, b0, m, Ei, ok, lip, emax); break;
+    case 3: if constexpr (RSMAX >= 3) return sweep_lanes<3, RSMAX>(lp, pk, SW, b0, m, Ei, ok, lip, emax); break;
+    case 4: if constexpr (RSMAX >= 4) return sweep_lanes<4, RSMAX>(lp, pk, SW, b0, m, Ei, ok, lip, emax); break;
+    case 5: if constexpr (RSMAX >= 5) return sweep_lanes<5, RSMAX>(lp, pk, SW, b0, m, Ei, ok, lip, emax); break;
+    case 6: if constexpr (RSMAX >= 6) return sweep_lanes<6, RSMAX>(lp, pk, SW, b0, m, Ei, ok, lip, emax); break;
+    case 7: if constexpr (RSMAX >= 7) return sweep_lanes<7, RSMAX>(lp, pk, SW, b0, m, Ei, ok, lip, emax); break;
+    case 8: if constexpr (RSMAX >= 8) return sweep_lanes<8, RSMAX>(lp, pk, SW, b0, m, Ei, ok, lip, emax); break;
+    default: break;
+    }
+    return 0;       // no such shape is planned for this slice width
+}
+
 template <int RSMAX>
 __global__ __launch_bounds__(256) void k_persist(const PItem* __restrict__ items, int n_items, int* __restrict__ head,
                                                  const int64_t* __restrict__ perm, const uint32_t* __restrict__ pk,
@@ -66,17 +106,7 @@ __global__ __launch_bounds__(256) void k_persist(const PItem* __restrict__ items
         const int Ei = ok ? Epp[pi] : 0;
         const int lip = lane % LP;
         const int64_t b0 = offsets[pi];
-        int c = 0;
-        switch (rs) {
-        case 1: c = wave::sweep_pair<1, 0>(pk, SW, b0, m, Ei, ok, LP, lip, emax); break;
-        case 2: if (RSMAX >= 2) c = wave::sweep_pair<(RSMAX >= 2 ? 2 : 1), 0>(pk, SW, b0, m, Ei, ok, LP, lip, emax); break;
-        case 3: if (RSMAX >= 3) c = wave::sweep_pair<(RSMAX >= 3 ? 3 : 1), 0>(pk, SW, b0, m, Ei, ok, LP, lip, emax); break;
-        case 4: if (RSMAX >= 4) c = wave::sweep_pair<(RSMAX >= 4 ? 4 : 1), 0>(pk, SW, b0, m, Ei, ok, LP, lip, emax); break;
-        case 5: if (RSMAX >= 5) c = wave::sweep_pair<(RSMAX >= 5 ? 5 : 1), 0>(pk, SW, b0, m, Ei, ok, LP, lip, emax); break;
-        case 6: if (RSMAX >= 6) c = wave::sweep_pair<(RSMAX >= 6 ? 6 : 1), 0>(pk, SW, b0, m, Ei, ok, LP, lip, emax); break;
-        case 7: if (RSMAX >= 7) c = wave::sweep_pair<(RSMAX >= 7 ? 7 : 1), 0>(pk, SW, b0, m, Ei, ok, LP, lip, emax); break;
-        default: if (RSMAX >= 8) c = wave::sweep_pair<(RSMAX >= 8 ? 8 : 1), 0>(pk, SW, b0, m, Ei, ok, LP, lip, emax); break;
-        }
+        const int c = sweep_shape<RSMAX>(rs, LP, pk, SW, b0, m, Ei, ok, lip, emax);
         if (ok && lip == 0) out[pi] = wave::result_word(c, Ei);
     }
 }

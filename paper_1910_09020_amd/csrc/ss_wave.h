@@ -55,14 +55,30 @@ __host__ __device__ inline void shape_for(int32_t E, int RSMAX, int* lp, int* rs
     *rs = (SL + L - 1) / L;
 }
 
+// OR of x over the pair's LP lanes (aligned runs of LP lanes; LP a power of
+// two, uniform across the wavefront).  Within 16-lane rows by DPP (quad
+// permutes, then half-row and row mirrors), across rows by lane shuffles.
+__device__ __forceinline__ uint32_t group_or(uint32_t x, int LP)
+{
+    if (LP >= 2) x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0xB1, 0xF, 0xF, false);   // quad_perm 1,0,3,2
+    if (LP >= 4) x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x4E, 0xF, 0xF, false);   // quad_perm 2,3,0,1
+    if (LP >= 8) x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x141, 0xF, 0xF, false);  // row_half_mirror
+    if (LP >= 16) x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x140, 0xF, 0xF, false); // row_mirror
+    if (LP >= 32) x |= (uint32_t)__shfl_xor((int)x, 16);
+    if (LP >= 64) x |= (uint32_t)__shfl_xor((int)x, 32);
+    return x;
+}
+
 // One 32-column block of the sweep for the calling lane's RS slices.
 // MASK: apply the query-range mask (columns whose rows may index outside [0, m)).
+// The per-column bookkeeping is lane-mask arithmetic (finm: all ones once the
+// pair's walk has ended), so that a column is straight-line vector code.
 template <int RS, bool MASK>
 __device__ __forceinline__ void sweep_block(uint32_t (&alive)[RS], const uint32_t (&rmask)[RS],
                                             const uint32_t (&q0lo)[RS], const uint32_t (&q0hi)[RS],
                                             const uint32_t (&q1lo)[RS], const uint32_t (&q1hi)[RS], uint32_t rw0,
                                             uint32_t rw1, int jb, int jend, int m, int Ei, int Emax, int LP,
-                                            int lip, int grp, int& count, bool& fin)
+                                            int lip, int& count, uint32_t& finm)
 {
     for (int jj = 0; jj < jend; jj++) {
         const int j = jb + jj;
@@ -81,17 +97,15 @@ __device__ __forceinline__ void sweep_block(uint32_t (&alive)[RS], const uint32_
             alive[t] = a;
             any |= a;
         }
-        bool pany = any != 0u;
-        if (LP > 1) {
-            const uint64_t bal = __ballot(pany);
-            const uint64_t gm = LP >= 64 ? bal : (bal >> (grp * LP)) & ((1ull << (LP & 63)) - 1ull);
-            pany = gm != 0ull;
-        }
-        const bool dead = !fin && j < m && !pany;
-        count += dead ? 1 : 0;
+        any = group_or(any, LP);
+        // dead column: no row of the pair still free, the walk not ended, j inside the pair
+        const uint32_t live = j < m ? ~finm : 0u;
+        const uint32_t deadm = any == 0u ? live : 0u;
+        count -= (int)deadm;                                                 // +1 on a dead column
 #pragma unroll
-        for (int t = 0; t < RS; t++) alive[t] = dead ? rmask[t] : alive[t];
-        fin = fin || (dead && count > Ei) || (j + 1 >= m);
+        for (int t = 0; t < RS; t++)
+            alive[t] = __builtin_amdgcn_bitop3_b32(alive[t], rmask[t], deadm, 0xD8);   // deadm ? rmask : alive
+        finm |= (count > Ei ? deadm : 0u) | (j + 1 >= m ? ~0u : 0u);
     }
 }
 
@@ -108,8 +122,6 @@ __device__ __forceinline__ int sweep_pair(const uint32_t* __restrict__ pk, int64
                                           bool pair_ok, int LP_rt, int lip, int Emax)
 {
     const int LP = LPC > 0 ? LPC : LP_rt;
-    const int lane = threadIdx.x & 63;
-    const int grp = lane / LP;
     const uint32_t* __restrict__ Q0 = pk;
     const uint32_t* __restrict__ Q1 = pk + SW;
     const uint32_t* __restrict__ R0 = pk + 2 * SW;
@@ -127,7 +139,8 @@ __device__ __forceinline__ int sweep_pair(const uint32_t* __restrict__ pk, int64
         q0lo[t] = q0hi[t] = q1lo[t] = q1hi[t] = n0[t] = n1[t] = 0u;
     }
     int count = 0;
-    bool fin = !pair_ok || m == 0;
+    uint32_t finm = (!pair_ok || m == 0) ? ~0u : 0u;
+    const bool fin = finm != 0u;
     // interior blocks of columns need no query-range mask for any pair of the wavefront
     int mmin = fin ? 0x7FFFFFFF : m;
     int mmax = fin ? 0 : m;
@@ -152,11 +165,11 @@ __device__ __forceinline__ int sweep_pair(const uint32_t* __restrict__ pk, int64
     }
     uint32_t nr0 = fin ? 0u : bits32(R0, SW, b0), nr1 = fin ? 0u : bits32(R1, SW, b0);
     for (int jb = 0; jb < mmax; jb += 32) {
-        if (__all(fin)) break;
+        if (__all(finm != 0u)) break;
 #pragma unroll
         for (int t = 0; t < RS; t++) { q0hi[t] = n0[t]; q1hi[t] = n1[t]; }
         const uint32_t rw0 = nr0, rw1 = nr1;
-        if (jb + 32 < mmax && !fin) {
+        if (jb + 32 < mmax && finm == 0u) {
 #pragma unroll
             for (int t = 0; t < RS; t++) {
                 const int64_t a = b0 + jb + 64 - Emax + 32 * (int64_t)(lip + LP * t);
@@ -169,10 +182,10 @@ __device__ __forceinline__ int sweep_pair(const uint32_t* __restrict__ pk, int64
         const int jend = min(32, mmax - jb);
         if ((jb >= Emax) && (jb + 31 + Emax < mmin))
             sweep_block<RS, false>(alive, rmask, q0lo, q0hi, q1lo, q1hi, rw0, rw1, jb, jend, m, Ei, Emax, LP, lip,
-                                   grp, count, fin);
+                                   count, finm);
         else
             sweep_block<RS, true>(alive, rmask, q0lo, q0hi, q1lo, q1hi, rw0, rw1, jb, jend, m, Ei, Emax, LP, lip,
-                                  grp, count, fin);
+                                  count, finm);
 #pragma unroll
         for (int t = 0; t < RS; t++) { q0lo[t] = q0hi[t]; q1lo[t] = q1hi[t]; }
     }
