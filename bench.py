@@ -290,18 +290,31 @@ def mixed_leg(a, torch, ss, gen, runner, oracle):
     idx = np.sort(np.concatenate([rng.choice(short_idx, size=min(50000, len(short_idx)), replace=False),
                                   rng.choice(long_idx, size=min(400, len(long_idx)), replace=False)]))
     w = oracle.batch(b["reads"], b["refs"], b["offsets"][idx], b["lengths"][idx], E_per_pair=b["E"][idx],
-                     threads=min(16, os.cpu_count() or 1))
+                     threads=min(16, os.cpu_count() or 1), want_stats=True)
     mism = int(np.sum((w["accept"] != acc[idx]) | (w["edits"] != ed[idx])))
     ss.ss_plan_destroy(plan)
+    # roofline by the op model of a row-wise bit-parallel walk: (2E+1) (5 ceil(c_last/32) + 3 K) 32-bit ops
+    # per pair, c_last and the checkpoints K from the oracle's stats on the sample, scaled to the batch
+    # by class (short / long)
+    Es = b["E"][idx].astype(np.float64)
+    ops = (2 * Es + 1) * (5 * np.ceil(w["stats"][:, 1] / 32.0) + 3 * w["stats"][:, 0])
+    is_long = b["lengths"][idx] >= 10000
+    model_ops = float(ops[~is_long].mean() * len(short_idx) + (ops[is_long].mean() * len(long_idx) if len(long_idx) else 0))
+    achieved_tops = model_ops / (bat_ms * 1e-3) / 1e12
     res = dict(workload="5M short (100/150/250 bp) + 20k x 10 kbp, per-pair E = ceil(rate x m), rate in "
                         "{1,2,5,10}%", n_pairs=n, encode_ms=round(enc_ms, 4), batched_ms=round(bat_ms, 4),
                batched_pairs_per_s=n / (1e-3 * bat_ms), step_pairs_per_s=n / (1e-3 * (bat_ms + enc_ms)),
                unbucketed_ms=round(flat_ms, 4), unbucketed_pairs_per_s=n / (1e-3 * flat_ms),
                speedup_vs_unbucketed=flat_ms / bat_ms, identical_outputs=identical, plan_seconds=round(plan_s, 3),
                plan=info, tuned_slices_per_lane=chosen, oracle_sample_pairs=int(len(idx)),
-               oracle_sample_mismatches=mism)
+               oracle_sample_mismatches=mism,
+               roofline={"bound": "alu", "model": "(2E+1)(5 ceil(c_last/32) + 3 checkpoints) 32-bit ops per pair "
+                                                   "(oracle stats on the sample, scaled to the batch by class)",
+                         "model_ops": model_ops, "achieved": achieved_tops, "peak": VALU_PEAK_TOPS,
+                         "unit": "T ops/s", "frac": achieved_tops / VALU_PEAK_TOPS})
     log(f"mixed: batched {bat_ms:.3f} ms, unbucketed {flat_ms:.3f} ms, identical={identical}, "
-        f"oracle mismatches {mism}/{len(idx)}, plan {plan_s:.2f}s {info}")
+        f"oracle mismatches {mism}/{len(idx)}, plan {plan_s:.2f}s {info}; op model {model_ops / 1e9:.1f} G ops "
+        f"-> {achieved_tops:.1f} T ops/s ({100 * achieved_tops / VALU_PEAK_TOPS:.0f}% of {VALU_PEAK_TOPS} T)")
     del db, ps, out, uout
     torch.cuda.empty_cache()
     return res
