@@ -251,7 +251,8 @@ int ss_select_accepted_async(ss_ctx* ctx, const uint16_t* results, int64_t n, in
  * latency per pair at some cost in total work)
  * from its threshold; pairs are sorted by shape and length, cut into work
  * items of one 256-thread block round, and the items ordered largest
- * estimated cost first.  The plan owns its device buffers (permutation, item
+ * estimated cost first (by input position among items of about the same
+ * cost).  The plan owns its device buffers (permutation, item
  * table, queue counter) and is bound to the device current at creation.
  * A pair's 2E+1 rows must fit one wavefront (64 lanes x slices_per_lane x 32
  * rows): slices_per_lane is raised to the smallest width that holds the

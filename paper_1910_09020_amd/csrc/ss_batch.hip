@@ -4,8 +4,10 @@
 // pair LP and 32-row slices per lane rs, see wave::shape_for).  Pairs are
 // sorted by class and length, cut into work items of one block-round (four
 // wavefronts of 64 / LP pairs each) and the items are ordered by estimated
-// cost, largest first, so that the long pairs start early and the short ones
-// fill in behind.
+// cost, largest first (in levels of powers of four, by input position within
+// a level), so that the long pairs start early, the short ones fill in
+// behind, and short items that read the same stretch of the input run
+// together.
 //
 // Launch: one persistent kernel; each 256-thread block pops the next item
 // from a device counter and runs the wavefront sweep of ss_wave.h on it, until
@@ -41,41 +43,65 @@ __global__ void k_zero_counter(int* c) { if (threadIdx.x == 0 && blockIdx.x == 0
 // a pair's lanes compiles to straight-line code.  Shapes from wave::shape_for:
 // one lane with 1..RSMAX slices, or several lanes with more than RSMAX/2 slices
 // each; any other shape takes the generic form (lanes per pair at run time).
-template <int RS, int RSMAX>
-__device__ __forceinline__ int sweep_lanes(int lp, const uint32_t* __restrict__ pk, int64_t SW, int64_t b0, int m,
-                                           int Ei, bool ok, int lip, int emax)
+template <int RS, int RSMAX, class LD>
+__device__ __forceinline__ int sweep_lanes(int lp, const LD& ld, int64_t b0, int m, int Ei, bool ok, int lip,
+                                           int emax)
 {
     constexpr bool multi = 2 * RS > RSMAX;          // shapes with several lanes per pair
     switch (lp) {
-    case 1: return wave::sweep_pair<RS, 1>(pk, SW, b0, m, Ei, ok, 1, lip, emax);
-    case 2: if constexpr (multi) return wave::sweep_pair<RS, 2>(pk, SW, b0, m, Ei, ok, 2, lip, emax); break;
-    case 4: if constexpr (multi) return wave::sweep_pair<RS, 4>(pk, SW, b0, m, Ei, ok, 4, lip, emax); break;
-    case 8: if constexpr (multi) return wave::sweep_pair<RS, 8>(pk, SW, b0, m, Ei, ok, 8, lip, emax); break;
-    case 16: if constexpr (multi) return wave::sweep_pair<RS, 16>(pk, SW, b0, m, Ei, ok, 16, lip, emax); break;
-    case 32: if constexpr (multi) return wave::sweep_pair<RS, 32>(pk, SW, b0, m, Ei, ok, 32, lip, emax); break;
-    case 64: if constexpr (multi) return wave::sweep_pair<RS, 64>(pk, SW, b0, m, Ei, ok, 64, lip, emax); break;
+    case 1: return wave::sweep_pair<RS, 1>(ld, b0, m, Ei, ok, 1, lip, emax);
+    case 2: if constexpr (multi) return wave::sweep_pair<RS, 2>(ld, b0, m, Ei, ok, 2, lip, emax); break;
+    case 4: if constexpr (multi) return wave::sweep_pair<RS, 4>(ld, b0, m, Ei, ok, 4, lip, emax); break;
+    case 8: if constexpr (multi) return wave::sweep_pair<RS, 8>(ld, b0, m, Ei, ok, 8, lip, emax); break;
+    case 16: if constexpr (multi) return wave::sweep_pair<RS, 16>(ld, b0, m, Ei, ok, 16, lip, emax); break;
+    case 32: if constexpr (multi) return wave::sweep_pair<RS, 32>(ld, b0, m, Ei, ok, 32, lip, emax); break;
+    case 64: if constexpr (multi) return wave::sweep_pair<RS, 64>(ld, b0, m, Ei, ok, 64, lip, emax); break;
     default: break;
     }
-    return wave::sweep_pair<RS, 0>(pk, SW, b0, m, Ei, ok, lp, lip, emax);
+    return wave::sweep_pair<RS, 0>(ld, b0, m, Ei, ok, lp, lip, emax);
 }
 
-template <int RSMAX>
-__device__ __forceinline__ int sweep_shape(int rs, int lp, const uint32_t* __restrict__ pk, int64_t SW, int64_t b0,
-                                           int m, int Ei, bool ok, int lip, int emax)
+template <int RSMAX, class LD>
+__device__ __forceinline__ int sweep_shape(int rs, int lp, const LD& ld, int64_t b0, int m, int Ei, bool ok, int lip,
+                                           int emax)
 {
     switch (rs) {
-    case 1: return sweep_lanes<1, RSMAX>(lp, pk, SW, b0, m, Ei, ok, lip, emax);
-    case 2: if constexpr (RSMAX >= 2) return sweep_lanes<2, RSMAX>(lp, pk, SW, b0, m, Ei, ok, lip, emax); break;
-    case 3: if constexpr (RSMAX >= 3) return sweep_lanes<3, RSMAX>(lp, pk, SW, b0, m, Ei, ok, lip, emax); break;
-    case 4: if constexpr (RSMAX >= 4) return sweep_lanes<4, RSMAX>(lp, pk, SW, b0, m, Ei, ok, lip, emax); break;
-    case 5: if constexpr (RSMAX >= 5) return sweep_lanes<5, RSMAX>(lp, pk, SW, b0, m, Ei, ok, lip, emax); break;
-    case 6: if constexpr (RSMAX >= 6) return sweep_lanes<6, RSMAX>(lp, pk, SW, b0, m, Ei, ok, lip, emax); break;
-    case 7: if constexpr (RSMAX >= 7) return sweep_lanes<7, RSMAX>(lp, pk, SW, b0, m, Ei, ok, lip, emax); break;
-    case 8: if constexpr (RSMAX >= 8) return sweep_lanes<8, RSMAX>(lp, pk, SW, b0, m, Ei, ok, lip, emax); break;
+    case 1: return sweep_lanes<1, RSMAX>(lp, ld, b0, m, Ei, ok, lip, emax);
+    case 2: if constexpr (RSMAX >= 2) return sweep_lanes<2, RSMAX>(lp, ld, b0, m, Ei, ok, lip, emax); break;
+    case 3: if constexpr (RSMAX >= 3) return sweep_lanes<3, RSMAX>(lp, ld, b0, m, Ei, ok, lip, emax); break;
+    case 4: if constexpr (RSMAX >= 4) return sweep_lanes<4, RSMAX>(lp, ld, b0, m, Ei, ok, lip, emax); break;
+    case 5: if constexpr (RSMAX >= 5) return sweep_lanes<5, RSMAX>(lp, ld, b0, m, Ei, ok, lip, emax); break;
+    case 6: if constexpr (RSMAX >= 6) return sweep_lanes<6, RSMAX>(lp, ld, b0, m, Ei, ok, lip, emax); break;
+    case 7: if constexpr (RSMAX >= 7) return sweep_lanes<7, RSMAX>(lp, ld, b0, m, Ei, ok, lip, emax); break;
+    case 8: if constexpr (RSMAX >= 8) return sweep_lanes<8, RSMAX>(lp, ld, b0, m, Ei, ok, lip, emax); break;
     default: break;
     }
     return 0;       // no such shape is planned for this slice width
 }
+
+// One-lane shapes from a stage in LDS.
+template <int RSMAX>
+__device__ __forceinline__ int sweep_staged(int rs, const wave::StagedPlanes& ld, int64_t b0, int m, int Ei, bool ok,
+                                            int emax)
+{
+    switch (rs) {
+    case 1: return wave::sweep_pair<1, 1>(ld, b0, m, Ei, ok, 1, 0, emax);
+    case 2: if constexpr (RSMAX >= 2) return wave::sweep_pair<2, 1>(ld, b0, m, Ei, ok, 1, 0, emax); break;
+    case 3: if constexpr (RSMAX >= 3) return wave::sweep_pair<3, 1>(ld, b0, m, Ei, ok, 1, 0, emax); break;
+    case 4: if constexpr (RSMAX >= 4) return wave::sweep_pair<4, 1>(ld, b0, m, Ei, ok, 1, 0, emax); break;
+    case 5: if constexpr (RSMAX >= 5) return wave::sweep_pair<5, 1>(ld, b0, m, Ei, ok, 1, 0, emax); break;
+    case 6: if constexpr (RSMAX >= 6) return wave::sweep_pair<6, 1>(ld, b0, m, Ei, ok, 1, 0, emax); break;
+    case 7: if constexpr (RSMAX >= 7) return wave::sweep_pair<7, 1>(ld, b0, m, Ei, ok, 1, 0, emax); break;
+    case 8: if constexpr (RSMAX >= 8) return wave::sweep_pair<8, 1>(ld, b0, m, Ei, ok, 1, 0, emax); break;
+    default: break;
+    }
+    return 0;
+}
+
+// Per-plane capacity of the LDS stage (words): an item of 256 one-lane pairs
+// that lie close together in the stream (the planner keeps them in input
+// order) spans about 256 m / 32 words per plane.
+constexpr int kStageWords = 2048;
 
 template <int RSMAX>
 __global__ __launch_bounds__(256) void k_persist(const PItem* __restrict__ items, int n_items, int* __restrict__ head,
@@ -85,6 +111,8 @@ __global__ __launch_bounds__(256) void k_persist(const PItem* __restrict__ items
                                                  const int32_t* __restrict__ Epp, uint16_t* __restrict__ out)
 {
     __shared__ int s_item;
+    __shared__ long long s_lo[4], s_hi[4];
+    __shared__ uint32_t s_stage[4 * kStageWords];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(head, 1);
@@ -106,7 +134,34 @@ __global__ __launch_bounds__(256) void k_persist(const PItem* __restrict__ items
         const int Ei = ok ? Epp[pi] : 0;
         const int lip = lane % LP;
         const int64_t b0 = offsets[pi];
-        const int c = sweep_shape<RSMAX>(rs, LP, pk, SW, b0, m, Ei, ok, lip, emax);
+        int c;
+        if (LP == 1) {
+            // one pair per lane: stage the words that hold the block's pairs, when they fit
+            long long lo = (ok && m > 0) ? (long long)(b0 >> 5) : LLONG_MAX;
+            long long hi = (ok && m > 0) ? (long long)((b0 + m - 1) >> 5) + 1 : 0;
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) {
+                lo = min(lo, (long long)__shfl_xor(lo, o));
+                hi = max(hi, (long long)__shfl_xor(hi, o));
+            }
+            if (lane == 0) { s_lo[wv] = lo; s_hi[wv] = hi; }
+            __syncthreads();
+            lo = min(min(s_lo[0], s_lo[1]), min(s_lo[2], s_lo[3]));
+            hi = max(max(s_hi[0], s_hi[1]), max(s_hi[2], s_hi[3]));
+            if (hi > lo && hi - lo <= kStageWords) {
+                const int nw = (int)(hi - lo);
+#pragma unroll
+                for (int p = 0; p < 4; p++)
+                    for (int i = threadIdx.x; i < nw; i += 256) s_stage[p * kStageWords + i] = pk[p * SW + lo + i];
+                __syncthreads();
+                const wave::StagedPlanes ld{s_stage, (int64_t)lo, nw, kStageWords};
+                c = sweep_staged<RSMAX>(rs, ld, b0, m, Ei, ok, emax);
+            } else {
+                c = sweep_shape<RSMAX>(rs, LP, wave::GlobalPlanes{pk, SW}, b0, m, Ei, ok, lip, emax);
+            }
+        } else {
+            c = sweep_shape<RSMAX>(rs, LP, wave::GlobalPlanes{pk, SW}, b0, m, Ei, ok, lip, emax);
+        }
         if (ok && lip == 0) out[pi] = wave::result_word(c, Ei);
     }
 }
@@ -151,11 +206,24 @@ bool plan_items(const int32_t* lengths, const int32_t* E, int64_t n, int rsmax, 
         cls[(size_t)i] = id;
     }
     *n_classes = (int)shapes.size();
-    // sort by (class, length desc, E desc): pairs of one wavefront share the column loop
+    // Sort by (class, chunk, length desc, E desc): pairs of one wavefront share
+    // the column loop.  One-lane classes are cut in chunks of one block round
+    // (256 pairs) in input order and sorted within a chunk, so that an item's
+    // pairs lie close together in the stream (the kernel stages them in LDS);
+    // other classes form a single chunk.
+    std::vector<int64_t> chunk((size_t)n, 0);
+    {
+        std::vector<int64_t> seen(shapes.size(), 0);
+        for (int64_t i = 0; i < n; i++) {
+            const int c = cls[(size_t)i];
+            if (shapes[(size_t)c].first == 1) chunk[(size_t)i] = seen[(size_t)c]++ / 256;
+        }
+    }
     perm.resize((size_t)n);
     std::iota(perm.begin(), perm.end(), (int64_t)0);
     std::stable_sort(perm.begin(), perm.end(), [&](int64_t a, int64_t b) {
         if (cls[(size_t)a] != cls[(size_t)b]) return cls[(size_t)a] < cls[(size_t)b];
+        if (chunk[(size_t)a] != chunk[(size_t)b]) return chunk[(size_t)a] < chunk[(size_t)b];
         if (lengths[a] != lengths[b]) return lengths[a] > lengths[b];
         return E[a] > E[b];
     });
@@ -192,10 +260,22 @@ bool plan_items(const int32_t* lengths, const int32_t* E, int64_t n, int rsmax, 
         *est_cost += work;
         i = j;
     }
-    // largest items first
+    // Largest items first, by cost level (powers of four); within a level, by
+    // the position of the item's first pair in the input, so that items of
+    // different (length, threshold) groups that read the same stretch of the
+    // bit stream run at about the same time and share its cache lines.
     std::vector<size_t> order(items.size());
     std::iota(order.begin(), order.end(), (size_t)0);
-    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
+    std::vector<int> level(items.size());
+    for (size_t k = 0; k < items.size(); k++) {
+        int l = 0;
+        for (double c = cost[k]; c >= 4.0; c *= 0.25) l++;
+        level[k] = l;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
+        if (level[a] != level[b]) return level[a] > level[b];
+        return perm[(size_t)items[a].first] < perm[(size_t)items[b].first];
+    });
     std::vector<PItem> sorted;
     sorted.reserve(order.size());
     for (size_t k : order) sorted.push_back(items[k]);

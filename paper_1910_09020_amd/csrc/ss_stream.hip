@@ -214,7 +214,7 @@ __global__ __launch_bounds__(256) void k_wave(const uint32_t* __restrict__ pk, i
     const int64_t pc = pair_ok ? pi : 0;
     const int m = pair_ok ? lengths[pc] : 0;
     const int Ei = Epp ? Epp[pc] : Emax;
-    const int c = wave::sweep_pair<RS, LP>(pk, SW, offsets[pc], m, Ei, pair_ok, LP, lip, Emax);
+    const int c = wave::sweep_pair<RS, LP>(wave::GlobalPlanes{pk, SW}, offsets[pc], m, Ei, pair_ok, LP, lip, Emax);
     if (pair_ok && lip == 0) out[pi] = wave::result_word(c, Ei);
 }
 

@@ -43,6 +43,33 @@ __device__ __forceinline__ uint32_t span_mask(int lo, int hi)
     return up & ~dn;
 }
 
+// Window loaders for the sweep: get(p, a) returns 32 bits of plane p
+// (0, 1: query; 2, 3: reference) starting at absolute stream bit a.
+struct GlobalPlanes {
+    const uint32_t* __restrict__ pk;
+    int64_t SW;
+    __device__ __forceinline__ uint32_t get(int p, int64_t a) const { return bits32(pk + p * SW, SW, a); }
+};
+
+// Words [lo, lo + nw) of each plane staged in LDS (plane p at st + p * cap);
+// words outside read as zero.  Every bit that can change a result lies inside
+// some pair's own [b0, b0 + m), so a stage that covers those spans of the
+// pairs being swept gives the same results as the global loader.
+struct StagedPlanes {
+    const uint32_t* st;
+    int64_t lo;
+    int nw, cap;
+    __device__ __forceinline__ uint32_t word(int p, int i) const
+    {
+        return (unsigned)i < (unsigned)nw ? st[p * cap + i] : 0u;
+    }
+    __device__ __forceinline__ uint32_t get(int p, int64_t a) const
+    {
+        const int i = (int)((a >> 5) - lo);
+        return __builtin_amdgcn_alignbit(word(p, i + 1), word(p, i), (uint32_t)(a & 31));
+    }
+};
+
 // Shape for a maximum threshold E: lanes per pair and slices per lane, with at
 // most RSMAX slices per lane.
 __host__ __device__ inline void shape_for(int32_t E, int RSMAX, int* lp, int* rs)
@@ -57,138 +84,209 @@ __host__ __device__ inline void shape_for(int32_t E, int RSMAX, int* lp, int* rs
 
 // OR of x over the pair's LP lanes (aligned runs of LP lanes; LP a power of
 // two, uniform across the wavefront).  Within 16-lane rows by DPP (quad
-// permutes, then half-row and row mirrors), across rows by lane shuffles.
+// permutes, then half-row and row mirrors), across rows by the permlane swaps
+// (rows 0<->1 and 2<->3, then the two halves), all vector ALU operations.
 __device__ __forceinline__ uint32_t group_or(uint32_t x, int LP)
 {
     if (LP >= 2) x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0xB1, 0xF, 0xF, false);   // quad_perm 1,0,3,2
     if (LP >= 4) x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x4E, 0xF, 0xF, false);   // quad_perm 2,3,0,1
     if (LP >= 8) x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x141, 0xF, 0xF, false);  // row_half_mirror
     if (LP >= 16) x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x140, 0xF, 0xF, false); // row_mirror
-    if (LP >= 32) x |= (uint32_t)__shfl_xor((int)x, 16);
-    if (LP >= 64) x |= (uint32_t)__shfl_xor((int)x, 32);
+    if (LP >= 32) {
+        const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+        x = r[0] | r[1];
+    }
+    if (LP >= 64) {
+        const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+        x = r[0] | r[1];
+    }
     return x;
 }
 
-// One 32-column block of the sweep for the calling lane's RS slices.
-// MASK: apply the query-range mask (columns whose rows may index outside [0, m)).
-// The per-column bookkeeping is lane-mask arithmetic (finm: all ones once the
-// pair's walk has ended), so that a column is straight-line vector code.
-template <int RS, bool MASK>
-__device__ __forceinline__ void sweep_block(uint32_t (&alive)[RS], const uint32_t (&rmask)[RS],
-                                            const uint32_t (&q0lo)[RS], const uint32_t (&q0hi)[RS],
-                                            const uint32_t (&q1lo)[RS], const uint32_t (&q1hi)[RS], uint32_t rw0,
-                                            uint32_t rw1, int jb, int jend, int m, int Ei, int Emax, int LP,
-                                            int lip, int& count, uint32_t& finm)
+// A lane's share of one pair's sweep.  Slice t of the lane holds rows
+// 32 s .. 32 s + 31 with s = lane_in_pair + LP t; within a 32-column block
+// starting at column jb, bit p of the 64-bit windows (hi:lo) of slice t stands
+// for query position jb - Emax + 32 s + p (pair-relative), so that column
+// jb + c reads bits [c, c + 32): row r = 32 s + p meets query position
+// j + r - Emax, as Equation 1 places the diagonals.
+template <int RS>
+struct Share {
+    uint32_t alive[RS];     // rows free since the checkpoint
+    uint32_t rmask[RS];     // rows of the pair: |r - Emax| <= E_pair and r < 2 Emax + 1
+    uint32_t nfin;          // all ones while the walk goes on, 0 once it has ended
+    int slack;              // E_pair - obstacles counted
+};
+
+// Block windows: query planes, the validity plane (query position in [0, m)),
+// and the block's 32 reference bits.
+template <int RS>
+struct Win {
+    uint32_t q0lo[RS], q0hi[RS], q1lo[RS], q1hi[RS], vlo[RS], vhi[RS];
+    uint32_t r0, r1;
+};
+
+// v_bitop3 truth tables
+constexpr int kSelect = 0xD8;   // src2 ? src1 : src0
+constexpr int kClearIf = 0x70;  // src0 & ~(src1 & src2)
+
+// One column of the walk at window shift sh.  MASK: AND each row with the
+// validity plane (rows whose query position falls outside [0, m) hold
+// obstacles); END: the pair's last column may lie in this block (column j).
+// A column where none of the pair's rows is still free holds the obstacle
+// that ends the longest escape segment: count it while the walk goes on,
+// stop the walk once the count exceeds the threshold, and free every row of
+// the pair again from the next column.
+template <int RS, int LPC, bool MASK, bool END>
+__device__ __forceinline__ void column(Share<RS>& S, const Win<RS>& W, int sh, int LP_rt, int j, int m)
 {
-    for (int jj = 0; jj < jend; jj++) {
-        const int j = jb + jj;
-        const uint32_t rb0 = (uint32_t)__builtin_amdgcn_sbfe((int)rw0, jj, 1);   // reference bit j, broadcast
-        const uint32_t rb1 = (uint32_t)__builtin_amdgcn_sbfe((int)rw1, jj, 1);
-        uint32_t any = 0;
+    const int LP = LPC > 0 ? LPC : LP_rt;
+    const uint32_t rb0 = (uint32_t)__builtin_amdgcn_sbfe((int)W.r0, sh, 1);   // reference bit, broadcast
+    const uint32_t rb1 = (uint32_t)__builtin_amdgcn_sbfe((int)W.r1, sh, 1);
+    uint32_t any = 0;
 #pragma unroll
-        for (int t = 0; t < RS; t++) {
-            const uint32_t x0 = __builtin_amdgcn_alignbit(q0hi[t], q0lo[t], jj);
-            const uint32_t x1 = __builtin_amdgcn_alignbit(q1hi[t], q1lo[t], jj);
-            uint32_t a = and_xnor(and_xnor(alive[t], x0, rb0), x1, rb1);
-            if (MASK) {
-                const int base = j - Emax + 32 * (lip + LP * t);      // query position of bit 0
-                a &= span_mask(-base, m - base);
-            }
-            alive[t] = a;
-            any |= a;
+    for (int t = 0; t < RS; t++) {
+        const uint32_t x0 = __builtin_amdgcn_alignbit(W.q0hi[t], W.q0lo[t], sh);
+        const uint32_t x1 = __builtin_amdgcn_alignbit(W.q1hi[t], W.q1lo[t], sh);
+        uint32_t a = and_xnor(and_xnor(S.alive[t], x0, rb0), x1, rb1);
+        if (MASK) a &= __builtin_amdgcn_alignbit(W.vhi[t], W.vlo[t], sh);
+        S.alive[t] = a;
+        any |= a;
+    }
+    any = group_or(any, LP);
+    const uint32_t deadm = any == 0u ? S.nfin : 0u;
+    S.slack += (int)deadm;                                               // -1 on a counted obstacle
+    S.nfin = __builtin_amdgcn_bitop3_b32(S.nfin, deadm, (uint32_t)(S.slack >> 31), kClearIf);
+    if (END) S.nfin = j + 1 >= m ? 0u : S.nfin;
+#pragma unroll
+    for (int t = 0; t < RS; t++) S.alive[t] = __builtin_amdgcn_bitop3_b32(S.alive[t], S.rmask[t], deadm, kSelect);
+}
+
+// Move every window of a block by 16 bit positions.
+template <int RS, bool MASK>
+__device__ __forceinline__ void advance16(Win<RS>& W)
+{
+#pragma unroll
+    for (int t = 0; t < RS; t++) {
+        W.q0lo[t] = __builtin_amdgcn_alignbit(W.q0hi[t], W.q0lo[t], 16);
+        W.q0hi[t] >>= 16;
+        W.q1lo[t] = __builtin_amdgcn_alignbit(W.q1hi[t], W.q1lo[t], 16);
+        W.q1hi[t] >>= 16;
+        if (MASK) {
+            W.vlo[t] = __builtin_amdgcn_alignbit(W.vhi[t], W.vlo[t], 16);
+            W.vhi[t] >>= 16;
         }
-        any = group_or(any, LP);
-        // dead column: no row of the pair still free, the walk not ended, j inside the pair
-        const uint32_t live = j < m ? ~finm : 0u;
-        const uint32_t deadm = any == 0u ? live : 0u;
-        count -= (int)deadm;                                                 // +1 on a dead column
+    }
+    W.r0 >>= 16;
+    W.r1 >>= 16;
+}
+
+// A full block of 32 columns as two passes of one 16-column body with
+// immediate shifts.
+template <int RS, int LPC, bool MASK>
+__device__ __forceinline__ void block_full(Share<RS>& S, Win<RS> W, int LP)
+{
+#pragma nounroll
+    for (int h = 0; h < 2; h++) {
 #pragma unroll
-        for (int t = 0; t < RS; t++)
-            alive[t] = __builtin_amdgcn_bitop3_b32(alive[t], rmask[t], deadm, 0xD8);   // deadm ? rmask : alive
-        finm |= (count > Ei ? deadm : 0u) | (j + 1 >= m ? ~0u : 0u);
+        for (int c = 0; c < 16; c++) column<RS, LPC, MASK, false>(S, W, c, LP, 0, 0);
+        if (h == 0) advance16<RS, MASK>(W);
     }
 }
 
+// A block in which a pair's walk may end: jend columns (uniform), masked, with
+// the end-of-pair test on every column.
+template <int RS, int LPC>
+__device__ __forceinline__ void block_end(Share<RS>& S, const Win<RS>& W, int LP, int jb, int jend, int m)
+{
+    for (int c = 0; c < jend; c++) column<RS, LPC, true, true>(S, W, c, LP, jb + c, m);
+}
+
 // Sweep one pair with the calling lane's share of its rows.  All 64 lanes of
-// the wavefront must call this together (it uses wavefront votes), with the
-// same LP.
+// the wavefront must call this together (it uses wavefront votes and lane
+// permutes), with the same LP.
+//   ld          : window loader (GlobalPlanes or StagedPlanes)
 //   b0, m, Ei   : the pair's stream bit offset, length and threshold
-//   pair_ok     : false for lanes without a pair (they still vote)
+//   pair_ok     : false for lanes without a pair (they still take part)
 //   LP, lip     : lanes per pair and this lane's index in its pair
 //   RS          : slices this lane holds; Emax: row layout threshold
 // Returns the count reported by the walk, min(count, Ei+1).
-template <int RS, int LPC>
-__device__ __forceinline__ int sweep_pair(const uint32_t* __restrict__ pk, int64_t SW, int64_t b0, int m, int Ei,
-                                          bool pair_ok, int LP_rt, int lip, int Emax)
+template <int RS, int LPC, class LD>
+__device__ __forceinline__ int sweep_pair(const LD& ld, int64_t b0, int m, int Ei, bool pair_ok, int LP_rt, int lip,
+                                          int Emax)
 {
     const int LP = LPC > 0 ? LPC : LP_rt;
-    const uint32_t* __restrict__ Q0 = pk;
-    const uint32_t* __restrict__ Q1 = pk + SW;
-    const uint32_t* __restrict__ R0 = pk + 2 * SW;
-    const uint32_t* __restrict__ R1 = pk + 3 * SW;
     const int NR = 2 * Emax + 1;
 
-    uint32_t alive[RS], rmask[RS], q0lo[RS], q0hi[RS], q1lo[RS], q1hi[RS], n0[RS], n1[RS];
+    Share<RS> S;
+    Win<RS> W;
+    uint32_t n0[RS], n1[RS];
 #pragma unroll
     for (int t = 0; t < RS; t++) {
         const int s = lip + LP * t;
         // rows r in [32s, 32s+32) that exist (r < NR) and whose |r - Emax| <= Ei
         const int lo = Emax - Ei - 32 * s, hi = Emax + Ei + 1 - 32 * s;
-        rmask[t] = span_mask(lo, hi < NR - 32 * s ? hi : NR - 32 * s);
-        alive[t] = rmask[t];
-        q0lo[t] = q0hi[t] = q1lo[t] = q1hi[t] = n0[t] = n1[t] = 0u;
+        S.rmask[t] = span_mask(lo, hi < NR - 32 * s ? hi : NR - 32 * s);
+        S.alive[t] = S.rmask[t];
+        W.q0lo[t] = W.q0hi[t] = W.q1lo[t] = W.q1hi[t] = W.vlo[t] = W.vhi[t] = n0[t] = n1[t] = 0u;
     }
-    int count = 0;
-    uint32_t finm = (!pair_ok || m == 0) ? ~0u : 0u;
-    const bool fin = finm != 0u;
-    // interior blocks of columns need no query-range mask for any pair of the wavefront
-    int mmin = fin ? 0x7FFFFFFF : m;
-    int mmax = fin ? 0 : m;
+    S.nfin = (!pair_ok || m == 0) ? 0u : ~0u;
+    S.slack = pair_ok ? Ei : 0;
+    const bool walking = S.nfin != 0u;
+    int mmax = walking ? m : 0;
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-        mmin = min(mmin, __shfl_xor(mmin, o));
-        mmax = max(mmax, __shfl_xor(mmax, o));
-    }
+    for (int o = 32; o >= 1; o >>= 1) mmax = max(mmax, __shfl_xor(mmax, o));
 
-    // Query window of slice s for block jb: pair-relative positions jb - Emax + 32 s + [0, 64).
     // The window moves by one word per block, so each block loads only the
     // next high word (and the next reference word), one block ahead.
-    if (!fin) {
+    if (walking) {
 #pragma unroll
         for (int t = 0; t < RS; t++) {
             const int64_t a = b0 - Emax + 32 * (int64_t)(lip + LP * t);
-            q0lo[t] = bits32(Q0, SW, a);
-            q1lo[t] = bits32(Q1, SW, a);
-            n0[t] = bits32(Q0, SW, a + 32);
-            n1[t] = bits32(Q1, SW, a + 32);
+            W.q0lo[t] = ld.get(0, a);
+            W.q1lo[t] = ld.get(1, a);
+            n0[t] = ld.get(0, a + 32);
+            n1[t] = ld.get(1, a + 32);
         }
     }
-    uint32_t nr0 = fin ? 0u : bits32(R0, SW, b0), nr1 = fin ? 0u : bits32(R1, SW, b0);
+    uint32_t nr0 = walking ? ld.get(2, b0) : 0u, nr1 = walking ? ld.get(3, b0) : 0u;
     for (int jb = 0; jb < mmax; jb += 32) {
-        if (__all(finm != 0u)) break;
+        if (!__any(S.nfin != 0u)) break;
 #pragma unroll
-        for (int t = 0; t < RS; t++) { q0hi[t] = n0[t]; q1hi[t] = n1[t]; }
-        const uint32_t rw0 = nr0, rw1 = nr1;
-        if (jb + 32 < mmax && finm == 0u) {
+        for (int t = 0; t < RS; t++) { W.q0hi[t] = n0[t]; W.q1hi[t] = n1[t]; }
+        W.r0 = nr0;
+        W.r1 = nr1;
+        if (jb + 32 < mmax && S.nfin != 0u) {
 #pragma unroll
             for (int t = 0; t < RS; t++) {
                 const int64_t a = b0 + jb + 64 - Emax + 32 * (int64_t)(lip + LP * t);
-                n0[t] = bits32(Q0, SW, a);
-                n1[t] = bits32(Q1, SW, a);
+                n0[t] = ld.get(0, a);
+                n1[t] = ld.get(1, a);
             }
-            nr0 = bits32(R0, SW, b0 + jb + 32);
-            nr1 = bits32(R1, SW, b0 + jb + 32);
+            nr0 = ld.get(2, b0 + jb + 32);
+            nr1 = ld.get(3, b0 + jb + 32);
         }
-        const int jend = min(32, mmax - jb);
-        if ((jb >= Emax) && (jb + 31 + Emax < mmin))
-            sweep_block<RS, false>(alive, rmask, q0lo, q0hi, q1lo, q1hi, rw0, rw1, jb, jend, m, Ei, Emax, LP, lip,
-                                   count, finm);
-        else
-            sweep_block<RS, true>(alive, rmask, q0lo, q0hi, q1lo, q1hi, rw0, rw1, jb, jend, m, Ei, Emax, LP, lip,
-                                  count, finm);
+        // block kind, uniform over the wavefront: a walking pair ends here;
+        // some row may meet a query position outside [0, m); neither
+        const bool end = __any(S.nfin != 0u && m <= jb + 32);
+        const bool mask = end || jb < Emax || __any(S.nfin != 0u && m <= jb + 31 + Emax);
+        if (mask) {
 #pragma unroll
-        for (int t = 0; t < RS; t++) { q0lo[t] = q0hi[t]; q1lo[t] = q1hi[t]; }
+            for (int t = 0; t < RS; t++) {
+                const int base = jb - Emax + 32 * (lip + LP * t);      // query position of window bit 0
+                W.vlo[t] = span_mask(-base, m - base);
+                W.vhi[t] = span_mask(-base - 32, m - base - 32);
+            }
+        }
+        if (end)
+            block_end<RS, LPC>(S, W, LP, jb, min(32, mmax - jb), m);
+        else if (mask)
+            block_full<RS, LPC, true>(S, W, LP);
+        else
+            block_full<RS, LPC, false>(S, W, LP);
+#pragma unroll
+        for (int t = 0; t < RS; t++) { W.q0lo[t] = W.q0hi[t]; W.q1lo[t] = W.q1hi[t]; }
     }
+    const int count = Ei - S.slack;
     return count > Ei + 1 ? Ei + 1 : count;
 }
 
