@@ -125,9 +125,11 @@ def verify_leg(torch, runner, db, out, n, E, steps):
     return r
 
 
-def sweep_leg(torch, ss, gen, runner, config, Es, steps, batch=None):
+def sweep_leg(torch, ss, gen, runner, config, Es, steps, batch=None, plain_and_wave=False):
     """Threshold sweep on one resident batch: the two-kernel path encodes once and sweeps each E;
-    the one-call path (fused up to E = 5, chunked above) runs per E.  Mean ms per launch."""
+    the one-call path (fused up to E = 5, chunked above) runs per E.  plain_and_wave: also the
+    one-pair-per-lane kernel and the wavefront-cooperative kernel on the bit-stream encoding, per E,
+    with outputs checked equal to the sweep's.  Mean ms per launch."""
     b = batch if batch is not None else gen.make(config, threads=min(16, os.cpu_count() or 1))
     db = runner.DeviceBatch(b)
     n, m = db.n, db.uniform_m
@@ -137,8 +139,10 @@ def sweep_leg(torch, ss, gen, runner, config, Es, steps, batch=None):
     db.pack_sliced(packed=packed)
     torch.cuda.synchronize()
     _, (enc_ms,) = timed_loop([lambda: db.pack_sliced(packed=packed)], steps, torch)
+    ps = db.pack_stream() if plain_and_wave else None
     per_E = {}
     same = True
+    same_pw = True
     for E in Es:
         db.filter_sliced(packed, E, out=out)
         db.filter_fused(E, out=out1)
@@ -147,6 +151,16 @@ def sweep_leg(torch, ss, gen, runner, config, Es, steps, batch=None):
         _, (sw_ms, one_ms) = timed_loop([lambda: db.filter_sliced(packed, E, out=out),
                                          lambda: db.filter_fused(E, out=out1)], steps, torch)
         per_E[E] = dict(sweep_ms=round(sw_ms, 4), one_call_ms=round(one_ms, 4))
+        if plain_and_wave:
+            db.filter_plain(ps, E, out=out1)
+            torch.cuda.synchronize()
+            same_pw = same_pw and bool(torch.equal(out, out1))
+            db.filter_wave(ps, E, out=out1)
+            torch.cuda.synchronize()
+            same_pw = same_pw and bool(torch.equal(out, out1))
+            _, (pl_ms, wv_ms) = timed_loop([lambda: db.filter_plain(ps, E, out=out1),
+                                            lambda: db.filter_wave(ps, E, out=out1)], steps, torch)
+            per_E[E].update(plain_ms=round(pl_ms, 4), wave_ms=round(wv_ms, 4))
     assert not db.bad_bases()
     total_sweep = enc_ms + sum(v["sweep_ms"] for v in per_E.values())
     log(f"sweep config {config} ({n} x {m} bp): encode {enc_ms:.3f} ms, E={Es[0]}..{Es[-1]} "
@@ -155,7 +169,13 @@ def sweep_leg(torch, ss, gen, runner, config, Es, steps, batch=None):
                whole_sweep_ms=round(total_sweep, 4),
                whole_sweep_pair_thresholds_per_s=n * len(Es) / (1e-3 * total_sweep),
                one_call_equals_two_kernel=same)
-    del db, packed, out, out1
+    if plain_and_wave:
+        pl = sum(v["plain_ms"] for v in per_E.values())
+        wv = sum(v["wave_ms"] for v in per_E.values())
+        res.update(plain_all_E_ms=round(pl, 4), wave_all_E_ms=round(wv, 4), plain_and_wave_identical=same_pw)
+        log(f"sweep config {config}: one pair per lane {pl:.3f} ms, wavefront-cooperative {wv:.3f} ms over "
+            f"E={Es[0]}..{Es[-1]} on the bit stream, identical={same_pw}")
+    del db, packed, out, out1, ps
     torch.cuda.empty_cache()
     return res
 
@@ -505,7 +525,8 @@ def main():
     sweeps = None
     if not a.no_sweep:
         sweeps = {"100bp_30M_E0-10": sweep_leg(torch, ss, gen, runner, 1, list(range(0, 11)), 5, batch=b),
-                  "250bp_10M_E0-25": sweep_leg(torch, ss, gen, runner, 2, list(range(0, 26)), 3)}
+                  "250bp_10M_E0-25": sweep_leg(torch, ss, gen, runner, 2, list(range(0, 26)), 3,
+                                               plain_and_wave=True)}
     long_pairs = None if a.no_sweep else long_leg(torch, ss, gen, runner, oracle)
 
     mixed = None

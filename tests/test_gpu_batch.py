@@ -181,3 +181,44 @@ def test_plan_width_raised_and_limit(env):
         ss.ss_server_submit(srv, b["reads"], b["refs"], b["lengths"], np.array([9000], np.int32), acc, ed)
     assert ei.value.status == ss.SS_ELEN
     ss.ss_server_destroy(srv)
+
+
+def _one_lane_batch(shuffle):
+    """Pairs whose rows fit one lane (2E+1 <= 31, and 32..63 at two slices): 100 bp pairs whose
+    block items fit the LDS stage, 3 kbp pairs whose items do not, and an empty and two one-base
+    pairs at the end of the stream.  shuffle: input order unrelated to stream order (every item's
+    span of stream words is then large, so the items read global memory)."""
+    rng = np.random.default_rng(7)
+    a = gen.make(0, n=700)
+    bl = gen.long_pairs(300, 3000, 300, 1500, seed=19)
+    base = len(a["reads"]) + len(bl["reads"])
+    reads = np.concatenate([a["reads"], bl["reads"], np.frombuffer(b"GA", np.uint8)])
+    refs = np.concatenate([a["refs"], bl["refs"], np.frombuffer(b"GC", np.uint8)])
+    offsets = np.concatenate([[base], a["offsets"], bl["offsets"] + len(a["reads"]), [base, base + 1]])
+    lengths = np.concatenate([[0], a["lengths"], bl["lengths"], [1, 1]])
+    n = len(lengths)
+    E = np.where(rng.random(n) < 0.2, rng.integers(16, 32, n), rng.integers(0, 16, n)).astype(np.int32)
+    order = rng.permutation(n) if shuffle else np.arange(n)
+    b = dict(n=n, reads=reads, refs=refs, offsets=offsets[order].astype(np.int64),
+             lengths=lengths[order].astype(np.int32), E=E)
+    want = oracle.batch(b["reads"], b["refs"], b["offsets"], b["lengths"], E_per_pair=b["E"], threads=8)
+    return b, (want["accept"], want["edits"])
+
+
+@pytest.mark.parametrize("shuffle", [False, True])
+def test_one_lane_items_staged_and_global(env, shuffle):
+    """Items of one-lane pairs: staged in LDS when their stream span fits, else read from global
+    memory; both against the oracle, at three slice widths."""
+    ss, runner, torch = env
+    b, want = _one_lane_batch(shuffle)
+    db = runner.DeviceBatch(b)
+    ps = db.pack_stream()
+    ctx = runner.context()
+    for spl in (1, 4, 8):
+        print(f"  shuffle={shuffle} slices_per_lane={spl}", flush=True)
+        plan = ss.ss_plan_create(ctx, b["lengths"], b["E"], spl)
+        out = db.new_out()
+        ss.ss_filter_planned_async(ctx, plan, ps, db.total, db.offsets, db.lengths, db.E, out)
+        torch.cuda.synchronize()
+        _check(runner.results_numpy(out, db.n), want, f"one-lane items shuffle={shuffle} spl={spl}")
+        ss.ss_plan_destroy(plan)
