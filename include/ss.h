@@ -283,12 +283,15 @@ int ss_plan_capture(ss_ctx* ctx, ss_plan* plan, const uint32_t* packed, int64_t 
                     const int64_t* offsets, const int32_t* lengths, const int32_t* E_per_pair, uint16_t* out);
 int ss_plan_launch(ss_plan* plan, void* stream);
 
-/* Autotuned plan: times the candidate shapes (1, 2, 4, 8 slices per lane) on
- * this batch with the given device buffers (out_dev is overwritten), keeps
- * the fastest and records it in the JSON file cache_path (may be NULL) under
- * a key made of the device architecture and a coarse signature of the batch;
- * a later call with a matching key skips the timing.  *chosen_slices (may be
- * NULL) receives the choice.  Synchronous. */
+/* Autotuned plan: times the candidate shapes (1, 2, 4, 8 slices per lane),
+ * each with the persistent grid at as many resident blocks per CU as fit and
+ * at two, on this batch with the given device buffers (out_dev is
+ * overwritten), keeps the fastest and records it in the JSON file cache_path
+ * (may be NULL; value = slices + 100 x blocks per CU, 0 meaning as many as
+ * fit) under a key made of the device architecture and a coarse signature of
+ * the batch; a later call with a matching key skips the timing.
+ * *chosen_slices (may be NULL) receives the slice width; ss_plan_info reports
+ * the grid.  Synchronous. */
 int ss_plan_create_tuned(ss_ctx* ctx, const int32_t* lengths, const int32_t* E_per_pair, int64_t n_pairs,
                          const uint32_t* packed, int64_t total_bases, const int64_t* offsets_dev,
                          const int32_t* lengths_dev, const int32_t* E_dev, uint16_t* out_dev,

@@ -9,10 +9,10 @@
 // behind, and short items that read the same stretch of the input run
 // together.
 //
-// Launch: one persistent kernel; each 256-thread block pops the next item
-// from a device counter and runs the wavefront sweep of ss_wave.h on it, until
-// the queue is empty.  Every block exits once the counter passes the number
-// of items, so the grid always drains.
+// Launch: one persistent kernel; each 256-thread block runs the wavefront
+// sweep of ss_wave.h on the item of its own index, then on items popped from
+// a device counter, until the queue is empty.  Every block exits once the
+// counter passes the number of items, so the grid always drains.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -114,11 +114,12 @@ __global__ __launch_bounds__(256) void k_persist(const PItem* __restrict__ items
     __shared__ long long s_lo[4], s_hi[4];
     __shared__ uint32_t s_stage[4 * kStageWords];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // The first item of a block is its own index: the items come largest first
+    // and blocks are dispatched round-robin over the CUs, so the most expensive
+    // items start one per CU instead of wherever the race for the counter puts
+    // them.  Later items are popped from the counter (offset by the grid).
+    int it = blockIdx.x;
     for (;;) {
-        if (threadIdx.x == 0) s_item = atomicAdd(head, 1);
-        __syncthreads();
-        const int it = __builtin_amdgcn_readfirstlane(s_item);
-        __syncthreads();
         if (it >= n_items) break;
         // the item is the same for the whole block: keep its fields in scalar registers
         const int64_t first = items[it].first;
@@ -163,6 +164,10 @@ __global__ __launch_bounds__(256) void k_persist(const PItem* __restrict__ items
             c = sweep_shape<RSMAX>(rs, LP, wave::GlobalPlanes{pk, SW}, b0, m, Ei, ok, lip, emax);
         }
         if (ok && lip == 0) out[pi] = wave::result_word(c, Ei);
+        if (threadIdx.x == 0) s_item = (int)gridDim.x + atomicAdd(head, 1);
+        __syncthreads();
+        it = __builtin_amdgcn_readfirstlane(s_item);
+        __syncthreads();
     }
 }
 
@@ -322,6 +327,7 @@ using namespace ss;
 // Tunables chosen per plan.
 struct PlanCfg {
     int rsmax = 8;          // slices per lane at most (1, 2, 4 or 8)
+    int blocks_per_cu = 0;  // resident blocks per CU of the persistent grid (0: as many as fit)
 };
 
 struct ss_plan {
@@ -375,7 +381,8 @@ int upload_plan(ss_plan* P)
     (void)hipGetDevice(&dev);
     hipDeviceProp_t prop;
     if ((e = hipGetDeviceProperties(&prop, dev)) != hipSuccess) return map_err(e);
-    const int per_cu = persist_blocks_per_cu(P->cfg.rsmax);
+    int per_cu = persist_blocks_per_cu(P->cfg.rsmax);
+    if (P->cfg.blocks_per_cu > 0) per_cu = std::min(per_cu, P->cfg.blocks_per_cu);
     P->grid = (int)std::min<int64_t>((int64_t)per_cu * prop.multiProcessorCount, std::max<size_t>(P->items.size(), 1));
     return SS_OK;
 }
@@ -509,9 +516,15 @@ extern "C" int ss_plan_launch(ss_plan* plan, void* stream)
 
 // ---------------------------------------------------------------- autotuner
 // Candidate configurations are timed on the batch itself (two launches each,
-// the faster counts); the winner is stored in a JSON cache keyed by device
-// architecture and a coarse signature of the batch (pair count, length and
-// threshold ranges), so later plans for similar batches skip the timing.
+// the faster counts): every slice width, each with the grid at as many
+// resident blocks per CU as fit and at two.  The work-group dispatcher fills
+// a CU's slots before the next CU's, so with three or more slots the first
+// (largest) items can land three to a CU and run a third as fast; two slots
+// avoid that for batches led by a few long pairs, while batches of short
+// pairs gain from the extra wavefronts.  The winner is stored in a JSON cache
+// keyed by device architecture and a coarse signature of the batch (pair
+// count, length and threshold ranges) as slices + 100 x blocks per CU, so
+// later plans for similar batches skip the timing.
 namespace {
 
 std::string signature(const char* arch, const int32_t* lengths, const int32_t* E, int64_t n)
@@ -588,16 +601,18 @@ extern "C" int ss_plan_create_tuned(ss_ctx* ctx, const int32_t* lengths, const i
             std::lock_guard<std::mutex> lk(g_cache_mu);
             auto m = read_cache(cache_path);
             auto it = m.find(key);
-            if (it != m.end() && (it->second == 1 || it->second == 2 || it->second == 4 || it->second == 8)) {
+            const int sl = it != m.end() ? it->second % 100 : 0, bpc = it != m.end() ? it->second / 100 : 0;
+            if (it != m.end() && (sl == 1 || sl == 2 || sl == 4 || sl == 8) && bpc >= 0 && bpc <= 64) {
                 PlanCfg cfg;
-                cfg.rsmax = std::max<int>(it->second, rsmin);
+                cfg.rsmax = std::max<int>(sl, rsmin);
+                cfg.blocks_per_cu = bpc;
                 if (chosen_slices) *chosen_slices = cfg.rsmax;
                 return make_plan(cfg, lengths, E_per_pair, n_pairs, out);
             }
         }
         const int cands[4] = {1, 2, 4, 8};
         float best_ms = 1e30f;
-        int best = 8;
+        int best = 8, best_bpc = 0;
         hipStream_t s = nullptr;
         hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
         if (e != hipSuccess) return map_err(e);
@@ -611,21 +626,28 @@ extern "C" int ss_plan_create_tuned(ss_ctx* ctx, const int32_t* lengths, const i
             ss_plan* P = nullptr;
             rc = make_plan(cfg, lengths, E_per_pair, n_pairs, &P);
             if (rc != SS_OK) break;
-            float ms = 1e30f;
-            for (int rep = 0; rep < 2 && rc == SS_OK; rep++) {
-                (void)hipEventRecord(a, s);
-                e = enqueue(P, packed, total_bases, offsets_dev, lengths_dev, E_dev, out_dev, s);
-                (void)hipEventRecord(b, s);
-                if (e == hipSuccess) e = hipEventSynchronize(b);
-                float t = 0;
-                if (e == hipSuccess) (void)hipEventElapsedTime(&t, a, b);
-                else rc = map_err(e);
-                ms = std::min(ms, t);
+            // the same plan at both grids (the grid is a launch parameter only)
+            const int full_grid = P->grid;
+            const int two_grid = (int)std::min<int64_t>(2 * (int64_t)prop.multiProcessorCount, full_grid);
+            for (int g = 0; g < 2 && rc == SS_OK; g++) {
+                if (g == 1 && two_grid == full_grid) break;
+                P->grid = g == 0 ? full_grid : two_grid;
+                float ms = 1e30f;
+                for (int rep = 0; rep < 2 && rc == SS_OK; rep++) {
+                    (void)hipEventRecord(a, s);
+                    e = enqueue(P, packed, total_bases, offsets_dev, lengths_dev, E_dev, out_dev, s);
+                    (void)hipEventRecord(b, s);
+                    if (e == hipSuccess) e = hipEventSynchronize(b);
+                    float t = 0;
+                    if (e == hipSuccess) (void)hipEventElapsedTime(&t, a, b);
+                    else rc = map_err(e);
+                    ms = std::min(ms, t);
+                }
+                if (rc == SS_OK && ms < best_ms) { best_ms = ms; best = c; best_bpc = g == 0 ? 0 : 2; }
             }
             free_plan(P);
             delete P;
             if (rc != SS_OK) break;
-            if (ms < best_ms) { best_ms = ms; best = c; }
         }
         (void)hipEventDestroy(a);
         (void)hipEventDestroy(b);
@@ -634,11 +656,12 @@ extern "C" int ss_plan_create_tuned(ss_ctx* ctx, const int32_t* lengths, const i
         if (cache_path && *cache_path) {
             std::lock_guard<std::mutex> lk(g_cache_mu);
             auto m = read_cache(cache_path);
-            m[key] = best;
+            m[key] = best + 100 * best_bpc;
             write_cache(cache_path, m);
         }
         PlanCfg cfg;
         cfg.rsmax = best;
+        cfg.blocks_per_cu = best_bpc;
         if (chosen_slices) *chosen_slices = best;
         return make_plan(cfg, lengths, E_per_pair, n_pairs, out);
     } catch (const std::bad_alloc&) {

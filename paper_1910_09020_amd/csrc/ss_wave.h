@@ -125,17 +125,17 @@ struct Win {
     uint32_t r0, r1;
 };
 
-// v_bitop3 truth tables
-constexpr int kSelect = 0xD8;   // src2 ? src1 : src0
-constexpr int kClearIf = 0x70;  // src0 & ~(src1 & src2)
+// v_bitop3 truth table: src2 ? src1 : src0
+constexpr int kSelect = 0xD8;
 
 // One column of the walk at window shift sh.  MASK: AND each row with the
 // validity plane (rows whose query position falls outside [0, m) hold
 // obstacles); END: the pair's last column may lie in this block (column j).
 // A column where none of the pair's rows is still free holds the obstacle
-// that ends the longest escape segment: count it while the walk goes on,
-// stop the walk once the count exceeds the threshold, and free every row of
-// the pair again from the next column.
+// that ends the longest escape segment: count it while the walk goes on and
+// free every row of the pair again from the next column.  The stop once the
+// count exceeds the threshold is taken at block boundaries: counting a few
+// columns further changes neither min(count, E+1) nor the decision.
 template <int RS, int LPC, bool MASK, bool END>
 __device__ __forceinline__ void column(Share<RS>& S, const Win<RS>& W, int sh, int LP_rt, int j, int m)
 {
@@ -155,7 +155,6 @@ __device__ __forceinline__ void column(Share<RS>& S, const Win<RS>& W, int sh, i
     any = group_or(any, LP);
     const uint32_t deadm = any == 0u ? S.nfin : 0u;
     S.slack += (int)deadm;                                               // -1 on a counted obstacle
-    S.nfin = __builtin_amdgcn_bitop3_b32(S.nfin, deadm, (uint32_t)(S.slack >> 31), kClearIf);
     if (END) S.nfin = j + 1 >= m ? 0u : S.nfin;
 #pragma unroll
     for (int t = 0; t < RS; t++) S.alive[t] = __builtin_amdgcn_bitop3_b32(S.alive[t], S.rmask[t], deadm, kSelect);
@@ -250,6 +249,7 @@ __device__ __forceinline__ int sweep_pair(const LD& ld, int64_t b0, int m, int E
     }
     uint32_t nr0 = walking ? ld.get(2, b0) : 0u, nr1 = walking ? ld.get(3, b0) : 0u;
     for (int jb = 0; jb < mmax; jb += 32) {
+        S.nfin = S.slack < 0 ? 0u : S.nfin;                             // the count exceeds the threshold: stop
         if (!__any(S.nfin != 0u)) break;
 #pragma unroll
         for (int t = 0; t < RS; t++) { W.q0hi[t] = n0[t]; W.q1hi[t] = n1[t]; }
