@@ -265,20 +265,29 @@ bool plan_items(const int32_t* lengths, const int32_t* E, int64_t n, int rsmax, 
         *est_cost += work;
         i = j;
     }
-    // Largest items first, by cost level (powers of four); within a level, by
-    // the position of the item's first pair in the input, so that items of
-    // different (length, threshold) groups that read the same stretch of the
-    // bit stream run at about the same time and share its cache lines.
+    // Largest items first, by cost level (powers of four).  The estimate above
+    // cannot see where a walk stops; a pair with a larger threshold tends to
+    // walk further before its count exceeds it, so within a level items of
+    // several lanes per pair go by threshold (powers of two, largest first).
+    // Then by the position of the item's first pair in the input, so that
+    // items of different (length, threshold) groups that read the same
+    // stretch of the bit stream run at about the same time and share its
+    // cache lines (one-lane items, which the kernel stages, rely on that).
     std::vector<size_t> order(items.size());
     std::iota(order.begin(), order.end(), (size_t)0);
-    std::vector<int> level(items.size());
+    std::vector<int> level(items.size()), elevel(items.size());
     for (size_t k = 0; k < items.size(); k++) {
         int l = 0;
         for (double c = cost[k]; c >= 4.0; c *= 0.25) l++;
         level[k] = l;
+        int e = 0;
+        if (items[k].lp > 1)
+            for (int64_t v = (int64_t)items[k].emax + 1; v > 1; v >>= 1) e++;
+        elevel[k] = e;
     }
     std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
         if (level[a] != level[b]) return level[a] > level[b];
+        if (elevel[a] != elevel[b]) return elevel[a] > elevel[b];
         return perm[(size_t)items[a].first] < perm[(size_t)items[b].first];
     });
     std::vector<PItem> sorted;
