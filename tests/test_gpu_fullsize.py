@@ -82,3 +82,41 @@ def test_100bp_30M_E5(rt):
 def test_250bp_10M_E25(rt):
     b = gen.make(2)
     _run(rt, b, [24, 25], 25, 20_000)
+
+
+def test_mixed_5M_planned(rt, tmp_path):
+    """The mixed-length batch at full size (5 M short pairs + 20,000 pairs of 10 kbp, per-pair E), in
+    the benchmark's launch configuration: an autotuned plan replayed from a captured graph.  Every
+    pair against one unbucketed wavefront launch laid out for the largest threshold; a sample of
+    short and long pairs against the oracle."""
+    torch, runner = rt
+    import paper_1910_09020_amd as ss
+    b = gen.make(3, threads=min(16, os.cpu_count() or 1))
+    db = runner.DeviceBatch(b)
+    ps = db.pack_stream()
+    ctx = runner.context()
+    out = db.new_out()
+    print(f"  tuned plan n={db.n}", flush=True)
+    plan, _ = ss.ss_plan_create_tuned(ctx, b["lengths"], b["E"], ps, db.total, db.offsets, db.lengths, db.E, out,
+                                      str(tmp_path / "tune.json"))
+    ss.ss_plan_capture(ctx, plan, ps, db.total, db.offsets, db.lengths, db.E, out)
+    out.fill_(-1)
+    ss.ss_plan_launch(plan, torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    acc, ed = runner.results_numpy(out, db.n)
+    ss.ss_plan_destroy(plan)
+    assert not db.bad_bases()
+    print(f"  unbucketed wavefront launch E={int(b['E'].max())}", flush=True)
+    flat = db.filter_wave(ps, int(b["E"].max()), per_pair=True)
+    torch.cuda.synchronize()
+    fa, fe = runner.results_numpy(flat, db.n)
+    assert np.array_equal(acc, fa) and np.array_equal(ed, fe), "planned launch != unbucketed launch"
+    assert np.all(ed <= b["E"] + 1) and np.array_equal(acc == 1, ed <= b["E"])
+    rng = np.random.default_rng(5)
+    long_idx = np.nonzero(b["lengths"] >= 10000)[0]
+    short_idx = np.nonzero(b["lengths"] < 10000)[0]
+    idx = np.sort(np.concatenate([rng.choice(short_idx, 20_000, replace=False), rng.choice(long_idx, 100, replace=False)]))
+    w = oracle.batch(b["reads"], b["refs"], b["offsets"][idx], b["lengths"][idx], E_per_pair=b["E"][idx],
+                     threads=min(16, os.cpu_count() or 1))
+    bad = np.nonzero((w["accept"] != acc[idx]) | (w["edits"] != ed[idx]))[0]
+    assert len(bad) == 0, f"{len(bad)} sampled mismatches, first pairs {idx[bad[:5]]}"
