@@ -65,6 +65,9 @@ const char* ss_status_str(int status);
 #define SS_MAX_LEN        (1 << 24)
 #define SS_MAX_LEN_FUSED  2048    /* fused encode-and-filter kernel: m <= 2048 */
 #define SS_MAX_LEN_VERIFY 256     /* verification kernel: m <= 256 */
+/* wavefront, batched and serving paths: a bit stream of at most this many
+ * bases (each plane under 4 GiB: its words are read with 32-bit offsets) */
+#define SS_MAX_STREAM_BASES (32LL * ((1LL << 30) - 64))
 
 /* Device result word, one per pair: bit 15 = accept, bits 0..14 = obstacle
  * count reported by the walk (min(count, E+1)). */
@@ -202,10 +205,10 @@ int ss_filter_plain_async(ss_ctx* ctx, const uint32_t* packed, int64_t total_bas
 
 /* Wavefront-cooperative filter: one or more pairs per 64-lane wavefront,
  * the 2E+1 rows spread over lanes as 32-row bit slices; every column is
- * one step of the sweep and a wavefront ballot decides whether any row is
- * still free since the checkpoint.  Any E up to SS_MAX_E.  Arguments as
- * ss_filter_plain_async (E is the per-launch maximum when E_per_pair is
- * given). */
+ * one step of the sweep and an OR over the pair's lanes decides whether any
+ * row is still free since the checkpoint.  Any E up to SS_MAX_E.  Arguments
+ * as ss_filter_plain_async (E is the per-launch maximum when E_per_pair is
+ * given); SS_ELEN for total_bases above SS_MAX_STREAM_BASES. */
 int ss_filter_wave_async(ss_ctx* ctx, const uint32_t* packed, int64_t total_bases,
                          const int64_t* offsets, const int32_t* lengths,
                          const int32_t* E_per_pair, int64_t n_pairs, int32_t E,
@@ -269,9 +272,10 @@ int ss_plan_info(const ss_plan* plan, int64_t* n_items, int32_t* n_classes, int3
                  int32_t* slices_per_lane);
 
 /* Run a plan on bit-stream encoded pairs (device arrays as for
- * ss_filter_wave_async; E_per_pair is required).  Enqueues a counter reset
- * and the persistent kernel on stream.  One call at a time per plan (the
- * queue counter is part of the plan). */
+ * ss_filter_wave_async; E_per_pair is required; SS_ELEN for total_bases
+ * above SS_MAX_STREAM_BASES, here and in the capture and autotuner calls).
+ * Enqueues a counter reset and the persistent kernel on stream.  One call at
+ * a time per plan (the queue counter is part of the plan). */
 int ss_filter_planned_async(ss_ctx* ctx, const ss_plan* plan, const uint32_t* packed, int64_t total_bases,
                             const int64_t* offsets, const int32_t* lengths, const int32_t* E_per_pair,
                             uint16_t* out, void* stream);
@@ -321,7 +325,8 @@ int64_t ss_server_footprint(int64_t n_pairs, int64_t total_bases);
  * required).  accept_out / edits_out (host, n_pairs entries) are written by
  * the server before the ticket reports done, and must stay valid until then.
  * SS_EBUDGET if the request alone needs more than the budget; SS_ELEN for a
- * threshold above SS_MAX_E_PLANNED.  Validation of lengths and thresholds
+ * threshold above SS_MAX_E_PLANNED or more than SS_MAX_STREAM_BASES bases.
+ * Validation of lengths and thresholds
  * happens here; the alphabet is checked on the device and reported by
  * ss_server_wait (outputs then untouched). */
 int ss_server_submit(ss_server* server, const uint8_t* reads, const uint8_t* refs, const int32_t* lengths,

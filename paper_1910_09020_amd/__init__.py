@@ -25,8 +25,10 @@ SS_MAX_E_SLICED = 32
 SS_MAX_E_PLAIN = 31
 SS_MAX_E = 16383
 SS_MAX_E_PLANNED = 8191
+SS_MAX_LEN = 1 << 24
 SS_MAX_LEN_FUSED = 2048
 SS_MAX_LEN_VERIFY = 256
+SS_MAX_STREAM_BASES = 32 * ((1 << 30) - 64)
 SS_RESULT_ACCEPT = 0x8000
 SS_RESULT_COUNT = 0x7FFF
 

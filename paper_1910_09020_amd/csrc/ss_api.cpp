@@ -245,7 +245,7 @@ extern "C" int ss_filter_wave_async(ss_ctx* ctx, const uint32_t* packed, int64_t
                                     int64_t n_pairs, int32_t E, uint16_t* out, void* stream)
 {
     if (!ctx || n_pairs < 0 || total_bases < 0 || E < 0) return SS_EINVAL;
-    if (E > SS_MAX_E) return SS_ELEN;
+    if (E > SS_MAX_E || total_bases > SS_MAX_STREAM_BASES) return SS_ELEN;
     if (n_pairs == 0) return SS_OK;
     if (!packed || !offsets || !lengths || !out) return SS_EINVAL;
     return map_err(launch_wave(packed, ss_stream_words(total_bases), offsets, lengths, E_per_pair, n_pairs, E, out,

@@ -486,6 +486,7 @@ extern "C" int ss_filter_planned_async(ss_ctx* ctx, const ss_plan* plan, const u
                                        uint16_t* out, void* stream)
 {
     if (!ctx || !plan || total_bases < 0) return SS_EINVAL;
+    if (total_bases > SS_MAX_STREAM_BASES) return SS_ELEN;
     if (plan->n == 0) return SS_OK;
     if (!packed || !offsets || !lengths || !E_per_pair || !out) return SS_EINVAL;
     return map_err(enqueue(plan, packed, total_bases, offsets, lengths, E_per_pair, out, (hipStream_t)stream));
@@ -497,7 +498,8 @@ extern "C" int ss_plan_capture(ss_ctx* ctx, ss_plan* plan, const uint32_t* packe
                                const int64_t* offsets, const int32_t* lengths, const int32_t* E_per_pair,
                                uint16_t* out)
 {
-    if (!ctx || !plan) return SS_EINVAL;
+    if (!ctx || !plan || total_bases < 0) return SS_EINVAL;
+    if (total_bases > SS_MAX_STREAM_BASES) return SS_ELEN;
     if (plan->n > 0 && (!packed || !offsets || !lengths || !E_per_pair || !out)) return SS_EINVAL;
     if (plan->exec) { (void)hipGraphExecDestroy(plan->exec); plan->exec = nullptr; }
     if (plan->graph) { (void)hipGraphDestroy(plan->graph); plan->graph = nullptr; }
@@ -598,6 +600,8 @@ extern "C" int ss_plan_create_tuned(ss_ctx* ctx, const int32_t* lengths, const i
     int rc = validate_plan_inputs(lengths, E_per_pair, n_pairs);
     if (rc != SS_OK) return rc;
     if (n_pairs > 0 && (!packed || !offsets_dev || !lengths_dev || !E_dev || !out_dev)) return SS_EINVAL;
+    if (total_bases < 0) return SS_EINVAL;
+    if (total_bases > SS_MAX_STREAM_BASES) return SS_ELEN;
     const int rsmin = plan_min_slices(E_per_pair, n_pairs);
     if (rsmin == 0) return SS_ELEN;
     int dev = 0;

@@ -420,6 +420,7 @@ extern "C" int ss_server_submit(ss_server* S, const uint8_t* reads, const uint8_
         if (lengths[i] > SS_MAX_LEN || E_per_pair[i] > SS_MAX_E) return SS_ELEN;
         T += lengths[i];
     }
+    if (T > SS_MAX_STREAM_BASES) return SS_ELEN;
     Request* r = nullptr;
     try {
         r = new Request();

@@ -5,11 +5,12 @@
 // 2E+1 rows (slice s = lane_in_pair + LP * t holds rows 32s..32s+31, row index
 // r = k + Emax for diagonal offset k).  Each column is one step of the greedy
 // walk of Section 2.4 read column-wise: a row still free since the checkpoint
-// stays alive if its Equation 1 cell is 0; a wavefront ballot tells whether
-// any row of the pair is still alive; if none, the column holds the obstacle
-// that closes the longest escape segment: count it, and every row is free
-// again from the next column (the new checkpoint).  A pair stops counting once
-// its count exceeds its threshold (step 4) and reports min(count, E+1).
+// stays alive if its Equation 1 cell is 0; an OR over the pair's lanes (lane
+// permutes) tells whether any row of the pair is still alive; if none, the
+// column holds the obstacle that closes the longest escape segment: count it,
+// and every row is free again from the next column (the new checkpoint).  A
+// pair stops counting once its count exceeds its threshold (step 4, taken at
+// 32-column block boundaries) and reports min(count, E+1).
 #pragma once
 #include "ss_common.h"
 
@@ -43,12 +44,24 @@ __device__ __forceinline__ uint32_t span_mask(int lo, int hi)
     return up & ~dn;
 }
 
-// Window loaders for the sweep: get(p, a) returns 32 bits of plane p
-// (0, 1: query; 2, 3: reference) starting at absolute stream bit a.
+// Word loaders for the sweep: word(p, w) returns word w of plane p (0, 1:
+// query; 2, 3: reference), zero outside the plane.
+//
+// From HBM through buffer loads: the hardware range check returns zero for an
+// offset past the plane, and every word index outside [0, SW) (negative ones
+// included) is sent to one such offset, so each load is issued
+// unconditionally, with no branch around it.  A plane must be smaller than
+// 2^30 - 64 words (SS_MAX_STREAM_BASES).
 struct GlobalPlanes {
-    const uint32_t* __restrict__ pk;
+    const uint32_t* pk;
     int64_t SW;
-    __device__ __forceinline__ uint32_t get(int p, int64_t a) const { return bits32(pk + p * SW, SW, a); }
+    __device__ __forceinline__ uint32_t word(int p, int w) const
+    {
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<uint32_t*>(pk + p * SW), (short)0, (int)(uint32_t)(SW * 4), 0x00020000);
+        const uint32_t off = (uint32_t)w < (uint32_t)SW ? (uint32_t)w << 2 : 0xFFFFFFF0u;
+        return (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0);
+    }
 };
 
 // Words [lo, lo + nw) of each plane staged in LDS (plane p at st + p * cap);
@@ -59,14 +72,10 @@ struct StagedPlanes {
     const uint32_t* st;
     int64_t lo;
     int nw, cap;
-    __device__ __forceinline__ uint32_t word(int p, int i) const
+    __device__ __forceinline__ uint32_t word(int p, int w) const
     {
+        const int i = (int)(w - lo);
         return (unsigned)i < (unsigned)nw ? st[p * cap + i] : 0u;
-    }
-    __device__ __forceinline__ uint32_t get(int p, int64_t a) const
-    {
-        const int i = (int)((a >> 5) - lo);
-        return __builtin_amdgcn_alignbit(word(p, i + 1), word(p, i), (uint32_t)(a & 31));
     }
 };
 
@@ -226,28 +235,39 @@ __device__ __forceinline__ int sweep_pair(const LD& ld, int64_t b0, int m, int E
         const int lo = Emax - Ei - 32 * s, hi = Emax + Ei + 1 - 32 * s;
         S.rmask[t] = span_mask(lo, hi < NR - 32 * s ? hi : NR - 32 * s);
         S.alive[t] = S.rmask[t];
-        W.q0lo[t] = W.q0hi[t] = W.q1lo[t] = W.q1hi[t] = W.vlo[t] = W.vhi[t] = n0[t] = n1[t] = 0u;
+        W.vlo[t] = W.vhi[t] = 0u;
     }
     S.nfin = (!pair_ok || m == 0) ? 0u : ~0u;
     S.slack = pair_ok ? Ei : 0;
-    const bool walking = S.nfin != 0u;
-    int mmax = walking ? m : 0;
+    int mmax = S.nfin != 0u ? m : 0;
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) mmax = max(mmax, __shfl_xor(mmax, o));
 
-    // The window moves by one word per block, so each block loads only the
-    // next high word (and the next reference word), one block ahead.
-    if (walking) {
+    // Window words.  Slice t's query window at block jb starts at stream bit
+    // b0 - Emax + 32 s + jb, i.e. at bit shq of word wq + s + jb/32; the
+    // reference bits of block jb start at bit shr of word wr + jb/32.  The
+    // window moves by one word per block, so each block loads one new word
+    // per plane and slice (and per reference plane), one block ahead, and
+    // keeps the last one (c0, c1, cr0, cr1) for the next funnel shift.
+    const int64_t aq = b0 - Emax;
+    const int wq = (int)(aq >> 5), wr = (int)(b0 >> 5);       // arithmetic shift: floor
+    const uint32_t shq = (uint32_t)(aq & 31), shr = (uint32_t)(b0 & 31);
+    uint32_t c0[RS], c1[RS];
 #pragma unroll
-        for (int t = 0; t < RS; t++) {
-            const int64_t a = b0 - Emax + 32 * (int64_t)(lip + LP * t);
-            W.q0lo[t] = ld.get(0, a);
-            W.q1lo[t] = ld.get(1, a);
-            n0[t] = ld.get(0, a + 32);
-            n1[t] = ld.get(1, a + 32);
-        }
+    for (int t = 0; t < RS; t++) {
+        const int w = wq + lip + LP * t;
+        const uint32_t a0 = ld.word(0, w), b0w = ld.word(0, w + 1), d0 = ld.word(0, w + 2);
+        const uint32_t a1 = ld.word(1, w), b1w = ld.word(1, w + 1), d1 = ld.word(1, w + 2);
+        W.q0lo[t] = __builtin_amdgcn_alignbit(b0w, a0, shq);
+        W.q1lo[t] = __builtin_amdgcn_alignbit(b1w, a1, shq);
+        n0[t] = __builtin_amdgcn_alignbit(d0, b0w, shq);
+        n1[t] = __builtin_amdgcn_alignbit(d1, b1w, shq);
+        c0[t] = d0;
+        c1[t] = d1;
     }
-    uint32_t nr0 = walking ? ld.get(2, b0) : 0u, nr1 = walking ? ld.get(3, b0) : 0u;
+    uint32_t cr0 = ld.word(2, wr + 1), cr1 = ld.word(3, wr + 1);
+    uint32_t nr0 = __builtin_amdgcn_alignbit(cr0, ld.word(2, wr), shr);
+    uint32_t nr1 = __builtin_amdgcn_alignbit(cr1, ld.word(3, wr), shr);
     for (int jb = 0; jb < mmax; jb += 32) {
         S.nfin = S.slack < 0 ? 0u : S.nfin;                             // the count exceeds the threshold: stop
         if (!__any(S.nfin != 0u)) break;
@@ -255,15 +275,22 @@ __device__ __forceinline__ int sweep_pair(const LD& ld, int64_t b0, int m, int E
         for (int t = 0; t < RS; t++) { W.q0hi[t] = n0[t]; W.q1hi[t] = n1[t]; }
         W.r0 = nr0;
         W.r1 = nr1;
-        if (jb + 32 < mmax && S.nfin != 0u) {
+        if (jb + 32 < mmax) {
+            const int k = jb >> 5;
 #pragma unroll
             for (int t = 0; t < RS; t++) {
-                const int64_t a = b0 + jb + 64 - Emax + 32 * (int64_t)(lip + LP * t);
-                n0[t] = ld.get(0, a);
-                n1[t] = ld.get(1, a);
+                const int w = wq + lip + LP * t + k + 3;
+                const uint32_t x0 = ld.word(0, w), x1 = ld.word(1, w);
+                n0[t] = __builtin_amdgcn_alignbit(x0, c0[t], shq);
+                n1[t] = __builtin_amdgcn_alignbit(x1, c1[t], shq);
+                c0[t] = x0;
+                c1[t] = x1;
             }
-            nr0 = ld.get(2, b0 + jb + 32);
-            nr1 = ld.get(3, b0 + jb + 32);
+            const uint32_t y0 = ld.word(2, wr + k + 2), y1 = ld.word(3, wr + k + 2);
+            nr0 = __builtin_amdgcn_alignbit(y0, cr0, shr);
+            nr1 = __builtin_amdgcn_alignbit(y1, cr1, shr);
+            cr0 = y0;
+            cr1 = y1;
         }
         // block kind, uniform over the wavefront: a walking pair ends here;
         // some row may meet a query position outside [0, m); neither

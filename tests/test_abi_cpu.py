@@ -57,3 +57,15 @@ def test_missing_library_fails_loudly(tmp_path):
             "try:\n    ss.lib()\nexcept RuntimeError as e:\n    print('RAISED', e)\n" % str(tmp_path / "none.so"))
     r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True)
     assert "RAISED" in r.stdout and "no CPU fallback" in r.stdout
+
+
+def test_header_limits_match_binding():
+    """Every SS_MAX_* limit of include/ss.h has the same value in the binding."""
+    import paper_1910_09020_amd as ss
+    text = open(os.path.join(ROOT, "include", "ss.h")).read()
+    found = 0
+    for name, expr in re.findall(r"^#define\s+(SS_MAX_\w+)\s+(.+?)\s*(?:/\*.*)?$", text, flags=re.M):
+        value = eval(re.sub(r"(\d+)LL", r"\1", expr), {})      # integer literals and shifts only
+        assert getattr(ss, name) == value, name
+        found += 1
+    assert found >= 8

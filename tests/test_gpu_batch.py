@@ -224,3 +224,29 @@ def test_one_lane_items_staged_and_global(env, shuffle):
         torch.cuda.synchronize()
         _check(runner.results_numpy(out, db.n), want, f"one-lane items shuffle={shuffle} spl={spl}")
         ss.ss_plan_destroy(plan)
+
+
+def test_stream_limit_refused_before_launch(env):
+    """A bit stream longer than SS_MAX_STREAM_BASES (planes past 4 GiB) is refused with SS_ELEN by the
+    wavefront, planned and capture calls before anything is enqueued; outputs stay untouched."""
+    ss, runner, torch = env
+    b, _ = _mixed(n=2000, n_long=2)
+    db = runner.DeviceBatch(b)
+    ps = db.pack_stream()
+    ctx = runner.context()
+    plan = ss.ss_plan_create(ctx, b["lengths"], b["E"], 4)
+    out = db.new_out()
+    out.fill_(-1)
+    torch.cuda.synchronize()
+    too_long = ss.SS_MAX_STREAM_BASES + 1
+    calls = [lambda: ss.ss_filter_planned_async(ctx, plan, ps, too_long, db.offsets, db.lengths, db.E, out),
+             lambda: ss.ss_plan_capture(ctx, plan, ps, too_long, db.offsets, db.lengths, db.E, out),
+             lambda: ss.ss_filter_wave_async(ctx, ps, too_long, db.offsets, db.lengths, db.E, db.n,
+                                             int(b["E"].max()), out)]
+    for call in calls:
+        with pytest.raises(ss.SSError) as e:
+            call()
+        assert e.value.status == ss.SS_ELEN
+    torch.cuda.synchronize()
+    assert bool((out == -1).all())
+    ss.ss_plan_destroy(plan)
