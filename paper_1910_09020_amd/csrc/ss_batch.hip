@@ -114,10 +114,11 @@ __global__ __launch_bounds__(256) void k_persist(const PItem* __restrict__ items
     __shared__ long long s_lo[4], s_hi[4];
     __shared__ uint32_t s_stage[4 * kStageWords];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    // The first item of a block is its own index: the items come largest first
-    // and blocks are dispatched round-robin over the CUs, so the most expensive
-    // items start one per CU instead of wherever the race for the counter puts
-    // them.  Later items are popped from the counter (offset by the grid).
+    // The first item of a block is its own index (the grid starts on the
+    // largest items without a round of atomics); later items are popped from
+    // the counter, offset by the grid.  How those first items fall on the CUs
+    // is the dispatcher's: it fills a CU's resident slots before the next
+    // CU's, which is why the autotuner also tries two blocks per CU.
     int it = blockIdx.x;
     for (;;) {
         if (it >= n_items) break;
