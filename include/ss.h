@@ -267,6 +267,14 @@ typedef struct ss_plan ss_plan;
 int ss_plan_create(ss_ctx* ctx, const int32_t* lengths, const int32_t* E_per_pair, int64_t n_pairs,
                    int32_t slices_per_lane, ss_plan** out);
 int ss_plan_destroy(ss_plan* plan);
+/* Host only (no device work; for inspection and tests): the work items a plan
+ * for these pairs holds, in queue order.  *n_items receives their number;
+ * when items is non-null, up to max_items of them as five int64 each (first
+ * slot in the permutation, pairs, lanes per pair, slices per lane, largest
+ * threshold); when perm is non-null, the n_pairs-entry permutation (pair
+ * index per slot).  Errors as ss_plan_create. */
+int ss_plan_items_host(const int32_t* lengths, const int32_t* E_per_pair, int64_t n_pairs, int32_t slices_per_lane,
+                       int64_t* n_items, int64_t* items, int64_t max_items, int64_t* perm);
 /* Items in the queue, shape classes, persistent grid size, slices per lane. */
 int ss_plan_info(const ss_plan* plan, int64_t* n_items, int32_t* n_classes, int32_t* grid,
                  int32_t* slices_per_lane);

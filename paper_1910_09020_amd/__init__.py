@@ -71,6 +71,7 @@ def lib():
         "ss_unpack_results_async": ([vp, vp, i64, vp, vp, vp], ctypes.c_int),
         "ss_plan_create": ([vp, vp, vp, i64, i32, ctypes.POINTER(vp)], ctypes.c_int),
         "ss_plan_destroy": ([vp], ctypes.c_int),
+        "ss_plan_items_host": ([vp, vp, i64, i32, vp, vp, i64, vp], ctypes.c_int),
         "ss_plan_info": ([vp, vp, vp, vp, vp], ctypes.c_int),
         "ss_filter_planned_async": ([vp, vp, vp, i64, vp, vp, vp, vp, vp], ctypes.c_int),
         "ss_plan_capture": ([vp, vp, vp, i64, vp, vp, vp, vp], ctypes.c_int),
@@ -104,7 +105,8 @@ def exported_symbols():
             "ss_sliced_bytes", "ss_stream_words", "ss_pack_sliced_async", "ss_filter_sliced_async",
             "ss_filter_ascii_async", "ss_pack_stream_async", "ss_filter_plain_async", "ss_filter_wave_async",
             "ss_unpack_results_async", "ss_verify_async", "ss_select_accepted_async", "ss_filter_submaze_async",
-            "ss_plan_create", "ss_plan_destroy", "ss_plan_info", "ss_filter_planned_async", "ss_plan_capture",
+            "ss_plan_create", "ss_plan_items_host", "ss_plan_destroy", "ss_plan_info", "ss_filter_planned_async",
+            "ss_plan_capture",
             "ss_plan_launch", "ss_plan_create_tuned", "ss_server_create", "ss_server_submit", "ss_server_poll",
             "ss_server_wait", "ss_server_times", "ss_server_cancel", "ss_server_release", "ss_server_set_hold",
             "ss_server_stats", "ss_server_destroy", "ss_server_footprint", "ss_server_set_slices"]
@@ -252,6 +254,22 @@ def ss_plan_create(ctx, lengths, E_per_pair, slices_per_lane: int = 8) -> int:
     _check(lib().ss_plan_create(ctx, _ptr(lengths), _ptr(Epp), len(lengths), int(slices_per_lane), ctypes.byref(h)),
            "ss_plan_create")
     return h.value
+
+
+def ss_plan_items_host(lengths, E_per_pair, slices_per_lane: int = 8):
+    """The work items (rows: first slot, pairs, lanes per pair, slices per lane, largest E; queue order) and
+    the permutation a plan for these pairs holds, computed on the host."""
+    lengths = np.ascontiguousarray(lengths, dtype=np.int32)
+    Epp = np.ascontiguousarray(E_per_pair, dtype=np.int32)
+    n = len(lengths)
+    k = ctypes.c_int64(0)
+    _check(lib().ss_plan_items_host(_ptr(lengths), _ptr(Epp), n, int(slices_per_lane), ctypes.addressof(k), None, 0,
+                                    None), "ss_plan_items_host")
+    items = np.zeros((k.value, 5), dtype=np.int64)
+    perm = np.zeros(n, dtype=np.int64)
+    _check(lib().ss_plan_items_host(_ptr(lengths), _ptr(Epp), n, int(slices_per_lane), ctypes.addressof(k),
+                                    _ptr(items), k.value, _ptr(perm)), "ss_plan_items_host")
+    return items, perm
 
 
 def ss_plan_destroy(plan) -> None:

@@ -463,6 +463,40 @@ extern "C" int ss_plan_create(ss_ctx* ctx, const int32_t* lengths, const int32_t
     }
 }
 
+extern "C" int ss_plan_items_host(const int32_t* lengths, const int32_t* E_per_pair, int64_t n_pairs,
+                                  int32_t slices_per_lane, int64_t* n_items, int64_t* items, int64_t max_items,
+                                  int64_t* perm)
+{
+    if (!n_items) return SS_EINVAL;
+    if (slices_per_lane != 1 && slices_per_lane != 2 && slices_per_lane != 4 && slices_per_lane != 8) return SS_EINVAL;
+    int rc = validate_plan_inputs(lengths, E_per_pair, n_pairs);
+    if (rc != SS_OK) return rc;
+    if (n_pairs == 0) { *n_items = 0; return SS_OK; }
+    const int rsmin = plan_min_slices(E_per_pair, n_pairs);
+    if (rsmin == 0) return SS_ELEN;
+    try {
+        std::vector<PItem> it;
+        std::vector<int64_t> pm;
+        int nc = 0;
+        double cost = 0;
+        if (!plan_items(lengths, E_per_pair, n_pairs, std::max<int>(slices_per_lane, rsmin), it, pm, &nc, &cost))
+            return SS_ELEN;
+        *n_items = (int64_t)it.size();
+        if (items)
+            for (int64_t k = 0; k < std::min<int64_t>(max_items, (int64_t)it.size()); k++) {
+                items[5 * k + 0] = it[(size_t)k].first;
+                items[5 * k + 1] = it[(size_t)k].count;
+                items[5 * k + 2] = it[(size_t)k].lp;
+                items[5 * k + 3] = it[(size_t)k].rs;
+                items[5 * k + 4] = it[(size_t)k].emax;
+            }
+        if (perm) std::memcpy(perm, pm.data(), pm.size() * sizeof(int64_t));
+    } catch (const std::bad_alloc&) {
+        return SS_ENOMEM;
+    }
+    return SS_OK;
+}
+
 extern "C" int ss_plan_destroy(ss_plan* plan)
 {
     if (!plan) return SS_EINVAL;
