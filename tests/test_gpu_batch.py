@@ -41,7 +41,7 @@ def test_planned_matches_oracle(env):
     db = runner.DeviceBatch(b)
     ps = db.pack_stream()
     ctx = runner.context()
-    for spl in (4, 8):
+    for spl in (1, 2, 4, 8):       # 1 and 2: the 10 kbp pairs take 32 or 64 lanes (the permlane votes)
         print(f"  plan slices_per_lane={spl}", flush=True)
         plan = ss.ss_plan_create(ctx, b["lengths"], b["E"], spl)
         info = ss.ss_plan_info(plan)
