@@ -313,6 +313,16 @@ def mixed_leg(a, torch, ss, gen, runner, oracle):
                      threads=min(16, os.cpu_count() or 1), want_stats=True)
     mism = int(np.sum((w["accept"] != acc[idx]) | (w["edits"] != ed[idx])))
     ss.ss_plan_destroy(plan)
+    # the oracle's rate on this batch, per class (short, long) on the same samples, timed apart:
+    # the whole batch would take n_short / short rate + n_long / long rate on these threads
+    threads = min(16, os.cpu_count() or 1)
+    rates = {}
+    for name, cls_idx in (("short", idx[b["lengths"][idx] < 10000]), ("long", idx[b["lengths"][idx] >= 10000])):
+        t0 = time.perf_counter()
+        oracle.batch(b["reads"], b["refs"], b["offsets"][cls_idx], b["lengths"][cls_idx], E_per_pair=b["E"][cls_idx],
+                     threads=threads)
+        rates[name] = len(cls_idx) / max(time.perf_counter() - t0, 1e-9)
+    oracle_batch_s = len(short_idx) / rates["short"] + len(long_idx) / rates["long"]
     # roofline by the op model of a row-wise bit-parallel walk: (2E+1) (5 ceil(c_last/32) + 3 K) 32-bit ops
     # per pair, c_last and the checkpoints K from the oracle's stats on the sample, scaled to the batch
     # by class (short / long)
@@ -328,13 +338,20 @@ def mixed_leg(a, torch, ss, gen, runner, oracle):
                speedup_vs_unbucketed=flat_ms / bat_ms, identical_outputs=identical, plan_seconds=round(plan_s, 3),
                plan=info, tuned_slices_per_lane=chosen, oracle_sample_pairs=int(len(idx)),
                oracle_sample_mismatches=mism,
+               cpu_oracle={"threads": threads, "short_pairs_per_s": rates["short"], "long_pairs_per_s": rates["long"],
+                           "whole_batch_s": oracle_batch_s, "gpu_speedup": oracle_batch_s / (1e-3 * bat_ms),
+                           "sample": f"{int((b['lengths'][idx] < 10000).sum())} short and "
+                                     f"{int((b['lengths'][idx] >= 10000).sum())} long pairs of the batch, timed "
+                                     "apart; whole batch = n_short / short rate + n_long / long rate"},
                roofline={"bound": "alu", "model": "(2E+1)(5 ceil(c_last/32) + 3 checkpoints) 32-bit ops per pair "
                                                    "(oracle stats on the sample, scaled to the batch by class)",
                          "model_ops": model_ops, "achieved": achieved_tops, "peak": VALU_PEAK_TOPS,
                          "unit": "T ops/s", "frac": achieved_tops / VALU_PEAK_TOPS})
     log(f"mixed: batched {bat_ms:.3f} ms, unbucketed {flat_ms:.3f} ms, identical={identical}, "
         f"oracle mismatches {mism}/{len(idx)}, plan {plan_s:.2f}s {info}; op model {model_ops / 1e9:.1f} G ops "
-        f"-> {achieved_tops:.1f} T ops/s ({100 * achieved_tops / VALU_PEAK_TOPS:.0f}% of {VALU_PEAK_TOPS} T)")
+        f"-> {achieved_tops:.1f} T ops/s ({100 * achieved_tops / VALU_PEAK_TOPS:.0f}% of {VALU_PEAK_TOPS} T); oracle on "
+        f"{threads} threads: {rates['short'] / 1e6:.2f} M short + {rates['long']:.0f} long pairs/s -> whole batch "
+        f"{oracle_batch_s:.2f} s ({oracle_batch_s / (1e-3 * bat_ms):.0f}x the launch)")
     del db, ps, out, uout
     torch.cuda.empty_cache()
     return res
