@@ -444,7 +444,7 @@ def main():
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported (pairs shard independently "
-              "across GPUs with no collective; see the design notes).", file=sys.stderr)
+              "across GPUs with no collective on the path).", file=sys.stderr)
         sys.exit(2)
 
     import torch

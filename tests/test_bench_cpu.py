@@ -1,0 +1,24 @@
+"""Host-side checks of bench.py's contract that need no GPU: one GPU only, and the traffic summary
+it reads resolves for the sources as they stand."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], cwd=ROOT,
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode != 0
+    assert "one GPU only" in (r.stdout + r.stderr)
+    assert not r.stdout.strip().startswith("{")          # no JSON line
+
+
+def test_traffic_summary_matches_sources():
+    """The PMC traffic lines bench.py reports are valid only while the kernel sources hash to the values
+    recorded next to them; a stale summary must be re-taken, not reported."""
+    sys.path.insert(0, ROOT)
+    import bench
+    for name in ("k_fused_E5", "k_pack_tile", "k_sliced_E5"):
+        assert bench.measured_traffic(name) is not None, name
