@@ -26,7 +26,7 @@
  * Q is the query (read).  Bytes are case-folded; the oracle compares bytes and
  * does not validate the alphabet.
  *
- * Readings taken where the paper is silent (all listed in the design notes):
+ * Readings taken where the paper is silent:
  *   - a cell whose Q index falls outside 1..m is an obstacle (Eq. 1 "otherwise");
  *   - a row that reaches column m without an obstacle ends the walk without
  *     counting; an obstacle exactly at column m is counted;
