@@ -250,3 +250,58 @@ def test_stream_limit_refused_before_launch(env):
     torch.cuda.synchronize()
     assert bool((out == -1).all())
     ss.ss_plan_destroy(plan)
+
+
+def _random_batch(rng, n):
+    """n pairs of random lengths (0..2000, 32-bit word edges over-represented) and thresholds (0..250),
+    references made from the read by substitutions at a per-pair rate (some unrelated), stored back to back."""
+    edges = np.array([0, 1, 2, 31, 32, 33, 63, 64, 65, 95, 96, 97, 127, 128, 129, 255, 256, 257], np.int32)
+    lengths = np.where(rng.random(n) < 0.3, rng.choice(edges, n),
+                       np.exp(rng.uniform(0, np.log(2000), n)).astype(np.int32))
+    E = np.minimum(rng.integers(0, 251, n), np.maximum(lengths // 4, rng.integers(0, 6, n))).astype(np.int32)
+    bases = np.frombuffer(b"ACGT", np.uint8)
+    reads, refs = [], []
+    for m in lengths:
+        r = rng.choice(bases, int(m))
+        q = r.copy()
+        if rng.random() < 0.1:
+            q = rng.choice(bases, int(m))
+        else:
+            hit = rng.random(int(m)) < rng.uniform(0, 0.2)
+            q[hit] = rng.choice(bases, int(hit.sum()))
+        reads.append(q)
+        refs.append(r)
+    offsets = np.zeros(n, np.int64)
+    offsets[1:] = np.cumsum(lengths[:-1])
+    return dict(n=n, reads=np.concatenate(reads) if n else np.zeros(0, np.uint8),
+                refs=np.concatenate(refs) if n else np.zeros(0, np.uint8), offsets=offsets,
+                lengths=lengths.astype(np.int32), E=E)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_batches_against_oracle(env, seed):
+    """Random lengths and thresholds (every block kind of the wavefront sweep, partial last blocks, 1 to 64
+    lanes per pair, staged and unstaged one-lane items), in input order and shuffled, at every slice width:
+    the planned launch and the standalone wavefront kernel against the oracle."""
+    ss, runner, torch = env
+    rng = np.random.default_rng(1000 + seed)
+    b = _random_batch(rng, 1500)
+    if seed % 2:
+        order = rng.permutation(b["n"])
+        b = dict(b, offsets=b["offsets"][order], lengths=b["lengths"][order], E=b["E"][order])
+    want = oracle.batch(b["reads"], b["refs"], b["offsets"], b["lengths"], E_per_pair=b["E"], threads=8)
+    want = (want["accept"], want["edits"])
+    db = runner.DeviceBatch(b)
+    ps = db.pack_stream()
+    ctx = runner.context()
+    spl = (1, 2, 4, 8)[seed % 4]
+    print(f"  seed={seed} slices_per_lane={spl} Emax={int(b['E'].max())}", flush=True)
+    plan = ss.ss_plan_create(ctx, b["lengths"], b["E"], spl)
+    out = db.new_out()
+    ss.ss_filter_planned_async(ctx, plan, ps, db.total, db.offsets, db.lengths, db.E, out)
+    torch.cuda.synchronize()
+    _check(runner.results_numpy(out, db.n), want, f"planned seed={seed}")
+    ss.ss_plan_destroy(plan)
+    wout = db.filter_wave(ps, int(b["E"].max()), per_pair=True)
+    torch.cuda.synchronize()
+    _check(runner.results_numpy(wout, db.n), want, f"wavefront seed={seed}")
