@@ -156,18 +156,20 @@ int ss_filter_submaze_async(ss_ctx* ctx, const uint32_t* packed, int64_t n_pairs
  * results are identical to ss_pack_sliced_async followed by
  * ss_filter_sliced_async (Equation 1 operands, Section 2.4 walk); the schedule
  * depends on E:
- *   E <= 5 : one fused kernel.  Each workgroup encodes tile_groups groups of
- *            32 pairs into on-chip memory and sweeps them there, so the packed
- *            encoding never reaches device memory.
+ *   E <= 5 : one fused kernel.  Three wavefronts of each workgroup encode
+ *            tiles of tile_groups groups of 32 pairs into one of two on-chip
+ *            buffers while the fourth sweeps the previous tile from the other,
+ *            so the packed encoding never reaches device memory.
  *   E > 5  : the two kernels over chunks of about 400 MB of packed data, kept
  *            in a buffer owned by ctx (allocated on first use, grown when a
  *            longer m needs it): calls with E > 5 on one context must be
  *            ordered (one stream), or use one context per stream.
  *   n_pairs >= 0; 0 <= m <= SS_MAX_LEN_FUSED; 0 <= E <= SS_MAX_E_SLICED
- *   tile_groups : groups per workgroup of the fused kernel, 1..256, or 0 for
- *                 the automatic choice (the largest tile that keeps two
- *                 workgroups per CU); SS_EINVAL when the tile does not fit
- *                 on-chip memory
+ *   tile_groups : groups per tile of the fused kernel, 1..256, or 0 for the
+ *                 automatic choice (the largest tile whose two buffers keep
+ *                 two workgroups per CU: 16 at 100 bp); SS_EINVAL when two
+ *                 tiles and the staging do not fit on-chip memory (at
+ *                 100 bp, 40 groups fit and 64 do not)
  *   out         : n_pairs result words (see SS_RESULT_*), 16-byte aligned
  *   err         : one device uint32; bit 0 is OR-ed in when a byte outside
  *                 ACGTacgt is seen (the caller zeroes it beforehand); the

@@ -94,7 +94,7 @@ __global__ __launch_bounds__(256) void k_pack_tile(const uint8_t* __restrict__ r
     uint32_t bad = 0;
     tile::load_encode_groups(reads, refs, offsets, index, n_pairs, m, g0, GB, fast, lds,
                              reinterpret_cast<uint4*>(packed), G, g0, bad);
-    if (bad && err) atomicOr(err, 1u);
+    if (tile::invalid(bad) && err) atomicOr(err, 1u);
 }
 
 }  // namespace
@@ -143,18 +143,19 @@ hipError_t launch_sliced(const uint32_t* packed, int64_t n_pairs, int32_t m, int
     return launch_sliced_hi(E, packed, n_pairs, m, sub_width, out, s);
 }
 
-// Tile shape of the fused kernel: T groups per block, staged GB at a time.
-// Returns the LDS bytes per block, or 0 when no shape fits.
+// Tile shape of the fused kernel: T groups per tile buffer (two of them),
+// staged GB at a time.  Returns the LDS bytes per block, or 0 when no shape fits.
 size_t fused_shape(int32_t m, int tile_groups, int* T_out, int* GB_out)
 {
-    const int64_t mw = cdiv(m, 4);
     const int64_t stage_b = (int64_t)tile::stage_dwords(m) * 4;
-    const int64_t pk_b = 16 * 4 * mw;                     // four planes of 16-byte chunks per group
-    auto lds_for = [&](int64_t T, int64_t GB) { return ((GB * stage_b + 15) & ~(int64_t)15) + T * pk_b; };
-    // staging groups: the most whose bytes the fused kernel's loads cover (so the streaming path
-    // applies), and whose staging fits 32 KiB
+    const int64_t buf_b = 16ll * tile::fused_group_chunks(m);   // one group in one tile buffer
+    auto lds_for = [&](int64_t T, int64_t GB) { return ((GB * stage_b + 15) & ~(int64_t)15) + 2 * T * buf_b; };
+    // staging groups: the most whose bytes the encoding threads' loads cover (so the
+    // streaming path applies), and whose staging fits 32 KiB
     int GB = 8;
-    while (GB > 1 && (GB * stage_b > 32768 || tile::fast_mode(m, GB, true, tile::kFusedQ) == 0)) GB >>= 1;
+    while (GB > 1 &&
+           (GB * stage_b > 32768 || tile::fast_mode(m, GB, true, tile::kFusedQ, tile::kFusedThreads) == 0))
+        GB >>= 1;
     int T = tile_groups;
     if (T <= 0) {
         // largest multiple of GB that keeps two blocks per CU, else one
@@ -182,7 +183,8 @@ hipError_t launch_fused(const uint8_t* reads, const uint8_t* refs, int64_t n_pai
     int T = 0, GB = 0;
     const size_t shmem = fused_shape(m, tile_groups, &T, &GB);
     if (shmem == 0) return hipErrorInvalidValue;
-    const int fast = tile::fast_mode(m, GB, (((uintptr_t)reads | (uintptr_t)refs) & 15u) == 0, tile::kFusedQ);
+    const int fast = tile::fast_mode(m, GB, (((uintptr_t)reads | (uintptr_t)refs) & 15u) == 0, tile::kFusedQ,
+                                     tile::kFusedThreads);
     return launch_fused_lo(E, reads, refs, n_pairs, m, T, GB, fast, shmem, out, err, s);
 }
 

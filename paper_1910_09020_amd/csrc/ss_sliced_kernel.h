@@ -97,6 +97,49 @@ __device__ __forceinline__ uint32_t comp(const uint4& v, int t)
 
 __device__ __forceinline__ constexpr int floordiv(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
 
+// Decide and write (step 5) for the 32 pairs of group g from the thermometer
+// T (T[l-1]: count >= l): accept = count <= E, count in binary digits; one
+// 16-bit word per pair (bit 15 accept, low bits the count).
+template <int E>
+__device__ __forceinline__ void write_group(const uint32_t (&T)[E + 1], int64_t g, int64_t n_pairs,
+                                            uint16_t* __restrict__ out)
+{
+    constexpr int NB = (E + 1) < 2 ? 1 : (E + 1) < 4 ? 2 : (E + 1) < 8 ? 3 : (E + 1) < 16 ? 4 : (E + 1) < 32 ? 5 : 6;
+    uint32_t dig[NB];
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+        uint32_t x = 0;
+#pragma unroll
+        for (int i = 1; (i << b) <= E + 1; i++) x ^= T[(i << b) - 1];
+        dig[b] = x;
+    }
+    const uint32_t acc = ~T[E];
+    const int64_t p0 = g * 32;
+    uint32_t res[16];
+#pragma unroll
+    for (int s2 = 0; s2 < 16; s2++) {
+        uint32_t v[2];
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            const int s = 2 * s2 + h;
+            uint32_t x = ((acc >> s) & 1u) << 15;
+#pragma unroll
+            for (int b = 0; b < NB; b++) x |= ((dig[b] >> s) & 1u) << b;
+            v[h] = x;
+        }
+        res[s2] = v[0] | (v[1] << 16);
+    }
+    if (p0 + 32 <= n_pairs) {
+        uint4* o = reinterpret_cast<uint4*>(out + p0);
+#pragma unroll
+        for (int q = 0; q < 4; q++) o[q] = make_uint4(res[4 * q], res[4 * q + 1], res[4 * q + 2], res[4 * q + 3]);
+    } else {
+#pragma unroll
+        for (int s = 0; s < 32; s++)
+            if (p0 + s < n_pairs) out[p0 + s] = (uint16_t)(res[s >> 1] >> (16 * (s & 1)));
+    }
+}
+
 // Interior chunk loop variants.
 enum { MAIN_CIRC = 0, MAIN_SHIFT4 = 1 };
 
@@ -225,41 +268,7 @@ __device__ __forceinline__ void sweep_group(LD&& ld, int m, int64_t g, int64_t n
     }
     checked_range(max(EC, ct), nch);
 
-    // ---- decide and write (step 5): thermometer -> binary digits, one word per pair
-    constexpr int NB = (E + 1) < 2 ? 1 : (E + 1) < 4 ? 2 : (E + 1) < 8 ? 3 : (E + 1) < 16 ? 4 : (E + 1) < 32 ? 5 : 6;
-    uint32_t dig[NB];
-#pragma unroll
-    for (int b = 0; b < NB; b++) {
-        uint32_t x = 0;
-#pragma unroll
-        for (int i = 1; (i << b) <= E + 1; i++) x ^= st.T[(i << b) - 1];
-        dig[b] = x;
-    }
-    const uint32_t acc = ~st.T[E];
-    const int64_t p0 = g * 32;
-    uint32_t res[16];
-#pragma unroll
-    for (int s2 = 0; s2 < 16; s2++) {
-        uint32_t v[2];
-#pragma unroll
-        for (int h = 0; h < 2; h++) {
-            const int s = 2 * s2 + h;
-            uint32_t x = ((acc >> s) & 1u) << 15;
-#pragma unroll
-            for (int b = 0; b < NB; b++) x |= ((dig[b] >> s) & 1u) << b;
-            v[h] = x;
-        }
-        res[s2] = v[0] | (v[1] << 16);
-    }
-    if (p0 + 32 <= n_pairs) {
-        uint4* o = reinterpret_cast<uint4*>(out + p0);
-#pragma unroll
-        for (int q = 0; q < 4; q++) o[q] = make_uint4(res[4 * q], res[4 * q + 1], res[4 * q + 2], res[4 * q + 3]);
-    } else {
-#pragma unroll
-        for (int s = 0; s < 32; s++)
-            if (p0 + s < n_pairs) out[p0 + s] = (uint16_t)(res[s >> 1] >> (16 * (s & 1)));
-    }
+    write_group<E>(st.T, g, n_pairs, out);
 }
 
 template <int E, int MODE, bool SUB>
@@ -279,66 +288,227 @@ __global__ __launch_bounds__(256) void k_sliced(const uint32_t* __restrict__ pk,
         m, g, n_pairs, out, sub_width);
 }
 
+// ---------------------------------------------------------------- fused kernel
+// Roles in a fused block of 256 threads: waves 0..2 encode, wave 3 sweeps.
+constexpr int kFusedEnc = tile::kFusedThreads;
+constexpr int kFusedEncQ = tile::kFusedQ;
+
+// Lanes that sweep one group: for E > 0 the 2E+1 rows are split over a quad's
+// lanes, so the 16 groups of a 100 bp tile fill the sweeping wavefront and a
+// lane runs about 18 instructions per column (at E = 5) instead of 44.
+constexpr int fused_lanes(int E) { return E == 0 ? 1 : 4; }
+constexpr int kFusedCPI = 2;   // chunks per item of the sweep (one LDS round trip per item)
+
+// OR of x over the LPG consecutive lanes of one group (LPG = 1, 2 or 4; the
+// lanes of a group lie in one quad)
+template <int LPG>
+__device__ __forceinline__ uint32_t quad_or(uint32_t x)
+{
+    if (LPG >= 2) x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0xB1, 0xF, 0xF, false);   // quad_perm 1,0,3,2
+    if (LPG >= 4) x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x4E, 0xF, 0xF, false);   // quad_perm 2,3,0,1
+    return x;
+}
+
+// Column sweep of one group held in LDS in the group-major layout (word P of
+// plane p at gp[p * 4 * nch + P]; planes Q0, Q1, R0, R1) by LPG lanes, CPI
+// chunks of four columns per call, so that a sweep can be cut into pieces.
+// Lane h of the group takes SL = ceil((2E+1) / LPG) of the rows, diagonal
+// offsets sh - E .. sh - E + SL - 1 with sh = min(h * SL, 2E + 1 - SL) (the last
+// lane may repeat rows of the one before it, which leaves the OR over rows
+// unchanged); its slot i at column j compares reference position j with query
+// position j + vb + i, vb = sh - E.  A column's "some row is free" is the OR
+// over the group's lanes of each lane's own OR, so every lane keeps the same
+// count (the thermometer Tm, as in SweepState).
+template <int E, int LPG, int CPI>
+struct TileSweep {
+    static constexpr int NR = 2 * E + 1;
+    static constexpr int SL = (NR + LPG - 1) / LPG;
+    static constexpr int B = kChunk;
+    static constexpr int NC = B * CPI;        // columns per call
+    static constexpr int NQ = SL + NC - 1;    // query words they read, per lane and plane
+    static constexpr int EC = (E + B - 1) / B;
+    uint32_t S[SL];
+    uint32_t Tm[E + 1];
+
+    __device__ __forceinline__ static int first_query(int h) { return min(h * SL, NR - SL) - E; }
+
+    __device__ __forceinline__ void init()
+    {
+#pragma unroll
+        for (int i = 0; i < SL; i++) S[i] = ~0u;
+#pragma unroll
+        for (int l = 0; l <= E; l++) Tm[l] = 0u;
+    }
+
+    template <bool CHK>
+    __device__ __forceinline__ void columns(const uint32_t (&w0)[NQ], const uint32_t (&w1)[NQ],
+                                            const uint4 (&rr0)[CPI], const uint4 (&rr1)[CPI], int j0, int vb, int m)
+    {
+#pragma unroll
+        for (int t = 0; t < NC; t++) {
+            const int j = j0 + t;
+            if (CHK && j >= m) break;
+            const uint32_t r0 = comp(rr0[t / B], t % B), r1 = comp(rr1[t / B], t % B);
+            uint32_t any = 0;
+#pragma unroll
+            for (int i = 0; i < SL; i++) {
+                uint32_t a = and_xnor(and_xnor(S[i], r0, w0[t + i]), r1, w1[t + i]);
+                if (CHK && (unsigned)(j + vb + i) >= (unsigned)m) a = 0;
+                S[i] = a;
+                any |= a;
+            }
+            any = quad_or<LPG>(any);
+#pragma unroll
+            for (int l = E; l >= 1; l--) Tm[l] = or_and_not(Tm[l], Tm[l - 1], any);
+            Tm[0] = or_not(Tm[0], any);
+#pragma unroll
+            for (int i = 0; i < SL; i++) S[i] = or_not(S[i], any);
+        }
+    }
+
+    // chunks c .. c+CPI-1 (columns 4c .. 4c+NC-1, those below m); interior: every
+    // row of every lane reads a query position in [0, m) and every chunk is below
+    // nch (then all reads stay inside the group's planes)
+    __device__ __forceinline__ void chunks(const uint32_t* __restrict__ gp, int nch, int m, int vb, int c,
+                                           bool interior)
+    {
+        const uint4* __restrict__ gp4 = reinterpret_cast<const uint4*>(gp);
+        uint4 rr0[CPI], rr1[CPI];
+        uint32_t w0[NQ], w1[NQ];
+        if (interior) {
+#pragma unroll
+            for (int k = 0; k < CPI; k++) { rr0[k] = gp4[2 * nch + c + k]; rr1[k] = gp4[3 * nch + c + k]; }
+            const uint32_t* __restrict__ q0 = gp + 4 * c + vb;
+            const uint32_t* __restrict__ q1 = q0 + 4 * nch;
+#pragma unroll
+            for (int x = 0; x < NQ; x++) { w0[x] = q0[x]; w1[x] = q1[x]; }
+            columns<false>(w0, w1, rr0, rr1, 4 * c, vb, m);
+        } else {
+            // chunks past nch and positions outside [0, m) read clamped places: those
+            // columns are not run and those rows are masked
+#pragma unroll
+            for (int k = 0; k < CPI; k++) {
+                const int ck = min(c + k, nch - 1);
+                rr0[k] = gp4[2 * nch + ck];
+                rr1[k] = gp4[3 * nch + ck];
+            }
+#pragma unroll
+            for (int x = 0; x < NQ; x++) {
+                const int P = min(max(4 * c + vb + x, 0), m - 1);
+                w0[x] = gp[P];
+                w1[x] = gp[4 * nch + P];
+            }
+            columns<true>(w0, w1, rr0, rr1, 4 * c, vb, m);
+        }
+    }
+};
+
 // Fused encode and sweep.  Tiles of T consecutive groups are dealt to the
-// blocks round-robin (persistent blocks).  A block encodes a tile GB groups at
-// a time from the ASCII pairs (stored back to back, pair i at byte i*m) into an
-// LDS copy of the lane-sliced layout; then lanes 0..T-1 sweep one group each
-// from LDS.  The packed encoding never reaches HBM.  Two register buffers take
-// turns: the loads of the next GB groups (possibly of the block's next tile)
-// are in flight while the current ones are encoded and while the tile is
-// swept.  LDS: GB * stage_dwords(m) dwords of staging, then 4 * nch * T words.
-// No barrier is needed around the sweep: encode_groups ends with one (the
-// tile is complete) and the next encode writes the tile only after its own
-// first barrier.
-template <int E, int MODE>
+// blocks round-robin (persistent blocks).  Waves 0..2 encode a tile GB groups at
+// a time from the ASCII pairs (stored back to back, pair i at byte i*m) into
+// one of two LDS tile buffers (group-major lane-sliced layout), while wave 3
+// sweeps the previous tile from the other buffer.  The packed encoding never
+// reaches HBM.  Two register buffers take turns: the loads of the next GB
+// groups (possibly of the block's next tile) are in flight while the current
+// ones are encoded.
+//
+// Synchronisation: encoding GB groups passes four block barriers; the sweeping
+// wave takes part in every one of them.  While tile i is encoded (4 * steps(i)
+// barriers) it sweeps tile i-1, its work (passes of 64 / LPG groups times nch
+// chunks) cut into as many pieces as there are barriers, one piece before each
+// barrier.  Tile i-1's last words were written before the barrier that ends its
+// encoding, and its buffer is written again only for tile i+1, after the
+// barrier that ends tile i's encoding, by which the sweep has finished.  The
+// last tile is swept after the encoding waves are done, without barriers.
+// LDS: GB * stage_dwords(m) dwords of staging, then two buffers of
+// T * tile::fused_group_chunks(m) uint4.
+template <int E>
 __global__ __launch_bounds__(256) void k_fused(const uint8_t* __restrict__ reads, const uint8_t* __restrict__ refs,
                                                int64_t n_pairs, int m, int T, int GB, int fast,
                                                uint16_t* __restrict__ out, uint32_t* __restrict__ err)
 {
     extern __shared__ uint32_t lds[];
     const int nch = (m + kChunk - 1) / kChunk;
+    const int GS = tile::fused_group_chunks(m);
     const int64_t G = (n_pairs + 31) / 32;
     const int64_t ntiles = (G + T - 1) / T;
     const int stage_w = (GB * tile::stage_dwords(m) + 3) & ~3;
-    uint4* __restrict__ pk4 = reinterpret_cast<uint4*>(lds + stage_w);
-    uint32_t bad = 0;
-    int64_t tl = blockIdx.x;               // current tile and group offset in it
-    int sb = 0;
-    if (tl >= ntiles) return;
+    uint4* __restrict__ buf0 = reinterpret_cast<uint4*>(lds + stage_w);
+    const int64_t t0 = blockIdx.x;
+    if (t0 >= ntiles) return;
+    const int64_t nmine = (ntiles - t0 + gridDim.x - 1) / gridDim.x;   // tiles of this block
+    auto tile_of = [&](int64_t i) { return t0 + i * (int64_t)gridDim.x; };
     auto tile_groups = [&](int64_t t) { return (int)min<int64_t>(T, G - t * T); };
-    auto advance = [&](int64_t& t, int& b) {
-        b += GB;
-        if (b >= tile_groups(t)) { t += gridDim.x; b = 0; }
-    };
-    // one step: encode the current GB groups from cur while the next groups'
-    // loads (possibly of the block's next tile) run; after a tile's last
-    // groups, sweep it; false when the block is done
-    auto step = [&](const uint4 (&cur)[2][tile::kFusedQ], uint4 (&nxt)[2][tile::kFusedQ]) -> bool {
-        int64_t tn = tl;
-        int bn = sb;
-        advance(tn, bn);
-        tile::load_groups<tile::kFusedQ>(reads, refs, n_pairs, m, tn * T + bn, GB, fast && tn < ntiles, nxt);
-        tile::encode_groups<tile::kFusedQ>(reads, refs, nullptr, nullptr, n_pairs, m, tl * T + sb, GB, fast, cur,
-                                           lds, pk4, T, sb, bad);
-        if (tn != tl) {
-            const int gl = threadIdx.x;
-            if (gl < tile_groups(tl)) {
-                sweep_group<E, MODE>([&](int plane, int c) -> uint4 { return pk4[(plane * nch + c) * T + gl]; }, m,
-                                     tl * T + gl, n_pairs, out);
+    auto steps_of = [&](int64_t i) { return (tile_groups(tile_of(i)) + GB - 1) / GB; };
+    auto buffer = [&](int64_t i) { return buf0 + (i & 1) * (int64_t)T * GS; };
+
+    if (threadIdx.x < kFusedEnc) {
+        uint32_t bad = 0;
+        int64_t i = 0;                   // tile index (of this block) and step in it
+        int s = 0;
+        // one step: encode the current GB groups from cur while the next groups'
+        // loads (possibly of the block's next tile) run; false when the block is done
+        auto step = [&](const uint4 (&cur)[2][kFusedEncQ], uint4 (&nxt)[2][kFusedEncQ]) -> bool {
+            int64_t in = i;
+            int sn = s + 1;
+            if (sn >= steps_of(i)) { sn = 0; in++; }
+            tile::load_groups<kFusedEncQ, kFusedEnc>(reads, refs, n_pairs, m, tile_of(in) * T + sn * GB, GB,
+                                                     fast && in < nmine, nxt);
+            tile::encode_groups<kFusedEncQ, kFusedEnc>(reads, refs, nullptr, nullptr, n_pairs, m,
+                                                       tile_of(i) * T + s * GB, GB, fast, cur, lds, buffer(i), 1,
+                                                       s * GB, bad, GS);
+            i = in;
+            s = sn;
+            return i < nmine;
+        };
+        uint4 va[2][kFusedEncQ], vb[2][kFusedEncQ];
+        tile::load_groups<kFusedEncQ, kFusedEnc>(reads, refs, n_pairs, m, t0 * T, GB, fast != 0, va);
+        for (;;) {
+            if (!step(va, vb)) break;
+            if (!step(vb, va)) break;
+        }
+        if (tile::invalid(bad) && err) atomicOr(err, 1u);
+    } else {
+        constexpr int LPG = fused_lanes(E);
+        constexpr int GPP = 64 / LPG;                    // groups per pass of the wave
+        constexpr int CPI = kFusedCPI;                   // chunks per item
+        using SW = TileSweep<E, LPG, CPI>;
+        const int lane = threadIdx.x - kFusedEnc;
+        const int h = lane % LPG, gq = lane / LPG;
+        const int vb = SW::first_query(h);
+        const int ct = (m - kChunk - E >= 0) ? (m - kChunk - E) / kChunk + 1 : 0;   // interior chunks [EC, ct)
+        SW sw;
+        for (int64_t i = 0; i <= nmine; i++) {
+            const int nint = i < nmine ? 4 * steps_of(i) : 0;     // barriers of tile i's encoding
+            if (i == 0) {
+                for (int b = 0; b < nint; b++) __syncthreads();
+                continue;
+            }
+            const int64_t tp = tile_of(i - 1);
+            const int tg = tile_groups(tp);
+            const uint32_t* __restrict__ tb = reinterpret_cast<const uint32_t*>(buffer(i - 1));
+            const int nci = nch > 0 ? (nch + CPI - 1) / CPI : 1;     // items per group (m = 0: the write alone)
+            const int work = ((tg + GPP - 1) / GPP) * nci;       // (pass, item) items
+            int it = 0, pass = 0, c = 0;
+            const int npiece = nint > 0 ? nint : 1;
+            for (int b = 0; b < npiece; b++) {
+                // equal pieces (weighting them towards either phase of the encoding measured slower)
+                const int end = nint > 0 ? (int)((int64_t)work * (b + 1) / nint) : work;
+                for (; it < end; it++) {
+                    const int gl = pass * GPP + gq;
+                    if (gl < tg) {
+                        if (c == 0) sw.init();
+                        const int c0 = c * CPI;
+                        if (c0 < nch)
+                            sw.chunks(tb + (int64_t)gl * GS * 4, nch, m, vb, c0, c0 >= SW::EC && c0 + CPI <= ct);
+                        if (c == nci - 1 && h == 0) write_group<E>(sw.Tm, tp * T + gl, n_pairs, out);
+                    }
+                    if (++c == nci) { c = 0; pass++; }
+                }
+                if (nint > 0) __syncthreads();
             }
         }
-        tl = tn;
-        sb = bn;
-        return tl < ntiles;
-    };
-    static_assert(MODE == MAIN_CIRC, "the fused kernel is instantiated for small thresholds only");
-    uint4 va[2][tile::kFusedQ], vb[2][tile::kFusedQ];
-    tile::load_groups<tile::kFusedQ>(reads, refs, n_pairs, m, tl * T, GB, fast != 0, va);
-    for (;;) {
-        if (!step(va, vb)) break;
-        if (!step(vb, va)) break;
     }
-    if (bad && err) atomicOr(err, 1u);
 }
 
 template <int E>
@@ -363,22 +533,21 @@ hipError_t launch_fused_E(const uint8_t* reads, const uint8_t* refs, int64_t n_p
                           int fast, size_t shmem, uint16_t* out, uint32_t* err, hipStream_t s)
 {
     const int64_t G = cdiv(n_pairs, 32);
-    constexpr int mode = E <= 10 ? MAIN_CIRC : MAIN_SHIFT4;
     if (shmem > 65536) {
-        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fused<E, mode>),
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fused<E>),
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
         if (e != hipSuccess) return e;
     }
     // persistent blocks: as many as are resident at once (LDS and registers), at most one per tile
     int per_cu = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per_cu, reinterpret_cast<const void*>(&k_fused<E, mode>), 256, shmem);
+        &per_cu, reinterpret_cast<const void*>(&k_fused<E>), 256, shmem);
     if (e != hipSuccess) return e;
     int dev = 0, cus = 0;
     if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
     if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
     const int64_t grid = std::min<int64_t>(cdiv(G, T), (int64_t)std::max(1, per_cu) * cus);
-    hipLaunchKernelGGL((k_fused<E, mode>), dim3((unsigned)grid), dim3(256), shmem, s, reads, refs, n_pairs, m, T,
+    hipLaunchKernelGGL((k_fused<E>), dim3((unsigned)grid), dim3(256), shmem, s, reads, refs, n_pairs, m, T,
                        GB, fast, out, err);
     return hipGetLastError();
 }
