@@ -144,12 +144,13 @@ hipError_t launch_sliced(const uint32_t* packed, int64_t n_pairs, int32_t m, int
 }
 
 // Tile shape of the fused kernel: T groups per tile buffer (two of them),
-// staged GB at a time.  Returns the LDS bytes per block, or 0 when no shape fits.
+// staged GB at a time, and 16 bytes of counters.  Returns the LDS bytes per
+// block, or 0 when no shape fits.
 size_t fused_shape(int32_t m, int tile_groups, int* T_out, int* GB_out)
 {
     const int64_t stage_b = (int64_t)tile::stage_dwords(m) * 4;
     const int64_t buf_b = 16ll * tile::fused_group_chunks(m);   // one group in one tile buffer
-    auto lds_for = [&](int64_t T, int64_t GB) { return ((GB * stage_b + 15) & ~(int64_t)15) + 2 * T * buf_b; };
+    auto lds_for = [&](int64_t T, int64_t GB) { return ((GB * stage_b + 15) & ~(int64_t)15) + 2 * T * buf_b + 16; };
     // staging groups: the most whose bytes the encoding threads' loads cover (so the
     // streaming path applies), and whose staging fits 32 KiB
     int GB = 8;

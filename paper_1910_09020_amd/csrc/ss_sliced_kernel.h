@@ -298,6 +298,12 @@ constexpr int kFusedEncQ = tile::kFusedQ;
 // lane runs about 18 instructions per column (at E = 5) instead of 44.
 constexpr int fused_lanes(int E) { return E == 0 ? 1 : 4; }
 constexpr int kFusedCPI = 2;   // chunks per item of the sweep (one LDS round trip per item)
+// How the sweeping wavefront keeps pace with the encoding ones.  Lockstep: it
+// takes part in the encoders' block barriers, one piece of its sweep before
+// each.  Decoupled: the encoders meet at a barrier of their own (an LDS
+// counter) and the sweeping wave meets them once per tile.  Measured at 100 bp:
+// lockstep is faster while the sweep is short (E <= 3), decoupled above.
+constexpr bool fused_decoupled(int E) { return E >= 4; }
 
 // OR of x over the LPG consecutive lanes of one group (LPG = 1, 2 or 4; the
 // lanes of a group lie in one quad)
@@ -403,6 +409,50 @@ struct TileSweep {
     }
 };
 
+// ---- synchronisation inside a fused block, through counters in LDS
+enum { kCtrEnc = 0, kCtrDone = 1, kCtrSwept = 2, kFusedCtrs = 4 };   // 16 bytes after the tile buffers
+constexpr uint32_t kSpinLimit = 1u << 22;                           // ~0.1 s of polling
+
+// wait until *p >= v (every lane reads the same word); a wait that outlives
+// kSpinLimit polls ORs bit 1 into err and gives up, so that a broken count can
+// not hang the device
+__device__ __forceinline__ void wait_at_least(const uint32_t* p, uint32_t v, uint32_t* err)
+{
+    for (uint32_t k = 0; __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < v; k++) {
+        if (k == kSpinLimit) {
+            if (err && (threadIdx.x & 63) == 0) atomicOr(err, 2u);
+            break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
+// one count per wavefront, after its earlier LDS reads and writes have completed
+__device__ __forceinline__ void arrive(uint32_t* p)
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    if ((threadIdx.x & 63) == 0) __hip_atomic_fetch_add(p, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// barrier among the encoding wavefronts only (the sweeping one does not wait on
+// it); the last wavefront to arrive learns so from its own count and goes on
+struct EncodersBarrier {
+    uint32_t* ctr;
+    uint32_t* err;
+    uint32_t& passed;
+    __device__ __forceinline__ void operator()() const
+    {
+        const uint32_t target = ++passed * (uint32_t)(kFusedEnc / 64);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        uint32_t now = 0;
+        if ((threadIdx.x & 63) == 0)
+            now = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP) + 1u;
+        now = __builtin_amdgcn_readfirstlane(now);
+        if (now < target) wait_at_least(ctr, target, err);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    }
+};
+
 // Fused encode and sweep.  Tiles of T consecutive groups are dealt to the
 // blocks round-robin (persistent blocks).  Waves 0..2 encode a tile GB groups at
 // a time from the ASCII pairs (stored back to back, pair i at byte i*m) into
@@ -412,16 +462,23 @@ struct TileSweep {
 // groups (possibly of the block's next tile) are in flight while the current
 // ones are encoded.
 //
-// Synchronisation: encoding GB groups passes four block barriers; the sweeping
-// wave takes part in every one of them.  While tile i is encoded (4 * steps(i)
-// barriers) it sweeps tile i-1, its work (passes of 64 / LPG groups times nch
-// chunks) cut into as many pieces as there are barriers, one piece before each
-// barrier.  Tile i-1's last words were written before the barrier that ends its
-// encoding, and its buffer is written again only for tile i+1, after the
-// barrier that ends tile i's encoding, by which the sweep has finished.  The
-// last tile is swept after the encoding waves are done, without barriers.
-// LDS: GB * stage_dwords(m) dwords of staging, then two buffers of
-// T * tile::fused_group_chunks(m) uint4.
+// Synchronisation.  Encoding GB groups passes four barriers of the encoding
+// waves.  Lockstep (fused_decoupled false): these are block barriers and the
+// sweeping wave takes part in every one; while tile i is encoded
+// (4 * steps(i) barriers) it sweeps tile i-1, its work cut into as many pieces
+// as there are barriers, one piece before each.  Tile i-1's last words were
+// written before the barrier that ends its encoding, and its buffer is written
+// again only for tile i+1, after the barrier that ends tile i's encoding, by
+// which the sweep has finished; the last tile is swept after the encoders are
+// done, without barriers.  Decoupled: the encoding waves meet at a barrier of
+// their own (an LDS counter) and the sweeping wave meets them once per tile,
+// through two counters: tiles encoded (counted after the barrier that ends a
+// tile's last groups) and tiles swept.  The sweep of tile i waits for
+// "encoded > i"; the encoding of tile i, which overwrites the buffer of tile
+// i-2, waits for "swept > i-2" before its first writes to the buffer.  Every
+// wait on a counter is bounded (see wait_at_least).
+// LDS: GB * stage_dwords(m) dwords of staging, two buffers of
+// T * tile::fused_group_chunks(m) uint4, then the counters.
 template <int E>
 __global__ __launch_bounds__(256) void k_fused(const uint8_t* __restrict__ reads, const uint8_t* __restrict__ refs,
                                                int64_t n_pairs, int m, int T, int GB, int fast,
@@ -434,6 +491,7 @@ __global__ __launch_bounds__(256) void k_fused(const uint8_t* __restrict__ reads
     const int64_t ntiles = (G + T - 1) / T;
     const int stage_w = (GB * tile::stage_dwords(m) + 3) & ~3;
     uint4* __restrict__ buf0 = reinterpret_cast<uint4*>(lds + stage_w);
+    uint32_t* __restrict__ ctr = reinterpret_cast<uint32_t*>(buf0 + 2 * (int64_t)T * GS);
     const int64_t t0 = blockIdx.x;
     if (t0 >= ntiles) return;
     const int64_t nmine = (ntiles - t0 + gridDim.x - 1) / gridDim.x;   // tiles of this block
@@ -441,9 +499,17 @@ __global__ __launch_bounds__(256) void k_fused(const uint8_t* __restrict__ reads
     auto tile_groups = [&](int64_t t) { return (int)min<int64_t>(T, G - t * T); };
     auto steps_of = [&](int64_t i) { return (tile_groups(tile_of(i)) + GB - 1) / GB; };
     auto buffer = [&](int64_t i) { return buf0 + (i & 1) * (int64_t)T * GS; };
+    if (threadIdx.x < kFusedCtrs) ctr[threadIdx.x] = 0u;
+    __syncthreads();
 
+    constexpr bool DEC = fused_decoupled(E);
     if (threadIdx.x < kFusedEnc) {
-        uint32_t bad = 0;
+        uint32_t bad = 0, passed = 0;
+        const EncodersBarrier ebar{ctr + kCtrEnc, err, passed};
+        auto bar = [&]() {
+            if constexpr (DEC) ebar();
+            else __syncthreads();
+        };
         int64_t i = 0;                   // tile index (of this block) and step in it
         int s = 0;
         // one step: encode the current GB groups from cur while the next groups'
@@ -454,9 +520,12 @@ __global__ __launch_bounds__(256) void k_fused(const uint8_t* __restrict__ reads
             if (sn >= steps_of(i)) { sn = 0; in++; }
             tile::load_groups<kFusedEncQ, kFusedEnc>(reads, refs, n_pairs, m, tile_of(in) * T + sn * GB, GB,
                                                      fast && in < nmine, nxt);
+            if (DEC && s == 0 && i >= 2) wait_at_least(ctr + kCtrSwept, (uint32_t)(i - 1), err);
             tile::encode_groups<kFusedEncQ, kFusedEnc>(reads, refs, nullptr, nullptr, n_pairs, m,
                                                        tile_of(i) * T + s * GB, GB, fast, cur, lds, buffer(i), 1,
-                                                       s * GB, bad, GS);
+                                                       s * GB, bad, GS, bar);
+            if (DEC && sn == 0 && threadIdx.x == 0)
+                __hip_atomic_fetch_add(ctr + kCtrDone, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
             i = in;
             s = sn;
             return i < nmine;
@@ -471,41 +540,57 @@ __global__ __launch_bounds__(256) void k_fused(const uint8_t* __restrict__ reads
     } else {
         constexpr int LPG = fused_lanes(E);
         constexpr int GPP = 64 / LPG;                    // groups per pass of the wave
-        constexpr int CPI = kFusedCPI;                   // chunks per item
+        constexpr int CPI = kFusedCPI;                   // chunks per call
         using SW = TileSweep<E, LPG, CPI>;
         const int lane = threadIdx.x - kFusedEnc;
         const int h = lane % LPG, gq = lane / LPG;
         const int vb = SW::first_query(h);
         const int ct = (m - kChunk - E >= 0) ? (m - kChunk - E) / kChunk + 1 : 0;   // interior chunks [EC, ct)
         SW sw;
-        for (int64_t i = 0; i <= nmine; i++) {
-            const int nint = i < nmine ? 4 * steps_of(i) : 0;     // barriers of tile i's encoding
-            if (i == 0) {
-                for (int b = 0; b < nint; b++) __syncthreads();
-                continue;
-            }
-            const int64_t tp = tile_of(i - 1);
-            const int tg = tile_groups(tp);
-            const uint32_t* __restrict__ tb = reinterpret_cast<const uint32_t*>(buffer(i - 1));
-            const int nci = nch > 0 ? (nch + CPI - 1) / CPI : 1;     // items per group (m = 0: the write alone)
-            const int work = ((tg + GPP - 1) / GPP) * nci;       // (pass, item) items
-            int it = 0, pass = 0, c = 0;
-            const int npiece = nint > 0 ? nint : 1;
-            for (int b = 0; b < npiece; b++) {
-                // equal pieces (weighting them towards either phase of the encoding measured slower)
-                const int end = nint > 0 ? (int)((int64_t)work * (b + 1) / nint) : work;
-                for (; it < end; it++) {
-                    const int gl = pass * GPP + gq;
-                    if (gl < tg) {
-                        if (c == 0) sw.init();
-                        const int c0 = c * CPI;
-                        if (c0 < nch)
-                            sw.chunks(tb + (int64_t)gl * GS * 4, nch, m, vb, c0, c0 >= SW::EC && c0 + CPI <= ct);
-                        if (c == nci - 1 && h == 0) write_group<E>(sw.Tm, tp * T + gl, n_pairs, out);
-                    }
-                    if (++c == nci) { c = 0; pass++; }
+        // the sweep of group gl of tile tp from buffer tb, items c .. c+CPI-1 at a time
+        auto sweep_item = [&](const uint32_t* __restrict__ tb, int64_t tp, int gl, int c) {
+            if (c == 0) sw.init();
+            if (c < nch)
+                sw.chunks(tb + (int64_t)gl * GS * 4, nch, m, vb, c, c >= SW::EC && c + CPI <= ct);
+            if (c + CPI >= nch && h == 0) write_group<E>(sw.Tm, tp * T + gl, n_pairs, out);
+        };
+        if constexpr (DEC) {
+            for (int64_t i = 0; i < nmine; i++) {
+                wait_at_least(ctr + kCtrDone, (uint32_t)(i + 1), err);
+                const int64_t tp = tile_of(i);
+                const int tg = tile_groups(tp);
+                const uint32_t* __restrict__ tb = reinterpret_cast<const uint32_t*>(buffer(i));
+                for (int g0 = 0; g0 < tg; g0 += GPP) {
+                    const int gl = g0 + gq;
+                    if (gl < tg)
+                        for (int c = 0; c < (nch > 0 ? nch : 1); c += CPI) sweep_item(tb, tp, gl, c);
                 }
-                if (nint > 0) __syncthreads();
+                arrive(ctr + kCtrSwept);
+            }
+        } else {
+            const int nci = nch > 0 ? (nch + CPI - 1) / CPI : 1;    // items per group (m = 0: the write alone)
+            for (int64_t i = 0; i <= nmine; i++) {
+                const int nint = i < nmine ? 4 * steps_of(i) : 0;     // barriers of tile i's encoding
+                if (i == 0) {
+                    for (int b = 0; b < nint; b++) __syncthreads();
+                    continue;
+                }
+                const int64_t tp = tile_of(i - 1);
+                const int tg = tile_groups(tp);
+                const uint32_t* __restrict__ tb = reinterpret_cast<const uint32_t*>(buffer(i - 1));
+                const int work = ((tg + GPP - 1) / GPP) * nci;       // (pass, item) pairs
+                int it = 0, pass = 0, c = 0;
+                const int npiece = nint > 0 ? nint : 1;
+                for (int b = 0; b < npiece; b++) {
+                    // equal pieces (weighting them towards either phase of the encoding measured slower)
+                    const int end = nint > 0 ? (int)((int64_t)work * (b + 1) / nint) : work;
+                    for (; it < end; it++) {
+                        const int gl = pass * GPP + gq;
+                        if (gl < tg) sweep_item(tb, tp, gl, c * CPI);
+                        if (++c == nci) { c = 0; pass++; }
+                    }
+                    if (nint > 0) __syncthreads();
+                }
             }
         }
     }

@@ -88,6 +88,11 @@ __device__ __forceinline__ void load_groups(const uint8_t* __restrict__ reads, c
     }
 }
 
+// the barrier of a whole block
+struct BlockBarrier {
+    __device__ __forceinline__ void operator()() const { __syncthreads(); }
+};
+
 // Encode groups g0 .. g0+GB-1 (those that hold a slot below n_pairs); GB is a
 // power of two.  Slot i reads pair index[i] (or i) at offsets[pair] (or
 // pair * m).  The words of (plane p, chunk c, local group gl) go to
@@ -98,16 +103,17 @@ __device__ __forceinline__ void load_groups(const uint8_t* __restrict__ reads, c
 // stored back to back from a 16-byte aligned byte (index and offsets null)
 // and v holds load_groups' loads of these groups; 1 when m % 4 == 0 (codes
 // staged per slot row), 2 otherwise (raw bytes staged in source order, read
-// back per slot and chunk with a byte-align).  It synchronises the block four
-// times: every thread of the block takes part in those barriers.
-template <int KQ = kQ, int NT = 256>
+// back per slot and chunk with a byte-align).  It synchronises the encoding
+// threads four times through bar (by default the block barrier, in which every
+// thread of the block takes part).
+template <int KQ = kQ, int NT = 256, class BAR = BlockBarrier>
 __device__ __forceinline__ void encode_groups(const uint8_t* __restrict__ reads, const uint8_t* __restrict__ refs,
                                               const int64_t* __restrict__ offsets,
                                               const int64_t* __restrict__ index, int64_t n_pairs, int m,
                                               int64_t g0, int GB, int fast, const uint4 (&v)[2][KQ],
                                               uint32_t* __restrict__ stage, uint4* __restrict__ out4,
                                               int64_t ostride, int64_t obase, uint32_t& bad,
-                                              int64_t gstride = 1)
+                                              int64_t gstride = 1, const BAR& bar = BAR())
 {
     const int mw = (m + 3) >> 2;              // dwords per slot row
     const int gs = 32 * mw + 4;               // dwords per group
@@ -167,7 +173,7 @@ __device__ __forceinline__ void encode_groups(const uint8_t* __restrict__ reads,
                 lb[4 * ((p >> 5) * gs + (p & 31) * mw) + col] = (uint8_t)(c & 0x11u);
             }
         }
-        __syncthreads();
+        bar();
         for (int task = t; task < GB * nch; task += NT) {
             const int gl = task & (GB - 1), c = task >> lgb;
             if (32 * gl >= np) continue;
@@ -221,7 +227,7 @@ __device__ __forceinline__ void encode_groups(const uint8_t* __restrict__ reads,
             out4[((int64_t)(2 * side) * nch + c) * ostride + (obase + gl) * gstride] = make_uint4(wl[0], wl[1], wl[2], wl[3]);
             out4[((int64_t)(2 * side + 1) * nch + c) * ostride + (obase + gl) * gstride] = make_uint4(wh[0], wh[1], wh[2], wh[3]);
         }
-        __syncthreads();
+        bar();
     }
 }
 
