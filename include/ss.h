@@ -158,8 +158,10 @@ int ss_filter_submaze_async(ss_ctx* ctx, const uint32_t* packed, int64_t n_pairs
  * depends on E:
  *   E <= 5 : one fused kernel.  Three wavefronts of each workgroup encode
  *            tiles of tile_groups groups of 32 pairs into one of two on-chip
- *            buffers while the fourth sweeps the previous tile from the other,
- *            so the packed encoding never reaches device memory.
+ *            buffers while the fourth sweeps the previous tile from the other
+ *            (in step with the encoders' barriers for E <= 3, through
+ *            counters in on-chip memory once per tile above), so the packed
+ *            encoding never reaches device memory.
  *   E > 5  : the two kernels over chunks of about 400 MB of packed data, kept
  *            in a buffer owned by ctx (allocated on first use, grown when a
  *            longer m needs it): calls with E > 5 on one context must be
@@ -173,7 +175,9 @@ int ss_filter_submaze_async(ss_ctx* ctx, const uint32_t* packed, int64_t n_pairs
  *   out         : n_pairs result words (see SS_RESULT_*), 16-byte aligned
  *   err         : one device uint32; bit 0 is OR-ed in when a byte outside
  *                 ACGTacgt is seen (the caller zeroes it beforehand); the
- *                 results are then unspecified.
+ *                 results are then unspecified.  Bit 1 is OR-ed in if a wait
+ *                 between the fused kernel's wavefronts gave up after its
+ *                 bound (~0.1 s; not expected), with results unspecified.
  * Asynchronous on stream; the caller keeps every buffer alive until the
  * stream has passed this call. */
 int ss_filter_ascii_async(ss_ctx* ctx, const uint8_t* reads, const uint8_t* refs, int64_t n_pairs, int32_t m,

@@ -355,6 +355,7 @@ int filter_host(const uint8_t* reads, const uint8_t* refs, const int32_t* length
     uint32_t h_err = 0;
     SS_TRY(hipMemcpyAsync(&h_err, d_err, 4, hipMemcpyDeviceToHost, s));
     SS_TRY(hipStreamSynchronize(s));
+    if (h_err & 2u) return SS_EDEVICE;   // a bounded wait inside the fused kernel gave up
     if (h_err) return SS_EBASE;
 
     if (sliced && lengths[0] <= SS_MAX_LEN_FUSED) {
