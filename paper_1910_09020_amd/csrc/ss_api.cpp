@@ -170,8 +170,9 @@ extern "C" int ss_filter_ascii_async(ss_ctx* ctx, const uint8_t* reads, const ui
     if (n_pairs == 0) return SS_OK;
     if (!out || (m > 0 && (!reads || !refs))) return SS_EINVAL;
     if (((uintptr_t)out & 15u) != 0) return SS_EINVAL;
-    int T = 0, GB = 0;
-    if (fused_shape(m, tile_groups, &T, &GB) == 0) return SS_EINVAL;
+    int T = 0, GB = 0, U = 0;
+    const bool contiguous = (((uintptr_t)reads | (uintptr_t)refs) & 15u) == 0;
+    if (fused_shape(m, tile_groups, contiguous, &T, &GB, &U) == 0) return SS_EINVAL;
     const hipStream_t s = (hipStream_t)stream;
     if (E <= kMaxEFused)
         return map_err(launch_fused(reads, refs, n_pairs, m, E, tile_groups, out, err, s));

@@ -26,7 +26,7 @@ hipError_t launch_sliced(const uint32_t* packed, int64_t n_pairs, int32_t m, int
 // tile_groups: groups of 32 pairs per block (0: automatic).
 hipError_t launch_fused(const uint8_t* reads, const uint8_t* refs, int64_t n_pairs, int32_t m, int32_t E,
                         int tile_groups, uint16_t* out, uint32_t* err, hipStream_t s);
-size_t fused_shape(int32_t m, int tile_groups, int* T, int* GB);
+size_t fused_shape(int32_t m, int tile_groups, bool contiguous, int* T, int* GB, int* U);
 hipError_t launch_pack_stream(const uint8_t* reads, const uint8_t* refs, int64_t total_bases,
                               uint32_t* packed, uint32_t* err, hipStream_t s);
 hipError_t launch_plain(const uint32_t* packed, int64_t stream_words, const int64_t* offsets,

@@ -106,7 +106,7 @@ hipError_t launch_sliced_mid(int E, const uint32_t* packed, int64_t n, int32_t m
 hipError_t launch_sliced_hi(int E, const uint32_t* packed, int64_t n, int32_t m, int sub_width, uint16_t* out,
                            hipStream_t s);
 hipError_t launch_fused_lo(int E, const uint8_t* reads, const uint8_t* refs, int64_t n, int32_t m, int T, int GB,
-                          int fast, size_t shmem, uint16_t* out, uint32_t* err, hipStream_t s);
+                          int U, int fast, size_t shmem, uint16_t* out, uint32_t* err, hipStream_t s);
 
 hipError_t launch_pack_sliced(const uint8_t* reads, const uint8_t* refs, const int64_t* offsets,
                               const int64_t* index, int64_t n_pairs, int32_t m, uint32_t* packed,
@@ -143,37 +143,55 @@ hipError_t launch_sliced(const uint32_t* packed, int64_t n_pairs, int32_t m, int
     return launch_sliced_hi(E, packed, n_pairs, m, sub_width, out, s);
 }
 
-// Tile shape of the fused kernel: T groups per tile buffer (two of them),
-// staged GB at a time, and 16 bytes of counters.  Returns the LDS bytes per
-// block, or 0 when no shape fits.
-size_t fused_shape(int32_t m, int tile_groups, int* T_out, int* GB_out)
+// Tile shape of the fused kernel: T groups per tile buffer (two of them) and
+// 16 bytes of counters; U > 0 groups per unit when each encoding wavefront
+// encodes by itself (contiguous pairs whose U groups fit its loads), else U = 0
+// and GB groups staged at a time by the three together.  Returns the LDS bytes
+// per block, or 0 when no shape fits.
+size_t fused_shape(int32_t m, int tile_groups, bool contiguous, int* T_out, int* GB_out, int* U_out)
 {
     const int64_t stage_b = (int64_t)tile::stage_dwords(m) * 4;
     const int64_t buf_b = 16ll * tile::fused_group_chunks(m);   // one group in one tile buffer
-    auto lds_for = [&](int64_t T, int64_t GB) { return ((GB * stage_b + 15) & ~(int64_t)15) + 2 * T * buf_b + 16; };
+    // T: the given tile, else the largest step multiple that keeps two blocks per CU
+    // (a multiple of 16 from 16 on: the sweeping wave's groups per pass), else one
+    auto pick = [&](int step, auto&& lds_for) -> int {
+        if (tile_groups > 0)
+            return (tile_groups % step == 0 && lds_for(tile_groups) <= kMaxFusedLds) ? tile_groups : 0;
+        for (int blocks = 2; blocks >= 1; blocks--) {
+            int T = 0;
+            for (int t = step; t <= 256; t += step)
+                if ((t < 16 || t % 16 == 0) && blocks * lds_for(t) <= kMaxFusedLds) T = t;
+            if (T > 0) return T;
+        }
+        return 0;
+    };
+    for (int U = 2; U >= 1 && contiguous && m > 0; U >>= 1) {
+        if (tile::fast_mode(m, U, true, tile::kWaveQ, 64) == 0) continue;
+        const int64_t sw = 3 * ((U * stage_b + 15) & ~(int64_t)15);
+        auto lds_w = [&](int64_t T) { return sw + 2 * T * buf_b + 16; };
+        const int T = pick(U, lds_w);
+        if (T > 0) {
+            *T_out = T;
+            *GB_out = U;
+            *U_out = U;
+            return (size_t)lds_w(T);
+        }
+    }
     // staging groups: the most whose bytes the encoding threads' loads cover (so the
     // streaming path applies), and whose staging fits 32 KiB
     int GB = 8;
     while (GB > 1 &&
            (GB * stage_b > 32768 || tile::fast_mode(m, GB, true, tile::kFusedQ, tile::kFusedThreads) == 0))
         GB >>= 1;
-    int T = tile_groups;
-    if (T <= 0) {
-        // largest multiple of GB that keeps two blocks per CU, else one
-        T = 0;
-        for (int blocks = 2; blocks >= 1 && T == 0; blocks--)
-            for (int t = GB; t <= 256; t += GB)
-                if (blocks * lds_for(t, GB) <= kMaxFusedLds) T = t;
-        if (T == 0) T = GB;
-    } else {
-        if (T > 256) return 0;
-        while (GB > 1 && T % GB != 0) GB >>= 1;
-    }
-    const int64_t lds = lds_for(T, GB);
-    if (lds > kMaxFusedLds) return 0;
+    if (tile_groups > 0)
+        while (GB > 1 && tile_groups % GB != 0) GB >>= 1;
+    auto lds_b = [&](int64_t T) { return ((GB * stage_b + 15) & ~(int64_t)15) + 2 * T * buf_b + 16; };
+    const int T = pick(GB, lds_b);
+    if (T == 0) return 0;
     *T_out = T;
     *GB_out = GB;
-    return (size_t)lds;
+    *U_out = 0;
+    return (size_t)lds_b(T);
 }
 
 hipError_t launch_fused(const uint8_t* reads, const uint8_t* refs, int64_t n_pairs, int32_t m, int32_t E,
@@ -181,12 +199,13 @@ hipError_t launch_fused(const uint8_t* reads, const uint8_t* refs, int64_t n_pai
 {
     if (n_pairs == 0) return hipSuccess;
     if (E < 0 || E > kMaxEFused) return hipErrorInvalidValue;
-    int T = 0, GB = 0;
-    const size_t shmem = fused_shape(m, tile_groups, &T, &GB);
+    const bool contiguous = (((uintptr_t)reads | (uintptr_t)refs) & 15u) == 0;
+    int T = 0, GB = 0, U = 0;
+    const size_t shmem = fused_shape(m, tile_groups, contiguous, &T, &GB, &U);
     if (shmem == 0) return hipErrorInvalidValue;
-    const int fast = tile::fast_mode(m, GB, (((uintptr_t)reads | (uintptr_t)refs) & 15u) == 0, tile::kFusedQ,
-                                     tile::kFusedThreads);
-    return launch_fused_lo(E, reads, refs, n_pairs, m, T, GB, fast, shmem, out, err, s);
+    const int fast = U > 0 ? tile::fast_mode(m, U, true, tile::kWaveQ, 64)
+                           : tile::fast_mode(m, GB, contiguous, tile::kFusedQ, tile::kFusedThreads);
+    return launch_fused_lo(E, reads, refs, n_pairs, m, T, GB, U, fast, shmem, out, err, s);
 }
 
 }  // namespace ss

@@ -298,12 +298,6 @@ constexpr int kFusedEncQ = tile::kFusedQ;
 // lane runs about 18 instructions per column (at E = 5) instead of 44.
 constexpr int fused_lanes(int E) { return E == 0 ? 1 : 4; }
 constexpr int kFusedCPI = 2;   // chunks per item of the sweep (one LDS round trip per item)
-// How the sweeping wavefront keeps pace with the encoding ones.  Lockstep: it
-// takes part in the encoders' block barriers, one piece of its sweep before
-// each.  Decoupled: the encoders meet at a barrier of their own (an LDS
-// counter) and the sweeping wave meets them once per tile.  Measured at 100 bp:
-// lockstep is faster while the sweep is short (E <= 3), decoupled above.
-constexpr bool fused_decoupled(int E) { return E >= 4; }
 
 // OR of x over the LPG consecutive lanes of one group (LPG = 1, 2 or 4; the
 // lanes of a group lie in one quad)
@@ -390,27 +384,28 @@ struct TileSweep {
             for (int x = 0; x < NQ; x++) { w0[x] = q0[x]; w1[x] = q1[x]; }
             columns<false>(w0, w1, rr0, rr1, 4 * c, vb, m);
         } else {
-            // chunks past nch and positions outside [0, m) read clamped places: those
-            // columns are not run and those rows are masked
+            // chunks past nch read the last chunk (those columns are not run); query
+            // positions outside [0, m) are read unclamped, for rows that are masked:
+            // from at most E words before the group's planes (the previous group, or
+            // the staging before the first buffer) to at most 4 * CPI + E words past
+            // the end of a plane (still inside the group's four planes)
 #pragma unroll
             for (int k = 0; k < CPI; k++) {
                 const int ck = min(c + k, nch - 1);
                 rr0[k] = gp4[2 * nch + ck];
                 rr1[k] = gp4[3 * nch + ck];
             }
+            const uint32_t* __restrict__ q0 = gp + 4 * c + vb;
+            const uint32_t* __restrict__ q1 = q0 + 4 * nch;
 #pragma unroll
-            for (int x = 0; x < NQ; x++) {
-                const int P = min(max(4 * c + vb + x, 0), m - 1);
-                w0[x] = gp[P];
-                w1[x] = gp[4 * nch + P];
-            }
+            for (int x = 0; x < NQ; x++) { w0[x] = q0[x]; w1[x] = q1[x]; }
             columns<true>(w0, w1, rr0, rr1, 4 * c, vb, m);
         }
     }
 };
 
 // ---- synchronisation inside a fused block, through counters in LDS
-enum { kCtrEnc = 0, kCtrDone = 1, kCtrSwept = 2, kFusedCtrs = 4 };   // 16 bytes after the tile buffers
+enum { kCtrDone0 = 0, kCtrDone1 = 1, kCtrSwept = 2, kFusedCtrs = 4 };   // 16 bytes after the tile buffers
 constexpr uint32_t kSpinLimit = 1u << 22;                           // ~0.1 s of polling
 
 // wait until *p >= v (every lane reads the same word); a wait that outlives
@@ -434,54 +429,41 @@ __device__ __forceinline__ void arrive(uint32_t* p)
     if ((threadIdx.x & 63) == 0) __hip_atomic_fetch_add(p, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// barrier among the encoding wavefronts only (the sweeping one does not wait on
-// it); the last wavefront to arrive learns so from its own count and goes on
-struct EncodersBarrier {
-    uint32_t* ctr;
-    uint32_t* err;
-    uint32_t& passed;
-    __device__ __forceinline__ void operator()() const
-    {
-        const uint32_t target = ++passed * (uint32_t)(kFusedEnc / 64);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        uint32_t now = 0;
-        if ((threadIdx.x & 63) == 0)
-            now = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP) + 1u;
-        now = __builtin_amdgcn_readfirstlane(now);
-        if (now < target) wait_at_least(ctr, target, err);
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    }
-};
-
 // Fused encode and sweep.  Tiles of T consecutive groups are dealt to the
-// blocks round-robin (persistent blocks).  Waves 0..2 encode a tile GB groups at
-// a time from the ASCII pairs (stored back to back, pair i at byte i*m) into
-// one of two LDS tile buffers (group-major lane-sliced layout), while wave 3
-// sweeps the previous tile from the other buffer.  The packed encoding never
-// reaches HBM.  Two register buffers take turns: the loads of the next GB
-// groups (possibly of the block's next tile) are in flight while the current
-// ones are encoded.
+// blocks round-robin (persistent blocks).  Waves 0..2 encode tiles from the
+// ASCII pairs (stored back to back, pair i at byte i*m) into two LDS tile
+// buffers (group-major lane-sliced layout) in turn, while wave 3 sweeps the
+// previous tile from the other buffer.  The packed encoding never reaches HBM.
+// Two register buffers take turns in every encoding wave: the loads of its next
+// groups are in flight while the current ones are encoded.
 //
-// Synchronisation.  Encoding GB groups passes four barriers of the encoding
-// waves.  Lockstep (fused_decoupled false): these are block barriers and the
-// sweeping wave takes part in every one; while tile i is encoded
-// (4 * steps(i) barriers) it sweeps tile i-1, its work cut into as many pieces
-// as there are barriers, one piece before each.  Tile i-1's last words were
-// written before the barrier that ends its encoding, and its buffer is written
-// again only for tile i+1, after the barrier that ends tile i's encoding, by
-// which the sweep has finished; the last tile is swept after the encoders are
-// done, without barriers.  Decoupled: the encoding waves meet at a barrier of
-// their own (an LDS counter) and the sweeping wave meets them once per tile,
-// through two counters: tiles encoded (counted after the barrier that ends a
-// tile's last groups) and tiles swept.  The sweep of tile i waits for
-// "encoded > i"; the encoding of tile i, which overwrites the buffer of tile
-// i-2, waits for "swept > i-2" before its first writes to the buffer.  Every
-// wait on a counter is bounded (see wait_at_least).
-// LDS: GB * stage_dwords(m) dwords of staging, two buffers of
+// Wave mode (U > 0, pairs of up to a few hundred bases stored from 16-byte
+// aligned bases): each encoding wave encodes units of U groups by itself, with
+// staging of its own, so the encoders never wait for each other; wave w takes
+// the block's units w, w+3, ... (T / U units per tile, in tile order).  They
+// meet the sweeping wave through counters in LDS: per tile buffer, units
+// encoded into it, and tiles swept.  The sweep of tile i waits until the
+// buffer of tile i has counted all units of its tiles up to i; the encoding of
+// a unit of tile i, which overwrites the buffer of tile i-2, waits for
+// "swept > i-2".  (No unit of tile i+2 can start before tile i is swept, so the
+// per-buffer count reaches tile i's target only when tile i is complete.)
+// Every wait on a counter is bounded (see wait_at_least).
+//
+// Block mode (U == 0): the three waves encode GB groups at a time together,
+// passing four block barriers per GB groups, and the sweeping wave takes part in
+// every one: while tile i is encoded (4 * steps(i) barriers) it sweeps tile
+// i-1, its work cut into as many pieces as there are barriers, one piece
+// before each.  Tile i-1's last words were written before the barrier that
+// ends its encoding, and its buffer is written again only for tile i+1, after
+// the barrier that ends tile i's encoding, by which the sweep has finished; the
+// last tile is swept after the encoders are done, without barriers.
+//
+// LDS: the staging (wave mode: three regions of U * stage_dwords(m) dwords;
+// block mode: GB * stage_dwords(m) dwords), two buffers of
 // T * tile::fused_group_chunks(m) uint4, then the counters.
 template <int E>
 __global__ __launch_bounds__(256) void k_fused(const uint8_t* __restrict__ reads, const uint8_t* __restrict__ refs,
-                                               int64_t n_pairs, int m, int T, int GB, int fast,
+                                               int64_t n_pairs, int m, int T, int GB, int U, int fast,
                                                uint16_t* __restrict__ out, uint32_t* __restrict__ err)
 {
     extern __shared__ uint32_t lds[];
@@ -489,7 +471,8 @@ __global__ __launch_bounds__(256) void k_fused(const uint8_t* __restrict__ reads
     const int GS = tile::fused_group_chunks(m);
     const int64_t G = (n_pairs + 31) / 32;
     const int64_t ntiles = (G + T - 1) / T;
-    const int stage_w = (GB * tile::stage_dwords(m) + 3) & ~3;
+    const int wave_stage = (U * tile::stage_dwords(m) + 3) & ~3;
+    const int stage_w = U > 0 ? 3 * wave_stage : (GB * tile::stage_dwords(m) + 3) & ~3;
     uint4* __restrict__ buf0 = reinterpret_cast<uint4*>(lds + stage_w);
     uint32_t* __restrict__ ctr = reinterpret_cast<uint32_t*>(buf0 + 2 * (int64_t)T * GS);
     const int64_t t0 = blockIdx.x;
@@ -501,40 +484,74 @@ __global__ __launch_bounds__(256) void k_fused(const uint8_t* __restrict__ reads
     auto buffer = [&](int64_t i) { return buf0 + (i & 1) * (int64_t)T * GS; };
     if (threadIdx.x < kFusedCtrs) ctr[threadIdx.x] = 0u;
     __syncthreads();
+    const int upt = U > 0 ? T / U : 0;     // units per tile (wave mode)
 
-    constexpr bool DEC = fused_decoupled(E);
     if (threadIdx.x < kFusedEnc) {
-        uint32_t bad = 0, passed = 0;
-        const EncodersBarrier ebar{ctr + kCtrEnc, err, passed};
-        auto bar = [&]() {
-            if constexpr (DEC) ebar();
-            else __syncthreads();
-        };
-        int64_t i = 0;                   // tile index (of this block) and step in it
-        int s = 0;
-        // one step: encode the current GB groups from cur while the next groups'
-        // loads (possibly of the block's next tile) run; false when the block is done
-        auto step = [&](const uint4 (&cur)[2][kFusedEncQ], uint4 (&nxt)[2][kFusedEncQ]) -> bool {
-            int64_t in = i;
-            int sn = s + 1;
-            if (sn >= steps_of(i)) { sn = 0; in++; }
-            tile::load_groups<kFusedEncQ, kFusedEnc>(reads, refs, n_pairs, m, tile_of(in) * T + sn * GB, GB,
-                                                     fast && in < nmine, nxt);
-            if (DEC && s == 0 && i >= 2) wait_at_least(ctr + kCtrSwept, (uint32_t)(i - 1), err);
-            tile::encode_groups<kFusedEncQ, kFusedEnc>(reads, refs, nullptr, nullptr, n_pairs, m,
-                                                       tile_of(i) * T + s * GB, GB, fast, cur, lds, buffer(i), 1,
-                                                       s * GB, bad, GS, bar);
-            if (DEC && sn == 0 && threadIdx.x == 0)
-                __hip_atomic_fetch_add(ctr + kCtrDone, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
-            i = in;
-            s = sn;
-            return i < nmine;
-        };
-        uint4 va[2][kFusedEncQ], vb[2][kFusedEncQ];
-        tile::load_groups<kFusedEncQ, kFusedEnc>(reads, refs, n_pairs, m, t0 * T, GB, fast != 0, va);
-        for (;;) {
-            if (!step(va, vb)) break;
-            if (!step(vb, va)) break;
+        uint32_t bad = 0;
+        if (U > 0) {
+            const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+            uint32_t* __restrict__ stage = lds + w * wave_stage;
+            const int64_t total = nmine * upt;
+            // unit k: groups k % upt * U .. +U-1 of the block's tile k / upt (none past the batch)
+            auto unit_groups = [&](int64_t k) -> int {
+                if (k >= total) return 0;
+                const int64_t i = k / upt;
+                return min(U, tile_groups(tile_of(i)) - (int)(k - i * upt) * U);
+            };
+            auto unit_g0 = [&](int64_t k) {
+                const int64_t i = k / upt;
+                return tile_of(i) * T + (k - i * upt) * U;
+            };
+            int64_t k = w;
+            auto step = [&](const uint4 (&cur)[2][tile::kWaveQ], uint4 (&nxt)[2][tile::kWaveQ]) -> bool {
+                const int64_t kn = k + 3;
+                tile::load_groups<tile::kWaveQ, 64>(reads, refs, n_pairs, m, unit_g0(kn), U,
+                                                    fast && unit_groups(kn) > 0, nxt, lane);
+                const int64_t i = k / upt;
+                const int u = (int)(k - i * upt);
+                if (unit_groups(k) > 0) {
+                    if (i >= 2) wait_at_least(ctr + kCtrSwept, (uint32_t)(i - 1), err);
+                    tile::encode_groups<tile::kWaveQ, 64>(reads, refs, nullptr, nullptr, n_pairs, m, unit_g0(k), U,
+                                                          fast, cur, stage, buffer(i), 1, u * U, bad, GS,
+                                                          tile::WaveSync(), lane);
+                }
+                arrive(ctr + kCtrDone0 + (i & 1));
+                k = kn;
+                return k < total;
+            };
+            if (k < total) {
+                uint4 va[2][tile::kWaveQ], vb[2][tile::kWaveQ];
+                tile::load_groups<tile::kWaveQ, 64>(reads, refs, n_pairs, m, unit_g0(k), U,
+                                                    fast && unit_groups(k) > 0, va, lane);
+                for (;;) {
+                    if (!step(va, vb)) break;
+                    if (!step(vb, va)) break;
+                }
+            }
+        } else {
+            int64_t i = 0;               // tile index (of this block) and step in it
+            int s = 0;
+            // one step: encode the current GB groups from cur while the next groups'
+            // loads (possibly of the block's next tile) run; false when the block is done
+            auto step = [&](const uint4 (&cur)[2][kFusedEncQ], uint4 (&nxt)[2][kFusedEncQ]) -> bool {
+                int64_t in = i;
+                int sn = s + 1;
+                if (sn >= steps_of(i)) { sn = 0; in++; }
+                tile::load_groups<kFusedEncQ, kFusedEnc>(reads, refs, n_pairs, m, tile_of(in) * T + sn * GB, GB,
+                                                         fast && in < nmine, nxt);
+                tile::encode_groups<kFusedEncQ, kFusedEnc>(reads, refs, nullptr, nullptr, n_pairs, m,
+                                                           tile_of(i) * T + s * GB, GB, fast, cur, lds, buffer(i), 1,
+                                                           s * GB, bad, GS);
+                i = in;
+                s = sn;
+                return i < nmine;
+            };
+            uint4 va[2][kFusedEncQ], vb[2][kFusedEncQ];
+            tile::load_groups<kFusedEncQ, kFusedEnc>(reads, refs, n_pairs, m, t0 * T, GB, fast != 0, va);
+            for (;;) {
+                if (!step(va, vb)) break;
+                if (!step(vb, va)) break;
+            }
         }
         if (tile::invalid(bad) && err) atomicOr(err, 1u);
     } else {
@@ -547,16 +564,16 @@ __global__ __launch_bounds__(256) void k_fused(const uint8_t* __restrict__ reads
         const int vb = SW::first_query(h);
         const int ct = (m - kChunk - E >= 0) ? (m - kChunk - E) / kChunk + 1 : 0;   // interior chunks [EC, ct)
         SW sw;
-        // the sweep of group gl of tile tp from buffer tb, items c .. c+CPI-1 at a time
+        // the sweep of group gl of tile tp from buffer tb, chunks c .. c+CPI-1
         auto sweep_item = [&](const uint32_t* __restrict__ tb, int64_t tp, int gl, int c) {
             if (c == 0) sw.init();
             if (c < nch)
                 sw.chunks(tb + (int64_t)gl * GS * 4, nch, m, vb, c, c >= SW::EC && c + CPI <= ct);
             if (c + CPI >= nch && h == 0) write_group<E>(sw.Tm, tp * T + gl, n_pairs, out);
         };
-        if constexpr (DEC) {
+        if (U > 0) {
             for (int64_t i = 0; i < nmine; i++) {
-                wait_at_least(ctr + kCtrDone, (uint32_t)(i + 1), err);
+                wait_at_least(ctr + kCtrDone0 + (i & 1), (uint32_t)(upt * (i / 2 + 1)), err);
                 const int64_t tp = tile_of(i);
                 const int tg = tile_groups(tp);
                 const uint32_t* __restrict__ tb = reinterpret_cast<const uint32_t*>(buffer(i));
@@ -615,7 +632,7 @@ hipError_t launch_sliced_E(const uint32_t* packed, int64_t n_pairs, int32_t m, i
 
 template <int E>
 hipError_t launch_fused_E(const uint8_t* reads, const uint8_t* refs, int64_t n_pairs, int32_t m, int T, int GB,
-                          int fast, size_t shmem, uint16_t* out, uint32_t* err, hipStream_t s)
+                          int U, int fast, size_t shmem, uint16_t* out, uint32_t* err, hipStream_t s)
 {
     const int64_t G = cdiv(n_pairs, 32);
     if (shmem > 65536) {
@@ -633,17 +650,17 @@ hipError_t launch_fused_E(const uint8_t* reads, const uint8_t* refs, int64_t n_p
     if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
     const int64_t grid = std::min<int64_t>(cdiv(G, T), (int64_t)std::max(1, per_cu) * cus);
     hipLaunchKernelGGL((k_fused<E>), dim3((unsigned)grid), dim3(256), shmem, s, reads, refs, n_pairs, m, T,
-                       GB, fast, out, err);
+                       GB, U, fast, out, err);
     return hipGetLastError();
 }
 
 template <int... Es>
 struct FusedTable {
     static hipError_t run(int E, const uint8_t* reads, const uint8_t* refs, int64_t n, int32_t m, int T, int GB,
-                          int fast, size_t shmem, uint16_t* out, uint32_t* err, hipStream_t s)
+                          int U, int fast, size_t shmem, uint16_t* out, uint32_t* err, hipStream_t s)
     {
         hipError_t r = hipErrorInvalidValue;
-        ((E == Es ? (r = launch_fused_E<Es>(reads, refs, n, m, T, GB, fast, shmem, out, err, s), 0) : 0), ...);
+        ((E == Es ? (r = launch_fused_E<Es>(reads, refs, n, m, T, GB, U, fast, shmem, out, err, s), 0) : 0), ...);
         return r;
     }
 };

@@ -10,9 +10,9 @@ hipError_t launch_sliced_lo(int E, const uint32_t* packed, int64_t n, int32_t m,
 }
 
 hipError_t launch_fused_lo(int E, const uint8_t* reads, const uint8_t* refs, int64_t n, int32_t m, int T, int GB,
-                          int fast, size_t shmem, uint16_t* out, uint32_t* err, hipStream_t s)
+                          int U, int fast, size_t shmem, uint16_t* out, uint32_t* err, hipStream_t s)
 {
-    return sliced::FusedTable<0, 1, 2, 3, 4, 5>::run(E, reads, refs, n, m, T, GB, fast, shmem, out, err, s);
+    return sliced::FusedTable<0, 1, 2, 3, 4, 5>::run(E, reads, refs, n, m, T, GB, U, fast, shmem, out, err, s);
 }
 
 }  // namespace ss

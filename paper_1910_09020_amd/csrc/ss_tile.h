@@ -43,6 +43,7 @@ __device__ __forceinline__ bool invalid(uint32_t bad) { return (bad & 0xDFDFDFDF
 constexpr int kQ = 8;      // 16-byte loads per thread and side on the standalone encoder's fast path
 constexpr int kFusedThreads = 192;  // encoding threads of a fused block (waves 0..2; wave 3 sweeps)
 constexpr int kFusedQ = 9;         // their 16-byte loads per thread and side (192 * 9 * 16 B >= 8 groups of 100 bp)
+constexpr int kWaveQ = 7;          // 16-byte loads per lane and side when one wavefront encodes alone (64 * 7 * 16 B >= 2 groups of 100 bp)
 // uint4 words of one group in a fused tile buffer: the four planes of
 // ceil(m/4) chunks one after another (group-major, so the positions of a plane
 // are consecutive words), plus one uint4 of padding that spreads consecutive
@@ -61,8 +62,8 @@ __host__ __device__ inline int fast_mode(int m, int GB, bool contiguous, int kq 
     return m % 4 == 0 ? 1 : 2;
 }
 
-// Fast path: the block's 16-byte loads of groups g0 .. g0+GB-1, both sides
-// (encoding thread t of NT takes loads t, t + NT, ...).  Raw buffer loads over exactly the
+// Fast path: the 16-byte loads of groups g0 .. g0+GB-1, both sides, by NT
+// threads (thread tid of them takes loads tid, tid + NT, ...).  Raw buffer loads over exactly the
 // groups' bytes: the hardware range check returns zero for a load past the
 // end instead of touching memory, so every load is issued unconditionally
 // (straight-line code keeps all of them in flight together, and a caller can
@@ -71,7 +72,7 @@ __host__ __device__ inline int fast_mode(int m, int GB, bool contiguous, int kq 
 template <int KQ = kQ, int NT = 256>
 __device__ __forceinline__ void load_groups(const uint8_t* __restrict__ reads, const uint8_t* __restrict__ refs,
                                             int64_t n_pairs, int m, int64_t g0, int GB, bool present,
-                                            uint4 (&v)[2][KQ])
+                                            uint4 (&v)[2][KQ], int tid = (int)threadIdx.x)
 {
     const int64_t s0 = g0 * 32;
     const int np = present ? (int)min((int64_t)32 * GB, n_pairs - s0) : 0;
@@ -84,7 +85,7 @@ __device__ __forceinline__ void load_groups(const uint8_t* __restrict__ reads, c
 #pragma unroll
         for (int k = 0; k < KQ; k++)
             v[sd][k] = __builtin_bit_cast(
-                uint4, __builtin_amdgcn_raw_buffer_load_b128(rs, 16 * (threadIdx.x + NT * k), 0, 0));
+                uint4, __builtin_amdgcn_raw_buffer_load_b128(rs, 16 * (tid + NT * k), 0, 0));
     }
 }
 
@@ -93,12 +94,23 @@ struct BlockBarrier {
     __device__ __forceinline__ void operator()() const { __syncthreads(); }
 };
 
+// for NT = 64 (one wavefront encodes): its LDS accesses before, in order before
+// those after (no other wavefront takes part)
+struct WaveSync {
+    __device__ __forceinline__ void operator()() const
+    {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    }
+};
+
 // Encode groups g0 .. g0+GB-1 (those that hold a slot below n_pairs); GB is a
 // power of two.  Slot i reads pair index[i] (or i) at offsets[pair] (or
 // pair * m).  The words of (plane p, chunk c, local group gl) go to
 // out4[(p * nch + c) * ostride + (obase + gl) * gstride] (out4 may point to
 // global memory or to LDS).  stage: GB * stage_dwords(m) dwords of LDS, 16-byte
-// aligned.  NT threads (0 .. NT-1) do the work.
+// aligned.  NT threads (tid 0 .. NT-1) do the work.
 // fast (see fast_mode): 0 = any slots, byte loads; 1 or 2 = slots are pairs
 // stored back to back from a 16-byte aligned byte (index and offsets null)
 // and v holds load_groups' loads of these groups; 1 when m % 4 == 0 (codes
@@ -113,7 +125,8 @@ __device__ __forceinline__ void encode_groups(const uint8_t* __restrict__ reads,
                                               int64_t g0, int GB, int fast, const uint4 (&v)[2][KQ],
                                               uint32_t* __restrict__ stage, uint4* __restrict__ out4,
                                               int64_t ostride, int64_t obase, uint32_t& bad,
-                                              int64_t gstride = 1, const BAR& bar = BAR())
+                                              int64_t gstride = 1, const BAR& bar = BAR(),
+                                              int tid = (int)threadIdx.x)
 {
     const int mw = (m + 3) >> 2;              // dwords per slot row
     const int gs = 32 * mw + 4;               // dwords per group
@@ -121,7 +134,7 @@ __device__ __forceinline__ void encode_groups(const uint8_t* __restrict__ reads,
     const int64_t s0 = g0 * 32;
     const int np = (int)min((int64_t)32 * GB, n_pairs - s0);
     const int lgb = 31 - __builtin_clz((unsigned)GB);
-    const int t = threadIdx.x;
+    const int t = tid;
     const int ndw = np * mw;
     const int nq = ndw >> 2;
     // Staging index of source dword dw (slot p = dw / mw, column dw % mw):
