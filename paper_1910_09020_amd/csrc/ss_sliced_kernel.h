@@ -437,7 +437,7 @@ __device__ __forceinline__ void arrive(uint32_t* p)
 // Two register buffers take turns in every encoding wave: the loads of its next
 // groups are in flight while the current ones are encoded.
 //
-// Wave mode (U > 0, pairs of up to a few hundred bases stored from 16-byte
+// Wave mode (WAVE, U > 0; pairs of up to a few hundred bases stored from 16-byte
 // aligned bases): each encoding wave encodes units of U groups by itself, with
 // staging of its own, so the encoders never wait for each other; wave w takes
 // the block's units w, w+3, ... (T / U units per tile, in tile order).  They
@@ -449,7 +449,7 @@ __device__ __forceinline__ void arrive(uint32_t* p)
 // per-buffer count reaches tile i's target only when tile i is complete.)
 // Every wait on a counter is bounded (see wait_at_least).
 //
-// Block mode (U == 0): the three waves encode GB groups at a time together,
+// Block mode (not WAVE): the three waves encode GB groups at a time together,
 // passing four block barriers per GB groups, and the sweeping wave takes part in
 // every one: while tile i is encoded (4 * steps(i) barriers) it sweeps tile
 // i-1, its work cut into as many pieces as there are barriers, one piece
@@ -461,7 +461,7 @@ __device__ __forceinline__ void arrive(uint32_t* p)
 // LDS: the staging (wave mode: three regions of U * stage_dwords(m) dwords;
 // block mode: GB * stage_dwords(m) dwords), two buffers of
 // T * tile::fused_group_chunks(m) uint4, then the counters.
-template <int E>
+template <int E, bool WAVE>
 __global__ __launch_bounds__(256) void k_fused(const uint8_t* __restrict__ reads, const uint8_t* __restrict__ refs,
                                                int64_t n_pairs, int m, int T, int GB, int U, int fast,
                                                uint16_t* __restrict__ out, uint32_t* __restrict__ err)
@@ -471,8 +471,8 @@ __global__ __launch_bounds__(256) void k_fused(const uint8_t* __restrict__ reads
     const int GS = tile::fused_group_chunks(m);
     const int64_t G = (n_pairs + 31) / 32;
     const int64_t ntiles = (G + T - 1) / T;
-    const int wave_stage = (U * tile::stage_dwords(m) + 3) & ~3;
-    const int stage_w = U > 0 ? 3 * wave_stage : (GB * tile::stage_dwords(m) + 3) & ~3;
+    const int wave_stage = WAVE ? (U * tile::stage_dwords(m) + 3) & ~3 : 0;
+    const int stage_w = WAVE ? 3 * wave_stage : (GB * tile::stage_dwords(m) + 3) & ~3;
     uint4* __restrict__ buf0 = reinterpret_cast<uint4*>(lds + stage_w);
     uint32_t* __restrict__ ctr = reinterpret_cast<uint32_t*>(buf0 + 2 * (int64_t)T * GS);
     const int64_t t0 = blockIdx.x;
@@ -484,11 +484,12 @@ __global__ __launch_bounds__(256) void k_fused(const uint8_t* __restrict__ reads
     auto buffer = [&](int64_t i) { return buf0 + (i & 1) * (int64_t)T * GS; };
     if (threadIdx.x < kFusedCtrs) ctr[threadIdx.x] = 0u;
     __syncthreads();
-    const int upt = U > 0 ? T / U : 0;     // units per tile (wave mode)
+    const int upt = WAVE ? T / U : 0;      // units per tile (wave mode)
 
     if (threadIdx.x < kFusedEnc) {
         uint32_t bad = 0;
-        if (U > 0) {
+        if constexpr (WAVE) {
+            __builtin_assume(fast == 1 || fast == 2);     // wave mode is chosen only for the streaming loads
             const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
             uint32_t* __restrict__ stage = lds + w * wave_stage;
             const int64_t total = nmine * upt;
@@ -571,7 +572,7 @@ __global__ __launch_bounds__(256) void k_fused(const uint8_t* __restrict__ reads
                 sw.chunks(tb + (int64_t)gl * GS * 4, nch, m, vb, c, c >= SW::EC && c + CPI <= ct);
             if (c + CPI >= nch && h == 0) write_group<E>(sw.Tm, tp * T + gl, n_pairs, out);
         };
-        if (U > 0) {
+        if constexpr (WAVE) {
             for (int64_t i = 0; i < nmine; i++) {
                 wait_at_least(ctr + kCtrDone0 + (i & 1), (uint32_t)(upt * (i / 2 + 1)), err);
                 const int64_t tp = tile_of(i);
@@ -630,28 +631,35 @@ hipError_t launch_sliced_E(const uint32_t* packed, int64_t n_pairs, int32_t m, i
     return hipGetLastError();
 }
 
-template <int E>
-hipError_t launch_fused_E(const uint8_t* reads, const uint8_t* refs, int64_t n_pairs, int32_t m, int T, int GB,
-                          int U, int fast, size_t shmem, uint16_t* out, uint32_t* err, hipStream_t s)
+template <int E, bool WAVE>
+hipError_t launch_fused_mode(const uint8_t* reads, const uint8_t* refs, int64_t n_pairs, int32_t m, int T, int GB,
+                             int U, int fast, size_t shmem, uint16_t* out, uint32_t* err, hipStream_t s)
 {
     const int64_t G = cdiv(n_pairs, 32);
+    const void* fn = reinterpret_cast<const void*>(&k_fused<E, WAVE>);
     if (shmem > 65536) {
-        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fused<E>),
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+        const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
         if (e != hipSuccess) return e;
     }
     // persistent blocks: as many as are resident at once (LDS and registers), at most one per tile
     int per_cu = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per_cu, reinterpret_cast<const void*>(&k_fused<E>), 256, shmem);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, shmem);
     if (e != hipSuccess) return e;
     int dev = 0, cus = 0;
     if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
     if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
     const int64_t grid = std::min<int64_t>(cdiv(G, T), (int64_t)std::max(1, per_cu) * cus);
-    hipLaunchKernelGGL((k_fused<E>), dim3((unsigned)grid), dim3(256), shmem, s, reads, refs, n_pairs, m, T,
+    hipLaunchKernelGGL((k_fused<E, WAVE>), dim3((unsigned)grid), dim3(256), shmem, s, reads, refs, n_pairs, m, T,
                        GB, U, fast, out, err);
     return hipGetLastError();
+}
+
+template <int E>
+hipError_t launch_fused_E(const uint8_t* reads, const uint8_t* refs, int64_t n_pairs, int32_t m, int T, int GB,
+                          int U, int fast, size_t shmem, uint16_t* out, uint32_t* err, hipStream_t s)
+{
+    return U > 0 ? launch_fused_mode<E, true>(reads, refs, n_pairs, m, T, GB, U, fast, shmem, out, err, s)
+                 : launch_fused_mode<E, false>(reads, refs, n_pairs, m, T, GB, U, fast, shmem, out, err, s);
 }
 
 template <int... Es>
