@@ -159,9 +159,10 @@ int ss_filter_submaze_async(ss_ctx* ctx, const uint32_t* packed, int64_t n_pairs
  *   E <= 5 : one fused kernel.  Three wavefronts of each workgroup encode
  *            tiles of tile_groups groups of 32 pairs into one of two on-chip
  *            buffers while the fourth sweeps the previous tile from the other
- *            (in step with the encoders' barriers for E <= 3, through
- *            counters in on-chip memory once per tile above), so the packed
- *            encoding never reaches device memory.
+ *            (for 16-byte aligned reads and refs and m <= 224 each encoding
+ *            wavefront works alone and they meet the sweeping one through
+ *            counters in on-chip memory; otherwise the four share the block's
+ *            barriers), so the packed encoding never reaches device memory.
  *   E > 5  : the two kernels over chunks of about 400 MB of packed data, kept
  *            in a buffer owned by ctx (allocated on first use, grown when a
  *            longer m needs it): calls with E > 5 on one context must be
