@@ -596,7 +596,7 @@ def main():
     # roofline of the step's kernel (algorithmic bytes per launch / mean launch time on its stream)
     fused = E <= 5          # the one-call path runs the fused kernel up to E = 5
     if fused:
-        dom = "fused encode + column sweep (k_fused<%d>)" % E
+        dom = "fused encode + column sweep (k_fused<%d, true>, wave mode)" % E
         bytes_ = n * (2 * m + 2)                 # read two ASCII sequences, write one result word
         traffic = measured_traffic("k_fused_E%d" % E) if n == 30_000_000 else None
     else:
