@@ -143,11 +143,12 @@ hipError_t launch_sliced(const uint32_t* packed, int64_t n_pairs, int32_t m, int
     return launch_sliced_hi(E, packed, n_pairs, m, sub_width, out, s);
 }
 
-// Tile shape of the fused kernel: T groups per tile buffer (two of them) and
-// 16 bytes of counters; U > 0 groups per unit when each encoding wavefront
-// encodes by itself (contiguous pairs whose U groups fit its loads), else U = 0
-// and GB groups staged at a time by the three together.  Returns the LDS bytes
-// per block, or 0 when no shape fits.
+// Tile shape of the fused kernel: T groups per tile buffer (two of them), in
+// wave mode the sweep's column words, and 16 bytes of counters; U > 0 groups
+// per unit when each encoding wavefront encodes by itself (contiguous pairs
+// whose U groups fit its loads), else U = 0 and GB groups staged at a time by
+// the three together.  Returns the LDS bytes per block, or 0 when no shape
+// fits.
 size_t fused_shape(int32_t m, int tile_groups, bool contiguous, int* T_out, int* GB_out, int* U_out)
 {
     const int64_t stage_b = (int64_t)tile::stage_dwords(m) * 4;
@@ -168,7 +169,7 @@ size_t fused_shape(int32_t m, int tile_groups, bool contiguous, int* T_out, int*
     for (int U = 2; U >= 1 && contiguous && m > 0; U >>= 1) {
         if (tile::fast_mode(m, U, true, tile::kWaveQ, 64) == 0) continue;
         const int64_t sw = 3 * ((U * stage_b + 15) & ~(int64_t)15);
-        auto lds_w = [&](int64_t T) { return sw + 2 * T * buf_b + 16; };
+        auto lds_w = [&](int64_t T) { return sw + 2 * T * buf_b + 4ll * tile::fused_dead_words(m) + 16; };
         const int T = pick(U, lds_w);
         if (T > 0) {
             *T_out = T;

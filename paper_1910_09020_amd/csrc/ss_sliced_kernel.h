@@ -97,23 +97,13 @@ __device__ __forceinline__ uint32_t comp(const uint4& v, int t)
 
 __device__ __forceinline__ constexpr int floordiv(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
 
-// Decide and write (step 5) for the 32 pairs of group g from the thermometer
-// T (T[l-1]: count >= l): accept = count <= E, count in binary digits; one
-// 16-bit word per pair (bit 15 accept, low bits the count).
-template <int E>
-__device__ __forceinline__ void write_group(const uint32_t (&T)[E + 1], int64_t g, int64_t n_pairs,
-                                            uint16_t* __restrict__ out)
+// Write the 32 results of group g: acc (bit s: pair 32g+s accepted) and the
+// count's binary digits dig; one 16-bit word per pair (bit 15 accept, low bits
+// the count).
+template <int NB>
+__device__ __forceinline__ void write_digits(const uint32_t (&dig)[NB], uint32_t acc, int64_t g, int64_t n_pairs,
+                                             uint16_t* __restrict__ out)
 {
-    constexpr int NB = (E + 1) < 2 ? 1 : (E + 1) < 4 ? 2 : (E + 1) < 8 ? 3 : (E + 1) < 16 ? 4 : (E + 1) < 32 ? 5 : 6;
-    uint32_t dig[NB];
-#pragma unroll
-    for (int b = 0; b < NB; b++) {
-        uint32_t x = 0;
-#pragma unroll
-        for (int i = 1; (i << b) <= E + 1; i++) x ^= T[(i << b) - 1];
-        dig[b] = x;
-    }
-    const uint32_t acc = ~T[E];
     const int64_t p0 = g * 32;
     uint32_t res[16];
 #pragma unroll
@@ -138,6 +128,25 @@ __device__ __forceinline__ void write_group(const uint32_t (&T)[E + 1], int64_t 
         for (int s = 0; s < 32; s++)
             if (p0 + s < n_pairs) out[p0 + s] = (uint16_t)(res[s >> 1] >> (16 * (s & 1)));
     }
+}
+
+// Decide and write (step 5) for the 32 pairs of group g from the thermometer
+// T (T[l-1]: count >= l): accept = count <= E, count in binary digits; one
+// 16-bit word per pair (bit 15 accept, low bits the count).
+template <int E>
+__device__ __forceinline__ void write_group(const uint32_t (&T)[E + 1], int64_t g, int64_t n_pairs,
+                                            uint16_t* __restrict__ out)
+{
+    constexpr int NB = (E + 1) < 2 ? 1 : (E + 1) < 4 ? 2 : (E + 1) < 8 ? 3 : (E + 1) < 16 ? 4 : (E + 1) < 32 ? 5 : 6;
+    uint32_t dig[NB];
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+        uint32_t x = 0;
+#pragma unroll
+        for (int i = 1; (i << b) <= E + 1; i++) x ^= T[(i << b) - 1];
+        dig[b] = x;
+    }
+    write_digits<NB>(dig, ~T[E], g, n_pairs, out);
 }
 
 // Interior chunk loop variants.
@@ -319,7 +328,37 @@ __device__ __forceinline__ uint32_t quad_or(uint32_t x)
 // position j + vb + i, vb = sh - E.  A column's "some row is free" is the OR
 // over the group's lanes of each lane's own OR, so every lane keeps the same
 // count (the thermometer Tm, as in SweepState).
-template <int E, int LPG, int CPI>
+// Bit-sliced counts of three binary digits, each at most S (1 <= S <= 7).
+// sat3: count == S (for a count <= S, the AND of the digits S has set).
+template <int S>
+__device__ __forceinline__ uint32_t sat3(uint32_t b0, uint32_t b1, uint32_t b2)
+{
+    uint32_t r = ~0u;
+    if (S & 1) r &= b0;
+    if (S & 2) r &= b1;
+    if (S & 4) r &= b2;
+    return r;
+}
+
+// min(a + b, S) for counts a, b <= S
+template <int S>
+__device__ __forceinline__ void sat_add3(uint32_t (&a)[3], const uint32_t (&b)[3])
+{
+    const uint32_t s0 = a[0] ^ b[0], k0 = a[0] & b[0];
+    const uint32_t s1 = a[1] ^ b[1] ^ k0, k1 = __builtin_amdgcn_bitop3_b32(a[1], b[1], k0, 0xE8);   // majority
+    const uint32_t s2 = a[2] ^ b[2] ^ k1, k2 = __builtin_amdgcn_bitop3_b32(a[2], b[2], k1, 0xE8);
+    // ge: the 4-bit sum (k2 s2 s1 s0) >= S, from the low digit up
+    uint32_t ge = ~0u;
+    ge = (S & 1) ? (s0 & ge) : (s0 | ge);
+    ge = (S & 2) ? (s1 & ge) : (s1 | ge);
+    ge = (S & 4) ? (s2 & ge) : (s2 | ge);
+    ge |= k2;
+    a[0] = (S & 1) ? (s0 | ge) : (s0 & ~ge);
+    a[1] = (S & 2) ? (s1 | ge) : (s1 & ~ge);
+    a[2] = (S & 4) ? (s2 | ge) : (s2 & ~ge);
+}
+
+template <int E, int LPG, int CPI, bool DB = false>
 struct TileSweep {
     static constexpr int NR = 2 * E + 1;
     static constexpr int SL = (NR + LPG - 1) / LPG;
@@ -327,8 +366,14 @@ struct TileSweep {
     static constexpr int NC = B * CPI;        // columns per call
     static constexpr int NQ = SL + NC - 1;    // query words they read, per lane and plane
     static constexpr int EC = (E + B - 1) / B;
+    // DB: instead of a thermometer updated by every lane at every column, each
+    // column's OR word goes to dead[j] in LDS, and at the end the group's LPG
+    // lanes count a share of the columns each (saturating binary digits) and add
+    // the shares up through DPP (finish)
+    static_assert(!DB || (E + 1 <= 7 && LPG == 4), "counted words: E <= 6, four lanes per group");
     uint32_t S[SL];
-    uint32_t Tm[E + 1];
+    uint32_t Tm[DB ? 1 : E + 1];
+    uint32_t* dead = nullptr;                 // DB: this group's column words
 
     __device__ __forceinline__ static int first_query(int h) { return min(h * SL, NR - SL) - E; }
 
@@ -337,7 +382,7 @@ struct TileSweep {
 #pragma unroll
         for (int i = 0; i < SL; i++) S[i] = ~0u;
 #pragma unroll
-        for (int l = 0; l <= E; l++) Tm[l] = 0u;
+        for (int l = 0; l < (DB ? 1 : E + 1); l++) Tm[l] = 0u;
     }
 
     template <bool CHK>
@@ -358,49 +403,88 @@ struct TileSweep {
                 any |= a;
             }
             any = quad_or<LPG>(any);
+            if constexpr (DB) {
+                dead[j] = any;                // the group's lanes store the same word
+            } else {
 #pragma unroll
-            for (int l = E; l >= 1; l--) Tm[l] = or_and_not(Tm[l], Tm[l - 1], any);
-            Tm[0] = or_not(Tm[0], any);
+                for (int l = E; l >= 1; l--) Tm[l] = or_and_not(Tm[l], Tm[l - 1], any);
+                Tm[0] = or_not(Tm[0], any);
+            }
 #pragma unroll
             for (int i = 0; i < SL; i++) S[i] = or_not(S[i], any);
         }
     }
 
-    // chunks c .. c+CPI-1 (columns 4c .. 4c+NC-1, those below m); interior: every
-    // row of every lane reads a query position in [0, m) and every chunk is below
-    // nch (then all reads stay inside the group's planes)
+    // decide and write (step 5) for group g after its last column; every lane of
+    // the group calls it, lane 0 writes
+    __device__ __forceinline__ void finish(int h, int m, int64_t g, int64_t n_pairs, uint16_t* __restrict__ out)
+    {
+        if constexpr (DB) {
+            constexpr int SAT = E + 1;
+            tile::WaveSync()();               // the column words stored above, before they are read
+            uint32_t c[3] = {0u, 0u, 0u};     // count of columns with no row free, saturating at E + 1
+            const int q = (m + LPG - 1) / LPG;
+            const int j1 = min(m, (h + 1) * q);
+            for (int j = h * q; j < j1; j++) {
+                const uint32_t inc = ~dead[j] & ~sat3<SAT>(c[0], c[1], c[2]);
+                const uint32_t k0 = c[0] & inc;
+                c[0] ^= inc;
+                c[2] = __builtin_amdgcn_bitop3_b32(c[2], c[1], k0, 0x78);   // c2 ^ (c1 & k0)
+                c[1] ^= k0;
+            }
+            uint32_t o[3];
+#pragma unroll
+            for (int k = 0; k < 3; k++) o[k] = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)c[k], 0xB1, 0xF, 0xF, false);
+            sat_add3<SAT>(c, o);
+#pragma unroll
+            for (int k = 0; k < 3; k++) o[k] = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)c[k], 0x4E, 0xF, 0xF, false);
+            sat_add3<SAT>(c, o);
+            tile::WaveSync()();               // the reads above, before the group's next columns are stored
+            if (h == 0) write_digits<3>(c, ~sat3<SAT>(c[0], c[1], c[2]), g, n_pairs, out);
+        } else {
+            if (h == 0) write_group<E>(Tm, g, n_pairs, out);
+        }
+    }
+
+    // the words of chunks c .. c+CPI-1: reference words (chunks past nch read the
+    // last chunk; those columns are not run) and the lane's query window,
+    // positions 4c + vb .. 4c + vb + NQ - 1.  Positions outside [0, m) are read
+    // for rows that are masked: from at most E words before the group's planes
+    // (the previous group, or the staging before the first buffer) to at most
+    // 4 * CPI + E words past the end of a plane (still inside the group's planes)
+    struct Words {
+        uint4 rr0[CPI], rr1[CPI];
+        uint32_t w0[NQ], w1[NQ];
+    };
+    __device__ __forceinline__ static void load(Words& W, const uint32_t* __restrict__ gp, int nch, int vb, int c)
+    {
+        const uint4* __restrict__ gp4 = reinterpret_cast<const uint4*>(gp);
+#pragma unroll
+        for (int k = 0; k < CPI; k++) {
+            const int ck = min(c + k, nch - 1);
+            W.rr0[k] = gp4[2 * nch + ck];
+            W.rr1[k] = gp4[3 * nch + ck];
+        }
+        const uint32_t* __restrict__ q0 = gp + 4 * c + vb;
+        const uint32_t* __restrict__ q1 = q0 + 4 * nch;
+#pragma unroll
+        for (int x = 0; x < NQ; x++) { W.w0[x] = q0[x]; W.w1[x] = q1[x]; }
+    }
+
+    // columns 4c .. 4c+NC-1 (those below m); interior: every row of every lane
+    // reads a query position in [0, m) and every chunk is below nch
+    __device__ __forceinline__ void compute(const Words& W, int m, int vb, int c, bool interior)
+    {
+        if (interior) columns<false>(W.w0, W.w1, W.rr0, W.rr1, 4 * c, vb, m);
+        else columns<true>(W.w0, W.w1, W.rr0, W.rr1, 4 * c, vb, m);
+    }
+
     __device__ __forceinline__ void chunks(const uint32_t* __restrict__ gp, int nch, int m, int vb, int c,
                                            bool interior)
     {
-        const uint4* __restrict__ gp4 = reinterpret_cast<const uint4*>(gp);
-        uint4 rr0[CPI], rr1[CPI];
-        uint32_t w0[NQ], w1[NQ];
-        if (interior) {
-#pragma unroll
-            for (int k = 0; k < CPI; k++) { rr0[k] = gp4[2 * nch + c + k]; rr1[k] = gp4[3 * nch + c + k]; }
-            const uint32_t* __restrict__ q0 = gp + 4 * c + vb;
-            const uint32_t* __restrict__ q1 = q0 + 4 * nch;
-#pragma unroll
-            for (int x = 0; x < NQ; x++) { w0[x] = q0[x]; w1[x] = q1[x]; }
-            columns<false>(w0, w1, rr0, rr1, 4 * c, vb, m);
-        } else {
-            // chunks past nch read the last chunk (those columns are not run); query
-            // positions outside [0, m) are read unclamped, for rows that are masked:
-            // from at most E words before the group's planes (the previous group, or
-            // the staging before the first buffer) to at most 4 * CPI + E words past
-            // the end of a plane (still inside the group's four planes)
-#pragma unroll
-            for (int k = 0; k < CPI; k++) {
-                const int ck = min(c + k, nch - 1);
-                rr0[k] = gp4[2 * nch + ck];
-                rr1[k] = gp4[3 * nch + ck];
-            }
-            const uint32_t* __restrict__ q0 = gp + 4 * c + vb;
-            const uint32_t* __restrict__ q1 = q0 + 4 * nch;
-#pragma unroll
-            for (int x = 0; x < NQ; x++) { w0[x] = q0[x]; w1[x] = q1[x]; }
-            columns<true>(w0, w1, rr0, rr1, 4 * c, vb, m);
-        }
+        Words W;
+        load(W, gp, nch, vb, c);
+        compute(W, m, vb, c, interior);
     }
 };
 
@@ -460,7 +544,8 @@ __device__ __forceinline__ void arrive(uint32_t* p)
 //
 // LDS: the staging (wave mode: three regions of U * stage_dwords(m) dwords;
 // block mode: GB * stage_dwords(m) dwords), two buffers of
-// T * tile::fused_group_chunks(m) uint4, then the counters.
+// T * tile::fused_group_chunks(m) uint4, in wave mode the sweep's column words
+// (tile::fused_dead_words(m)), then the counters.
 template <int E, bool WAVE>
 __global__ __launch_bounds__(256) void k_fused(const uint8_t* __restrict__ reads, const uint8_t* __restrict__ refs,
                                                int64_t n_pairs, int m, int T, int GB, int U, int fast,
@@ -474,7 +559,8 @@ __global__ __launch_bounds__(256) void k_fused(const uint8_t* __restrict__ reads
     const int wave_stage = WAVE ? (U * tile::stage_dwords(m) + 3) & ~3 : 0;
     const int stage_w = WAVE ? 3 * wave_stage : (GB * tile::stage_dwords(m) + 3) & ~3;
     uint4* __restrict__ buf0 = reinterpret_cast<uint4*>(lds + stage_w);
-    uint32_t* __restrict__ ctr = reinterpret_cast<uint32_t*>(buf0 + 2 * (int64_t)T * GS);
+    uint32_t* __restrict__ deadbuf = reinterpret_cast<uint32_t*>(buf0 + 2 * (int64_t)T * GS);
+    uint32_t* __restrict__ ctr = deadbuf + (WAVE ? tile::fused_dead_words(m) : 0);
     const int64_t t0 = blockIdx.x;
     if (t0 >= ntiles) return;
     const int64_t nmine = (ntiles - t0 + gridDim.x - 1) / gridDim.x;   // tiles of this block
@@ -559,18 +645,20 @@ __global__ __launch_bounds__(256) void k_fused(const uint8_t* __restrict__ reads
         constexpr int LPG = fused_lanes(E);
         constexpr int GPP = 64 / LPG;                    // groups per pass of the wave
         constexpr int CPI = kFusedCPI;                   // chunks per call
-        using SW = TileSweep<E, LPG, CPI>;
+        constexpr bool DB = WAVE && E >= 3;              // column words counted at the end (wave mode)
+        using SW = TileSweep<E, LPG, CPI, DB>;
         const int lane = threadIdx.x - kFusedEnc;
         const int h = lane % LPG, gq = lane / LPG;
         const int vb = SW::first_query(h);
         const int ct = (m - kChunk - E >= 0) ? (m - kChunk - E) / kChunk + 1 : 0;   // interior chunks [EC, ct)
         SW sw;
         // the sweep of group gl of tile tp from buffer tb, chunks c .. c+CPI-1
+        if constexpr (DB) sw.dead = deadbuf + gq * (m | 1);
         auto sweep_item = [&](const uint32_t* __restrict__ tb, int64_t tp, int gl, int c) {
             if (c == 0) sw.init();
             if (c < nch)
                 sw.chunks(tb + (int64_t)gl * GS * 4, nch, m, vb, c, c >= SW::EC && c + CPI <= ct);
-            if (c + CPI >= nch && h == 0) write_group<E>(sw.Tm, tp * T + gl, n_pairs, out);
+            if (c + CPI >= nch) sw.finish(h, m, tp * T + gl, n_pairs, out);
         };
         if constexpr (WAVE) {
             for (int64_t i = 0; i < nmine; i++) {
@@ -580,8 +668,25 @@ __global__ __launch_bounds__(256) void k_fused(const uint8_t* __restrict__ reads
                 const uint32_t* __restrict__ tb = reinterpret_cast<const uint32_t*>(buffer(i));
                 for (int g0 = 0; g0 < tg; g0 += GPP) {
                     const int gl = g0 + gq;
-                    if (gl < tg)
-                        for (int c = 0; c < (nch > 0 ? nch : 1); c += CPI) sweep_item(tb, tp, gl, c);
+                    if (gl < tg) {
+                        // the next item's words are loaded while this item's columns run
+                        const uint32_t* __restrict__ gp = tb + (int64_t)gl * GS * 4;
+                        auto inner = [&](int c) { return c >= SW::EC && c + CPI <= ct; };
+                        sw.init();
+                        if (nch > 0) {
+                            typename SW::Words wa, wb;
+                            SW::load(wa, gp, nch, vb, 0);
+                            for (int c = 0;; c += 2 * CPI) {
+                                if (c + CPI < nch) SW::load(wb, gp, nch, vb, c + CPI);
+                                sw.compute(wa, m, vb, c, inner(c));
+                                if (c + CPI >= nch) break;
+                                if (c + 2 * CPI < nch) SW::load(wa, gp, nch, vb, c + 2 * CPI);
+                                sw.compute(wb, m, vb, c + CPI, inner(c + CPI));
+                                if (c + 2 * CPI >= nch) break;
+                            }
+                        }
+                        sw.finish(h, m, tp * T + gl, n_pairs, out);
+                    }
                 }
                 arrive(ctr + kCtrSwept);
             }

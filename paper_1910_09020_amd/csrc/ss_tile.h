@@ -49,6 +49,9 @@ constexpr int kWaveQ = 7;          // 16-byte loads per lane and side when one w
 // are consecutive words), plus one uint4 of padding that spreads consecutive
 // groups over the LDS banks
 __host__ __device__ inline int fused_group_chunks(int m) { return 4 * ((m + 3) >> 2) + 1; }
+// words of the fused sweep's column store in wave mode: 16 groups (a pass of the
+// sweeping wavefront at four lanes per group) of m words, at an odd stride
+__host__ __device__ inline int fused_dead_words(int m) { return 16 * (m | 1); }
 
 // Encoder mode for GB groups of pairs of length m stored back to back from
 // 16-byte aligned bases (contiguous), else 0: 1 when m % 4 == 0 and each side
