@@ -389,6 +389,12 @@ struct TileSweep {
     __device__ __forceinline__ void columns(const uint32_t (&w0)[NQ], const uint32_t (&w1)[NQ],
                                             const uint4 (&rr0)[CPI], const uint4 (&rr1)[CPI], int j0, int vb, int m)
     {
+        // CHK: vm[x] = ~0 when window position x (query position j0 + vb + x) is in [0, m)
+        uint32_t vm[CHK ? NQ : 1];
+        if constexpr (CHK) {
+#pragma unroll
+            for (int x = 0; x < NQ; x++) vm[x] = (unsigned)(j0 + vb + x) < (unsigned)m ? ~0u : 0u;
+        }
 #pragma unroll
         for (int t = 0; t < NC; t++) {
             const int j = j0 + t;
@@ -398,7 +404,7 @@ struct TileSweep {
 #pragma unroll
             for (int i = 0; i < SL; i++) {
                 uint32_t a = and_xnor(and_xnor(S[i], r0, w0[t + i]), r1, w1[t + i]);
-                if (CHK && (unsigned)(j + vb + i) >= (unsigned)m) a = 0;
+                if constexpr (CHK) a &= vm[t + i];
                 S[i] = a;
                 any |= a;
             }
