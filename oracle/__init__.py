@@ -2,7 +2,8 @@
 
 Thin ctypes wrapper over ``oracle/ss_oracle.c``: the plain, per-cell CPU
 implementation of the chip maze (Equation 1, Section 2.3) and the greedy walk
-(Section 2.4), Snake-on-Chip's sub-maze decomposition of it (Section 2.5), plus
+(Section 2.4), Snake-on-Chip's sub-maze decomposition of it (Section 2.5), pairs of
+unequal length (the note of Section 2.4 between steps 4 and 5), plus
 the two checkers that pin it (minimum-obstacle search over
 all signal nets, Theorem 2; Levenshtein DP, the quantity the filter bounds from
 below, Sections 1 and 2.1).
@@ -66,6 +67,16 @@ def _load():
     lib.ss_oracle_submaze_batch.argtypes = [u8p, u8p, i64p, i32p, ctypes.c_int64, ctypes.c_int, ctypes.c_int, u8p,
                                             i32p]
     lib.ss_oracle_submaze_batch.restype = None
+    lib.ss_oracle_pair_uneq.argtypes = [u8p, ctypes.c_int, u8p, ctypes.c_int, ctypes.c_int, i32p, i32p, i32p]
+    lib.ss_oracle_pair_uneq.restype = ctypes.c_int
+    lib.ss_oracle_min_obstacles_uneq.argtypes = [u8p, ctypes.c_int, u8p, ctypes.c_int, ctypes.c_int]
+    lib.ss_oracle_min_obstacles_uneq.restype = ctypes.c_int
+    lib.ss_oracle_batch_uneq.argtypes = [u8p, i64p, i32p, u8p, i64p, i32p, ctypes.c_int64, i32p, ctypes.c_int32,
+                                         ctypes.c_int, u8p, i32p]
+    lib.ss_oracle_batch_uneq.restype = ctypes.c_double
+    lib.ss_oracle_uneq_checks.argtypes = [u8p, i64p, i32p, u8p, i64p, i32p, ctypes.c_int64, ctypes.c_int32, i32p, i32p,
+                                          i32p]
+    lib.ss_oracle_uneq_checks.restype = None
     _lib = lib
     return lib
 
@@ -205,3 +216,62 @@ def levenshtein_batch(reads, refs, offsets, lengths) -> np.ndarray:
     _load().ss_oracle_levenshtein_batch(_u8(np.ascontiguousarray(reads)), _u8(np.ascontiguousarray(refs)),
                                         _i64(offsets), _i32(lengths), n, _i32(out))
     return out
+
+
+# ---------------------------------------------------------------------------- unequal lengths
+def pair_uneq(R, Q, E: int):
+    """Walk of Section 2.4 on a reference R and a query Q of any lengths, with the leading and
+    trailing obstacles caused by the fourth case of Equation 1 deducted (the reading is stated in
+    ss_oracle.c).  Returns (accept, reported count = min(count after the deduction, E+1), count
+    before the deduction)."""
+    r, q = _bytes(R), _bytes(Q)
+    e, f = ctypes.c_int32(0), ctypes.c_int32(0)
+    acc = _load().ss_oracle_pair_uneq(_u8(r), len(r), _u8(q), len(q), int(E), ctypes.byref(e), ctypes.byref(f),
+                                      None)
+    return int(acc), int(e.value), int(f.value)
+
+
+def min_obstacles_uneq(R, Q, E: int) -> int:
+    """Fewest obstacles outside fourth-case-only columns over all signal nets (exhaustive search)."""
+    r, q = _bytes(R), _bytes(Q)
+    return int(_load().ss_oracle_min_obstacles_uneq(_u8(r), len(r), _u8(q), len(q), int(E)))
+
+
+def batch_uneq(reads, read_offsets, read_lengths, refs, ref_offsets, ref_lengths, E=None, E_per_pair=None,
+               threads: int = 1) -> dict:
+    """pair_uneq over a batch: query p = reads[read_offsets[p]:+read_lengths[p]], reference p likewise
+    in refs.  Returns dict(accept=uint8[n], edits=int32[n], seconds)."""
+    reads = np.ascontiguousarray(reads, dtype=np.uint8)
+    refs = np.ascontiguousarray(refs, dtype=np.uint8)
+    ro = np.ascontiguousarray(read_offsets, dtype=np.int64)
+    rl = np.ascontiguousarray(read_lengths, dtype=np.int32)
+    fo = np.ascontiguousarray(ref_offsets, dtype=np.int64)
+    fl = np.ascontiguousarray(ref_lengths, dtype=np.int32)
+    n = len(rl)
+    assert len(ro) == n and len(fo) == n and len(fl) == n
+    if E_per_pair is not None:
+        E_per_pair = np.ascontiguousarray(E_per_pair, dtype=np.int32)
+    acc = np.zeros(n, dtype=np.uint8)
+    ed = np.zeros(n, dtype=np.int32)
+    secs = _load().ss_oracle_batch_uneq(_u8(reads), _i64(ro), _i32(rl), _u8(refs), _i64(fo), _i32(fl), n,
+                                        _i32(E_per_pair), int(E if E is not None else 0), int(threads), _u8(acc),
+                                        _i32(ed))
+    return dict(accept=acc, edits=ed, seconds=secs)
+
+
+def uneq_checks(reads, read_offsets, read_lengths, refs, ref_offsets, ref_lengths, E: int) -> dict:
+    """Per pair: the count after the deduction without the stop at E+1 (net), the exhaustive minimum
+    over nets (minobs) and the Levenshtein distance (ed); one thread."""
+    reads = np.ascontiguousarray(reads, dtype=np.uint8)
+    refs = np.ascontiguousarray(refs, dtype=np.uint8)
+    ro = np.ascontiguousarray(read_offsets, dtype=np.int64)
+    rl = np.ascontiguousarray(read_lengths, dtype=np.int32)
+    fo = np.ascontiguousarray(ref_offsets, dtype=np.int64)
+    fl = np.ascontiguousarray(ref_lengths, dtype=np.int32)
+    n = len(rl)
+    net = np.zeros(n, np.int32)
+    mo = np.zeros(n, np.int32)
+    ed = np.zeros(n, np.int32)
+    _load().ss_oracle_uneq_checks(_u8(reads), _i64(ro), _i32(rl), _u8(refs), _i64(fo), _i32(fl), n, int(E),
+                                  _i32(net), _i32(mo), _i32(ed))
+    return dict(net=net, minobs=mo, ed=ed)

@@ -15,6 +15,10 @@
  *     first obstacle (the "implicit chip maze" paragraph of Section 2.4);
  *   - Snake-on-Chip's decomposition (Section 2.5): the same walk run on
  *     non-overlapping sub-mazes of t columns, the counts summed;
+ *   - pairs of unequal length (the note of Section 2.4 between steps 4 and 5):
+ *     the maze over the longer length, the walk, and the deduction of the
+ *     leading and trailing obstacles caused by the fourth case of Equation 1
+ *     (the reading is stated at ss_oracle_pair_uneq);
  *   - two checkers used to pin the walk:
  *       * the minimum number of obstacles over every legal signal net, by an
  *         exhaustive dynamic programme over checkpoints (the quantity that
@@ -235,6 +239,165 @@ int ss_oracle_levenshtein(const uint8_t* a, int la, const uint8_t* b, int lb)
     return d;
 }
 
+/* ---- pairs of unequal length (Section 2.4, the note between steps 4 and 5) ----
+ *
+ * Reading taken here (the paper gives the rule in one sentence and no
+ * example):
+ *   - R has m characters, Q has n.  The maze has 2E+1 rows and as many columns
+ *     as the longer sequence, W = max(m, n); columns index R as in Equation 1.
+ *     A cell whose comparison needs a character that does not exist (a column
+ *     past the end of R, or a Q index outside 1..n) is an obstacle: the fourth
+ *     case of Equation 1.  For m = n this is exactly the maze of ss_oracle_cell.
+ *   - The walk of steps 1-4 runs over the W columns unchanged, to the
+ *     destination (the deduction needs the whole net).
+ *   - The obstacles "caused by the fourth case" are those lying in a column
+ *     that holds no comparison between two existing characters: every one of
+ *     its 2E+1 cells is a fourth-case cell, so the column carries no evidence of
+ *     a difference.  The leading ones (a run of such obstacles at the start of
+ *     the net) and the trailing ones (a run at its end) are deducted from the
+ *     count before the decision, which is then taken as in step 5.
+ *   - The count bounds the (global) edit distance between R and Q, the
+ *     distance Section 1 defines.  Columns with a real comparison are
+ *     1..min(m, n + E) when n >= 1 and none when n = 0, so for m = n nothing is
+ *     deducted.
+ * Returns 1 for accept; *edits = min(count after the deduction, E+1); *full
+ * and *net_out (optional) = the count before and after the deduction. */
+static int cell_uneq(const uint8_t* R, int m, const uint8_t* Q, int n, int E, int i, int j)
+{
+    int q;
+    if (i < 1 || i > 2 * E + 1) return 1;
+    if (i == E + 1)      q = j;
+    else if (i <= E)     q = j - i;
+    else                 q = j + i - E - 1;
+    if (j < 1 || j > m) return 1;          /* R has no j-th character */
+    if (q < 1 || q > n) return 1;          /* Q has no q-th character */
+    return fold(Q[q - 1]) == fold(R[j - 1]) ? 0 : 1;
+}
+
+/* 1 when some row of column j compares two existing characters */
+static int real_column(int m, int n, int E, int j)
+{
+    for (int i = 1; i <= 2 * E + 1; i++) {
+        int q = (i == E + 1) ? j : (i <= E ? j - i : j + i - E - 1);
+        if (j >= 1 && j <= m && q >= 1 && q <= n) return 1;
+    }
+    return 0;
+}
+
+int ss_oracle_pair_uneq(const uint8_t* R, int m, const uint8_t* Q, int n, int E, int32_t* edits, int32_t* full,
+                        int32_t* net_out)
+{
+    const int W = m > n ? m : n;
+    int* obst = (int*)malloc(sizeof(int) * (size_t)(W + 1));
+    int cnt = 0;
+    int c = 1;                                         /* step 1 */
+    while (c <= W) {                                   /* until the destination */
+        int best = -1;
+        for (int i = 1; i <= 2 * E + 1; i++) {         /* step 2: longest run over all rows */
+            int L = 0;
+            while (c + L <= W && cell_uneq(R, m, Q, n, E, i, c + L) == 0) L++;
+            if (L > best) best = L;
+        }
+        int end = c + best;
+        if (end <= W) obst[cnt++] = end;               /* the segment's obstacle */
+        c = end + 1;                                   /* step 3 */
+    }
+    int lead = 0;
+    while (lead < cnt && !real_column(m, n, E, obst[lead])) lead++;
+    int trail = 0;
+    while (trail < cnt - lead && !real_column(m, n, E, obst[cnt - 1 - trail])) trail++;
+    free(obst);
+    const int net = cnt - lead - trail;
+    if (full) *full = cnt;
+    if (net_out) *net_out = net;
+    if (edits) *edits = net <= E ? net : E + 1;
+    return net <= E ? 1 : 0;                           /* step 5 */
+}
+
+/* The fewest obstacles outside fourth-case-only columns over every legal
+ * signal net of the W-column maze above (exhaustive search over checkpoints,
+ * as ss_oracle_min_obstacles; an obstacle in a column without a real
+ * comparison costs nothing). */
+int ss_oracle_min_obstacles_uneq(const uint8_t* R, int m, const uint8_t* Q, int n, int E)
+{
+    const int W = m > n ? m : n;
+    if (W <= 0) return 0;
+    int* best = (int*)malloc(sizeof(int) * (size_t)(W + 2));
+    const int INF = 1 << 29;
+    for (int c = 0; c <= W + 1; c++) best[c] = INF;
+    best[1] = 0;
+    int answer = INF;
+    for (int c = 1; c <= W; c++) {
+        if (best[c] >= INF) continue;
+        for (int i = 1; i <= 2 * E + 1; i++) {
+            int L = 0;
+            while (c + L <= W && cell_uneq(R, m, Q, n, E, i, c + L) == 0) L++;
+            int end = c + L;
+            if (end > W) {
+                if (best[c] < answer) answer = best[c];
+            } else {
+                int cost = best[c] + real_column(m, n, E, end);
+                int nxt = end + 1;
+                if (nxt > W) { if (cost < answer) answer = cost; }
+                else if (cost < best[nxt]) best[nxt] = cost;
+            }
+        }
+    }
+    free(best);
+    return answer;
+}
+
+/* Unequal-length batch: query p at reads[read_off[p] .. + read_len[p]),
+ * reference p at refs[ref_off[p] .. + ref_len[p]).  Single thread per slice. */
+typedef struct {
+    const uint8_t* reads; const int64_t* read_off; const int32_t* read_len;
+    const uint8_t* refs; const int64_t* ref_off; const int32_t* ref_len;
+    const int32_t* E_per_pair; int32_t E; int64_t lo, hi;
+    uint8_t* accept; int32_t* edits;
+} uneq_job;
+
+static void* uneq_worker(void* arg)
+{
+    uneq_job* J = (uneq_job*)arg;
+    for (int64_t p = J->lo; p < J->hi; p++) {
+        int E = J->E_per_pair ? J->E_per_pair[p] : J->E;
+        int32_t e = 0;
+        int acc = ss_oracle_pair_uneq(J->refs + J->ref_off[p], J->ref_len[p], J->reads + J->read_off[p],
+                                      J->read_len[p], E, &e, NULL, NULL);
+        J->accept[p] = (uint8_t)acc;
+        J->edits[p] = e;
+    }
+    return NULL;
+}
+
+double ss_oracle_batch_uneq(const uint8_t* reads, const int64_t* read_off, const int32_t* read_len,
+                            const uint8_t* refs, const int64_t* ref_off, const int32_t* ref_len, int64_t n,
+                            const int32_t* E_per_pair, int32_t E, int threads, uint8_t* accept, int32_t* edits)
+{
+    if (threads < 1) threads = 1;
+    if (threads > 256) threads = 256;
+    if ((int64_t)threads > n) threads = n > 0 ? (int)n : 1;
+    uneq_job jobs[256];
+    pthread_t tid[256];
+    struct timespec t0, t1;
+    clock_gettime(CLOCK_MONOTONIC, &t0);
+    for (int t = 0; t < threads; t++) {
+        uneq_job* J = &jobs[t];
+        J->reads = reads; J->read_off = read_off; J->read_len = read_len;
+        J->refs = refs; J->ref_off = ref_off; J->ref_len = ref_len;
+        J->E_per_pair = E_per_pair; J->E = E;
+        J->lo = n * t / threads; J->hi = n * (t + 1) / threads;
+        J->accept = accept; J->edits = edits;
+    }
+    if (threads == 1) uneq_worker(&jobs[0]);
+    else {
+        for (int t = 0; t < threads; t++) pthread_create(&tid[t], NULL, uneq_worker, &jobs[t]);
+        for (int t = 0; t < threads; t++) pthread_join(tid[t], NULL);
+    }
+    clock_gettime(CLOCK_MONOTONIC, &t1);
+    return (double)(t1.tv_sec - t0.tv_sec) + 1e-9 * (double)(t1.tv_nsec - t0.tv_nsec);
+}
+
 /* ---- batch drivers (contiguous slices, one plain thread each) ---------- */
 
 typedef struct {
@@ -315,4 +478,21 @@ void ss_oracle_levenshtein_batch(const uint8_t* reads, const uint8_t* refs, cons
 {
     for (int64_t p = 0; p < n; p++)
         out[p] = ss_oracle_levenshtein(refs + offsets[p], lengths[p], reads + offsets[p], lengths[p]);
+}
+
+/* Checkers over an unequal-length batch (layout as ss_oracle_batch_uneq), one
+ * thread: the count after the deduction without the stop at E+1, the
+ * exhaustive minimum of ss_oracle_min_obstacles_uneq, and the Levenshtein
+ * distance (any of the outputs may be NULL). */
+void ss_oracle_uneq_checks(const uint8_t* reads, const int64_t* read_off, const int32_t* read_len,
+                           const uint8_t* refs, const int64_t* ref_off, const int32_t* ref_len, int64_t n, int32_t E,
+                           int32_t* net, int32_t* minobs, int32_t* ed)
+{
+    for (int64_t p = 0; p < n; p++) {
+        const uint8_t* R = refs + ref_off[p];
+        const uint8_t* Q = reads + read_off[p];
+        if (net) ss_oracle_pair_uneq(R, ref_len[p], Q, read_len[p], E, NULL, NULL, &net[p]);
+        if (minobs) minobs[p] = ss_oracle_min_obstacles_uneq(R, ref_len[p], Q, read_len[p], E);
+        if (ed) ed[p] = ss_oracle_levenshtein(R, ref_len[p], Q, read_len[p]);
+    }
 }

@@ -70,6 +70,11 @@ def _load():
     lib.ssgen_drive.restype = ctypes.c_int64
     lib.ssgen_drive_free.argtypes = [ctypes.c_int64, vp, vp]
     lib.ssgen_drive_free.restype = None
+    lib.ssgen_uneq_plan.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp]
+    lib.ssgen_uneq_plan.restype = ctypes.c_int64
+    lib.ssgen_uneq_fill.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                    vp, vp, vp]
+    lib.ssgen_uneq_fill.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -187,6 +192,25 @@ def drive(seed: int, arrivals_s: np.ndarray, submit_fn_ptr: int, server: int, th
                           _p(D.bases), ctypes.cast(D._acc, ctypes.c_void_p), ctypes.cast(D._ed, ctypes.c_void_p))
     D.submitted = int(got)
     return D
+
+
+def uneq(n: int, m: int = 100, kmax: int = 10, unrel_pct: int = 10, seed: int = 1910090206) -> dict:
+    """Pairs of unequal length: reads of m bases back to back; each reference is its read with
+    k ~ U{0..kmax} single-base edits (1/3 substitutions, insertions, deletions) at its natural length,
+    or an unrelated string of length in [m - kmax, m + kmax] for unrel_pct percent of the pairs."""
+    lib = _load()
+    ref_len = np.empty(n, dtype=np.int32)
+    total = int(lib.ssgen_uneq_plan(seed, n, m, kmax, unrel_pct, _p(ref_len)))
+    if total < 0:
+        raise ValueError("ssgen_uneq_plan: bad arguments")
+    ref_off = np.zeros(n, dtype=np.int64)
+    if n:
+        np.cumsum(ref_len[:-1], out=ref_off[1:])
+    reads = np.empty(n * m, dtype=np.uint8)
+    refs = np.empty(total, dtype=np.uint8)
+    lib.ssgen_uneq_fill(seed, n, m, kmax, unrel_pct, _p(ref_off), _p(reads), _p(refs))
+    return dict(n=n, reads=reads, refs=refs, read_offsets=np.arange(n, dtype=np.int64) * m,
+                read_lengths=np.full(n, m, np.int32), ref_offsets=ref_off, ref_lengths=ref_len)
 
 
 def concat(pairs) -> dict:

@@ -124,6 +124,87 @@ static void apply_events(rng_t* r, const uint8_t* read, int m, edit_ev* ev, int 
     if (o < m) rand_bases(r, out + o, m - o);
 }
 
+/* The same pass without the cut or pad: the edited string keeps its natural
+ * length (at most m plus the inserted bases), which is returned. */
+static int apply_events_free(rng_t* r, const uint8_t* read, int m, edit_ev* ev, int k, uint8_t* out)
+{
+    if (k > 1) qsort(ev, (size_t)k, sizeof(edit_ev), ev_cmp);
+    int o = 0, i = 0, e = 0;
+    while (i < m || e < k) {
+        if (e < k && ev[e].pos <= i) {
+            edit_ev* v = &ev[e++];
+            if (v->pos < i) continue;                 /* fell inside a deleted span */
+            if (v->type == EV_INS) {
+                for (int t = 0; t < v->len; t++) out[o++] = BASES[rng_below(r, 4)];
+            } else if (v->type == EV_DEL) {
+                i += v->len;
+            } else if (i < m) {
+                int code = 0;
+                while (BASES[code] != read[i]) code++;
+                out[o++] = BASES[(code + 1 + (int)rng_below(r, 3)) & 3];
+                i++;
+            }
+            continue;
+        }
+        if (i >= m) break;
+        out[o++] = read[i++];
+    }
+    return o;
+}
+
+/* ---------------------------------------------------------------------------
+ * Pairs of unequal length: read (query) p has m bases; its reference is the
+ * read with k ~ U{0..kmax} events (substitution, insertion or deletion with
+ * probability 1/3 each, length one, positions uniform) kept at its natural
+ * length, or, for unrel_pct percent of the pairs, an unrelated uniform string
+ * of a length uniform in [max(0, m - kmax), m + kmax].  Reads are stored back
+ * to back (read p at p*m); ssgen_uneq_plan gives the reference lengths (and
+ * returns their sum), ssgen_uneq_fill writes the bases, references at ref_off.
+ * ------------------------------------------------------------------------- */
+static int uneq_pair(uint64_t seed, int64_t p, int32_t m, int32_t kmax, int32_t unrel_pct, uint8_t* Q, uint8_t* R)
+{
+    rng_t r = rng_stream(seed, (uint64_t)p);
+    rand_bases(&r, Q, m);
+    if ((int32_t)rng_below(&r, 100) < unrel_pct) {
+        int lo = m - kmax < 0 ? 0 : m - kmax;
+        int len = lo + (int)rng_below(&r, (uint64_t)(m + kmax - lo + 1));
+        rand_bases(&r, R, len);
+        return len;
+    }
+    int k = (int)rng_below(&r, (uint64_t)kmax + 1);
+    edit_ev ev[64];
+    if (k > 64) k = 64;
+    for (int e = 0; e < k; e++) {
+        ev[e].ord = e; ev[e].len = 1;
+        ev[e].type = (int)rng_below(&r, 3);
+        ev[e].pos = (int)rng_below(&r, (uint64_t)(ev[e].type == EV_INS ? m + 1 : (m > 0 ? m : 1)));
+    }
+    return apply_events_free(&r, Q, m, ev, k, R);
+}
+
+int64_t ssgen_uneq_plan(uint64_t seed, int64_t n, int32_t m, int32_t kmax, int32_t unrel_pct, int32_t* ref_len)
+{
+    if (n < 0 || m < 0 || kmax < 0 || kmax > 64) return -1;
+    uint8_t* Q = (uint8_t*)malloc((size_t)m + 1);
+    uint8_t* R = (uint8_t*)malloc((size_t)(m + kmax) + 1);
+    int64_t total = 0;
+    for (int64_t p = 0; p < n; p++) {
+        ref_len[p] = uneq_pair(seed, p, m, kmax, unrel_pct, Q, R);
+        total += ref_len[p];
+    }
+    free(Q);
+    free(R);
+    return total;
+}
+
+int ssgen_uneq_fill(uint64_t seed, int64_t n, int32_t m, int32_t kmax, int32_t unrel_pct, const int64_t* ref_off,
+                    uint8_t* reads, uint8_t* refs)
+{
+    if (n < 0 || m < 0 || kmax < 0 || kmax > 64) return -1;
+    for (int64_t p = 0; p < n; p++) uneq_pair(seed, p, m, kmax, unrel_pct, reads + p * (int64_t)m, refs + ref_off[p]);
+    return 0;
+}
+
 /* ---------------------------------------------------------------------------
  * Configurations (all sizes are defaults; n can be overridden).
  *  0: n pairs, m=100, k~U{0..10}, types 1/3 each, length-1 indels.

@@ -196,3 +196,80 @@ def test_threads_do_not_change_results():
     b = oracle.batch(d["reads"], d["refs"], d["offsets"], d["lengths"], E=4, threads=4)
     np.testing.assert_array_equal(a["edits"], b["edits"])
     np.testing.assert_array_equal(a["accept"], b["accept"])
+
+
+# --------------------------------------------------------------------------- the walk's statistics
+# The oracle also reports, per pair, the checkpoints the walk visited (iterations of steps 2-3) and
+# the last column it reached; the mixed-batch roofline model is built from them.  They are pinned here
+# by the worked example, by closed forms a plain string scan gives, and by the structure of the walk.
+
+def _stats(pairs, E, stop_early=True):
+    """(checkpoints, last column, count) per (R, Q) pair."""
+    b = gen.concat([(q, r) for r, q in pairs])        # reads are the queries, refs the references
+    w = oracle.batch(b["reads"], b["refs"], b["offsets"], b["lengths"], E=E, stop_early=stop_early,
+                     want_stats=True)
+    return w["stats"][:, 0], w["stats"][:, 1], w["edits"]
+
+
+def test_stats_fig2(golden_fig2):
+    """Fig. 1/2 captions: three escape segments, the last obstacle in the last column."""
+    R, Q, E = golden_fig2["R"][0], golden_fig2["Q"][0], int(golden_fig2["E"][0])
+    cps, last, cnt = _stats([(R, Q)], E)
+    assert cps[0] == int(golden_fig2["segments"][0])
+    assert last[0] == int(golden_fig2["cols"][0])
+    assert cnt[0] == int(golden_fig2["obstacles"][0])
+
+
+@pytest.mark.parametrize("m", [0, 1, 2, 3, 4, 5])
+def test_stats_single_row_closed_form(m):
+    """E = 0 leaves one row, the main diagonal: every mismatching column closes a segment, and a
+    final segment runs free to the end when the last column matches.  Stopping after the first
+    obstacle leaves one checkpoint, ending at the first mismatch."""
+    pairs = [("".join(r), "".join(q)) for r in itertools.product("ACGT", repeat=m)
+             for q in itertools.product("ACGT", repeat=m)]
+    cps, last, cnt = _stats(pairs, 0, stop_early=False)
+    tcps, tlast, tcnt = _stats(pairs, 0, stop_early=True)
+    for k, (r, q) in enumerate(pairs):
+        mism = [j + 1 for j in range(m) if r[j] != q[j]]
+        want_cps = len(mism) + (1 if m and r[-1] == q[-1] else 0)
+        assert (cps[k], last[k], cnt[k]) == (want_cps, m, len(mism)), (r, q)
+        if mism:
+            assert (tcps[k], tlast[k], tcnt[k]) == (1, mism[0], 1), (r, q)
+        else:
+            assert (tcps[k], tlast[k], tcnt[k]) == ((1 if m else 0), m, 0), (r, q)
+
+
+def test_stats_closed_forms():
+    for m in (1, 7, 64, 100):
+        s = "".join("ACGT"[(7 * j + j // 3) % 4] for j in range(m))
+        for E in (0, 1, 5, 12):
+            cps, last, cnt = _stats([(s, s)], E)
+            assert (cps[0], last[0], cnt[0]) == (1, m, 0)            # one free segment to the end
+            # every cell of every row an obstacle: one obstacle per column until the count exceeds E
+            cps, last, cnt = _stats([("A" * m, "C" * m)], E)
+            k = min(m, E + 1)
+            assert (cps[0], last[0], cnt[0]) == (k, k, k)
+
+
+def test_stats_structure():
+    """On generated pairs: an accepted pair's walk reaches the last column; a rejected pair stops at the
+    column of its (E+1)-th obstacle after E+1 checkpoints, which is where the full walk's (E+1)-th
+    escape segment ends; a full walk has as many checkpoints as obstacles, or one more when its last
+    segment runs free to the end."""
+    d = gen.make(0, n=600)
+    for E in (0, 2, 5):
+        t = oracle.batch(d["reads"], d["refs"], d["offsets"], d["lengths"], E=E, want_stats=True)
+        f = oracle.batch(d["reads"], d["refs"], d["offsets"], d["lengths"], E=E, stop_early=False, want_stats=True)
+        assert np.all(f["stats"][:, 1] == d["lengths"])
+        extra = f["stats"][:, 0] - f["edits"]
+        assert np.all((extra == 0) | (extra == 1))
+        acc = t["accept"] == 1
+        assert np.all(t["stats"][acc, 1] == d["lengths"][acc])
+        assert np.all(t["stats"][acc] == f["stats"][acc])
+        assert np.all(t["stats"][~acc, 0] == E + 1)
+        for p in np.nonzero(~acc)[0][:50]:
+            o, L = d["offsets"][p], d["lengths"][p]
+            R = d["refs"][o:o + L].tobytes().decode()
+            Q = d["reads"][o:o + L].tobytes().decode()
+            _, _, segs = oracle.pair(R, Q, E, stop_early=False, segments=True)
+            assert t["stats"][p, 1] == segs[E][1]
