@@ -264,14 +264,13 @@ int ss_oracle_levenshtein(const uint8_t* a, int la, const uint8_t* b, int lb)
  * and *net_out (optional) = the count before and after the deduction. */
 static int cell_uneq(const uint8_t* R, int m, const uint8_t* Q, int n, int E, int i, int j)
 {
-    int q;
-    if (i < 1 || i > 2 * E + 1) return 1;
-    if (i == E + 1)      q = j;
-    else if (i <= E)     q = j - i;
-    else                 q = j + i - E - 1;
+    if (i < 1 || i > 2 * E + 1) return 1;  /* no such row */
     if (j < 1 || j > m) return 1;          /* R has no j-th character */
+    /* the Q index row i compares with R[j]: rows 1..E look back, row E+1 on the
+     * diagonal, rows E+2..2E+1 ahead (Equation 1) */
+    const int q = (i <= E) ? j - i : ((i == E + 1) ? j : j + i - (E + 1));
     if (q < 1 || q > n) return 1;          /* Q has no q-th character */
-    return fold(Q[q - 1]) == fold(R[j - 1]) ? 0 : 1;
+    return fold(R[j - 1]) != fold(Q[q - 1]);
 }
 
 /* 1 when some row of column j compares two existing characters */
@@ -300,7 +299,7 @@ int ss_oracle_pair_uneq(const uint8_t* R, int m, const uint8_t* Q, int n, int E,
         }
         int end = c + best;
         if (end <= W) obst[cnt++] = end;               /* the segment's obstacle */
-        c = end + 1;                                   /* step 3 */
+        c = end + 1;                /* step 3: the next checkpoint */
     }
     int lead = 0;
     while (lead < cnt && !real_column(m, n, E, obst[lead])) lead++;
