@@ -84,6 +84,9 @@ const char* ss_status_str(int status);
  *   accept_out  : n_pairs bytes, 1 = accept (alignment needed), 0 = reject.
  *   edits_out   : n_pairs obstacle counts, min(count, E+1).
  * Internally: copy to HBM, encode (2-bit planes), filter, copy back.
+ * The one-call host entry points (ss_filter_batch, ss_filter_batch_var,
+ * ss_filter_batch_pairs) share one context per device; concurrent calls from
+ * several host threads are safe and run one at a time.
  * ---------------------------------------------------------------------- */
 int ss_filter_batch(const uint8_t* reads, const uint8_t* refs, const int32_t* lengths,
                     int64_t n_pairs, int32_t E, uint8_t* accept_out, int32_t* edits_out);
@@ -92,6 +95,22 @@ int ss_filter_batch(const uint8_t* reads, const uint8_t* refs, const int32_t* le
 int ss_filter_batch_var(const uint8_t* reads, const uint8_t* refs, const int32_t* lengths,
                         const int32_t* E_per_pair, int64_t n_pairs,
                         uint8_t* accept_out, int32_t* edits_out);
+
+/* Pairs of unequal length, host pointers (the note of Section 2.4 between steps
+ * 4 and 5).  Read (query) i has read_lengths[i] bases, reference i has
+ * ref_lengths[i] (any lengths >= 0, <= SS_MAX_LEN); reads and refs are each the
+ * concatenation of their sequences.  The maze spans the longer of the two;
+ * a comparison with a character that does not exist is the fourth case of
+ * Equation 1, and the obstacles the walk meets in leading or trailing columns
+ * that hold no comparison of two existing characters are deducted before the
+ * decision.  The reported count is min(count after the deduction, E+1); it
+ * never exceeds the edit distance of the pair when that is <= E (Section 2.1),
+ * and for equal lengths the result is ss_filter_batch's.  E_per_pair (host,
+ * may be NULL) overrides E pair by pair.  Synchronous; alphabet errors return
+ * SS_EBASE with the outputs untouched. */
+int ss_filter_batch_pairs(const uint8_t* reads, const int32_t* read_lengths, const uint8_t* refs,
+                          const int32_t* ref_lengths, int64_t n_pairs, const int32_t* E_per_pair, int32_t E,
+                          uint8_t* accept_out, int32_t* edits_out);
 
 /* ------------------------------------------------------------------------
  * Context: owns device scratch, the plan/work-queue buffers of the batched
@@ -107,11 +126,15 @@ int ss_destroy(ss_ctx* ctx);
  * n_pairs pairs of common length m are encoded with base code A=0 C=1 G=2
  * T=3 split into a low-bit plane and a high-bit plane, transposed so that
  * bit s of a 32-bit word belongs to pair 32*g + s ("group" g).  Planes are
- * ordered Q0, Q1, R0, R1; positions are grouped in chunks of four; the word
- * for (plane p, position j, group g) sits at index
- *     ((p * ceil(m/4) + j/4) * G + g) * 4 + j%4,   G = ceil(n_pairs/32),
- * so that 64 lanes reading group-consecutive chunks read 1 KiB contiguous.
- * Slots of the last group beyond n_pairs are encoded as all-'A' pairs.
+ * ordered Q0, Q1, R0, R1; positions are grouped in chunks of four.  Groups
+ * come in blocks of 64, and a block's words are contiguous: with
+ * G = ceil(n_pairs/32), nc = ceil(m/4), b = g / 64 and Gb = min(64, G - 64 b)
+ * (the groups of block b), the word for (plane p, position j, group g) sits at
+ * index
+ *     (256 nc b + (p * nc + j/4) * Gb + g % 64) * 4 + j%4,
+ * so that the 64 lanes of a wavefront, one group each, read 1 KiB contiguous
+ * per chunk and one contiguous stretch over the whole sweep.  Slots of the
+ * last group beyond n_pairs are encoded as all-'A' pairs.
  * ---------------------------------------------------------------------- */
 
 /* Bytes of a lane-sliced buffer for n_pairs pairs of length m. */
@@ -163,10 +186,13 @@ int ss_filter_submaze_async(ss_ctx* ctx, const uint32_t* packed, int64_t n_pairs
  *            wavefront works alone and they meet the sweeping one through
  *            counters in on-chip memory; otherwise the four share the block's
  *            barriers), so the packed encoding never reaches device memory.
+ *            With tile_groups = 0 and 16-byte aligned reads and refs the
+ *            fused kernel runs only in the first form (m <= 224); longer
+ *            aligned pairs take the two kernels below, which are faster there.
  *   E > 5  : the two kernels over chunks of about 400 MB of packed data, kept
  *            in a buffer owned by ctx (allocated on first use, grown when a
- *            longer m needs it): calls with E > 5 on one context must be
- *            ordered (one stream), or use one context per stream.
+ *            longer m needs it): calls that take this schedule on one context
+ *            must be ordered (one stream), or use one context per stream.
  *   n_pairs >= 0; 0 <= m <= SS_MAX_LEN_FUSED; 0 <= E <= SS_MAX_E_SLICED
  *   tile_groups : groups per tile of the fused kernel, 1..256, or 0 for the
  *                 automatic choice (the largest tile whose two buffers keep
@@ -222,6 +248,84 @@ int ss_filter_wave_async(ss_ctx* ctx, const uint32_t* packed, int64_t total_base
                          uint16_t* out, void* stream);
 
 /* ------------------------------------------------------------------------
+ * One entry point for any batch: the batch descriptor.
+ *
+ * The problem of Section 2.1 and 2.3 for a batch: n_pairs (reference, query)
+ * pairs, a threshold per pair, one accept/count result per pair (Section 2.4,
+ * step 5).  The inputs are device buffers in one of three forms, and the
+ * kernel is chosen by the caller or, with SS_KERNEL_AUTO, from the pairs'
+ * shape:
+ *   - a lane-sliced buffer (SS_INPUT_PACKED_SLICED)      -> the column sweep;
+ *   - a plan given                                      -> its persistent launch;
+ *   - ASCII, one length, one threshold <= SS_MAX_E_SLICED -> the one-call path
+ *     (fused encode + sweep) when the pairs lie back to back (offsets NULL) and
+ *     m <= SS_MAX_LEN_FUSED, else encode to the lane-sliced layout + sweep;
+ *   - anything else (several lengths, unequal lengths, thresholds per pair,
+ *     larger thresholds, bit streams) -> the wavefront kernel.
+ * Forcing a kernel whose conditions the batch does not meet returns SS_EINVAL
+ * (or SS_ELEN for a length or threshold beyond its limit).
+ * ---------------------------------------------------------------------- */
+#define SS_INPUT_ASCII          0x0u   /* reads / refs: ASCII bases (device) */
+#define SS_INPUT_PACKED         0x1u   /* reads / refs: each side packed apart by ss_pack */
+#define SS_INPUT_PACKED_SLICED  0x2u   /* reads: ss_pack_sliced_async's buffer (both sides); refs unused */
+#define SS_INPUT_MASK           0x0Fu
+#define SS_KERNEL_AUTO          0x00u
+#define SS_KERNEL_FUSED         0x10u  /* ASCII back to back, one length <= SS_MAX_LEN_FUSED, E <= SS_MAX_E_SLICED */
+#define SS_KERNEL_SLICED        0x20u  /* one length, one threshold <= SS_MAX_E_SLICED (ASCII or lane-sliced input) */
+#define SS_KERNEL_PLAIN         0x30u  /* one pair per lane, equal lengths, E <= SS_MAX_E_PLAIN (ASCII or ss_pack input) */
+#define SS_KERNEL_WAVE          0x40u  /* wavefront-cooperative sweep: any lengths, E <= SS_MAX_E */
+#define SS_KERNEL_PERSISTENT    0x50u  /* the persistent launch of desc->plan (equal lengths, E_per_pair required) */
+#define SS_KERNEL_MASK          0xF0u
+
+typedef struct ss_plan ss_plan;
+
+typedef struct ss_batch_desc {
+    const void* reads;            /* device: queries in the input form of flags */
+    const void* refs;             /* device: references (NULL for SS_INPUT_PACKED_SLICED) */
+    const int64_t* offsets;       /* device, n_pairs: first base of query i in reads (bit for ss_pack input),
+                                     and of reference i when ref_offsets is NULL; NULL: i * length */
+    const int32_t* lengths;       /* device, n_pairs: query lengths (and reference lengths when ref_lengths is
+                                     NULL); NULL: every pair has `length` bases */
+    const int64_t* ref_offsets;   /* device, may be NULL: references at offsets[] */
+    const int32_t* ref_lengths;   /* device, may be NULL: references as long as their queries; given together
+                                     with ref_offsets, for pairs of unequal length (ss_filter_batch_pairs) */
+    const int32_t* E_per_pair;    /* device, may be NULL: threshold of each pair, each <= E */
+    const ss_plan* plan;          /* for SS_KERNEL_PERSISTENT: a plan of these pairs' host lengths and
+                                     thresholds (ss_plan_create) on this context's device */
+    int64_t n_pairs;
+    int64_t read_bases;           /* bases in reads (the concatenation; ASCII and ss_pack input) */
+    int64_t ref_bases;            /* bases in refs */
+    int32_t length;               /* >= 0: every pair (both sides) has this many bases; -1: see lengths */
+    int32_t E;                    /* the threshold, or the largest of E_per_pair */
+    uint32_t flags;               /* SS_INPUT_* | SS_KERNEL_* */
+    uint32_t reserved;            /* 0 */
+    uint16_t* out;                /* device, n_pairs result words (SS_RESULT_*), 16-byte aligned */
+    uint32_t* err;                /* device word (required for ASCII input; the caller zeroes it): bit 0 a byte
+                                     outside ACGTacgt, bit 1 a wait in the fused kernel that gave up; the results
+                                     are then unspecified */
+} ss_batch_desc;
+
+/* Words ss_pack writes for `bases` bases: two planes (low and high bit of the
+ * code A=0 C=1 G=2 T=3) of the bit-stream layout above, each
+ * ss_stream_words(bases) words; -1 for a negative count. */
+int64_t ss_pack_words(int64_t bases);
+
+/* Encode one side (reads or refs, ASCII in device memory) into the 2-bit
+ * planes of ss_pack_words(bases) words at packed (device).  err as for
+ * ss_pack_stream_async.  SS_ELEN above SS_MAX_STREAM_BASES.  Asynchronous on
+ * stream. */
+int ss_pack(ss_ctx* ctx, const uint8_t* ascii, int64_t bases, uint32_t* packed, uint32_t* err, void* stream);
+
+/* Filter the batch a descriptor describes (rows a1-a5: encode when the input
+ * is ASCII, build the Equation 1 rows, walk, decide and write), enqueued on
+ * stream; the caller synchronises.  Device arrays (offsets, lengths, thresholds)
+ * cannot be checked on the host: the caller guarantees that every pair lies
+ * inside its buffers and that each E_per_pair[i] <= E.  Buffers the context
+ * owns (encodings of ASCII input) are reused by the next call on the context:
+ * calls on one context must be ordered (one stream). */
+int ss_filter_batch_ex(ss_ctx* ctx, const ss_batch_desc* desc, void* stream);
+
+/* ------------------------------------------------------------------------
  * Verification (not part of SneakySnake): the step a pre-alignment filter
  * exists to shorten (Section 1: only accepted pairs go on to alignment;
  * Section 3 measures the filter's false accept rate against the exact edit
@@ -270,7 +374,6 @@ int ss_select_accepted_async(ss_ctx* ctx, const uint16_t* results, int64_t n, in
  * above SS_MAX_E_PLANNED return SS_ELEN (the standalone wavefront kernel,
  * ss_filter_wave_async, covers them up to SS_MAX_E).
  * ---------------------------------------------------------------------- */
-typedef struct ss_plan ss_plan;
 int ss_plan_create(ss_ctx* ctx, const int32_t* lengths, const int32_t* E_per_pair, int64_t n_pairs,
                    int32_t slices_per_lane, ss_plan** out);
 int ss_plan_destroy(ss_plan* plan);

@@ -31,6 +31,19 @@ SS_MAX_LEN_VERIFY = 256
 SS_MAX_STREAM_BASES = 32 * ((1 << 30) - 64)
 SS_RESULT_ACCEPT = 0x8000
 SS_RESULT_COUNT = 0x7FFF
+SS_INPUT_ASCII, SS_INPUT_PACKED, SS_INPUT_PACKED_SLICED = 0x0, 0x1, 0x2
+SS_KERNEL_AUTO, SS_KERNEL_FUSED, SS_KERNEL_SLICED, SS_KERNEL_PLAIN, SS_KERNEL_WAVE, SS_KERNEL_PERSISTENT = (
+    0x00, 0x10, 0x20, 0x30, 0x40, 0x50)
+
+
+class BatchDesc(ctypes.Structure):
+    """ss_batch_desc of include/ss.h (field for field)."""
+    _fields_ = [("reads", ctypes.c_void_p), ("refs", ctypes.c_void_p), ("offsets", ctypes.c_void_p),
+                ("lengths", ctypes.c_void_p), ("ref_offsets", ctypes.c_void_p), ("ref_lengths", ctypes.c_void_p),
+                ("E_per_pair", ctypes.c_void_p), ("plan", ctypes.c_void_p), ("n_pairs", ctypes.c_int64),
+                ("read_bases", ctypes.c_int64), ("ref_bases", ctypes.c_int64), ("length", ctypes.c_int32),
+                ("E", ctypes.c_int32), ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("out", ctypes.c_void_p), ("err", ctypes.c_void_p)]
 
 _lib = None
 
@@ -90,6 +103,10 @@ def lib():
         "ss_server_destroy": ([vp], ctypes.c_int),
         "ss_server_footprint": ([i64, i64], i64),
         "ss_server_set_slices": ([vp, i32], ctypes.c_int),
+        "ss_pack_words": ([i64], i64),
+        "ss_pack": ([vp, vp, i64, vp, vp, vp], ctypes.c_int),
+        "ss_filter_batch_ex": ([vp, ctypes.POINTER(BatchDesc), vp], ctypes.c_int),
+        "ss_filter_batch_pairs": ([vp, vp, vp, vp, i64, vp, i32, vp, vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -109,7 +126,8 @@ def exported_symbols():
             "ss_plan_capture",
             "ss_plan_launch", "ss_plan_create_tuned", "ss_server_create", "ss_server_submit", "ss_server_poll",
             "ss_server_wait", "ss_server_times", "ss_server_cancel", "ss_server_release", "ss_server_set_hold",
-            "ss_server_stats", "ss_server_destroy", "ss_server_footprint", "ss_server_set_slices"]
+            "ss_server_stats", "ss_server_destroy", "ss_server_footprint", "ss_server_set_slices", "ss_pack_words",
+            "ss_pack", "ss_filter_batch_ex", "ss_filter_batch_pairs"]
 
 
 def status_str(status: int) -> str:
@@ -174,6 +192,22 @@ def ss_filter_batch_var(reads, refs, lengths, E_per_pair):
     return acc, ed
 
 
+def ss_filter_batch_pairs(reads, read_lengths, refs, ref_lengths, E: int = 0, E_per_pair=None):
+    """Pairs of unequal length from host numpy arrays; returns (accept uint8[n], edits int32[n])."""
+    reads = np.ascontiguousarray(reads, dtype=np.uint8)
+    refs = np.ascontiguousarray(refs, dtype=np.uint8)
+    rl = np.ascontiguousarray(read_lengths, dtype=np.int32)
+    fl = np.ascontiguousarray(ref_lengths, dtype=np.int32)
+    Epp = None if E_per_pair is None else np.ascontiguousarray(E_per_pair, dtype=np.int32)
+    n = len(rl)
+    acc = np.zeros(n, dtype=np.uint8)
+    ed = np.zeros(n, dtype=np.int32)
+    rc = lib().ss_filter_batch_pairs(_ptr(reads), _ptr(rl), _ptr(refs), _ptr(fl), n, _ptr(Epp), int(E), _ptr(acc),
+                                     _ptr(ed))
+    _check(rc, "ss_filter_batch_pairs")
+    return acc, ed
+
+
 # ---------------------------------------------------------------- context and device entry points
 def ss_create(device: int = 0) -> int:
     h = ctypes.c_void_p()
@@ -207,6 +241,26 @@ def ss_filter_ascii_async(ctx, reads, refs, n_pairs, m, E, tile_groups, out, err
     _check(lib().ss_filter_ascii_async(ctx, _ptr(reads), _ptr(refs), int(n_pairs), int(m), int(E),
                                        int(tile_groups), _ptr(out), _ptr(err), _stream(stream)),
            "ss_filter_ascii_async")
+
+
+def ss_pack_words(bases: int) -> int:
+    return int(lib().ss_pack_words(int(bases)))
+
+
+def ss_pack(ctx, ascii_dev, bases, packed, err, stream=None):
+    _check(lib().ss_pack(ctx, _ptr(ascii_dev), int(bases), _ptr(packed), _ptr(err), _stream(stream)), "ss_pack")
+
+
+def batch_desc(reads, refs, n_pairs, E, flags, out, err=None, offsets=None, lengths=None, ref_offsets=None,
+               ref_lengths=None, E_per_pair=None, plan=None, read_bases=0, ref_bases=0, length=-1) -> BatchDesc:
+    """An ss_batch_desc from buffers (torch tensors, raw addresses or None)."""
+    return BatchDesc(_ptr(reads), _ptr(refs), _ptr(offsets), _ptr(lengths), _ptr(ref_offsets), _ptr(ref_lengths),
+                     _ptr(E_per_pair), plan, int(n_pairs), int(read_bases), int(ref_bases), int(length), int(E),
+                     int(flags), 0, _ptr(out), _ptr(err))
+
+
+def ss_filter_batch_ex(ctx, desc: BatchDesc, stream=None):
+    _check(lib().ss_filter_batch_ex(ctx, ctypes.byref(desc), _stream(stream)), "ss_filter_batch_ex")
 
 
 def ss_filter_submaze_async(ctx, packed, n_pairs, m, E, sub_width, out, stream=None):

@@ -12,6 +12,7 @@
 
 #include "ss.h"
 #include "ss_common.h"
+#include "ss_ctx.h"
 
 using namespace ss;
 
@@ -31,34 +32,6 @@ int map_err(hipError_t e)
     } while (0)
 
 }  // namespace
-
-// Device buffers that grow on demand and are reused across calls.
-struct DevBuf {
-    void* p = nullptr;
-    size_t cap = 0;
-    hipError_t ensure(size_t bytes)
-    {
-        if (bytes <= cap) return hipSuccess;
-        if (p) { (void)hipFree(p); p = nullptr; cap = 0; }
-        size_t want = std::max(bytes, (size_t)256);
-        hipError_t e = hipMalloc(&p, want);
-        if (e == hipSuccess) cap = want;
-        return e;
-    }
-    void release()
-    {
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        cap = 0;
-    }
-};
-
-struct ss_ctx {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    DevBuf reads, refs, offsets, lengths, epp, packed, results, err;
-    DevBuf chunk;      // lane-sliced chunk of ss_filter_ascii_async's two-kernel schedule
-};
 
 extern "C" const char* ss_status_str(int status)
 {
@@ -109,7 +82,8 @@ extern "C" int ss_destroy(ss_ctx* ctx)
     (void)hipSetDevice(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     for (DevBuf* b : {&ctx->reads, &ctx->refs, &ctx->offsets, &ctx->lengths, &ctx->epp, &ctx->packed,
-                      &ctx->results, &ctx->err, &ctx->chunk})
+                      &ctx->results, &ctx->err, &ctx->chunk, &ctx->qside, &ctx->rside, &ctx->uoff, &ctx->ulen,
+                      &ctx->roff, &ctx->rlen})
         b->release();
     if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
     (void)hipSetDevice(prev);
@@ -174,7 +148,10 @@ extern "C" int ss_filter_ascii_async(ss_ctx* ctx, const uint8_t* reads, const ui
     const bool contiguous = (((uintptr_t)reads | (uintptr_t)refs) & 15u) == 0;
     if (fused_shape(m, tile_groups, contiguous, &T, &GB, &U) == 0) return SS_EINVAL;
     const hipStream_t s = (hipStream_t)stream;
-    if (E <= kMaxEFused)
+    // The fused kernel in wave mode (aligned pairs of up to a few hundred bases) beats the two kernels;
+    // in block mode it does not for aligned inputs (250 bp: 2.2-2.4 ms against 1.7 ms), so with the
+    // automatic tile those go to the chunked schedule.  A tile the caller gives asks for the fused kernel.
+    if (E <= kMaxEFused && (tile_groups > 0 || U > 0 || !contiguous))
         return map_err(launch_fused(reads, refs, n_pairs, m, E, tile_groups, out, err, s));
     // chunks of whole groups; slot offsets keep the encoder's and the sweep's alignment
     const int64_t per_pair = std::max<int64_t>(1, ss_sliced_bytes(32, m) / 32);
@@ -264,11 +241,11 @@ extern "C" int ss_unpack_results_async(ss_ctx* ctx, const uint16_t* results, int
 
 // ---------------------------------------------------------------- one-call host API
 namespace {
-
 std::mutex g_default_mu;
 std::vector<ss_ctx*> g_default;   // one per device, created on first use
+}  // namespace
 
-int default_ctx(ss_ctx** out)
+int ss_default_ctx(ss_ctx** out)
 {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return SS_EDEVICE;
@@ -281,6 +258,8 @@ int default_ctx(ss_ctx** out)
     *out = g_default[dev];
     return SS_OK;
 }
+
+namespace {
 
 // Shared implementation: E_per_pair == nullptr means a single threshold E.
 int filter_host(const uint8_t* reads, const uint8_t* refs, const int32_t* lengths, const int32_t* E_per_pair,
@@ -312,8 +291,10 @@ int filter_host(const uint8_t* reads, const uint8_t* refs, const int32_t* length
     }
 
     ss_ctx* ctx = nullptr;
-    int rc = default_ctx(&ctx);
+    int rc = ss_default_ctx(&ctx);
     if (rc != SS_OK) return rc;
+    // the device's default context is shared by every host thread: one call at a time uses its buffers
+    std::lock_guard<std::mutex> lk(ctx->host_mu);
     hipStream_t s = ctx->stream;
     SS_TRY(ctx->reads.ensure((size_t)std::max<int64_t>(total, 1)));
     SS_TRY(ctx->refs.ensure((size_t)std::max<int64_t>(total, 1)));

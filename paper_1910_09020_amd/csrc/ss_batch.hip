@@ -105,8 +105,8 @@ constexpr int kStageWords = 2048;
 
 template <int RSMAX>
 __global__ __launch_bounds__(256) void k_persist(const PItem* __restrict__ items, int n_items, int* __restrict__ head,
-                                                 const int64_t* __restrict__ perm, const uint32_t* __restrict__ pk,
-                                                 int64_t SW, const int64_t* __restrict__ offsets,
+                                                 const int64_t* __restrict__ perm, wave::GlobalPlanes planes,
+                                                 const int64_t* __restrict__ offsets,
                                                  const int32_t* __restrict__ lengths,
                                                  const int32_t* __restrict__ Epp, uint16_t* __restrict__ out)
 {
@@ -153,16 +153,21 @@ __global__ __launch_bounds__(256) void k_persist(const PItem* __restrict__ items
             if (hi > lo && hi - lo <= kStageWords) {
                 const int nw = (int)(hi - lo);
 #pragma unroll
-                for (int p = 0; p < 4; p++)
-                    for (int i = threadIdx.x; i < nw; i += 256) s_stage[p * kStageWords + i] = pk[p * SW + lo + i];
+                for (int p = 0; p < 4; p++) {
+                    const uint32_t* __restrict__ src = p < 2 ? planes.q + p * planes.SWq : planes.r + (p - 2) * planes.SWr;
+                    const uint64_t SWp = (uint64_t)(p < 2 ? planes.SWq : planes.SWr);
+                    // words outside the plane (offsets the caller got wrong) read as zero
+                    for (int i = threadIdx.x; i < nw; i += 256)
+                        s_stage[p * kStageWords + i] = (uint64_t)(lo + i) < SWp ? src[lo + i] : 0u;
+                }
                 __syncthreads();
                 const wave::StagedPlanes ld{s_stage, (int64_t)lo, nw, kStageWords};
                 c = sweep_staged<RSMAX>(rs, ld, b0, m, Ei, ok, emax);
             } else {
-                c = sweep_shape<RSMAX>(rs, LP, wave::GlobalPlanes{pk, SW}, b0, m, Ei, ok, lip, emax);
+                c = sweep_shape<RSMAX>(rs, LP, planes, b0, m, Ei, ok, lip, emax);
             }
         } else {
-            c = sweep_shape<RSMAX>(rs, LP, wave::GlobalPlanes{pk, SW}, b0, m, Ei, ok, lip, emax);
+            c = sweep_shape<RSMAX>(rs, LP, planes, b0, m, Ei, ok, lip, emax);
         }
         if (ok && lip == 0) out[pi] = wave::result_word(c, Ei);
         if (threadIdx.x == 0) s_item = (int)gridDim.x + atomicAdd(head, 1);
@@ -310,15 +315,16 @@ int persist_blocks_per_cu(int rsmax)
     return per_cu < 1 ? 1 : per_cu;
 }
 
-hipError_t launch_persist(int rsmax, int grid, const PItem* d_items, int n_items, int* d_head, const int64_t* d_perm,
-                          const uint32_t* packed, int64_t total_bases, const int64_t* offsets, const int32_t* lengths,
-                          const int32_t* Epp, uint16_t* out, hipStream_t s)
+hipError_t launch_persist_planes(int rsmax, int grid, const PItem* d_items, int n_items, int* d_head,
+                                 const int64_t* d_perm, const uint32_t* qpk, int64_t SWq, const uint32_t* rpk,
+                                 int64_t SWr, const int64_t* offsets, const int32_t* lengths, const int32_t* Epp,
+                                 uint16_t* out, hipStream_t s)
 {
     if (n_items == 0) return hipSuccess;
-    const int64_t SW = cdiv(total_bases, 32) + 2;
+    const wave::GlobalPlanes planes{qpk, rpk, SWq, SWr};
     hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, s, d_head);
 #define SS_PERSIST(RS)                                                                                     \
-    hipLaunchKernelGGL(k_persist<RS>, dim3(grid), dim3(256), 0, s, d_items, n_items, d_head, d_perm, packed, SW, \
+    hipLaunchKernelGGL(k_persist<RS>, dim3(grid), dim3(256), 0, s, d_items, n_items, d_head, d_perm, planes, \
                        offsets, lengths, Epp, out)
     switch (rsmax) {
     case 1: SS_PERSIST(1); break;
@@ -328,6 +334,15 @@ hipError_t launch_persist(int rsmax, int grid, const PItem* d_items, int n_items
     }
 #undef SS_PERSIST
     return hipGetLastError();
+}
+
+hipError_t launch_persist(int rsmax, int grid, const PItem* d_items, int n_items, int* d_head, const int64_t* d_perm,
+                          const uint32_t* packed, int64_t total_bases, const int64_t* offsets, const int32_t* lengths,
+                          const int32_t* Epp, uint16_t* out, hipStream_t s)
+{
+    const int64_t SW = cdiv(total_bases, 32) + 2;
+    return launch_persist_planes(rsmax, grid, d_items, n_items, d_head, d_perm, packed, SW, packed + 2 * SW, SW,
+                                 offsets, lengths, Epp, out, s);
 }
 
 }  // namespace ss
@@ -515,6 +530,26 @@ extern "C" int ss_plan_info(const ss_plan* plan, int64_t* n_items, int32_t* n_cl
     if (slices_per_lane) *slices_per_lane = plan->cfg.rsmax;
     return SS_OK;
 }
+
+namespace ss {
+// A plan's launch over the two sides packed apart (used by ss_filter_batch_ex).
+hipError_t plan_enqueue_planes(const ss_plan* P, const uint32_t* qpk, int64_t SWq, const uint32_t* rpk, int64_t SWr,
+                               const int64_t* offsets, const int32_t* lengths, const int32_t* Epp, uint16_t* out,
+                               hipStream_t s)
+{
+    return launch_persist_planes(P->cfg.rsmax, P->grid, P->d_items, (int)P->items.size(), P->d_head, P->d_perm, qpk,
+                                 SWq, rpk, SWr, offsets, lengths, Epp, out, s);
+}
+
+int64_t plan_pairs(const ss_plan* P) { return P->n; }
+int plan_device(const ss_plan* P) { return P->device; }
+int32_t plan_max_e(const ss_plan* P)
+{
+    int32_t e = 0;
+    for (const PItem& it : P->items) e = std::max(e, it.emax);
+    return e;
+}
+}  // namespace ss
 
 extern "C" int ss_filter_planned_async(ss_ctx* ctx, const ss_plan* plan, const uint32_t* packed, int64_t total_bases,
                                        const int64_t* offsets, const int32_t* lengths, const int32_t* E_per_pair,

@@ -5,6 +5,8 @@
 
 #include <vector>
 
+typedef struct ss_plan ss_plan;
+
 namespace ss {
 
 constexpr int kChunk = 4;              // positions per chunk in the lane-sliced layout
@@ -14,6 +16,7 @@ constexpr int kMaxEFused = 5;                  // fused encode + sweep kernel (l
 constexpr int64_t kMaxFusedLds = 160 * 1024;   // LDS per workgroup on gfx950
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
 
 // ---- launchers (all asynchronous on the given stream; return hipError_t) ----
 hipError_t launch_pack_sliced(const uint8_t* reads, const uint8_t* refs, const int64_t* offsets,
@@ -29,6 +32,20 @@ hipError_t launch_fused(const uint8_t* reads, const uint8_t* refs, int64_t n_pai
 size_t fused_shape(int32_t m, int tile_groups, bool contiguous, int* T, int* GB, int* U);
 hipError_t launch_pack_stream(const uint8_t* reads, const uint8_t* refs, int64_t total_bases,
                               uint32_t* packed, uint32_t* err, hipStream_t s);
+// One side (reads or refs) into two planes of cdiv(total_bases, 32) + 2 words.
+hipError_t launch_pack_side(const uint8_t* ascii, int64_t total_bases, uint32_t* packed, uint32_t* err, hipStream_t s);
+// The wavefront sweep over two sides packed apart (launch_pack_side): query i is
+// qlen[i] bases from bit qoff[i] of qpk, reference i rlen[i] bases from bit
+// roff[i] of rpk; any lengths (unequal lengths walk the columns that hold a
+// real comparison).
+hipError_t launch_wave_sides(const uint32_t* qpk, int64_t q_words, const uint32_t* rpk, int64_t r_words,
+                             const int64_t* qoff, const int32_t* qlen, const int64_t* roff, const int32_t* rlen,
+                             const int32_t* Epp, int64_t n, int32_t E, uint16_t* out, hipStream_t s);
+// The one-pair-per-lane walk over the two sides packed apart (pairs of equal
+// length at common offsets).
+hipError_t launch_plain_sides(const uint32_t* qpk, int64_t q_words, const uint32_t* rpk, int64_t r_words,
+                              const int64_t* offsets, const int32_t* lengths, const int32_t* Epp, int64_t n,
+                              int32_t E, uint16_t* out, hipStream_t s);
 hipError_t launch_plain(const uint32_t* packed, int64_t stream_words, const int64_t* offsets,
                         const int32_t* lengths, const int32_t* Epp, int64_t n, int32_t E, uint16_t* out,
                         hipStream_t s);
@@ -68,8 +85,22 @@ int plan_min_slices(const int32_t* E, int64_t n);
 // Resident blocks per CU of the persistent kernel for this slice width.
 int persist_blocks_per_cu(int rsmax);
 // Counter reset + persistent kernel on stream s.
+// The same over the two sides packed apart (launch_pack_side).
+hipError_t launch_persist_planes(int rsmax, int grid, const PItem* d_items, int n_items, int* d_head,
+                                 const int64_t* d_perm, const uint32_t* qpk, int64_t SWq, const uint32_t* rpk,
+                                 int64_t SWr, const int64_t* offsets, const int32_t* lengths, const int32_t* Epp,
+                                 uint16_t* out, hipStream_t s);
 hipError_t launch_persist(int rsmax, int grid, const PItem* d_items, int n_items, int* d_head, const int64_t* d_perm,
                           const uint32_t* packed, int64_t total_bases, const int64_t* offsets, const int32_t* lengths,
                           const int32_t* Epp, uint16_t* out, hipStream_t s);
+
+// A plan's persistent launch over the two sides packed apart, and what a plan
+// was made for (ss_batch.hip).
+hipError_t plan_enqueue_planes(const ss_plan* P, const uint32_t* qpk, int64_t SWq, const uint32_t* rpk, int64_t SWr,
+                               const int64_t* offsets, const int32_t* lengths, const int32_t* Epp, uint16_t* out,
+                               hipStream_t s);
+int64_t plan_pairs(const ss_plan* P);
+int plan_device(const ss_plan* P);
+int32_t plan_max_e(const ss_plan* P);
 
 }  // namespace ss

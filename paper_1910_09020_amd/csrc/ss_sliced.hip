@@ -7,6 +7,7 @@
 #include <algorithm>
 
 #include "ss_common.h"
+#include "ss_sliced_ops.h"
 #include "ss_tile.h"
 
 namespace ss {
@@ -73,7 +74,8 @@ __global__ __launch_bounds__(64) void k_pack_sliced(const uint8_t* __restrict__ 
                     const uint64_t b = p == 0 ? bq0[t] : (p == 1 ? bq1[t] : (p == 2 ? br0[t] : br1[t]));
                     w[t] = (uint32_t)(b >> (32 * hh));
                 }
-                out4[((int64_t)p * nch + cc) * G + g] = make_uint4(w[0], w[1], w[2], w[3]);
+                out4[sliced_block_base(g, nch) + ((int64_t)p * nch + cc) * sliced_block_groups(g, G) +
+                     g % kSlicedBlock] = make_uint4(w[0], w[1], w[2], w[3]);
             }
         }
     }
@@ -92,8 +94,11 @@ __global__ __launch_bounds__(256) void k_pack_tile(const uint8_t* __restrict__ r
     extern __shared__ uint32_t lds[];
     const int64_t g0 = (int64_t)blockIdx.x * GB;
     uint32_t bad = 0;
+    // GB divides kSlicedBlock, so the block's groups share one layout block
+    const int64_t nch = (m + kChunk - 1) / kChunk;
     tile::load_encode_groups(reads, refs, offsets, index, n_pairs, m, g0, GB, fast, lds,
-                             reinterpret_cast<uint4*>(packed), G, g0, bad);
+                             reinterpret_cast<uint4*>(packed) + sliced_block_base(g0, nch),
+                             sliced_block_groups(g0, G), g0 % kSlicedBlock, bad);
     if (tile::invalid(bad) && err) atomicOr(err, 1u);
 }
 

@@ -1,5 +1,6 @@
 // Column-sweep kernels for thresholds E = 0..10 and fused encode-and-sweep kernels for E = 0..5.
 #include "ss_sliced_kernel.h"
+#include "ss_fused.h"
 
 namespace ss {
 

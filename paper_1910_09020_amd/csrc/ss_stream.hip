@@ -26,6 +26,9 @@ __device__ __forceinline__ void code4(uint32_t x, uint32_t& lo, uint32_t& hi, ui
     }
 }
 
+// TWO: reads and refs into planes Q0, Q1, R0, R1; otherwise one side (reads)
+// into two planes.
+template <bool TWO>
 __global__ __launch_bounds__(256) void k_pack_stream(const uint8_t* __restrict__ reads,
                                                      const uint8_t* __restrict__ refs, int64_t total,
                                                      int64_t SW, int aligned, uint32_t* __restrict__ packed,
@@ -39,41 +42,54 @@ __global__ __launch_bounds__(256) void k_pack_stream(const uint8_t* __restrict__
         const int64_t nb = total - b < 32 ? total - b : 32;
         if (nb == 32 && aligned) {
             const uint4* a4 = reinterpret_cast<const uint4*>(reads + b);
-            const uint4* f4 = reinterpret_cast<const uint4*>(refs + b);
-            uint4 a[2] = {a4[0], a4[1]}, f[2] = {f4[0], f4[1]};
+            uint4 a[2] = {a4[0], a4[1]};
             uint32_t xa[8] = {a[0].x, a[0].y, a[0].z, a[0].w, a[1].x, a[1].y, a[1].z, a[1].w};
-            uint32_t xf[8] = {f[0].x, f[0].y, f[0].z, f[0].w, f[1].x, f[1].y, f[1].z, f[1].w};
 #pragma unroll
             for (int k = 0; k < 8; k++) {
                 uint32_t lo, hi;
                 code4(xa[k], lo, hi, bad);
                 q0 |= lo << (4 * k);
                 q1 |= hi << (4 * k);
-                code4(xf[k], lo, hi, bad);
-                r0 |= lo << (4 * k);
-                r1 |= hi << (4 * k);
+            }
+            if constexpr (TWO) {
+                const uint4* f4 = reinterpret_cast<const uint4*>(refs + b);
+                uint4 f[2] = {f4[0], f4[1]};
+                uint32_t xf[8] = {f[0].x, f[0].y, f[0].z, f[0].w, f[1].x, f[1].y, f[1].z, f[1].w};
+#pragma unroll
+                for (int k = 0; k < 8; k++) {
+                    uint32_t lo, hi;
+                    code4(xf[k], lo, hi, bad);
+                    r0 |= lo << (4 * k);
+                    r1 |= hi << (4 * k);
+                }
             }
         } else {
             for (int k = 0; k < nb; k++) {
-                const uint32_t xa = reads[b + k], xf = refs[b + k];
                 uint32_t lo, hi, bb = 0;
+                const uint32_t xa = reads[b + k];
                 code4(xa, lo, hi, bb);
                 q0 |= (lo & 1u) << k;
                 q1 |= (hi & 1u) << k;
-                code4(xf, lo, hi, bb);
-                r0 |= (lo & 1u) << k;
-                r1 |= (hi & 1u) << k;
                 // code4 judged three zero bytes too; only the low byte counts
-                const uint32_t va = (xa | 0x20u) - 0x61u, vf = (xf | 0x20u) - 0x61u;
+                const uint32_t va = (xa | 0x20u) - 0x61u;
                 bad |= (va < 20u) ? (((0x80045u >> va) & 1u) ^ 1u) : 1u;
-                bad |= (vf < 20u) ? (((0x80045u >> vf) & 1u) ^ 1u) : 1u;
+                if constexpr (TWO) {
+                    const uint32_t xf = refs[b + k];
+                    code4(xf, lo, hi, bb);
+                    r0 |= (lo & 1u) << k;
+                    r1 |= (hi & 1u) << k;
+                    const uint32_t vf = (xf | 0x20u) - 0x61u;
+                    bad |= (vf < 20u) ? (((0x80045u >> vf) & 1u) ^ 1u) : 1u;
+                }
             }
         }
     }
     packed[w] = q0;
     packed[SW + w] = q1;
-    packed[2 * SW + w] = r0;
-    packed[3 * SW + w] = r1;
+    if constexpr (TWO) {
+        packed[2 * SW + w] = r0;
+        packed[3 * SW + w] = r1;
+    }
     if (bad && err) atomicOr(err, 1u);
 }
 
@@ -89,7 +105,8 @@ using wave::span_mask;
 // escape segment; a borrow that runs off bit 31 carries the segment into the
 // next word (one carry bit per row).
 template <int E, bool VAR_E>
-__global__ __launch_bounds__(256) void k_plain(const uint32_t* __restrict__ pk, int64_t SW,
+__global__ __launch_bounds__(256) void k_plain(const uint32_t* __restrict__ qpk, int64_t SWq,
+                                               const uint32_t* __restrict__ rpk, int64_t SWr,
                                                const int64_t* __restrict__ offsets,
                                                const int32_t* __restrict__ lengths,
                                                const int32_t* __restrict__ Epp, int64_t n,
@@ -102,11 +119,12 @@ __global__ __launch_bounds__(256) void k_plain(const uint32_t* __restrict__ pk, 
     const int m = lane_ok ? lengths[ii] : 0;
     const int Ei = VAR_E ? Epp[ii] : E;
     const int64_t b0 = offsets[ii];
-    const uint32_t* __restrict__ Q0 = pk;
-    const uint32_t* __restrict__ Q1 = pk + SW;
-    const uint32_t* __restrict__ R0 = pk + 2 * SW;
-    const uint32_t* __restrict__ R1 = pk + 3 * SW;
-    auto word = [&](const uint32_t* P, int u) { return bits32(P, SW, b0 + 32 * (int64_t)u); };
+    const uint32_t* __restrict__ Q0 = qpk;
+    const uint32_t* __restrict__ Q1 = qpk + SWq;
+    const uint32_t* __restrict__ R0 = rpk;
+    const uint32_t* __restrict__ R1 = rpk + SWr;
+    auto qword = [&](const uint32_t* P, int u) { return bits32(P, SWq, b0 + 32 * (int64_t)u); };
+    auto rword = [&](const uint32_t* P, int u) { return bits32(P, SWr, b0 + 32 * (int64_t)u); };
     auto vword = [&](int u) { return span_mask(0 - 32 * u, m - 32 * u); };   // query positions inside [0, m)
 
     const int W = (m + 31) >> 5;
@@ -116,17 +134,17 @@ __global__ __launch_bounds__(256) void k_plain(const uint32_t* __restrict__ pk, 
 #pragma unroll
     for (int r = 0; r < NR; r++) { cin[r] = 0u; D[r] = 0u; M[r] = ~0u; }
     uint32_t qp0 = 0, qp1 = 0, vp = 0;
-    uint32_t qc0 = done ? 0u : word(Q0, 0), qc1 = done ? 0u : word(Q1, 0), vc = vword(0);
+    uint32_t qc0 = done ? 0u : qword(Q0, 0), qc1 = done ? 0u : qword(Q1, 0), vc = vword(0);
 
     for (int w = 0;; w++) {
         const bool act0 = !done && w < W;
         if (!__any(act0)) break;
         uint32_t qn0 = 0, qn1 = 0, r0 = 0, r1 = 0;
         if (act0) {
-            qn0 = word(Q0, w + 1);
-            qn1 = word(Q1, w + 1);
-            r0 = word(R0, w);
-            r1 = word(R1, w);
+            qn0 = qword(Q0, w + 1);
+            qn1 = qword(Q1, w + 1);
+            r0 = rword(R0, w);
+            r1 = rword(R1, w);
         }
         const uint32_t vn = vword(w + 1);
 #pragma unroll
@@ -197,13 +215,16 @@ __global__ __launch_bounds__(256) void k_plain(const uint32_t* __restrict__ pk, 
 
 // --------------------------------------------------------------- wavefront-cooperative
 // Standalone launch of the sweep in ss_wave.h: LP lanes per pair, RS slices per
-// lane, pairs in input order (64 / LP pairs per wavefront).
+// lane, pairs in input order (64 / LP pairs per wavefront).  The query of pair
+// i is qlen[i] bases from stream bit qoff[i] of the query planes, its
+// reference rlen[i] bases from bit roff[i] of the reference planes;
+// with equal lengths the walk covers every column, otherwise the columns that
+// hold a comparison of two existing characters (wave::columns_walked).
 template <int LP, int RS>
-__global__ __launch_bounds__(256) void k_wave(const uint32_t* __restrict__ pk, int64_t SW,
-                                              const int64_t* __restrict__ offsets,
-                                              const int32_t* __restrict__ lengths,
-                                              const int32_t* __restrict__ Epp, int64_t n, int Emax,
-                                              uint16_t* __restrict__ out)
+__global__ __launch_bounds__(256) void k_wave(wave::GlobalPlanes planes, const int64_t* __restrict__ qoff,
+                                              const int32_t* __restrict__ qlen, const int64_t* __restrict__ roff,
+                                              const int32_t* __restrict__ rlen, const int32_t* __restrict__ Epp,
+                                              int64_t n, int Emax, uint16_t* __restrict__ out)
 {
     constexpr int PW = 64 / LP;
     const int lane = threadIdx.x & 63;
@@ -212,9 +233,11 @@ __global__ __launch_bounds__(256) void k_wave(const uint32_t* __restrict__ pk, i
     const int64_t pi = wv * PW + grp;
     const bool pair_ok = pi < n;
     const int64_t pc = pair_ok ? pi : 0;
-    const int m = pair_ok ? lengths[pc] : 0;
+    const int nq = pair_ok ? qlen[pc] : 0;
+    const int m = pair_ok ? rlen[pc] : 0;
     const int Ei = Epp ? Epp[pc] : Emax;
-    const int c = wave::sweep_pair<RS, LP>(wave::GlobalPlanes{pk, SW}, offsets[pc], m, Ei, pair_ok, LP, lip, Emax);
+    const int mw = wave::columns_walked(m, nq, Ei);
+    const int c = wave::sweep_pair2<RS, LP>(planes, qoff[pc], roff[pc], mw, nq, Ei, pair_ok, LP, lip, Emax);
     if (pair_ok && lip == 0) out[pi] = wave::result_word(c, Ei);
 }
 
@@ -229,51 +252,82 @@ __global__ __launch_bounds__(256) void k_unpack(const uint16_t* __restrict__ res
 }
 
 template <int E>
-hipError_t launch_plain_E(const uint32_t* pk, int64_t SW, const int64_t* off, const int32_t* len,
-                          const int32_t* Epp, int64_t n, uint16_t* out, hipStream_t s)
+hipError_t launch_plain_E(const uint32_t* qpk, int64_t SWq, const uint32_t* rpk, int64_t SWr, const int64_t* off,
+                          const int32_t* len, const int32_t* Epp, int64_t n, uint16_t* out, hipStream_t s)
 {
     const int threads = 256;
     const unsigned blocks = (unsigned)cdiv(n, threads);
-    if (Epp) hipLaunchKernelGGL((k_plain<E, true>), dim3(blocks), dim3(threads), 0, s, pk, SW, off, len, Epp, n, out);
-    else hipLaunchKernelGGL((k_plain<E, false>), dim3(blocks), dim3(threads), 0, s, pk, SW, off, len, Epp, n, out);
+    if (Epp)
+        hipLaunchKernelGGL((k_plain<E, true>), dim3(blocks), dim3(threads), 0, s, qpk, SWq, rpk, SWr, off, len, Epp,
+                           n, out);
+    else
+        hipLaunchKernelGGL((k_plain<E, false>), dim3(blocks), dim3(threads), 0, s, qpk, SWq, rpk, SWr, off, len, Epp,
+                           n, out);
     return hipGetLastError();
 }
 
 template <int... Es>
 struct PlainTable {
-    static hipError_t run(int E, const uint32_t* pk, int64_t SW, const int64_t* off, const int32_t* len,
-                          const int32_t* Epp, int64_t n, uint16_t* out, hipStream_t s)
+    static hipError_t run(int E, const uint32_t* qpk, int64_t SWq, const uint32_t* rpk, int64_t SWr,
+                          const int64_t* off, const int32_t* len, const int32_t* Epp, int64_t n, uint16_t* out,
+                          hipStream_t s)
     {
         hipError_t r = hipErrorInvalidValue;
-        ((E == Es ? (r = launch_plain_E<Es>(pk, SW, off, len, Epp, n, out, s), 0) : 0), ...);
+        ((E == Es ? (r = launch_plain_E<Es>(qpk, SWq, rpk, SWr, off, len, Epp, n, out, s), 0) : 0), ...);
         return r;
     }
 };
 
+struct WaveArgs {
+    wave::GlobalPlanes planes;
+    const int64_t* qoff;
+    const int32_t* qlen;
+    const int64_t* roff;
+    const int32_t* rlen;
+    const int32_t* Epp;
+    int64_t n;
+    int E;
+    uint16_t* out;
+};
+
 template <int LP, int RS>
-hipError_t launch_wave_LR(const uint32_t* pk, int64_t SW, const int64_t* off, const int32_t* len,
-                          const int32_t* Epp, int64_t n, int E, uint16_t* out, hipStream_t s)
+hipError_t launch_wave_LR(const WaveArgs& a, hipStream_t s)
 {
     constexpr int PW = 64 / LP;
-    const int64_t waves = cdiv(n, PW);
+    const int64_t waves = cdiv(a.n, PW);
     const int threads = 256;
     const unsigned blocks = (unsigned)cdiv(waves * 64, threads);
-    hipLaunchKernelGGL((k_wave<LP, RS>), dim3(blocks), dim3(threads), 0, s, pk, SW, off, len, Epp, n, E, out);
+    hipLaunchKernelGGL((k_wave<LP, RS>), dim3(blocks), dim3(threads), 0, s, a.planes, a.qoff, a.qlen, a.roff, a.rlen,
+                       a.Epp, a.n, a.E, a.out);
     return hipGetLastError();
 }
 
 template <int RS>
-hipError_t launch_wave_R(int LP, const uint32_t* pk, int64_t SW, const int64_t* off, const int32_t* len,
-                         const int32_t* Epp, int64_t n, int E, uint16_t* out, hipStream_t s)
+hipError_t launch_wave_R(int LP, const WaveArgs& a, hipStream_t s)
 {
     switch (LP) {
-    case 1: return launch_wave_LR<1, RS>(pk, SW, off, len, Epp, n, E, out, s);
-    case 2: return launch_wave_LR<2, RS>(pk, SW, off, len, Epp, n, E, out, s);
-    case 4: return launch_wave_LR<4, RS>(pk, SW, off, len, Epp, n, E, out, s);
-    case 8: return launch_wave_LR<8, RS>(pk, SW, off, len, Epp, n, E, out, s);
-    case 16: return launch_wave_LR<16, RS>(pk, SW, off, len, Epp, n, E, out, s);
-    case 32: return launch_wave_LR<32, RS>(pk, SW, off, len, Epp, n, E, out, s);
-    case 64: return launch_wave_LR<64, RS>(pk, SW, off, len, Epp, n, E, out, s);
+    case 1: return launch_wave_LR<1, RS>(a, s);
+    case 2: return launch_wave_LR<2, RS>(a, s);
+    case 4: return launch_wave_LR<4, RS>(a, s);
+    case 8: return launch_wave_LR<8, RS>(a, s);
+    case 16: return launch_wave_LR<16, RS>(a, s);
+    case 32: return launch_wave_LR<32, RS>(a, s);
+    case 64: return launch_wave_LR<64, RS>(a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_wave_args(const WaveArgs& a, hipStream_t s)
+{
+    if (a.n == 0) return hipSuccess;
+    int LP, RS;
+    wave_shape(a.E, &LP, &RS);
+    switch (RS) {
+    case 1: return launch_wave_R<1>(LP, a, s);
+    case 2: return launch_wave_R<2>(LP, a, s);
+    case 4: return launch_wave_R<4>(LP, a, s);
+    case 8: return launch_wave_R<8>(LP, a, s);
+    case 16: return launch_wave_R<16>(LP, a, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -298,8 +352,18 @@ hipError_t launch_pack_stream(const uint8_t* reads, const uint8_t* refs, int64_t
     const int64_t SW = cdiv(total_bases, 32) + 2;
     const int aligned = ((((uintptr_t)reads) | ((uintptr_t)refs)) & 15u) == 0;
     const int threads = 256;
-    hipLaunchKernelGGL(k_pack_stream, dim3((unsigned)cdiv(SW, threads)), dim3(threads), 0, s, reads, refs,
+    hipLaunchKernelGGL(k_pack_stream<true>, dim3((unsigned)cdiv(SW, threads)), dim3(threads), 0, s, reads, refs,
                        total_bases, SW, aligned, packed, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_side(const uint8_t* ascii, int64_t total_bases, uint32_t* packed, uint32_t* err, hipStream_t s)
+{
+    const int64_t SW = cdiv(total_bases, 32) + 2;
+    const int aligned = (((uintptr_t)ascii) & 15u) == 0;
+    const int threads = 256;
+    hipLaunchKernelGGL(k_pack_stream<false>, dim3((unsigned)cdiv(SW, threads)), dim3(threads), 0, s, ascii,
+                       (const uint8_t*)nullptr, total_bases, SW, aligned, packed, err);
     return hipGetLastError();
 }
 
@@ -308,26 +372,35 @@ hipError_t launch_plain(const uint32_t* packed, int64_t stream_words, const int6
                         hipStream_t s)
 {
     if (n == 0) return hipSuccess;
+    return launch_plain_sides(packed, stream_words, packed + 2 * stream_words, stream_words, offsets, lengths, Epp,
+                              n, E, out, s);
+}
+
+hipError_t launch_plain_sides(const uint32_t* qpk, int64_t q_words, const uint32_t* rpk, int64_t r_words,
+                              const int64_t* offsets, const int32_t* lengths, const int32_t* Epp, int64_t n,
+                              int32_t E, uint16_t* out, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
     using Tab = PlainTable<0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18, 19, 20, 21, 22, 23,
                            24, 25, 26, 27, 28, 29, 30, 31>;
-    return Tab::run(E, packed, stream_words, offsets, lengths, Epp, n, out, s);
+    return Tab::run(E, qpk, q_words, rpk, r_words, offsets, lengths, Epp, n, out, s);
 }
 
 hipError_t launch_wave(const uint32_t* packed, int64_t stream_words, const int64_t* offsets,
                        const int32_t* lengths, const int32_t* Epp, int64_t n, int32_t E, uint16_t* out,
                        hipStream_t s)
 {
-    if (n == 0) return hipSuccess;
-    int LP, RS;
-    wave_shape(E, &LP, &RS);
-    switch (RS) {
-    case 1: return launch_wave_R<1>(LP, packed, stream_words, offsets, lengths, Epp, n, E, out, s);
-    case 2: return launch_wave_R<2>(LP, packed, stream_words, offsets, lengths, Epp, n, E, out, s);
-    case 4: return launch_wave_R<4>(LP, packed, stream_words, offsets, lengths, Epp, n, E, out, s);
-    case 8: return launch_wave_R<8>(LP, packed, stream_words, offsets, lengths, Epp, n, E, out, s);
-    case 16: return launch_wave_R<16>(LP, packed, stream_words, offsets, lengths, Epp, n, E, out, s);
-    default: return hipErrorInvalidValue;
-    }
+    const WaveArgs a{wave::GlobalPlanes{packed, packed + 2 * stream_words, stream_words, stream_words},
+                     offsets, lengths, offsets, lengths, Epp, n, E, out};
+    return launch_wave_args(a, s);
+}
+
+hipError_t launch_wave_sides(const uint32_t* qpk, int64_t q_words, const uint32_t* rpk, int64_t r_words,
+                             const int64_t* qoff, const int32_t* qlen, const int64_t* roff, const int32_t* rlen,
+                             const int32_t* Epp, int64_t n, int32_t E, uint16_t* out, hipStream_t s)
+{
+    const WaveArgs a{wave::GlobalPlanes{qpk, rpk, q_words, r_words}, qoff, qlen, roff, rlen, Epp, n, E, out};
+    return launch_wave_args(a, s);
 }
 
 hipError_t launch_unpack(const uint16_t* res, int64_t n, uint8_t* accept, int32_t* edits, hipStream_t s)

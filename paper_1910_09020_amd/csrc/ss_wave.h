@@ -52,13 +52,23 @@ __device__ __forceinline__ uint32_t span_mask(int lo, int hi)
 // included) is sent to one such offset, so each load is issued
 // unconditionally, with no branch around it.  A plane must be smaller than
 // 2^30 - 64 words (SS_MAX_STREAM_BASES).
+// The query planes (0, 1) and the reference planes (2, 3) may live in two
+// buffers of their own sizes (each side packed by itself), or in one buffer of
+// four planes of SW words (four()).
 struct GlobalPlanes {
-    const uint32_t* pk;
-    int64_t SW;
+    const uint32_t* q;       // plane p = 0, 1 at q + p * SWq
+    const uint32_t* r;       // plane p = 2, 3 at r + (p - 2) * SWr
+    int64_t SWq, SWr;
+    __device__ __forceinline__ static GlobalPlanes four(const uint32_t* pk, int64_t SW)
+    {
+        return GlobalPlanes{pk, pk + 2 * SW, SW, SW};
+    }
     __device__ __forceinline__ uint32_t word(int p, int w) const
     {
+        const int64_t SW = p < 2 ? SWq : SWr;
+        const uint32_t* base = p < 2 ? q + p * SWq : r + (p - 2) * SWr;
         const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-            const_cast<uint32_t*>(pk + p * SW), (short)0, (int)(uint32_t)(SW * 4), 0x00020000);
+            const_cast<uint32_t*>(base), (short)0, (int)(uint32_t)(SW * 4), 0x00020000);
         const uint32_t off = (uint32_t)w < (uint32_t)SW ? (uint32_t)w << 2 : 0xFFFFFFF0u;
         return (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0);
     }
@@ -213,14 +223,19 @@ __device__ __forceinline__ void block_end(Share<RS>& S, const Win<RS>& W, int LP
 // the wavefront must call this together (it uses wavefront votes and lane
 // permutes), with the same LP.
 //   ld          : window loader (GlobalPlanes or StagedPlanes)
-//   b0, m, Ei   : the pair's stream bit offset, length and threshold
+//   bq, br      : stream bit offsets of the pair's query and reference
+//   m           : columns walked (the reference's length for pairs of equal
+//                 length; see columns_walked for pairs of unequal length)
+//   nq          : the query's length (cells whose query position falls outside
+//                 [0, nq) are obstacles, the fourth case of Equation 1)
+//   Ei          : the pair's threshold
 //   pair_ok     : false for lanes without a pair (they still take part)
 //   LP, lip     : lanes per pair and this lane's index in its pair
 //   RS          : slices this lane holds; Emax: row layout threshold
 // Returns the count reported by the walk, min(count, Ei+1).
 template <int RS, int LPC, class LD>
-__device__ __forceinline__ int sweep_pair(const LD& ld, int64_t b0, int m, int Ei, bool pair_ok, int LP_rt, int lip,
-                                          int Emax)
+__device__ __forceinline__ int sweep_pair2(const LD& ld, int64_t bq, int64_t br, int m, int nq, int Ei, bool pair_ok,
+                                           int LP_rt, int lip, int Emax)
 {
     const int LP = LPC > 0 ? LPC : LP_rt;
     const int NR = 2 * Emax + 1;
@@ -244,14 +259,14 @@ __device__ __forceinline__ int sweep_pair(const LD& ld, int64_t b0, int m, int E
     for (int o = 32; o >= 1; o >>= 1) mmax = max(mmax, __shfl_xor(mmax, o));
 
     // Window words.  Slice t's query window at block jb starts at stream bit
-    // b0 - Emax + 32 s + jb, i.e. at bit shq of word wq + s + jb/32; the
+    // bq - Emax + 32 s + jb, i.e. at bit shq of word wq + s + jb/32; the
     // reference bits of block jb start at bit shr of word wr + jb/32.  The
     // window moves by one word per block, so each block loads one new word
     // per plane and slice (and per reference plane), one block ahead, and
     // keeps the last one (c0, c1, cr0, cr1) for the next funnel shift.
-    const int64_t aq = b0 - Emax;
-    const int wq = (int)(aq >> 5), wr = (int)(b0 >> 5);       // arithmetic shift: floor
-    const uint32_t shq = (uint32_t)(aq & 31), shr = (uint32_t)(b0 & 31);
+    const int64_t aq = bq - Emax;
+    const int wq = (int)(aq >> 5), wr = (int)(br >> 5);       // arithmetic shift: floor
+    const uint32_t shq = (uint32_t)(aq & 31), shr = (uint32_t)(br & 31);
     uint32_t c0[RS], c1[RS];
 #pragma unroll
     for (int t = 0; t < RS; t++) {
@@ -293,15 +308,15 @@ __device__ __forceinline__ int sweep_pair(const LD& ld, int64_t b0, int m, int E
             cr1 = y1;
         }
         // block kind, uniform over the wavefront: a walking pair ends here;
-        // some row may meet a query position outside [0, m); neither
+        // some row may meet a query position outside [0, nq); neither
         const bool end = __any(S.nfin != 0u && m <= jb + 32);
-        const bool mask = end || jb < Emax || __any(S.nfin != 0u && m <= jb + 31 + Emax);
+        const bool mask = end || jb < Emax || __any(S.nfin != 0u && nq <= jb + 31 + Emax);
         if (mask) {
 #pragma unroll
             for (int t = 0; t < RS; t++) {
                 const int base = jb - Emax + 32 * (lip + LP * t);      // query position of window bit 0
-                W.vlo[t] = span_mask(-base, m - base);
-                W.vhi[t] = span_mask(-base - 32, m - base - 32);
+                W.vlo[t] = span_mask(-base, nq - base);
+                W.vhi[t] = span_mask(-base - 32, nq - base - 32);
             }
         }
         if (end)
@@ -315,6 +330,27 @@ __device__ __forceinline__ int sweep_pair(const LD& ld, int64_t b0, int m, int E
     }
     const int count = Ei - S.slack;
     return count > Ei + 1 ? Ei + 1 : count;
+}
+
+// Pairs of equal length m: query and reference at the same stream offset.
+template <int RS, int LPC, class LD>
+__device__ __forceinline__ int sweep_pair(const LD& ld, int64_t b0, int m, int Ei, bool pair_ok, int LP_rt, int lip,
+                                          int Emax)
+{
+    return sweep_pair2<RS, LPC>(ld, b0, b0, m, m, Ei, pair_ok, LP_rt, lip, Emax);
+}
+
+// Columns walked for a reference of m bases and a query of n (unequal lengths,
+// the note of Section 2.4 between steps 4 and 5): the maze over the longer
+// sequence holds a comparison of two existing characters only in columns
+// 1 .. min(m, n + E) (none when n = 0); the obstacles the walk meets beyond
+// them are the trailing ones caused by the fourth case of Equation 1, which
+// are deducted before the decision, so the walk stops there.  For m = n this
+// is m.
+__host__ __device__ __forceinline__ int columns_walked(int m, int n, int E)
+{
+    if (n <= 0 || m <= 0) return 0;
+    return (int64_t)n + E < (int64_t)m ? n + E : m;
 }
 
 __device__ __forceinline__ uint16_t result_word(int count, int Ei)

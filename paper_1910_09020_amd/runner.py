@@ -79,8 +79,28 @@ class DeviceBatch:
                              stream or torch.cuda.current_stream(self.device))
         return packed
 
+    def err_bits(self) -> int:
+        """The error word the encoders and the fused kernel OR into: bit 0 a byte outside ACGTacgt,
+        bit 1 a bounded wait between the fused kernel's wavefronts that gave up."""
+        return int(self.err.item())
+
     def bad_bases(self) -> bool:
-        return bool(self.err.item() != 0)
+        return bool(self.err_bits() & 1)
+
+    def wait_gave_up(self) -> bool:
+        return bool(self.err_bits() & 2)
+
+    def check_err(self, where: str) -> None:
+        """Raise if the error word is set (either bit): results written since it was cleared are
+        unspecified."""
+        e = self.err_bits()
+        if e:
+            what = []
+            if e & 1:
+                what.append("byte outside ACGTacgt")
+            if e & 2:
+                what.append("a wait inside the fused kernel gave up")
+            raise RuntimeError(f"{where}: error word {e:#x} ({', '.join(what) or 'unknown bit'})")
 
     # ---- filters ---------------------------------------------------------------
     def new_out(self, n=None) -> torch.Tensor:

@@ -69,3 +69,21 @@ def test_header_limits_match_binding():
         assert getattr(ss, name) == value, name
         found += 1
     assert found >= 8
+
+
+def test_batch_desc_layout_matches_header(tmp_path):
+    """The binding's mirror of ss_batch_desc has the C struct's size and field offsets (a C program built
+    against include/ss.h prints them)."""
+    import paper_1910_09020_amd as ss
+    fields = [f for f, _ in ss.BatchDesc._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "ss.h"\nint main(void){\n'
+                   '  printf("%zu\\n", sizeof(ss_batch_desc));\n' +
+                   "".join(f'  printf("%zu\\n", offsetof(ss_batch_desc, {f}));\n' for f in fields) +
+                   "  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    vals = [int(x) for x in subprocess.check_output([str(exe)], text=True).split()]
+    assert vals[0] == ctypes.sizeof(ss.BatchDesc)
+    assert vals[1:] == [getattr(ss.BatchDesc, f).offset for f in fields]
+    assert ss.ss_pack_words(0) == 4 and ss.ss_pack_words(33) == 2 * (2 + 2) and ss.ss_pack_words(-1) == -1

@@ -20,5 +20,17 @@ def test_traffic_summary_matches_sources():
     recorded next to them; a stale summary must be re-taken, not reported."""
     sys.path.insert(0, ROOT)
     import bench
-    for name in ("k_fused_E5", "k_pack_tile", "k_sliced_E5"):
-        assert bench.measured_traffic(name) is not None, name
+    assert bench.measured_traffic("k_fused_E5") is not None
+    for name in ("k_sliced_E5", "k_pack_tile"):
+        assert bench.measured_traffic(name, profile="sliced_sweep_100bp_E5_pmc.md") is not None, name
+
+
+def test_trace_summary_matches_sources():
+    """The kernel trace summary of the headline kernel names the source hash it was taken at; it must be
+    the hash of the sources as they stand."""
+    import hashlib
+    text = open(os.path.join(ROOT, "profiles", "sliced_sweep_100bp_E5_kernel_trace.md")).read()
+    h = hashlib.sha256()
+    for src in ("ss_sliced_kernel.h", "ss_sliced_ops.h", "ss_sliced_lo.hip"):
+        h.update(open(os.path.join(ROOT, "paper_1910_09020_amd", "csrc", src), "rb").read())
+    assert f"sha256_16={h.hexdigest()[:16]}" in text

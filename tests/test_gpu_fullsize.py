@@ -1,9 +1,14 @@
-"""Parity at the full workload sizes, in the launch configuration the benchmark times.
+"""Parity at the full workload sizes, in the launch configurations the benchmark times.
 
-The oracle checks a random sample pair by pair; every pair is checked by
-properties that hold at any size: the lane-sliced sweep, the one-call path
-(fused or chunked) and the one-pair-per-lane walk agree on all pairs, the accept decision is monotone in E, a reported
-count never exceeds E+1 and the decision is exactly count <= E.
+Every pair of every size is compared with the CPU oracle (run on the host cores, 16 threads), bit for
+bit on the accept decision and the reported count:
+  - 30 M pairs of 100 bp at E = 0, 3, 5 (the one-call path runs the fused kernel) and E = 6, 10 (the
+    chunked two-kernel schedule), through the lane-sliced sweep on the resident planes and through the
+    one-call path from ASCII; the one-pair-per-lane kernel at E = 5;
+  - 10 M pairs of 250 bp at E = 0, 8, 25, lane-sliced sweep and one-call path; the wavefront kernel at
+    E = 25 and the one-pair-per-lane kernel at E = 8;
+  - the mixed batch (5 M short pairs + 20,000 pairs of 10 kbp, per-pair E) through an autotuned plan
+    replayed from a captured graph.
 """
 import os
 
@@ -14,6 +19,8 @@ import oracle
 from paper_1910_09020_amd import gen
 
 pytestmark = pytest.mark.gpu
+
+THREADS = min(16, os.cpu_count() or 1)
 
 
 @pytest.fixture(scope="module")
@@ -27,96 +34,84 @@ def rt():
     return torch, runner
 
 
-def _sample_check(b, E, acc, ed, k, seed):
-    rng = np.random.default_rng(seed)
-    idx = np.sort(rng.choice(b["n"], size=k, replace=False))
-    w = oracle.batch(b["reads"], b["refs"], b["offsets"][idx], b["lengths"][idx], E=E,
-                     threads=min(16, os.cpu_count() or 1))
-    bad = np.nonzero((w["accept"] != acc[idx]) | (w["edits"] != ed[idx]))[0]
-    assert len(bad) == 0, f"E={E}: {len(bad)} sampled mismatches, first pairs {idx[bad[:5]]}"
+def say(msg):
+    print(msg, flush=True)
 
 
-def _run(rt, b, Es, plain_E, sample):
+def oracle_all(b, E=None, E_per_pair=None):
+    w = oracle.batch(b["reads"], b["refs"], b["offsets"], b["lengths"], E=E, E_per_pair=E_per_pair,
+                     threads=THREADS)
+    return w["accept"], w["edits"]
+
+
+def check(name, got, want):
+    acc, ed = got
+    wa, we = want
+    bad = np.nonzero((acc != wa) | (ed != we))[0]
+    assert len(bad) == 0, f"{name}: {len(bad)} of {len(wa)} pairs differ from the oracle, first {bad[:5]}"
+
+
+def _every_pair(rt, b, Es, plain_E, wave_E=None):
     torch, runner = rt
     db = runner.DeviceBatch(b)
     pk = db.pack_sliced()
     out = db.new_out()
-    res = {}
     for E in Es:
-        print(f"  sliced n={db.n} m={db.uniform_m} E={E}", flush=True)
+        say(f"  oracle n={db.n} m={db.uniform_m} E={E}")
+        want = oracle_all(b, E)
+        say(f"  sliced E={E}")
         db.filter_sliced(pk, E, out=out)
         torch.cuda.synchronize()
-        res[E] = runner.results_numpy(out, db.n)
-    assert not db.bad_bases()
-    del pk
-    # the one-call path (fused kernel for small E, chunked two-kernel schedule
-    # above) must give the same words for every pair
-    for E in Es:
-        print(f"  one-call n={db.n} E={E}", flush=True)
-        f = db.filter_fused(E)
+        check(f"sliced E={E}", runner.results_numpy(out, db.n), want)
+        say(f"  one-call E={E}")
+        db.filter_fused(E, out=out)
         torch.cuda.synchronize()
-        fa, fe = runner.results_numpy(f, db.n)
-        assert np.array_equal(fa, res[E][0]) and np.array_equal(fe, res[E][1]), f"one-call E={E}"
-        del f
-    ps = db.pack_stream()
-    print(f"  plain E={plain_E}", flush=True)
-    pout = db.filter_plain(ps, plain_E)
-    torch.cuda.synchronize()
-    pacc, ped = runner.results_numpy(pout, db.n)
-    assert np.array_equal(pacc, res[plain_E][0]) and np.array_equal(ped, res[plain_E][1])
-    for E in Es:
-        acc, ed = res[E]
-        assert np.all(ed <= E + 1)
-        assert np.array_equal(acc == 1, ed <= E)
-    for E0, E1 in zip(Es, Es[1:]):
-        assert np.all(res[E1][0] >= res[E0][0]), f"accept not monotone between E={E0} and E={E1}"
-    _sample_check(b, plain_E, *res[plain_E], sample, 3)
-    return res
+        db.check_err(f"one-call E={E}")
+        check(f"one-call E={E}", runner.results_numpy(out, db.n), want)
+        if E == plain_E or E == wave_E:
+            ps = db.pack_stream()
+            if E == plain_E:
+                say(f"  one pair per lane E={E}")
+                db.filter_plain(ps, E, out=out)
+                torch.cuda.synchronize()
+                check(f"plain E={E}", runner.results_numpy(out, db.n), want)
+            if E == wave_E:
+                say(f"  wavefront E={E}")
+                db.filter_wave(ps, E, out=out)
+                torch.cuda.synchronize()
+                check(f"wave E={E}", runner.results_numpy(out, db.n), want)
+            del ps
+        del want
+    db.check_err("encode")
 
 
-def test_100bp_30M_E5(rt):
-    b = gen.make(1)
-    _run(rt, b, [4, 5, 6], 5, 100_000)
+def test_100bp_30M_every_pair(rt):
+    _every_pair(rt, gen.make(1, threads=THREADS), [0, 3, 5, 6, 10], plain_E=5)
 
 
-def test_250bp_10M_E25(rt):
-    b = gen.make(2)
-    _run(rt, b, [24, 25], 25, 20_000)
+def test_250bp_10M_every_pair(rt):
+    _every_pair(rt, gen.make(2, threads=THREADS), [0, 8, 25], plain_E=8, wave_E=25)
 
 
-def test_mixed_5M_planned(rt, tmp_path):
-    """The mixed-length batch at full size (5 M short pairs + 20,000 pairs of 10 kbp, per-pair E), in
-    the benchmark's launch configuration: an autotuned plan replayed from a captured graph.  Every
-    pair against one unbucketed wavefront launch laid out for the largest threshold; a sample of
-    short and long pairs against the oracle."""
+def test_mixed_5M_planned_every_pair(rt, tmp_path):
+    """The mixed-length batch at full size in the benchmark's launch configuration: an autotuned plan
+    replayed from a captured graph, every pair (short and long) against the oracle."""
     torch, runner = rt
     import paper_1910_09020_amd as ss
-    b = gen.make(3, threads=min(16, os.cpu_count() or 1))
+    b = gen.make(3, threads=THREADS)
     db = runner.DeviceBatch(b)
     ps = db.pack_stream()
     ctx = runner.context()
     out = db.new_out()
-    print(f"  tuned plan n={db.n}", flush=True)
+    say(f"  tuned plan n={db.n}")
     plan, _ = ss.ss_plan_create_tuned(ctx, b["lengths"], b["E"], ps, db.total, db.offsets, db.lengths, db.E, out,
                                       str(tmp_path / "tune.json"))
     ss.ss_plan_capture(ctx, plan, ps, db.total, db.offsets, db.lengths, db.E, out)
     out.fill_(-1)
     ss.ss_plan_launch(plan, torch.cuda.current_stream())
     torch.cuda.synchronize()
-    acc, ed = runner.results_numpy(out, db.n)
+    got = runner.results_numpy(out, db.n)
     ss.ss_plan_destroy(plan)
-    assert not db.bad_bases()
-    print(f"  unbucketed wavefront launch E={int(b['E'].max())}", flush=True)
-    flat = db.filter_wave(ps, int(b["E"].max()), per_pair=True)
-    torch.cuda.synchronize()
-    fa, fe = runner.results_numpy(flat, db.n)
-    assert np.array_equal(acc, fa) and np.array_equal(ed, fe), "planned launch != unbucketed launch"
-    assert np.all(ed <= b["E"] + 1) and np.array_equal(acc == 1, ed <= b["E"])
-    rng = np.random.default_rng(5)
-    long_idx = np.nonzero(b["lengths"] >= 10000)[0]
-    short_idx = np.nonzero(b["lengths"] < 10000)[0]
-    idx = np.sort(np.concatenate([rng.choice(short_idx, 20_000, replace=False), rng.choice(long_idx, 100, replace=False)]))
-    w = oracle.batch(b["reads"], b["refs"], b["offsets"][idx], b["lengths"][idx], E_per_pair=b["E"][idx],
-                     threads=min(16, os.cpu_count() or 1))
-    bad = np.nonzero((w["accept"] != acc[idx]) | (w["edits"] != ed[idx]))[0]
-    assert len(bad) == 0, f"{len(bad)} sampled mismatches, first pairs {idx[bad[:5]]}"
+    db.check_err("encode")
+    say("  oracle on every pair")
+    check("planned launch", got, oracle_all(b, E_per_pair=b["E"]))
