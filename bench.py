@@ -378,7 +378,7 @@ def serving_leg(a, ss, gen, runner, oracle):
     for t in D.tickets:
         rc = ss.ss_server_wait(srv, int(t), -1)
         assert rc == ss.SS_OK, rc
-    lat, svc, wait, lag = [], [], [], []
+    lat, svc, wait, lag, stages = [], [], [], [], []
     done_last = 0
     for i in range(nreq):
         sub, adm, done = ss.ss_server_times(srv, int(D.tickets[i]))
@@ -387,8 +387,23 @@ def serving_leg(a, ss, gen, runner, oracle):
         svc.append((done - adm) / 1e6)
         wait.append((adm - sub) / 1e6)
         lag.append((sub - due) / 1e6)
+        stages.append(ss.ss_server_stages(srv, int(D.tickets[i])))
         done_last = max(done_last, done)
     lat = np.array(lat)
+    # where the time of a request goes: submission lag, queue, host enqueue, device spans (copy in,
+    # encode + filter, copy out), and the rest of the service time (waiting on the device behind other
+    # slots' work, and the completion thread's polling); means over all requests and over those at or
+    # above the p99 latency
+    st = np.array(stages, dtype=np.float64) / 1e6
+    parts = np.stack([np.array(lag), np.array(wait), st[:, 0], st[:, 1], st[:, 2], st[:, 3],
+                      np.array(svc) - st.sum(axis=1)], axis=1)
+    names = ["submit_lag", "queue", "host_enqueue", "copy_in", "encode_filter", "copy_out", "device_wait_and_poll"]
+    tail = lat >= np.percentile(lat, 99)
+    breakdown = {"all_mean_ms": dict(zip(names, [round(float(x), 4) for x in parts.mean(axis=0)])),
+                 "p99_tail_mean_ms": dict(zip(names, [round(float(x), 4) for x in parts[tail].mean(axis=0)])),
+                 "p99_tail_requests": int(tail.sum()),
+                 "p99_tail_mean_pairs": float(np.mean(D.pairs[tail])),
+                 "all_mean_pairs": float(np.mean(D.pairs))}
     pct = lambda v, q: float(np.percentile(np.array(v), q))
     pairs = int(D.pairs.sum())
     bases = int(D.bases.sum())
@@ -412,11 +427,15 @@ def serving_leg(a, ss, gen, runner, oracle):
                max_ms=float(lat.max()), service_p50_ms=pct(svc, 50), service_p99_ms=pct(svc, 99),
                queue_p50_ms=pct(wait, 50), queue_p99_ms=pct(wait, 99), submit_lag_p50_ms=pct(lag, 50),
                submit_lag_p99_ms=pct(lag, 99), slots=a.serve_slots, hbm_budget_bytes=32 << 30, stats=st,
-               hw_queues=os.environ.get("GPU_MAX_HW_QUEUES", "default"), distinct_requests=pool or nreq,
+               hw_queues=os.environ.get("GPU_MAX_HW_QUEUES", "HIP default"), distinct_requests=pool or nreq,
+               breakdown=breakdown,
+               generation=("every request generated from its own seed just ahead of its arrival" if not pool else
+                           f"{pool} requests generated before the clock, replayed in a cycle"),
                slices_per_lane=a.serve_slices,
                oracle_checked_requests=int(len(chk)), oracle_mismatches=mism)
     log(f"serving: {nreq} requests, {pairs} pairs in {span:.2f}s, p50 {res['p50_ms']:.3f} ms, "
         f"p99 {res['p99_ms']:.3f} ms, service p50/p99 {res['service_p50_ms']:.3f}/{res['service_p99_ms']:.3f} ms, "
+        f"tail breakdown {breakdown['p99_tail_mean_ms']}, "
         f"queue p50/p99 {res['queue_p50_ms']:.3f}/{res['queue_p99_ms']:.3f} ms, submit lag p50/p99 "
         f"{res['submit_lag_p50_ms']:.3f}/{res['submit_lag_p99_ms']:.3f} ms, stats {st}, oracle mismatches {mism}")
     return res
@@ -491,9 +510,10 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=2000.0, help="Poisson arrival rate, requests/s")
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--serve-slices", type=int, default=1, help="32-row slices per lane for served requests")
-    ap.add_argument("--serve-pool", type=int, default=0,
-                    help="distinct requests generated before the clock starts (0: every request generated "
-                         "from its own seed just ahead of its arrival)")
+    ap.add_argument("--serve-pool", type=int, default=4000,
+                    help="distinct requests generated before the clock starts and replayed in a cycle (0: every "
+                         "request generated from its own seed just ahead of its arrival, which the host's "
+                         "generator threads cannot sustain at 2,000 requests/s)")
     ap.add_argument("--serve-only", action="store_true", help="run only the serving leg (diagnostics)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-sclk", action="store_true")

@@ -458,6 +458,12 @@ int ss_server_poll(ss_server* server, ss_ticket ticket, int* done);
 int ss_server_wait(ss_server* server, ss_ticket ticket, int64_t timeout_us);
 /* Steady-clock nanoseconds of submission, admission and completion (0 = not yet). */
 int ss_server_times(ss_server* server, ss_ticket ticket, int64_t* submit_ns, int64_t* admit_ns, int64_t* done_ns);
+/* Where a finished request's time went (nanoseconds, 0 until it is done): the
+ * host's time to enqueue its work on its slot's stream after admission, and,
+ * from timing events on that stream, the copy of its inputs to the device,
+ * the encoding and filter kernels, and the copy of its results back. */
+int ss_server_stages(ss_server* server, ss_ticket ticket, int64_t* enqueue_ns, int64_t* h2d_ns, int64_t* compute_ns,
+                     int64_t* d2h_ns);
 /* Cancel a request that is still queued (SS_EAGAIN once admitted). */
 int ss_server_cancel(ss_server* server, ss_ticket ticket);
 /* Forget a finished ticket (SS_EAGAIN while queued or running). */

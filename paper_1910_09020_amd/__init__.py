@@ -107,6 +107,7 @@ def lib():
         "ss_pack": ([vp, vp, i64, vp, vp, vp], ctypes.c_int),
         "ss_filter_batch_ex": ([vp, ctypes.POINTER(BatchDesc), vp], ctypes.c_int),
         "ss_filter_batch_pairs": ([vp, vp, vp, vp, i64, vp, i32, vp, vp], ctypes.c_int),
+        "ss_server_stages": ([vp, ctypes.c_uint64, vp, vp, vp, vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -127,7 +128,7 @@ def exported_symbols():
             "ss_plan_launch", "ss_plan_create_tuned", "ss_server_create", "ss_server_submit", "ss_server_poll",
             "ss_server_wait", "ss_server_times", "ss_server_cancel", "ss_server_release", "ss_server_set_hold",
             "ss_server_stats", "ss_server_destroy", "ss_server_footprint", "ss_server_set_slices", "ss_pack_words",
-            "ss_pack", "ss_filter_batch_ex", "ss_filter_batch_pairs"]
+            "ss_pack", "ss_filter_batch_ex", "ss_filter_batch_pairs", "ss_server_stages"]
 
 
 def status_str(status: int) -> str:
@@ -399,6 +400,13 @@ def ss_server_times(server, ticket):
     _check(lib().ss_server_times(server, ticket, ctypes.addressof(a), ctypes.addressof(b), ctypes.addressof(c)),
            "ss_server_times")
     return a.value, b.value, c.value
+
+
+def ss_server_stages(server, ticket):
+    """(enqueue, copy in, encode + filter, copy out) of a finished request, nanoseconds."""
+    v = [ctypes.c_int64(0) for _ in range(4)]
+    _check(lib().ss_server_stages(server, ticket, *[ctypes.addressof(x) for x in v]), "ss_server_stages")
+    return tuple(x.value for x in v)
 
 
 def ss_server_cancel(server, ticket) -> int:

@@ -146,7 +146,7 @@ extern "C" int ss_filter_ascii_async(ss_ctx* ctx, const uint8_t* reads, const ui
     if (((uintptr_t)out & 15u) != 0) return SS_EINVAL;
     int T = 0, GB = 0, U = 0;
     const bool contiguous = (((uintptr_t)reads | (uintptr_t)refs) & 15u) == 0;
-    if (fused_shape(m, tile_groups, contiguous, &T, &GB, &U) == 0) return SS_EINVAL;
+    if (fused_shape(m, tile_groups, contiguous, &T, &GB, &U, fused_tile_cap(n_pairs)) == 0) return SS_EINVAL;
     const hipStream_t s = (hipStream_t)stream;
     // The fused kernel in wave mode (aligned pairs of up to a few hundred bases) beats the two kernels;
     // in block mode it does not for aligned inputs (250 bp: 2.2-2.4 ms against 1.7 ms), so with the

@@ -29,7 +29,10 @@ hipError_t launch_sliced(const uint32_t* packed, int64_t n_pairs, int32_t m, int
 // tile_groups: groups of 32 pairs per block (0: automatic).
 hipError_t launch_fused(const uint8_t* reads, const uint8_t* refs, int64_t n_pairs, int32_t m, int32_t E,
                         int tile_groups, uint16_t* out, uint32_t* err, hipStream_t s);
-size_t fused_shape(int32_t m, int tile_groups, bool contiguous, int* T, int* GB, int* U);
+// max_t caps the automatic tile (tile_groups = 0); fused_tile_cap gives the cap
+// that leaves no CU without a tile for a batch of n_pairs.
+size_t fused_shape(int32_t m, int tile_groups, bool contiguous, int* T, int* GB, int* U, int max_t = 256);
+int fused_tile_cap(int64_t n_pairs);
 hipError_t launch_pack_stream(const uint8_t* reads, const uint8_t* refs, int64_t total_bases,
                               uint32_t* packed, uint32_t* err, hipStream_t s);
 // One side (reads or refs) into two planes of cdiv(total_bases, 32) + 2 words.

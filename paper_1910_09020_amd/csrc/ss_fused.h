@@ -248,8 +248,10 @@ __device__ __forceinline__ void arrive(uint32_t* p)
 // encoded into it, and tiles swept.  The sweep of tile i waits until the
 // buffer of tile i has counted all units of its tiles up to i; the encoding of
 // a unit of tile i, which overwrites the buffer of tile i-2, waits for
-// "swept > i-2".  (No unit of tile i+2 can start before tile i is swept, so the
-// per-buffer count reaches tile i's target only when tile i is complete.)
+// "swept > i-2"; so does a unit without groups (past the batch's last group),
+// which encodes nothing but still counts.  (No unit of tile i+2 can count
+// before tile i is swept, so the per-buffer count reaches tile i's target only
+// when tile i is complete.)
 // Every wait on a counter is bounded (see wait_at_least).
 //
 // Block mode (not WAVE): the three waves encode GB groups at a time together,
@@ -315,8 +317,12 @@ __global__ __launch_bounds__(256) void k_fused(const uint8_t* __restrict__ reads
                                                     fast && unit_groups(kn) > 0, nxt, lane);
                 const int64_t i = k / upt;
                 const int u = (int)(k - i * upt);
+                // every unit of tile i >= 2 waits for the sweep of the buffer's previous tile, also one
+                // without groups (past the batch's last group): it still counts toward the buffer's done
+                // count, and counted early it could complete tile i - 2's target before that tile is
+                // encoded (a CPU model of this schedule finds such interleavings)
+                if (i >= 2) wait_at_least(ctr + kCtrSwept, (uint32_t)(i - 1), err);
                 if (unit_groups(k) > 0) {
-                    if (i >= 2) wait_at_least(ctr + kCtrSwept, (uint32_t)(i - 1), err);
                     tile::encode_groups<tile::kWaveQ, 64>(reads, refs, nullptr, nullptr, n_pairs, m, unit_g0(k), U,
                                                           fast, cur, stage, buffer(i), 1, u * U, bad, GS,
                                                           tile::WaveSync(), lane);

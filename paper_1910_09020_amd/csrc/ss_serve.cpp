@@ -94,6 +94,9 @@ struct Request {
     int32_t* edits_out = nullptr;
     size_t footprint = 0;
     int64_t t_submit = 0, t_admit = 0, t_done = 0;
+    // stages: host time to enqueue the request's work, and the device spans between the slot's
+    // timing events (copy in, encode + filter, copy out), in nanoseconds
+    int64_t ns_enqueue = 0, ns_h2d = 0, ns_compute = 0, ns_d2h = 0;
     int status = SS_OK;
     State state = QUEUED;
     int slot = -1;
@@ -102,6 +105,8 @@ struct Request {
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};   // timing: before the copy in, after it,
+                                                               // after the kernel, after the copy out
     void* arena = nullptr;           // the running request's device memory (stream-ordered)
     size_t arena_cap = 0;
     void* pinned = nullptr;
@@ -212,6 +217,7 @@ int launch_request(ss_server* S, Slot& sl, Request* r)
         std::memcpy(h, r->page.data(), L.in_bytes);
     }
     r->stage = h;
+    const int64_t t0 = now_ns();
     hipStream_t s = sl.stream;
     void* arena = nullptr;
     hipError_t e = hipMallocAsync(&arena, r->footprint, s);
@@ -219,8 +225,10 @@ int launch_request(ss_server* S, Slot& sl, Request* r)
     sl.arena = arena;
     sl.arena_cap = r->footprint;
     uint8_t* d = (uint8_t*)arena;
-    e = hipMemcpyAsync(d, h, L.in_bytes, hipMemcpyHostToDevice, s);
+    e = hipEventRecord(sl.ev[0], s);
+    if (e == hipSuccess) e = hipMemcpyAsync(d, h, L.in_bytes, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemsetAsync(d + L.err, 0, 4, s);
+    if (e == hipSuccess) e = hipEventRecord(sl.ev[1], s);
     if (e == hipSuccess)
         e = launch_pack_stream(d + L.reads, d + L.refs, r->total, (uint32_t*)(d + L.packed), (uint32_t*)(d + L.err), s);
     if (e == hipSuccess) {
@@ -231,16 +239,19 @@ int launch_request(ss_server* S, Slot& sl, Request* r)
                            (const int64_t*)(d + L.offsets), (const int32_t*)(d + L.lengths),
                            (const int32_t*)(d + L.E), (uint16_t*)(d + L.results), s);
     }
+    if (e == hipSuccess) e = hipEventRecord(sl.ev[2], s);
     const size_t hres = L.in_bytes, herr = L.in_bytes + al((size_t)r->n * 2);
     if (e == hipSuccess && r->n)
         e = hipMemcpyAsync(h + hres, d + L.results, (size_t)r->n * 2, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipMemcpyAsync(h + herr, d + L.err, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipEventRecord(sl.ev[3], s);
     // the memory returns to the pool once the stream has passed this point
     const hipError_t ef = hipFreeAsync(arena, s);
     if (e == hipSuccess) e = ef;
     sl.arena = nullptr;
     sl.arena_cap = 0;
     if (e == hipSuccess) e = hipEventRecord(sl.done, s);
+    r->ns_enqueue = now_ns() - t0;
     return map_err(e);
 }
 
@@ -336,6 +347,12 @@ void completer_main(ss_server* S)
             Request* r = sl.cur;
             int status = map_err(q);
             if (status == SS_OK) {
+                float ms[3] = {0.f, 0.f, 0.f};
+                for (int k = 0; k < 3; k++)
+                    if (hipEventElapsedTime(&ms[k], sl.ev[k], sl.ev[k + 1]) != hipSuccess) ms[k] = 0.f;
+                r->ns_h2d = (int64_t)(1e6 * ms[0]);
+                r->ns_compute = (int64_t)(1e6 * ms[1]);
+                r->ns_d2h = (int64_t)(1e6 * ms[2]);
                 const Layout L(r->n, r->total, r->n_items);
                 const uint8_t* h = r->stage;
                 const uint16_t* res = (const uint16_t*)(h + L.in_bytes);
@@ -393,9 +410,12 @@ extern "C" int ss_server_create(ss_ctx* ctx, size_t hbm_budget_bytes, int32_t n_
     for (auto& sl : S->slots) {
         hipError_t e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+        for (int k = 0; k < 4 && e == hipSuccess; k++) e = hipEventCreate(&sl.ev[k]);
         if (e != hipSuccess) {
             for (auto& o : S->slots) {
                 if (o.done) (void)hipEventDestroy(o.done);
+                for (hipEvent_t x : o.ev)
+                    if (x) (void)hipEventDestroy(x);
                 if (o.stream) (void)hipStreamDestroy(o.stream);
             }
             delete S;
@@ -530,6 +550,21 @@ extern "C" int ss_server_times(ss_server* S, ss_ticket t, int64_t* submit_ns, in
     return SS_OK;
 }
 
+extern "C" int ss_server_stages(ss_server* S, ss_ticket t, int64_t* enqueue_ns, int64_t* h2d_ns, int64_t* compute_ns,
+                                int64_t* d2h_ns)
+{
+    if (!S) return SS_EINVAL;
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->reqs.find(t);
+    if (it == S->reqs.end()) return SS_EINVAL;
+    const Request* r = it->second;
+    if (enqueue_ns) *enqueue_ns = r->ns_enqueue;
+    if (h2d_ns) *h2d_ns = r->ns_h2d;
+    if (compute_ns) *compute_ns = r->ns_compute;
+    if (d2h_ns) *d2h_ns = r->ns_d2h;
+    return SS_OK;
+}
+
 extern "C" int ss_server_cancel(ss_server* S, ss_ticket t)
 {
     if (!S) return SS_EINVAL;
@@ -613,6 +648,8 @@ extern "C" int ss_server_destroy(ss_server* S)
         if (sl.stream) (void)hipStreamSynchronize(sl.stream);
         if (sl.pinned) (void)hipHostFree(sl.pinned);
         if (sl.done) (void)hipEventDestroy(sl.done);
+        for (hipEvent_t x : sl.ev)
+            if (x) (void)hipEventDestroy(x);
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
     }
     for (auto& kv : S->reqs) delete kv.second;

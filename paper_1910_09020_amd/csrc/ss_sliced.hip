@@ -154,7 +154,18 @@ hipError_t launch_sliced(const uint32_t* packed, int64_t n_pairs, int32_t m, int
 // whose U groups fit its loads), else U = 0 and GB groups staged at a time by
 // the three together.  Returns the LDS bytes per block, or 0 when no shape
 // fits.
-size_t fused_shape(int32_t m, int tile_groups, bool contiguous, int* T_out, int* GB_out, int* U_out)
+int fused_tile_cap(int64_t n_pairs)
+{
+    // the automatic tile leaves no CU without a tile: at most G / CUs groups per tile
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                                hipSuccess || cus <= 0)
+        return 256;
+    const int64_t G = cdiv(n_pairs, 32);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(256, G / cus));
+}
+
+size_t fused_shape(int32_t m, int tile_groups, bool contiguous, int* T_out, int* GB_out, int* U_out, int max_t)
 {
     const int64_t stage_b = (int64_t)tile::stage_dwords(m) * 4;
     const int64_t buf_b = 16ll * tile::fused_group_chunks(m);   // one group in one tile buffer
@@ -165,7 +176,7 @@ size_t fused_shape(int32_t m, int tile_groups, bool contiguous, int* T_out, int*
             return (tile_groups % step == 0 && lds_for(tile_groups) <= kMaxFusedLds) ? tile_groups : 0;
         for (int blocks = 2; blocks >= 1; blocks--) {
             int T = 0;
-            for (int t = step; t <= 256; t += step)
+            for (int t = step; t <= std::min(256, std::max(max_t, step)); t += step)
                 if ((t < 16 || t % 16 == 0) && blocks * lds_for(t) <= kMaxFusedLds) T = t;
             if (T > 0) return T;
         }
@@ -207,7 +218,7 @@ hipError_t launch_fused(const uint8_t* reads, const uint8_t* refs, int64_t n_pai
     if (E < 0 || E > kMaxEFused) return hipErrorInvalidValue;
     const bool contiguous = (((uintptr_t)reads | (uintptr_t)refs) & 15u) == 0;
     int T = 0, GB = 0, U = 0;
-    const size_t shmem = fused_shape(m, tile_groups, contiguous, &T, &GB, &U);
+    const size_t shmem = fused_shape(m, tile_groups, contiguous, &T, &GB, &U, fused_tile_cap(n_pairs));
     if (shmem == 0) return hipErrorInvalidValue;
     const int fast = U > 0 ? tile::fast_mode(m, U, true, tile::kWaveQ, 64)
                            : tile::fast_mode(m, GB, contiguous, tile::kFusedQ, tile::kFusedThreads);
