@@ -211,6 +211,25 @@ int ss_filter_ascii_async(ss_ctx* ctx, const uint8_t* reads, const uint8_t* refs
                           int32_t E, int32_t tile_groups, uint16_t* out, uint32_t* err, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Without allocation: for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid it).
+ *
+ * ss_filter_ascii_noalloc is ss_filter_ascii_async with the automatic tile
+ * (same arguments, same results, same limits: m <= SS_MAX_LEN_FUSED and
+ * E <= SS_MAX_E_SLICED, else SS_ELEN) that calls no hipMalloc, hipFree or
+ * allocating routine.  Where ss_filter_ascii_async would encode a chunk into a
+ * buffer the context allocates, this one uses a scratch array of
+ * SS_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it runs on
+ * until the process ends (looked up by ss_create), processing the batch in
+ * chunks that fit it; the fused schedule needs no scratch.  Every call on one
+ * GPU shares that array, so calls that overlap on one GPU (several streams,
+ * several threads) race and must be ordered by the caller.  The context gives
+ * the device; no buffer of the context is used.  Asynchronous on stream. */
+#define SS_NOALLOC_SCRATCH_BYTES (32LL << 20)
+int ss_filter_ascii_noalloc(ss_ctx* ctx, const uint8_t* reads, const uint8_t* refs, int64_t n_pairs, int32_t m,
+                            int32_t E, uint16_t* out, uint32_t* err, void* stream);
+
+/* ------------------------------------------------------------------------
  * Bit-stream layout (any lengths).
  *
  * Four planes (Q0, Q1, R0, R1), each a little-endian stream of total_bases

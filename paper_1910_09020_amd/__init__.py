@@ -29,6 +29,7 @@ SS_MAX_LEN = 1 << 24
 SS_MAX_LEN_FUSED = 2048
 SS_MAX_LEN_VERIFY = 256
 SS_MAX_STREAM_BASES = 32 * ((1 << 30) - 64)
+SS_NOALLOC_SCRATCH_BYTES = 32 << 20
 SS_RESULT_ACCEPT = 0x8000
 SS_RESULT_COUNT = 0x7FFF
 SS_INPUT_ASCII, SS_INPUT_PACKED, SS_INPUT_PACKED_SLICED = 0x0, 0x1, 0x2
@@ -107,6 +108,7 @@ def lib():
         "ss_pack": ([vp, vp, i64, vp, vp, vp], ctypes.c_int),
         "ss_filter_batch_ex": ([vp, ctypes.POINTER(BatchDesc), vp], ctypes.c_int),
         "ss_filter_batch_pairs": ([vp, vp, vp, vp, i64, vp, i32, vp, vp], ctypes.c_int),
+        "ss_filter_ascii_noalloc": ([vp, vp, vp, i64, i32, i32, vp, vp, vp], ctypes.c_int),
         "ss_server_stages": ([vp, ctypes.c_uint64, vp, vp, vp, vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
@@ -128,7 +130,8 @@ def exported_symbols():
             "ss_plan_launch", "ss_plan_create_tuned", "ss_server_create", "ss_server_submit", "ss_server_poll",
             "ss_server_wait", "ss_server_times", "ss_server_cancel", "ss_server_release", "ss_server_set_hold",
             "ss_server_stats", "ss_server_destroy", "ss_server_footprint", "ss_server_set_slices", "ss_pack_words",
-            "ss_pack", "ss_filter_batch_ex", "ss_filter_batch_pairs", "ss_server_stages"]
+            "ss_pack", "ss_filter_batch_ex", "ss_filter_batch_pairs", "ss_filter_ascii_noalloc",
+            "ss_server_stages"]
 
 
 def status_str(status: int) -> str:
@@ -262,6 +265,11 @@ def batch_desc(reads, refs, n_pairs, E, flags, out, err=None, offsets=None, leng
 
 def ss_filter_batch_ex(ctx, desc: BatchDesc, stream=None):
     _check(lib().ss_filter_batch_ex(ctx, ctypes.byref(desc), _stream(stream)), "ss_filter_batch_ex")
+
+
+def ss_filter_ascii_noalloc(ctx, reads, refs, n_pairs, m, E, out, err, stream=None):
+    _check(lib().ss_filter_ascii_noalloc(ctx, _ptr(reads), _ptr(refs), int(n_pairs), int(m), int(E), _ptr(out),
+                                         _ptr(err), _stream(stream)), "ss_filter_ascii_noalloc")
 
 
 def ss_filter_submaze_async(ctx, packed, n_pairs, m, E, sub_width, out, stream=None):

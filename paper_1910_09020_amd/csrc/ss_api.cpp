@@ -65,10 +65,13 @@ extern "C" int ss_create(ss_ctx** out, int hip_device)
     (void)hipGetDevice(&prev);
     hipError_t e = hipSetDevice(hip_device);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    // with the device current: the address of the no-allocation entry point's scratch on it
+    const int rc = e == hipSuccess ? ss_noalloc_init_device(hip_device) : SS_OK;
     (void)hipSetDevice(prev);
-    if (e != hipSuccess) {
+    if (e != hipSuccess || rc != SS_OK) {
+        if (c->stream) (void)hipStreamDestroy(c->stream);
         delete c;
-        return map_err(e);
+        return e != hipSuccess ? map_err(e) : rc;
     }
     *out = c;
     return SS_OK;

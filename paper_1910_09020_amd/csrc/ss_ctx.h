@@ -42,3 +42,7 @@ struct ss_ctx {
 // The process-wide context of the current HIP device (created on first use),
 // used by the one-call host entry points.
 int ss_default_ctx(ss_ctx** out);
+
+// Called by ss_create with hip_device current: looks up the device address of
+// the no-allocation entry point's scratch array on that device (ss_noalloc.hip).
+int ss_noalloc_init_device(int dev);
