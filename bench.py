@@ -360,20 +360,32 @@ def mixed_leg(a, torch, ss, gen, runner, oracle):
     return res
 
 
-def serving_leg(a, ss, gen, runner, oracle):
+def serving_leg(a, ss, gen, runner, oracle, mode=None, seconds=None):
     """Continuous batching: Poisson arrivals, requests of 1..4096 pairs of 100..10,000 bp (log-uniform)
     with one threshold rate per request, generated by native worker threads just ahead of their arrival
     and submitted at their scheduled times to one server; latency = completion - scheduled arrival."""
     import ctypes
     seed = 1910090204
-    arr = gen.arrivals(seed, a.serve_rate, a.serve_seconds)
+    mode = mode or a.serve_mode
+    seconds = seconds or a.serve_seconds
+    arr = gen.arrivals(seed, a.serve_rate, seconds)
     nreq = len(arr)
     ctx = runner.context()
-    srv = ss.ss_server_create(ctx, 32 << 30, a.serve_slots)
-    ss.ss_server_set_slices(srv, a.serve_slices)
+    if mode == "loop":
+        # device-resident loop: one persistent kernel, requests handed over through host memory
+        budget = 4 << 30
+        srv = ss.ss_server_create_loop(ctx, budget, a.serve_loop_slots, a.serve_slices)
+    else:
+        budget = 32 << 30
+        srv = ss.ss_server_create(ctx, budget, a.serve_slots)
+        ss.ss_server_set_slices(srv, a.serve_slices)
     submit_ptr = ctypes.cast(ss.lib().ss_server_submit, ctypes.c_void_p).value
     pool = min(nreq, a.serve_pool)
-    D = gen.drive(seed, arr, submit_ptr, srv, threads=min(16, max(4, os.cpu_count() or 1)), pool=pool)
+    # on the fly: generator threads run up to 2,048 requests ahead of the clock (a head start of as many
+    # before it starts), and 8 submitter threads hand each request over at its due time
+    # (12 generator threads leave the server's threads cores of their own on a 16-core host share)
+    D = gen.drive(seed, arr, submit_ptr, srv, threads=12 if pool == 0 else min(16, max(4, os.cpu_count() or 1)),
+                  pool=pool)
     assert D.submitted == nreq, f"submission failed: {D.submitted}"
     for t in D.tickets:
         rc = ss.ss_server_wait(srv, int(t), -1)
@@ -422,18 +434,21 @@ def serving_leg(a, ss, gen, runner, oracle):
         mism += int(np.sum((w["accept"] != acc) | (w["edits"] != ed)))
     D.free()
     ss.ss_server_destroy(srv)
-    res = dict(arrival_rate=a.serve_rate, seconds=a.serve_seconds, requests=nreq, pairs=pairs, bases=bases,
+    res = dict(mode=("device-resident loop (one persistent kernel)" if mode == "loop" else
+                     "host dispatcher (kernels and copies on slot streams)"),
+               arrival_rate=a.serve_rate, seconds=seconds, requests=nreq, pairs=pairs, bases=bases,
                pairs_per_s=pairs / span, p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
                max_ms=float(lat.max()), service_p50_ms=pct(svc, 50), service_p99_ms=pct(svc, 99),
                queue_p50_ms=pct(wait, 50), queue_p99_ms=pct(wait, 99), submit_lag_p50_ms=pct(lag, 50),
-               submit_lag_p99_ms=pct(lag, 99), slots=a.serve_slots, hbm_budget_bytes=32 << 30, stats=st,
+               submit_lag_p99_ms=pct(lag, 99), slots=a.serve_loop_slots if mode == "loop" else a.serve_slots,
+               hbm_budget_bytes=budget, stats=st,
                hw_queues=os.environ.get("GPU_MAX_HW_QUEUES", "HIP default"), distinct_requests=pool or nreq,
                breakdown=breakdown,
-               generation=("every request generated from its own seed just ahead of its arrival" if not pool else
+               generation=("every request generated from its own seed, up to 2,048 ahead of the clock" if not pool else
                            f"{pool} requests generated before the clock, replayed in a cycle"),
                slices_per_lane=a.serve_slices,
                oracle_checked_requests=int(len(chk)), oracle_mismatches=mism)
-    log(f"serving: {nreq} requests, {pairs} pairs in {span:.2f}s, p50 {res['p50_ms']:.3f} ms, "
+    log(f"serving ({mode}): {nreq} requests, {pairs} pairs in {span:.2f}s, p50 {res['p50_ms']:.3f} ms, "
         f"p99 {res['p99_ms']:.3f} ms, service p50/p99 {res['service_p50_ms']:.3f}/{res['service_p99_ms']:.3f} ms, "
         f"tail breakdown {breakdown['p99_tail_mean_ms']}, "
         f"queue p50/p99 {res['queue_p50_ms']:.3f}/{res['queue_p99_ms']:.3f} ms, submit lag p50/p99 "
@@ -508,12 +523,14 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=60.0, help="serving schedule length (60 s in full)")
     ap.add_argument("--serve-rate", type=float, default=2000.0, help="Poisson arrival rate, requests/s")
-    ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-slots", type=int, default=8, help="slot streams of the host-dispatch server")
+    ap.add_argument("--serve-loop-slots", type=int, default=64, help="request slots of the device-resident loop")
+    ap.add_argument("--serve-mode", choices=["loop", "host"], default="loop",
+                    help="serving leg: device-resident loop (default) or host dispatcher")
     ap.add_argument("--serve-slices", type=int, default=1, help="32-row slices per lane for served requests")
-    ap.add_argument("--serve-pool", type=int, default=4000,
-                    help="distinct requests generated before the clock starts and replayed in a cycle (0: every "
-                         "request generated from its own seed just ahead of its arrival, which the host's "
-                         "generator threads cannot sustain at 2,000 requests/s)")
+    ap.add_argument("--serve-pool", type=int, default=0,
+                    help="0 (default): every request generated from its own seed, ahead of its arrival; N > 0: "
+                         "N distinct requests generated before the clock starts and replayed in a cycle")
     ap.add_argument("--serve-only", action="store_true", help="run only the serving leg (diagnostics)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-sclk", action="store_true")
@@ -662,9 +679,12 @@ def main():
     if not a.no_mixed:
         mixed = mixed_leg(a, torch, ss, gen, runner, oracle)
 
-    serving = None
+    serving = serving_host = None
     if not a.no_serve:
         serving = serving_leg(a, ss, gen, runner, oracle)
+        if a.serve_mode == "loop":
+            # the host-dispatch server on the same schedule's first seconds, for comparison
+            serving_host = serving_leg(a, ss, gen, runner, oracle, mode="host", seconds=min(15.0, a.serve_seconds))
 
     latency = None
     if not a.no_sweep:
@@ -743,6 +763,7 @@ def main():
         "long_100kbp": long_pairs,
         "mixed": mixed,
         "serving": serving,
+        "serving_host_dispatch": serving_host,
     }
     print(json.dumps(line), flush=True)
     if full_mism:

@@ -458,6 +458,35 @@ int ss_server_create(ss_ctx* ctx, size_t hbm_budget_bytes, int32_t n_slots, ss_s
  * share of the budget); -1 for negative arguments. */
 int64_t ss_server_footprint(int64_t n_pairs, int64_t total_bases);
 
+/* The same server with a device-resident request loop (not part of the
+ * paper): one persistent kernel serves every request.  An admitted request is
+ * handed over by writing its descriptor into one of n_slots (at most 64)
+ * slots of a control block in coherent pinned host memory; no HIP call is
+ * made per request.  The kernel's scheduling wavefront activates published
+ * requests; its other blocks encode each request's ASCII straight from its
+ * staging block (coherent pinned host memory) into bit planes and sweep the
+ * request's plan (the batched launch's items), oldest admission first, writing
+ * the result words into the staging block; the block that finishes a
+ * request's last item marks the slot done, and the completion thread polls
+ * those marks.  The kernel ends after 200 ms with nothing to do and is launched
+ * again when a request arrives; while it runs it holds every CU it fits on.
+ * Device memory: hbm_budget_bytes are reserved at creation as one arena; a
+ * request takes the room of its four bit planes, 16 * (ceil(total_bases / 32)
+ * + 2) bytes rounded up to 256, from it, and admission waits while the arena
+ * has no such room.  slices_per_lane (1, 2, 4 or 8) is fixed: a request with
+ * a threshold that needs wider slices is refused (SS_ELEN), as is one whose
+ * plan has more than 2^24 - 1 items or encoding units.  Every other call
+ * below works on either kind of server, except ss_server_set_slices
+ * (SS_EINVAL here); ss_server_stages reports no enqueue stream events here:
+ * h2d_ns is the device time from activation to the end of encoding (reading
+ * the ASCII over the host link), compute_ns the rest up to the last item,
+ * d2h_ns 0 (results are written in place).  If the kernel cannot be launched
+ * or reports that no unit finished for 2 s with requests active, requests in
+ * flight fail with SS_EDEVICE and later submissions are refused with
+ * SS_EDEVICE. */
+int ss_server_create_loop(ss_ctx* ctx, size_t hbm_budget_bytes, int32_t n_slots, int32_t slices_per_lane,
+                          ss_server** out);
+
 /* Submit one request (host arrays, copied before returning; E_per_pair is
  * required).  accept_out / edits_out (host, n_pairs entries) are written by
  * the server before the ticket reports done, and must stay valid until then.

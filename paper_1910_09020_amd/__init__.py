@@ -93,6 +93,7 @@ def lib():
         "ss_plan_create_tuned": ([vp, vp, vp, i64, vp, i64, vp, vp, vp, vp, ctypes.c_char_p, ctypes.POINTER(vp),
                                   vp], ctypes.c_int),
         "ss_server_create": ([vp, ctypes.c_size_t, i32, ctypes.POINTER(vp)], ctypes.c_int),
+        "ss_server_create_loop": ([vp, ctypes.c_size_t, i32, i32, ctypes.POINTER(vp)], ctypes.c_int),
         "ss_server_submit": ([vp, vp, vp, vp, vp, i64, vp, vp, ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
         "ss_server_poll": ([vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
         "ss_server_wait": ([vp, ctypes.c_uint64, i64], ctypes.c_int),
@@ -131,7 +132,7 @@ def exported_symbols():
             "ss_server_wait", "ss_server_times", "ss_server_cancel", "ss_server_release", "ss_server_set_hold",
             "ss_server_stats", "ss_server_destroy", "ss_server_footprint", "ss_server_set_slices", "ss_pack_words",
             "ss_pack", "ss_filter_batch_ex", "ss_filter_batch_pairs", "ss_filter_ascii_noalloc",
-            "ss_server_stages"]
+            "ss_server_stages", "ss_server_create_loop"]
 
 
 def status_str(status: int) -> str:
@@ -379,6 +380,14 @@ def ss_plan_create_tuned(ctx, lengths, E_per_pair, packed, total_bases, offsets_
 def ss_server_create(ctx, hbm_budget_bytes: int, n_slots: int = 8) -> int:
     h = ctypes.c_void_p()
     _check(lib().ss_server_create(ctx, int(hbm_budget_bytes), int(n_slots), ctypes.byref(h)), "ss_server_create")
+    return h.value
+
+
+def ss_server_create_loop(ctx, hbm_budget_bytes: int, n_slots: int = 32, slices_per_lane: int = 1) -> int:
+    """A server whose requests are run by one device-resident loop kernel (see ss.h)."""
+    h = ctypes.c_void_p()
+    _check(lib().ss_server_create_loop(ctx, int(hbm_budget_bytes), int(n_slots), int(slices_per_lane),
+                                       ctypes.byref(h)), "ss_server_create_loop")
     return h.value
 
 

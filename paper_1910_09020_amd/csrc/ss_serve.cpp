@@ -15,6 +15,18 @@
 // that arrive while others are running are admitted as soon as a slot and
 // memory are free.  A completion thread polls the slots' events, writes the
 // results to the caller's arrays and timestamps the completion.
+//
+// Device-resident mode (ss_server_create_loop): the same queue and admission,
+// but an admitted request is handed to the persistent loop kernel of
+// ss_loop.hip instead of being enqueued on a stream: the dispatcher writes its
+// descriptor into a slot of a control block in coherent host memory and
+// publishes it, the kernel encodes the request's ASCII straight from the
+// staging block and sweeps its plan, writes the result words into the staging
+// block and marks the slot finished, and the completion thread polls those
+// marks.  No HIP call is made per request; the kernel is launched again when
+// it has ended after an idle period and a request is waiting.  Its device
+// memory is one arena of the budget's size, reserved at creation, from which
+// each request takes the room of its bit planes.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -23,6 +35,7 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <map>
 #include <mutex>
 #include <new>
 #include <thread>
@@ -31,6 +44,7 @@
 
 #include "ss.h"
 #include "ss_common.h"
+#include "ss_loop.h"
 
 using namespace ss;
 
@@ -93,6 +107,8 @@ struct Request {
     uint8_t* accept_out = nullptr;
     int32_t* edits_out = nullptr;
     size_t footprint = 0;
+    size_t arena_off = 0;          // device-resident mode: offset of the request's planes in the arena
+    uint64_t gen = 0;              // device-resident mode: the generation it was published under
     int64_t t_submit = 0, t_admit = 0, t_done = 0;
     // stages: host time to enqueue the request's work, and the device spans between the slot's
     // timing events (copy in, encode + filter, copy out), in nanoseconds
@@ -123,6 +139,7 @@ struct PinnedPool {
     std::unordered_map<size_t, std::vector<void*>> free_blocks;
     size_t total = 0;
     size_t cap = (size_t)4 << 30;
+    unsigned flags = hipHostMallocDefault;     // coherent in device-resident mode (the kernel reads it)
     void* get(size_t need, size_t* cls)
     {
         size_t c = (size_t)1 << 20;
@@ -140,7 +157,7 @@ struct PinnedPool {
             total += c;
         }
         void* p = nullptr;
-        if (hipHostMalloc(&p, c, hipHostMallocDefault) != hipSuccess) {
+        if (hipHostMalloc(&p, c, flags) != hipSuccess) {
             std::lock_guard<std::mutex> lk(mu);
             total -= c;
             return nullptr;
@@ -163,6 +180,44 @@ struct PinnedPool {
     }
 };
 
+// First-fit allocator over the device-resident mode's arena (offsets, 256-byte units).
+struct Arena {
+    std::map<size_t, size_t> free_ranges;      // offset -> bytes
+    void reset(size_t bytes)
+    {
+        free_ranges.clear();
+        if (bytes) free_ranges[0] = bytes;
+    }
+    bool alloc(size_t bytes, size_t* off)
+    {
+        for (auto it = free_ranges.begin(); it != free_ranges.end(); ++it) {
+            if (it->second < bytes) continue;
+            *off = it->first;
+            const size_t left = it->second - bytes, at = it->first + bytes;
+            free_ranges.erase(it);
+            if (left) free_ranges[at] = left;
+            return true;
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes)
+    {
+        auto it = free_ranges.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_ranges.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_ranges.erase(nx);
+        }
+        if (it != free_ranges.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_ranges.erase(it);
+            }
+        }
+    }
+};
+
 struct ss_server {
     ss_ctx* ctx = nullptr;
     PinnedPool pool;
@@ -180,9 +235,29 @@ struct ss_server {
     std::thread dispatcher, completer;
     bool stop = false;
     bool hold = false;
+    bool broken = false;             // device-resident mode: the loop kernel could not run; submissions fail
     int running = 0;
     // statistics
     int64_t admitted = 0, deferred = 0, completed = 0, peak_used = 0, peak_running = 0;
+    // device-resident mode
+    bool loop = false;
+    int loop_rs = 1;                 // slice width the loop kernel is built for
+    int loop_grid = 0;
+    size_t loop_lds_pad = 0;
+    loop::Host* H = nullptr;         // control block (coherent host memory)
+    loop::Host* H_dev = nullptr;     // the same as the kernel addresses it
+    loop::Dev* D = nullptr;          // device-side slot table
+    uint8_t* arena = nullptr;
+    Arena arena_alloc;               // guarded by mu
+    uint64_t gen[loop::kSlots] = {};
+    std::mutex loop_mu;              // guards the kernel's launch state
+    hipStream_t loop_stream = nullptr;
+    hipEvent_t loop_ev = nullptr;
+    bool loop_launched = false;
+    uint32_t epoch = 0;
+    uint64_t idle_ticks = 0;
+    double tick_ns = 10.0;
+    int64_t loop_launches = 0;
 };
 
 namespace {
@@ -195,6 +270,79 @@ size_t footprint_of(int64_t n, int64_t T)
 
 // Bytes of a request's staging: the device layout's inputs, results, error word.
 size_t stage_bytes(const Layout& L, int64_t n) { return L.in_bytes + al((size_t)n * 2) + 256; }
+
+// Device-resident mode: a request's device memory is its four bit planes.
+size_t loop_footprint(int64_t T) { return al((size_t)(cdiv(T, 32) + 2) * 16); }
+
+// Device-resident mode: make sure a loop kernel is running (launch one when the
+// last has ended).  Returns SS_EDEVICE when the last launch failed.
+int ensure_loop(ss_server* S)
+{
+    std::lock_guard<std::mutex> lk(S->loop_mu);
+    if (S->loop_launched) {
+        const hipError_t q = hipEventQuery(S->loop_ev);
+        if (q == hipErrorNotReady) return SS_OK;
+        S->loop_launched = false;
+        if (q != hipSuccess) return map_err(q);
+    }
+    if (__atomic_load_n(&S->H->stalled, __ATOMIC_ACQUIRE) != 0) return SS_EDEVICE;
+    S->epoch++;
+    hipError_t e = loop::launch_loop(S->loop_rs, S->loop_grid, S->loop_lds_pad, S->H_dev, S->D, S->epoch,
+                                     S->idle_ticks, S->loop_stream);
+    if (e == hipSuccess) e = hipEventRecord(S->loop_ev, S->loop_stream);
+    if (e != hipSuccess) return map_err(e);
+    S->loop_launched = true;
+    S->loop_launches++;
+    return SS_OK;
+}
+
+// Device-resident mode: publish the request in its slot.  Called without the lock.
+int launch_request_loop(ss_server* S, Slot& sl, int si, Request* r)
+{
+    const Layout L(r->n, r->total, r->n_items);
+    uint8_t* h = (uint8_t*)r->pin;
+    if (!h) {
+        const size_t need = stage_bytes(L, r->n);
+        if (sl.pinned_cap < need) {
+            if (sl.pinned) (void)hipHostFree(sl.pinned);
+            sl.pinned = nullptr;
+            sl.pinned_cap = 0;
+            const size_t want = std::max(need, (size_t)1 << 20);
+            hipError_t e = hipHostMalloc(&sl.pinned, want, hipHostMallocCoherent | hipHostMallocMapped);
+            if (e != hipSuccess) return map_err(e);
+            sl.pinned_cap = want;
+        }
+        h = (uint8_t*)sl.pinned;
+        std::memcpy(h, r->page.data(), L.in_bytes);
+    }
+    r->stage = h;
+    const int64_t t0 = now_ns();
+    uint8_t* hd = nullptr;
+    hipError_t e = hipHostGetDevicePointer((void**)&hd, h, 0);
+    if (e != hipSuccess) return map_err(e);
+    loop::Desc& d = S->H->desc[si];
+    d.reads = hd + L.reads;
+    d.refs = hd + L.refs;
+    d.offsets = (const int64_t*)(hd + L.offsets);
+    d.lengths = (const int32_t*)(hd + L.lengths);
+    d.E = (const int32_t*)(hd + L.E);
+    d.items = (const PItem*)(hd + L.items);
+    d.perm = (const int64_t*)(hd + L.perm);
+    d.results = (uint16_t*)(hd + L.in_bytes);
+    d.packed = (uint32_t*)(S->arena + r->arena_off);
+    d.total = r->total;
+    d.SW = cdiv(r->total, 32) + 2;
+    d.n_items = (int32_t)r->n_items;
+    d.n_pack = (int32_t)cdiv(d.SW, loop::kPackWords);
+    d.aligned = ((((uintptr_t)d.reads) | ((uintptr_t)d.refs)) & 15u) == 0;
+    d.pad = 0;
+    r->gen = ++S->gen[si];
+    // the descriptor is complete before the publication word changes
+    __atomic_store_n(&S->H->pub[si], r->gen, __ATOMIC_RELEASE);
+    const int rc = ensure_loop(S);
+    r->ns_enqueue = now_ns() - t0;
+    return rc;
+}
 
 // Enqueue the whole request on its slot's stream.  Called without the lock.
 int launch_request(ss_server* S, Slot& sl, Request* r)
@@ -262,6 +410,7 @@ int admit_slot(ss_server* S, Request* r)
     if (S->used + r->footprint > S->budget) return -1;
     for (int i = 0; i < (int)S->slots.size(); i++) {
         if (S->slots[(size_t)i].cur) continue;
+        if (S->loop && !S->arena_alloc.alloc(r->footprint, &r->arena_off)) return -1;
         S->used += r->footprint;
         S->peak_used = std::max<int64_t>(S->peak_used, (int64_t)S->used);
         return i;
@@ -272,7 +421,10 @@ int admit_slot(ss_server* S, Request* r)
 void finish(ss_server* S, Request* r, int status)
 {
     // lock held
-    if (r->state == RUNNING) S->used -= r->footprint;
+    if (r->state == RUNNING) {
+        S->used -= r->footprint;
+        if (S->loop) S->arena_alloc.release(r->arena_off, r->footprint);
+    }
     r->status = status;
     r->state = DONE;
     r->t_done = now_ns();
@@ -309,11 +461,15 @@ void dispatcher_main(ss_server* S)
         S->running++;
         S->peak_running = std::max<int64_t>(S->peak_running, S->running);
         lk.unlock();
-        const int rc = launch_request(S, sl, r);
+        const int rc = S->loop ? launch_request_loop(S, sl, si, r) : launch_request(S, sl, r);
         lk.lock();
-        if (rc != SS_OK) {
+        if (rc != SS_OK && S->loop && r->gen != 0) {
+            // published, but the kernel could not be launched: the completion thread retries the
+            // launch and fails the request if the device has failed
+            sl.launched = true;
+        } else if (rc != SS_OK) {
             // the stream may hold part of the work: wait for it before reusing the slot
-            (void)hipStreamSynchronize(sl.stream);
+            if (!S->loop) (void)hipStreamSynchronize(sl.stream);
             sl.cur = nullptr;
             S->running--;
             finish(S, r, rc);
@@ -340,8 +496,56 @@ void completer_main(ss_server* S)
             }
         }
         bool any = false;
+        if (S->loop) {
+            // a request may wait for a launch (the last kernel ended idle just before it was published)
+            const int rc = ensure_loop(S);
+            if (rc != SS_OK) {
+                std::lock_guard<std::mutex> lk(S->mu);
+                for (int i : busy) {
+                    Slot& sl = S->slots[(size_t)i];
+                    Request* r = sl.cur;
+                    // the staging block stays with the request: a kernel may still write into it
+                    r->pin = nullptr;
+                    sl.cur = nullptr;
+                    sl.launched = false;
+                    S->running--;
+                    finish(S, r, rc);
+                }
+                S->broken = true;
+                S->cv_work.notify_all();
+                continue;
+            }
+        }
         for (int i : busy) {
             Slot& sl = S->slots[(size_t)i];
+            if (S->loop) {
+                Request* r = sl.cur;
+                if (__atomic_load_n(&S->H->fin[i], __ATOMIC_ACQUIRE) != r->gen) continue;
+                const uint64_t ta = S->H->t_act[i], tp = S->H->t_packed[i], td = S->H->t_done[i];
+                const bool ordered = ta <= tp && tp <= td;
+                r->ns_h2d = ordered ? (int64_t)(S->tick_ns * (double)(tp - ta)) : 0;
+                r->ns_compute = (int64_t)(S->tick_ns * (double)(td - (ordered ? tp : ta)));
+                r->ns_d2h = 0;
+                const Layout L(r->n, r->total, r->n_items);
+                const uint16_t* res = (const uint16_t*)(r->stage + L.in_bytes);
+                int status = SS_OK;
+                if (S->H->err[i]) {
+                    status = SS_EBASE;                 // outputs untouched
+                } else {
+                    for (int64_t k = 0; k < r->n; k++) {
+                        r->accept_out[k] = (uint8_t)(res[k] >> 15);
+                        r->edits_out[k] = (int32_t)(res[k] & SS_RESULT_COUNT);
+                    }
+                }
+                std::lock_guard<std::mutex> lk(S->mu);
+                sl.cur = nullptr;
+                sl.launched = false;
+                S->running--;
+                finish(S, r, status);
+                S->cv_work.notify_all();
+                any = true;
+                continue;
+            }
             const hipError_t q = hipEventQuery(sl.done);
             if (q == hipErrorNotReady) continue;
             Request* r = sl.cur;
@@ -375,7 +579,9 @@ void completer_main(ss_server* S)
             S->cv_work.notify_all();
             any = true;
         }
-        if (!any) std::this_thread::sleep_for(std::chrono::microseconds(20));
+        // requests in flight: look again at once (a sleep here costs its timer slack and, on a busy
+        // host, a wake-up delay in the completion latency)
+        if (!any) std::this_thread::yield();
     }
 }
 
@@ -428,6 +634,84 @@ extern "C" int ss_server_create(ss_ctx* ctx, size_t hbm_budget_bytes, int32_t n_
     return SS_OK;
 }
 
+namespace {
+
+constexpr int kLoopIdleMs = 200;     // the loop kernel ends after this long with nothing to do
+
+void free_loop(ss_server* S)
+{
+    if (S->loop_stream) (void)hipStreamSynchronize(S->loop_stream);
+    if (S->loop_ev) (void)hipEventDestroy(S->loop_ev);
+    if (S->loop_stream) (void)hipStreamDestroy(S->loop_stream);
+    if (S->arena) (void)hipFree(S->arena);
+    if (S->D) (void)hipFree(S->D);
+    if (S->H) (void)hipHostFree(S->H);
+    S->loop_ev = nullptr;
+    S->loop_stream = nullptr;
+    S->arena = nullptr;
+    S->D = nullptr;
+    S->H = nullptr;
+}
+
+}  // namespace
+
+extern "C" int ss_server_create_loop(ss_ctx* ctx, size_t hbm_budget_bytes, int32_t n_slots, int32_t slices_per_lane,
+                                     ss_server** out)
+{
+    if (!ctx || !out || n_slots < 1 || n_slots > loop::kSlots || hbm_budget_bytes < 4096) return SS_EINVAL;
+    if (slices_per_lane != 1 && slices_per_lane != 2 && slices_per_lane != 4 && slices_per_lane != 8)
+        return SS_EINVAL;
+    ss_server* S = new (std::nothrow) ss_server();
+    if (!S) return SS_ENOMEM;
+    S->ctx = ctx;
+    (void)hipGetDevice(&S->device);
+    S->budget = hbm_budget_bytes;
+    S->loop = true;
+    S->loop_rs = slices_per_lane;
+    S->rsmax = slices_per_lane;
+    S->pool.flags = hipHostMallocCoherent | hipHostMallocMapped;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, S->device) != hipSuccess) { delete S; return SS_EDEVICE; }
+    {
+        // One block per CU, so that a request's long items each own a CU's four SIMDs: every block
+        // reserves more than half of a CU's LDS, and the dispatcher cannot stack two on one CU (with
+        // as many blocks per CU as fit, items shared CUs and the 99th percentile of the service time
+        // measured 1.6 times longer).
+        const size_t lds_cu = (size_t)prop.maxSharedMemoryPerMultiProcessor;
+        const size_t st = loop::loop_static_lds(slices_per_lane);
+        S->loop_lds_pad = lds_cu / 2 + 1024 > st ? lds_cu / 2 + 1024 - st : 0;
+        S->loop_grid = prop.multiProcessorCount;
+    }
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, S->device) != hipSuccess || khz <= 0)
+        khz = 100000;
+    S->tick_ns = 1e6 / (double)khz;
+    S->idle_ticks = (uint64_t)khz * kLoopIdleMs;
+    hipError_t e = hipHostMalloc((void**)&S->H, sizeof(loop::Host), hipHostMallocCoherent | hipHostMallocMapped);
+    if (e == hipSuccess) {
+        std::memset((void*)S->H, 0, sizeof(loop::Host));
+        e = hipHostGetDevicePointer((void**)&S->H_dev, S->H, 0);
+    }
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->loop_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&S->loop_ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipMalloc((void**)&S->D, sizeof(loop::Dev));
+    // zeroed on the loop's own stream, so before any launch of the loop
+    if (e == hipSuccess) e = hipMemsetAsync(S->D, 0, sizeof(loop::Dev), S->loop_stream);
+    if (e == hipSuccess) e = hipMalloc((void**)&S->arena, hbm_budget_bytes);
+    if (e == hipSuccess) e = hipStreamSynchronize(S->loop_stream);
+    if (e != hipSuccess) {
+        free_loop(S);
+        delete S;
+        return map_err(e);
+    }
+    S->arena_alloc.reset(hbm_budget_bytes);
+    S->slots.resize((size_t)n_slots);
+    S->dispatcher = std::thread(dispatcher_main, S);
+    S->completer = std::thread(completer_main, S);
+    *out = S;
+    return SS_OK;
+}
+
 extern "C" int ss_server_submit(ss_server* S, const uint8_t* reads, const uint8_t* refs, const int32_t* lengths,
                                 const int32_t* E_per_pair, int64_t n_pairs, uint8_t* accept_out, int32_t* edits_out,
                                 ss_ticket* ticket)
@@ -441,18 +725,19 @@ extern "C" int ss_server_submit(ss_server* S, const uint8_t* reads, const uint8_
         T += lengths[i];
     }
     if (T > SS_MAX_STREAM_BASES) return SS_ELEN;
+    if (S->loop && cdiv(cdiv(T, 32) + 2, loop::kPackWords) > loop::kMaxUnits) return SS_ELEN;
     Request* r = nullptr;
     try {
         r = new Request();
         r->n = n_pairs;
         r->total = T;
-        r->footprint = footprint_of(n_pairs, T);
+        r->footprint = S->loop ? loop_footprint(T) : footprint_of(n_pairs, T);
         if (r->footprint > S->budget) {
             delete r;
             return SS_EBUDGET;
         }
         const int rsmin = plan_min_slices(E_per_pair, n_pairs);
-        if (rsmin == 0) {
+        if (rsmin == 0 || (S->loop && rsmin > S->loop_rs)) {
             delete r;
             return SS_ELEN;
         }
@@ -464,7 +749,8 @@ extern "C" int ss_server_submit(ss_server* S, const uint8_t* reads, const uint8_
         std::vector<int64_t> perm;
         int nc = 0;
         double cost = 0;
-        if (!plan_items(lengths, E_per_pair, n_pairs, r->rsmax, items, perm, &nc, &cost)) {
+        if (!plan_items(lengths, E_per_pair, n_pairs, r->rsmax, items, perm, &nc, &cost) ||
+            (S->loop && (int64_t)items.size() > loop::kMaxUnits)) {
             delete r;
             return SS_ELEN;
         }
@@ -498,10 +784,10 @@ extern "C" int ss_server_submit(ss_server* S, const uint8_t* reads, const uint8_
     r->edits_out = edits_out;
     r->t_submit = now_ns();
     std::lock_guard<std::mutex> lk(S->mu);
-    if (S->stop) {
+    if (S->stop || S->broken) {
         if (r->pin) S->pool.put(r->pin, r->pin_cls);
         delete r;
-        return SS_EINVAL;
+        return S->broken ? SS_EDEVICE : SS_EINVAL;
     }
     r->id = S->next_id++;
     S->reqs[r->id] = r;
@@ -607,6 +893,7 @@ extern "C" int ss_server_set_slices(ss_server* S, int32_t slices_per_lane)
 {
     if (!S) return SS_EINVAL;
     if (slices_per_lane != 1 && slices_per_lane != 2 && slices_per_lane != 4 && slices_per_lane != 8) return SS_EINVAL;
+    if (S->loop) return SS_EINVAL;       // the loop kernel's slice width is fixed at creation
     std::lock_guard<std::mutex> lk(S->mu);
     S->rsmax = slices_per_lane;
     return SS_OK;
@@ -644,6 +931,11 @@ extern "C" int ss_server_destroy(ss_server* S)
     }
     S->dispatcher.join();
     S->completer.join();
+    if (S->loop) {
+        // nothing is in flight any more: the loop kernel ends at its next look at the stop word
+        __atomic_store_n(&S->H->stop, 1ull, __ATOMIC_RELEASE);
+        free_loop(S);
+    }
     for (auto& sl : S->slots) {
         if (sl.stream) (void)hipStreamSynchronize(sl.stream);
         if (sl.pinned) (void)hipHostFree(sl.pinned);

@@ -59,12 +59,32 @@ static inline uint64_t rng_below(rng_t* r, uint64_t n)
 
 static inline double rng_unit(rng_t* r) { return (double)(rng_next(r) >> 11) * (1.0 / 9007199254740992.0); }
 
+/* ASCII of the four bases held by one byte of a random word, lowest bit pair first. */
+static uint32_t QUAD[256];
+static pthread_once_t quad_once = PTHREAD_ONCE_INIT;
+
+static void quad_init(void)
+{
+    for (int v = 0; v < 256; v++) {
+        uint8_t c[4];
+        for (int t = 0; t < 4; t++) c[t] = BASES[(v >> (2 * t)) & 3];
+        memcpy(&QUAD[v], c, 4);
+    }
+}
+
+/* n uniform bases: each random word gives 32 of them, two bits each, lowest pair first. */
 static void rand_bases(rng_t* r, uint8_t* dst, int64_t n)
 {
+    pthread_once(&quad_once, quad_init);
     int64_t i = 0;
-    while (i < n) {
+    while (n - i >= 32) {
         uint64_t x = rng_next(r);
-        for (int b = 0; b < 32 && i < n; b++, i++) { dst[i] = BASES[x & 3]; x >>= 2; }
+        for (int j = 0; j < 8; j++, x >>= 8) memcpy(dst + i + 4 * j, &QUAD[x & 255], 4);
+        i += 32;
+    }
+    if (i < n) {
+        uint64_t x = rng_next(r);
+        for (; i < n; i++) { dst[i] = BASES[x & 3]; x >>= 2; }
     }
 }
 
@@ -97,10 +117,39 @@ static int ev_cmp(const void* a, const void* b)
     return x->ord < y->ord ? -1 : (x->ord > y->ord);
 }
 
+/* Events in (position, draw order) order.  Every caller numbers its events by
+ * draw order (ord = index), so this is a stable sort by position: insertion
+ * sort for a few events, a counting sort over the positions 0..maxpos else. */
+static void sort_events(edit_ev* ev, int k, int maxpos)
+{
+    if (k <= 1) return;
+    if (k <= 24) {
+        for (int a = 1; a < k; a++) {
+            edit_ev v = ev[a];
+            int b = a - 1;
+            while (b >= 0 && ev_cmp(&ev[b], &v) > 0) { ev[b + 1] = ev[b]; b--; }
+            ev[b + 1] = v;
+        }
+        return;
+    }
+    int* cnt = (int*)calloc((size_t)maxpos + 2, sizeof(int));
+    edit_ev* tmp = (edit_ev*)malloc(sizeof(edit_ev) * (size_t)k);
+    if (!cnt || !tmp) {
+        free(cnt); free(tmp);
+        qsort(ev, (size_t)k, sizeof(edit_ev), ev_cmp);
+        return;
+    }
+    for (int a = 0; a < k; a++) cnt[ev[a].pos + 1]++;
+    for (int p = 0; p <= maxpos; p++) cnt[p + 1] += cnt[p];
+    for (int a = 0; a < k; a++) tmp[cnt[ev[a].pos]++] = ev[a];
+    memcpy(ev, tmp, sizeof(edit_ev) * (size_t)k);
+    free(cnt); free(tmp);
+}
+
 /* Apply sorted events to read[0..m) producing exactly m bases in out. */
 static void apply_events(rng_t* r, const uint8_t* read, int m, edit_ev* ev, int k, uint8_t* out)
 {
-    if (k > 1) qsort(ev, (size_t)k, sizeof(edit_ev), ev_cmp);
+    sort_events(ev, k, m);
     int o = 0, i = 0, e = 0;
     while (o < m && (i < m || e < k)) {
         if (e < k && ev[e].pos <= i) {
@@ -119,7 +168,13 @@ static void apply_events(rng_t* r, const uint8_t* read, int m, edit_ev* ev, int 
             continue;
         }
         if (i >= m) break;
-        out[o++] = read[i++];
+        /* copy the read up to the next event (or until the output is full) */
+        int run = (e < k ? ev[e].pos : m) - i;
+        if (run > m - i) run = m - i;
+        if (run > m - o) run = m - o;
+        memcpy(out + o, read + i, (size_t)run);
+        o += run;
+        i += run;
     }
     if (o < m) rand_bases(r, out + o, m - o);
 }
@@ -128,7 +183,7 @@ static void apply_events(rng_t* r, const uint8_t* read, int m, edit_ev* ev, int 
  * length (at most m plus the inserted bases), which is returned. */
 static int apply_events_free(rng_t* r, const uint8_t* read, int m, edit_ev* ev, int k, uint8_t* out)
 {
-    if (k > 1) qsort(ev, (size_t)k, sizeof(edit_ev), ev_cmp);
+    sort_events(ev, k, m);
     int o = 0, i = 0, e = 0;
     while (i < m || e < k) {
         if (e < k && ev[e].pos <= i) {
@@ -147,7 +202,11 @@ static int apply_events_free(rng_t* r, const uint8_t* read, int m, edit_ev* ev, 
             continue;
         }
         if (i >= m) break;
-        out[o++] = read[i++];
+        int run = (e < k ? ev[e].pos : m) - i;
+        if (run > m - i) run = m - i;
+        memcpy(out + o, read + i, (size_t)run);
+        o += run;
+        i += run;
     }
     return o;
 }
@@ -473,6 +532,11 @@ typedef struct {
 typedef struct {
     uint64_t seed; int64_t n_req; int32_t max_pairs, min_len, max_len;
     pool_req* pool; int64_t n_pool; _Atomic int64_t next_pool;
+    /* on the fly: a ring of `lead` requests generated ahead of the clock; slot k holds position
+     * ring_pos[k] once generated (-1: free) */
+    pool_req* ring; _Atomic int64_t* ring_pos; int64_t lead;
+    _Atomic int64_t next_gen;
+    _Atomic int stop_gen;
     const double* arrivals; int64_t t0_ns;
     ssgen_submit_fn submit; void* server;
     uint64_t* tickets; int64_t* due_ns; int32_t* pairs; int64_t* bases;
@@ -530,19 +594,48 @@ static void* pool_worker(void* arg)
     return NULL;
 }
 
-/* Each worker takes the next schedule position i, sleeps until it is due and
- * submits request (i mod pool size) itself, so the submit-time copies run on
- * all workers.  Without a pool the worker generates request i first. */
+static void nap_us(long us)
+{
+    struct timespec ts = {0, us * 1000L};
+    nanosleep(&ts, NULL);
+}
+
+/* On the fly: generator threads make the requests in schedule order into the
+ * ring, each waiting for its slot to be freed by the submission of the
+ * request `lead` positions earlier. */
+static void* gen_worker(void* arg)
+{
+    drive_ctx* D = (drive_ctx*)arg;
+    for (;;) {
+        const int64_t i = atomic_fetch_add(&D->next_gen, 1);
+        if (i >= D->n_req) break;
+        const int64_t k = i % D->lead;
+        while (atomic_load(&D->ring_pos[k]) != -1) {
+            if (atomic_load(&D->stop_gen)) return NULL;
+            nap_us(50);
+        }
+        make_request(D, i, &D->ring[k]);
+        atomic_store(&D->ring_pos[k], i);
+    }
+    return NULL;
+}
+
+/* Each submitter takes the next schedule position i, sleeps until it is due
+ * and submits request (i mod pool size) itself, so the submit-time copies run
+ * on all submitters.  Without a pool it first waits for request i in the ring
+ * and frees the slot after submitting. */
 static void* drive_worker(void* arg)
 {
     drive_ctx* D = (drive_ctx*)arg;
     for (;;) {
         const int64_t i = atomic_fetch_add(&D->next, 1);
         if (i >= D->n_req || atomic_load(&D->failed)) break;
-        pool_req own;
         const pool_req* q;
         if (D->n_pool > 0) q = &D->pool[i % D->n_pool];
-        else { make_request(D, i, &own); q = &own; }
+        else {
+            while (atomic_load(&D->ring_pos[i % D->lead]) != i) nap_us(20);
+            q = &D->ring[i % D->lead];
+        }
         const size_t nn = (size_t)(q->n > 0 ? q->n : 1);
         const int64_t due = D->t0_ns + (int64_t)(D->arrivals[i] * 1e9);
         D->accept_out[i] = (uint8_t*)malloc(nn);
@@ -553,7 +646,11 @@ static void* drive_worker(void* arg)
         sleep_until(due);
         const int rc = D->submit(D->server, q->reads, q->refs, q->lengths, q->E, q->n, D->accept_out[i],
                                  D->edits_out[i], &D->tickets[i]);
-        if (D->n_pool <= 0) { free(own.reads); free(own.refs); free(own.lengths); free(own.E); }
+        if (D->n_pool <= 0) {
+            pool_req* own = &D->ring[i % D->lead];
+            free(own->reads); free(own->refs); free(own->lengths); free(own->E);
+            atomic_store(&D->ring_pos[i % D->lead], -1);
+        }
         if (rc != 0) {
             int zero = 0;
             atomic_compare_exchange_strong(&D->failed, &zero, rc);
@@ -564,14 +661,17 @@ static void* drive_worker(void* arg)
     return NULL;
 }
 
-/* Runs the whole schedule on `threads` workers; returns the number of
- * requests submitted, or -1 + (status of a failed submission).  Per request
- * (n_req entries, indexed by schedule position): ticket, due time
- * (CLOCK_MONOTONIC ns), pairs, bases, and output buffers owned here until
- * ssgen_drive_free.  pool > 0: requests 0..pool-1 are generated before the
- * schedule starts and position i replays request i mod pool; pool = 0: each
- * position generates its own request on the fly.  t0_ns: schedule time zero
- * (0 = 100 ms after the pool is ready). */
+/* Runs the whole schedule; returns the number of requests submitted, or
+ * -1 + (status of a failed submission).  Per request (n_req entries, indexed
+ * by schedule position): ticket, due time (CLOCK_MONOTONIC ns), pairs, bases,
+ * and output buffers owned here until ssgen_drive_free.  pool > 0: requests
+ * 0..pool-1 are generated (on `threads` threads) before the schedule starts,
+ * and position i replays request i mod pool, submitted by `threads`
+ * submitters.  pool = 0: every position's request is generated from its own
+ * seed on the fly by `threads` generator threads, running up to
+ * min(n_req, 2048) positions ahead of the submissions (the first ones before
+ * the clock starts), and submitted by 8 submitters.  t0_ns: schedule time zero
+ * (0 = 100 ms after the pool or the head start is ready). */
 int64_t ssgen_drive(uint64_t seed, const double* arrivals, int64_t n_req, int32_t max_pairs, int32_t min_len,
                     int32_t max_len, ssgen_submit_fn submit, void* server, int threads, int64_t pool,
                     int64_t t0_ns, uint64_t* tickets, int64_t* due_ns, int32_t* pairs, int64_t* bases,
@@ -588,18 +688,44 @@ int64_t ssgen_drive(uint64_t seed, const double* arrivals, int64_t n_req, int32_
     D.n_pool = pool > 0 ? pool : 0;
     D.pool = (pool_req*)calloc((size_t)(D.n_pool > 0 ? D.n_pool : 1), sizeof(pool_req));
     atomic_store(&D.next_pool, 0);
-    {
+    D.lead = D.n_pool > 0 ? 1 : (n_req < 2048 ? (n_req > 0 ? n_req : 1) : 2048);
+    D.ring = (pool_req*)calloc((size_t)D.lead, sizeof(pool_req));
+    D.ring_pos = (_Atomic int64_t*)malloc(sizeof(_Atomic int64_t) * (size_t)D.lead);
+    for (int64_t k = 0; k < D.lead; k++) atomic_store(&D.ring_pos[k], -1);
+    atomic_store(&D.next_gen, 0);
+    atomic_store(&D.stop_gen, 0);
+    pthread_t gt[64];
+    int n_gen = 0;
+    if (D.n_pool > 0) {
         pthread_t pt[64];
         for (int t = 0; t < threads; t++) pthread_create(&pt[t], NULL, pool_worker, &D);
         for (int t = 0; t < threads; t++) pthread_join(pt[t], NULL);
+    } else {
+        n_gen = threads;
+        for (int t = 0; t < n_gen; t++) pthread_create(&gt[t], NULL, gen_worker, &D);
+        /* head start: the ring full (or every request) before the clock starts */
+        const int64_t head = D.lead < n_req ? D.lead : n_req;
+        for (int64_t k = 0; k < head; k++)
+            while (atomic_load(&D.ring_pos[k]) != k) nap_us(200);
     }
     D.t0_ns = t0_ns ? t0_ns : mono_ns() + 100000000LL;
     atomic_store(&D.next, 0);
     atomic_store(&D.failed, 0);
     atomic_store(&D.submitted, 0);
+    const int n_sub = D.n_pool > 0 ? threads : 8;
     pthread_t tid[64];
-    for (int t = 0; t < threads; t++) pthread_create(&tid[t], NULL, drive_worker, &D);
-    for (int t = 0; t < threads; t++) pthread_join(tid[t], NULL);
+    for (int t = 0; t < n_sub; t++) pthread_create(&tid[t], NULL, drive_worker, &D);
+    for (int t = 0; t < n_sub; t++) pthread_join(tid[t], NULL);
+    atomic_store(&D.stop_gen, 1);
+    for (int t = 0; t < n_gen; t++) pthread_join(gt[t], NULL);
+    for (int64_t k = 0; k < D.lead; k++) {
+        /* requests generated but never submitted (a submission failed) */
+        if (D.n_pool == 0 && atomic_load(&D.ring_pos[k]) != -1) {
+            free(D.ring[k].reads); free(D.ring[k].refs); free(D.ring[k].lengths); free(D.ring[k].E);
+        }
+    }
+    free(D.ring);
+    free((void*)D.ring_pos);
     for (int64_t k = 0; k < D.n_pool; k++) {
         free(D.pool[k].reads); free(D.pool[k].refs); free(D.pool[k].lengths); free(D.pool[k].E);
     }
