@@ -316,6 +316,36 @@ def mixed_leg(a, torch, ss, gen, runner, oracle):
                      threads=min(16, os.cpu_count() or 1), want_stats=True)
     mism = int(np.sum((w["accept"] != acc[idx]) | (w["edits"] != ed[idx])))
     ss.ss_plan_destroy(plan)
+    # verification of every pair on the GPU (short pairs one per lane, long ones one per wavefront): the
+    # false accept rate over the whole batch, long pairs included, and no false reject
+    ver = {}
+    ed_all = np.zeros(n, dtype=np.int64)
+    for name, cls_idx, ml in (("short", short_idx, int(b["lengths"][short_idx].max())),
+                              ("long", long_idx, int(b["lengths"][long_idx].max()) if len(long_idx) else 0)):
+        if not len(cls_idx):
+            continue
+        ix = torch.from_numpy(cls_idx.astype(np.int64)).cuda()
+        vout = torch.empty(len(cls_idx), dtype=torch.int32, device="cuda")
+        fn = lambda: db.verify(ps, index=ix, n=len(cls_idx), max_len=ml, out=vout)
+        fn(); torch.cuda.synchronize()
+        _, (v_ms,) = timed_loop([fn], 2, torch)
+        ed_all[cls_idx] = vout.cpu().numpy()
+        ver[f"{name}_verify_ms"] = round(v_ms, 4)
+        ver[f"{name}_pairs"] = int(len(cls_idx))
+    over = ed_all > b["E"]
+    fa = acc.astype(bool) & over
+    ver.update(pairs_over_E=int(over.sum()), false_accepts=int(fa.sum()),
+               false_accept_rate=float(fa.sum() / max(1, over.sum())),
+               false_accept_rate_long=float(fa[long_idx].sum() / max(1, over[long_idx].sum())) if len(long_idx) else None,
+               false_rejects=int((~acc.astype(bool) & ~over).sum()),
+               verified_sample_vs_oracle_levenshtein=None)
+    # the GPU distances against the oracle's Levenshtein on a few pairs of each class
+    chk = np.concatenate([short_idx[:2000], long_idx[:8]])
+    lev = oracle.levenshtein_batch(b["reads"], b["refs"], b["offsets"][chk], b["lengths"][chk])
+    ver["verified_sample_vs_oracle_levenshtein"] = {"pairs": int(len(chk)),
+                                                    "mismatches": int(np.sum(lev != ed_all[chk]))}
+    del vout
+    log(f"mixed verify: {ver}")
     # the oracle's rate on this batch, per class (short, long) on the same samples, timed apart:
     # the whole batch would take n_short / short rate + n_long / long rate on these threads
     threads = min(16, os.cpu_count() or 1)
@@ -340,7 +370,7 @@ def mixed_leg(a, torch, ss, gen, runner, oracle):
                unbucketed_ms=round(flat_ms, 4), unbucketed_pairs_per_s=n / (1e-3 * flat_ms),
                speedup_vs_unbucketed=flat_ms / bat_ms, identical_outputs=identical, plan_seconds=round(plan_s, 3),
                plan=info, tuned_slices_per_lane=chosen, oracle_sample_pairs=int(len(idx)),
-               oracle_sample_mismatches=mism,
+               oracle_sample_mismatches=mism, verify=ver,
                cpu_oracle={"threads": threads, "short_pairs_per_s": rates["short"], "long_pairs_per_s": rates["long"],
                            "whole_batch_s": oracle_batch_s, "gpu_speedup": oracle_batch_s / (1e-3 * bat_ms),
                            "sample": f"{int((b['lengths'][idx] < 10000).sum())} short and "
@@ -641,12 +671,22 @@ def main():
         t0 = time.perf_counter()
         hacc, hed = ss.ss_filter_batch(b["reads"], b["refs"], b["lengths"], E)
         host_s = time.perf_counter() - t0
-        host = dict(entry="ss_filter_batch", seconds=round(host_s, 4), pairs_per_s=n / host_s,
+        host = dict(entry="ss_filter_batch", input="pageable", seconds=round(host_s, 4), pairs_per_s=n / host_s,
                     host_bytes_in=int(len(b["reads"]) + len(b["refs"])),
                     identical_outputs=bool(np.array_equal(hacc, acc) and np.array_equal(hed, ed)))
-        log(f"host entry point (PCIe-inclusive): {host_s:.3f} s -> {n / host_s / 1e6:.1f} M pairs/s, "
-            f"identical={host['identical_outputs']}")
         del hacc, hed
+        # the same from pinned host arrays: chunks copied straight to the device, overlapping the filter
+        pr, pf = torch.from_numpy(b["reads"]).pin_memory(), torch.from_numpy(b["refs"]).pin_memory()
+        ss.ss_filter_batch(pr.numpy(), pf.numpy(), b["lengths"], E)
+        t0 = time.perf_counter()
+        hacc, hed = ss.ss_filter_batch(pr.numpy(), pf.numpy(), b["lengths"], E)
+        pin_s = time.perf_counter() - t0
+        host["pinned_input"] = dict(seconds=round(pin_s, 4), pairs_per_s=n / pin_s,
+                                    identical_outputs=bool(np.array_equal(hacc, acc) and np.array_equal(hed, ed)))
+        del hacc, hed, pr, pf
+        log(f"host entry point (PCIe-inclusive): pageable {host_s:.3f} s -> {n / host_s / 1e6:.1f} M pairs/s, "
+            f"pinned {pin_s:.3f} s -> {n / pin_s / 1e6:.1f} M pairs/s, identical={host['identical_outputs']}/"
+            f"{host['pinned_input']['identical_outputs']}")
 
     # HBM calibration: a device-to-device copy of 2 GiB (reads and writes 2 GiB each)
     del db.reads, db.refs, packed

@@ -64,7 +64,7 @@ const char* ss_status_str(int status);
 #define SS_MAX_E_PLANNED  8191    /* batched launch and serving: 2E+1 rows in 64 lanes x 8 slices */
 #define SS_MAX_LEN        (1 << 24)
 #define SS_MAX_LEN_FUSED  2048    /* fused encode-and-filter kernel: m <= 2048 */
-#define SS_MAX_LEN_VERIFY 256     /* verification kernel: m <= 256 */
+#define SS_MAX_LEN_VERIFY 65536   /* verification: m <= 65536 (one pair per lane up to 256) */
 /* wavefront, batched and serving paths: a bit stream of at most this many
  * bases (each plane under 4 GiB: its words are read with 32-bit offsets) */
 #define SS_MAX_STREAM_BASES (32LL * ((1LL << 30) - 64))
@@ -357,8 +357,13 @@ int ss_filter_batch_ex(ss_ctx* ctx, const ss_batch_desc* desc, void* stream);
  * for ss_filter_wave_async).  index: optional n pair indices (entry k
  * verifies pair index[k]; NULL: pairs 0..n-1).  max_len >= every listed
  * pair's length, <= SS_MAX_LEN_VERIFY (SS_ELEN beyond).  ed_out[k] (device,
- * int32) = edit distance of the k-th listed pair.  One pair per lane, Myers'
- * bit-vector algorithm (J. ACM 1999) in its global-distance form.
+ * int32) = edit distance of the k-th listed pair (-1 for a pair longer than
+ * max_len).  Myers' bit-vector algorithm (J. ACM 1999) in its
+ * global-distance form: one pair per lane for max_len <= 256, else one pair
+ * per wavefront (each lane a 32 W-position stretch of the query, W the
+ * smallest power of two with 2048 W >= max_len; the addition's carries cross
+ * lanes by one carry-lookahead step per column), so a batch of short and
+ * long pairs is best verified in two calls, each over its own index list.
  * Asynchronous on stream. */
 int ss_verify_async(ss_ctx* ctx, const uint32_t* packed, int64_t total_bases, const int64_t* offsets,
                     const int32_t* lengths, const int64_t* index, int64_t n, int32_t max_len, int32_t* ed_out,

@@ -27,7 +27,7 @@ SS_MAX_E = 16383
 SS_MAX_E_PLANNED = 8191
 SS_MAX_LEN = 1 << 24
 SS_MAX_LEN_FUSED = 2048
-SS_MAX_LEN_VERIFY = 256
+SS_MAX_LEN_VERIFY = 65536
 SS_MAX_STREAM_BASES = 32 * ((1 << 30) - 64)
 SS_NOALLOC_SCRATCH_BYTES = 32 << 20
 SS_RESULT_ACCEPT = 0x8000

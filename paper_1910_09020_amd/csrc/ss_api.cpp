@@ -6,8 +6,11 @@
 #include <algorithm>
 #include <cstdint>
 #include <cstring>
+#include <condition_variable>
+#include <functional>
 #include <mutex>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "ss.h"
@@ -84,10 +87,15 @@ extern "C" int ss_destroy(ss_ctx* ctx)
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->copy_stream) (void)hipStreamSynchronize(ctx->copy_stream);
     for (DevBuf* b : {&ctx->reads, &ctx->refs, &ctx->offsets, &ctx->lengths, &ctx->epp, &ctx->packed,
                       &ctx->results, &ctx->err, &ctx->chunk, &ctx->qside, &ctx->rside, &ctx->uoff, &ctx->ulen,
-                      &ctx->roff, &ctx->rlen})
+                      &ctx->roff, &ctx->rlen, &ctx->dstage[0], &ctx->dstage[1]})
         b->release();
+    ctx->hres.release();
+    for (hipEvent_t ev : {ctx->ev_h2d[0], ctx->ev_h2d[1], ctx->ev_used[0], ctx->ev_used[1]})
+        if (ev) (void)hipEventDestroy(ev);
+    if (ctx->copy_stream) (void)hipStreamDestroy(ctx->copy_stream);
     if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
     (void)hipSetDevice(prev);
     delete ctx;
@@ -264,6 +272,163 @@ int ss_default_ctx(ss_ctx** out)
 
 namespace {
 
+// ---------------------------------------------------------------- host entry point pipeline
+
+// Host threads that split a loop between them for the length of one host call.
+class Crew {
+public:
+    explicit Crew(int n) : n_(std::max(1, n))
+    {
+        for (int i = 1; i < n_; i++) th_.emplace_back([this, i] { loop(i); });
+    }
+    ~Crew()
+    {
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            stop_ = true;
+            gen_++;
+        }
+        cv_.notify_all();
+        for (auto& t : th_) t.join();
+    }
+    // fn(a, b) over [0, n) cut in one piece per thread; returns when all are done
+    void parallel(size_t n, const std::function<void(size_t, size_t)>& fn)
+    {
+        if (n_ == 1 || n < 4096) {
+            fn(0, n);
+            return;
+        }
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            fn_ = &fn;
+            count_ = n;
+            left_ = n_ - 1;
+            gen_++;
+        }
+        cv_.notify_all();
+        piece(0);
+        std::unique_lock<std::mutex> lk(mu_);
+        done_cv_.wait(lk, [&] { return left_ == 0; });
+        fn_ = nullptr;
+    }
+
+private:
+    void piece(int i)
+    {
+        const size_t per = (count_ + (size_t)n_ - 1) / (size_t)n_;
+        const size_t a = std::min(count_, per * (size_t)i), b = std::min(count_, a + per);
+        if (b > a) (*fn_)(a, b);
+    }
+    void loop(int i)
+    {
+        uint64_t seen = 0;
+        for (;;) {
+            std::unique_lock<std::mutex> lk(mu_);
+            cv_.wait(lk, [&] { return gen_ != seen; });
+            seen = gen_;
+            if (stop_) return;
+            lk.unlock();
+            piece(i);
+            lk.lock();
+            if (--left_ == 0) done_cv_.notify_one();
+        }
+    }
+    int n_;
+    std::vector<std::thread> th_;
+    std::mutex mu_;
+    std::condition_variable cv_, done_cv_;
+    uint64_t gen_ = 0;
+    bool stop_ = false;
+    const std::function<void(size_t, size_t)>* fn_ = nullptr;
+    size_t count_ = 0;
+    int left_ = 0;
+};
+
+int host_threads()
+{
+    const unsigned h = std::thread::hardware_concurrency();
+    return (int)std::min(16u, std::max(1u, h));
+}
+
+constexpr int64_t kStageBytes = 256ll << 20;      // one chunk of reads and refs (both sides)
+
+// True when p is pinned host memory (hipHostMalloc, or a pinned tensor of a framework built on it).
+bool is_pinned_host(const void* p)
+{
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();          // pageable memory is reported as an error; clear it
+        return false;
+    }
+    return a.type == hipMemoryTypeHost;
+}
+
+// Pairs of one length m, one threshold E <= SS_MAX_E_SLICED, m <= SS_MAX_LEN_FUSED, in pinned host
+// memory: the one-call filter over chunks copied straight from the caller's arrays by the copy
+// engine into two device staging buffers (the context's copy stream), chunk i's copy overlapping
+// the filter of chunk i-1 (the context's stream); results come back once and are expanded by host
+// threads.  (From pageable memory a staging copy on the host is needed, which measured slower than
+// the runtime's own pageable copy, so pageable input takes the plain path.)
+int filter_host_pipelined(ss_ctx* ctx, const uint8_t* reads, const uint8_t* refs, int64_t n, int32_t m, int32_t E,
+                          uint8_t* accept_out, int32_t* edits_out)
+{
+    const hipStream_t s = ctx->stream;
+    // chunks of a multiple of 2048 pairs: each chunk's bases and results start 16-byte aligned
+    int64_t K = std::max<int64_t>(2048, (kStageBytes / std::max<int64_t>(1, 2 * (int64_t)m)) / 2048 * 2048);
+    if (K > n) K = n;
+    const int64_t nchunks = cdiv(n, K);
+    const size_t side = (size_t)((K * (int64_t)m + 15) & ~(int64_t)15);    // refs start here in a stage
+    const size_t stage_bytes = 2 * side + 64;
+    if (!ctx->copy_stream) SS_TRY(hipStreamCreateWithFlags(&ctx->copy_stream, hipStreamNonBlocking));
+    for (int b = 0; b < 2; b++) {
+        if (!ctx->ev_h2d[b]) SS_TRY(hipEventCreateWithFlags(&ctx->ev_h2d[b], hipEventDisableTiming));
+        if (!ctx->ev_used[b]) SS_TRY(hipEventCreateWithFlags(&ctx->ev_used[b], hipEventDisableTiming));
+        SS_TRY(ctx->dstage[b].ensure(stage_bytes));
+    }
+    const size_t err_at = ((size_t)n * 2 + 15) / 16 * 16;
+    SS_TRY(ctx->hres.ensure(err_at + 16));
+    SS_TRY(ctx->results.ensure((size_t)n * 2 + 16));
+    SS_TRY(ctx->err.ensure(16));
+    uint16_t* d_res = (uint16_t*)ctx->results.p;
+    uint32_t* d_err = (uint32_t*)ctx->err.p;
+    SS_TRY(hipMemsetAsync(d_err, 0, 4, s));
+    // host threads for the expansion of the results
+    Crew crew(n >= (1 << 20) ? host_threads() : 1);
+    for (int64_t i = 0; i < nchunks; i++) {
+        const int b = (int)(i & 1);
+        const int64_t s0 = i * K, k = std::min(K, n - s0);
+        uint8_t* ds = (uint8_t*)ctx->dstage[b].p;
+        if (i >= 2) SS_TRY(hipStreamWaitEvent(ctx->copy_stream, ctx->ev_used[b], 0));   // chunk i-2 was filtered
+        SS_TRY(hipMemcpyAsync(ds, reads + s0 * m, (size_t)(k * m), hipMemcpyHostToDevice, ctx->copy_stream));
+        SS_TRY(hipMemcpyAsync(ds + side, refs + s0 * m, (size_t)(k * m), hipMemcpyHostToDevice, ctx->copy_stream));
+        SS_TRY(hipEventRecord(ctx->ev_h2d[b], ctx->copy_stream));
+        SS_TRY(hipStreamWaitEvent(s, ctx->ev_h2d[b], 0));
+        const int rc = ss_filter_ascii_async(ctx, ds, ds + side, k, m, E, 0, d_res + s0, d_err, s);
+        if (rc != SS_OK) {
+            (void)hipStreamSynchronize(s);
+            (void)hipStreamSynchronize(ctx->copy_stream);
+            return rc;
+        }
+        SS_TRY(hipEventRecord(ctx->ev_used[b], s));
+    }
+    uint8_t* hr = (uint8_t*)ctx->hres.p;
+    SS_TRY(hipMemcpyAsync(hr, d_res, (size_t)n * 2, hipMemcpyDeviceToHost, s));
+    SS_TRY(hipMemcpyAsync(hr + err_at, d_err, 4, hipMemcpyDeviceToHost, s));
+    SS_TRY(hipStreamSynchronize(s));
+    uint32_t h_err = 0;
+    std::memcpy(&h_err, hr + err_at, 4);
+    if (h_err & 2u) return SS_EDEVICE;   // a bounded wait inside the fused kernel gave up
+    if (h_err) return SS_EBASE;          // outputs untouched
+    const uint16_t* res = (const uint16_t*)hr;
+    crew.parallel((size_t)n, [&](size_t a, size_t e) {
+        for (size_t i = a; i < e; i++) {
+            accept_out[i] = (uint8_t)(res[i] >> 15);
+            edits_out[i] = (int32_t)(res[i] & SS_RESULT_COUNT);
+        }
+    });
+    return SS_OK;
+}
+
 // Shared implementation: E_per_pair == nullptr means a single threshold E.
 int filter_host(const uint8_t* reads, const uint8_t* refs, const int32_t* lengths, const int32_t* E_per_pair,
                 int64_t n, int32_t E, uint8_t* accept_out, int32_t* edits_out)
@@ -298,6 +463,9 @@ int filter_host(const uint8_t* reads, const uint8_t* refs, const int32_t* length
     if (rc != SS_OK) return rc;
     // the device's default context is shared by every host thread: one call at a time uses its buffers
     std::lock_guard<std::mutex> lk(ctx->host_mu);
+    if (uniform && !E_per_pair && E <= SS_MAX_E_SLICED && lengths[0] > 0 && lengths[0] <= SS_MAX_LEN_FUSED &&
+        is_pinned_host(reads) && is_pinned_host(refs))
+        return filter_host_pipelined(ctx, reads, refs, n, lengths[0], E, accept_out, edits_out);
     hipStream_t s = ctx->stream;
     SS_TRY(ctx->reads.ensure((size_t)std::max<int64_t>(total, 1)));
     SS_TRY(ctx->refs.ensure((size_t)std::max<int64_t>(total, 1)));
@@ -353,13 +521,17 @@ int filter_host(const uint8_t* reads, const uint8_t* refs, const int32_t* length
                                   n, Emax, d_res, s);
     }
     if (rc != SS_OK) return rc;
-    std::vector<uint16_t> res((size_t)n);
-    SS_TRY(hipMemcpyAsync(res.data(), d_res, (size_t)n * 2, hipMemcpyDeviceToHost, s));
+    SS_TRY(ctx->hres.ensure((size_t)n * 2 + 16));
+    const uint16_t* res = (const uint16_t*)ctx->hres.p;
+    SS_TRY(hipMemcpyAsync(ctx->hres.p, d_res, (size_t)n * 2, hipMemcpyDeviceToHost, s));
     SS_TRY(hipStreamSynchronize(s));
-    for (int64_t i = 0; i < n; i++) {
-        accept_out[i] = (uint8_t)(res[(size_t)i] >> 15);
-        edits_out[i] = (int32_t)(res[(size_t)i] & SS_RESULT_COUNT);
-    }
+    Crew crew(n >= (1 << 20) ? host_threads() : 1);
+    crew.parallel((size_t)n, [&](size_t a, size_t e) {
+        for (size_t i = a; i < e; i++) {
+            accept_out[i] = (uint8_t)(res[i] >> 15);
+            edits_out[i] = (int32_t)(res[i] & SS_RESULT_COUNT);
+        }
+    });
     return SS_OK;
 }
 

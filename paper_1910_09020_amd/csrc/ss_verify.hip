@@ -9,8 +9,14 @@
 // over the query positions, and every reference character updates them with a
 // handful of word operations; the horizontal difference entering the top row
 // is +1 in every column (D[0][j] = j), and the score follows the bottom row.
-// One pair per lane; W 32-bit words cover a query of up to 32 W positions,
-// with the additions and shifts carried from word to word.
+// Up to 256 positions: one pair per lane; W 32-bit words cover a query of up
+// to 32 W positions, with the additions and shifts carried from word to word.
+// Longer pairs: one pair per wavefront, lane L holding query positions
+// [32 W L, 32 W (L + 1)); the carries of the addition cross lanes through one
+// carry-lookahead step over the wavefront (each lane's segment either
+// generates a carry, propagates one, or neither: with G and P those lanes' bit
+// masks, the lanes that receive a carry are (G + (G | P)) ^ P), and the
+// one-position shifts cross lanes through a shuffle.
 #include "ss_wave.h"
 
 namespace ss {
@@ -75,6 +81,102 @@ __global__ __launch_bounds__(256) void k_verify(const uint32_t* __restrict__ pk,
     ed_out[k] = score;
 }
 
+// One pair per wavefront (four per block), query positions [32 W L, 32 W (L + 1))
+// on lane L: pairs of up to 2048 W positions.
+template <int W>
+__global__ __launch_bounds__(256) void k_verify_wave(const uint32_t* __restrict__ pk, int64_t SW,
+                                                     const int64_t* __restrict__ offsets,
+                                                     const int32_t* __restrict__ lengths,
+                                                     const int64_t* __restrict__ index, int64_t n,
+                                                     int32_t* __restrict__ ed_out)
+{
+    const int lane = (int)(threadIdx.x & 63);
+    const int64_t k = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    if (k >= n) return;                                  // the whole wavefront
+    const int64_t p = index ? index[k] : k;
+    const int m = __builtin_amdgcn_readfirstlane(lengths[p]);
+    const int64_t b0 = offsets[p];
+    const uint32_t* __restrict__ Q0 = pk;
+    const uint32_t* __restrict__ Q1 = pk + SW;
+    const uint32_t* __restrict__ R0 = pk + 2 * SW;
+    const uint32_t* __restrict__ R1 = pk + 3 * SW;
+    if (m == 0 || m > 2048 * W) {
+        // (a pair longer than the caller's max_len is reported as -1)
+        if (lane == 0) ed_out[k] = m == 0 ? 0 : -1;
+        return;
+    }
+    // this lane's query positions (positions at or past m read as any value: carries and shifts
+    // only move information upwards, and the score is read at position m - 1)
+    uint32_t q0[W], q1[W], pv[W], mv[W];
+#pragma unroll
+    for (int w = 0; w < W; w++) {
+        const int64_t at = b0 + 32 * ((int64_t)W * lane + w);
+        q0[w] = wave::bits32(Q0, SW, at);
+        q1[w] = wave::bits32(Q1, SW, at);
+        pv[w] = ~0u;
+        mv[w] = 0u;
+    }
+    const int last = m - 1;
+    const int l_lane = last / (32 * W), l_word = (last >> 5) % W, l_bit = last & 31;
+    int score = m;
+    for (int jb = 0; jb < m; jb += 32) {
+        const uint32_t rw0 = __builtin_amdgcn_readfirstlane(wave::bits32(R0, SW, b0 + jb));
+        const uint32_t rw1 = __builtin_amdgcn_readfirstlane(wave::bits32(R1, SW, b0 + jb));
+        const int jend = m - jb < 32 ? m - jb : 32;
+        for (int jj = 0; jj < jend; jj++) {
+            const uint32_t rb0 = (uint32_t)__builtin_amdgcn_sbfe((int)rw0, jj, 1);
+            const uint32_t rb1 = (uint32_t)__builtin_amdgcn_sbfe((int)rw1, jj, 1);
+            // (Eq & Pv) + Pv over this lane's segment with no carry in
+            uint32_t eq[W], sum[W], carry = 0, ones = ~0u;
+#pragma unroll
+            for (int w = 0; w < W; w++) {
+                eq[w] = wave::and_xnor(wave::and_xnor(~0u, q0[w], rb0), q1[w], rb1);
+                const uint64_t s = (uint64_t)(eq[w] & pv[w]) + pv[w] + carry;
+                sum[w] = (uint32_t)s;
+                carry = (uint32_t)(s >> 32);
+                ones &= sum[w];
+            }
+            // carry lookahead over the lanes (a segment that generates cannot also be all ones)
+            const uint64_t G = __ballot(carry != 0u);
+            const uint64_t P = __ballot(ones == ~0u);
+            uint32_t cin = (uint32_t)((((G + (G | P)) ^ P) >> lane) & 1ull);
+            // the pass with the carry in, then the rest of the column step
+            uint32_t ph[W], mh[W];
+#pragma unroll
+            for (int w = 0; w < W; w++) {
+                const uint32_t sw = sum[w] + cin;
+                cin = sw < cin ? 1u : 0u;
+                const uint32_t xh = (sw ^ pv[w]) | eq[w];
+                ph[w] = mv[w] | ~(xh | pv[w]);
+                mh[w] = pv[w] & xh;
+            }
+            // the bottom row's horizontal difference
+            uint32_t dp = 0, dm = 0;
+#pragma unroll
+            for (int w = 0; w < W; w++) {
+                if (w == l_word) {
+                    dp = (ph[w] >> l_bit) & 1u;
+                    dm = (mh[w] >> l_bit) & 1u;
+                }
+            }
+            score += (int)__builtin_amdgcn_readlane(dp, l_lane) - (int)__builtin_amdgcn_readlane(dm, l_lane);
+            // shift up by one position: lane 0 takes +1 (D[0][j] = j) and 0; others the previous lane's top bits
+            const uint32_t ph_top = __shfl_up(ph[W - 1] >> 31, 1), mh_top = __shfl_up(mh[W - 1] >> 31, 1);
+            uint32_t ph_in = lane == 0 ? 1u : ph_top, mh_in = lane == 0 ? 0u : mh_top;
+#pragma unroll
+            for (int w = 0; w < W; w++) {
+                const uint32_t xv = eq[w] | mv[w];
+                const uint32_t phs = (ph[w] << 1) | ph_in, mhs = (mh[w] << 1) | mh_in;
+                ph_in = ph[w] >> 31;
+                mh_in = mh[w] >> 31;
+                pv[w] = mhs | ~(xv | phs);
+                mv[w] = phs & xv;
+            }
+        }
+    }
+    if (lane == 0) ed_out[k] = score;
+}
+
 __global__ void k_zero_count(unsigned long long* count) { *count = 0ull; }
 
 // Indices of accepted pairs (result bit 15 set).  A block takes 4096 results
@@ -129,11 +231,30 @@ static void launch_verify_W(dim3 grid, hipStream_t s, const uint32_t* packed, in
     hipLaunchKernelGGL(k_verify<W>, grid, dim3(256), 0, s, packed, SW, offsets, lengths, index, n, ed_out);
 }
 
+template <int W>
+static void launch_verify_wave_W(hipStream_t s, const uint32_t* packed, int64_t SW, const int64_t* offsets,
+                                 const int32_t* lengths, const int64_t* index, int64_t n, int32_t* ed_out)
+{
+    hipLaunchKernelGGL(k_verify_wave<W>, dim3((unsigned)cdiv(n, 4)), dim3(256), 0, s, packed, SW, offsets, lengths,
+                       index, n, ed_out);
+}
+
 hipError_t launch_verify(const uint32_t* packed, int64_t stream_words, const int64_t* offsets, const int32_t* lengths,
                          const int64_t* index, int64_t n, int32_t max_len, int32_t* ed_out, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     const dim3 grid((unsigned)cdiv(n, 256));
+    if (max_len > 256) {
+        // one pair per wavefront: 2048 positions per word of each lane
+        const int64_t SW = stream_words;
+        if (max_len <= 2048) launch_verify_wave_W<1>(s, packed, SW, offsets, lengths, index, n, ed_out);
+        else if (max_len <= 4096) launch_verify_wave_W<2>(s, packed, SW, offsets, lengths, index, n, ed_out);
+        else if (max_len <= 8192) launch_verify_wave_W<4>(s, packed, SW, offsets, lengths, index, n, ed_out);
+        else if (max_len <= 16384) launch_verify_wave_W<8>(s, packed, SW, offsets, lengths, index, n, ed_out);
+        else if (max_len <= 32768) launch_verify_wave_W<16>(s, packed, SW, offsets, lengths, index, n, ed_out);
+        else launch_verify_wave_W<32>(s, packed, SW, offsets, lengths, index, n, ed_out);
+        return hipGetLastError();
+    }
     if (max_len <= 32) launch_verify_W<1>(grid, s, packed, stream_words, offsets, lengths, index, n, ed_out);
     else if (max_len <= 64) launch_verify_W<2>(grid, s, packed, stream_words, offsets, lengths, index, n, ed_out);
     else if (max_len <= 128) launch_verify_W<4>(grid, s, packed, stream_words, offsets, lengths, index, n, ed_out);

@@ -216,3 +216,52 @@ def test_host_api_errors_leave_outputs(rt):
     assert rc == ss.SS_EINVAL
     assert np.all(acc == 7)
     assert L.ss_filter_batch(None, None, None, 0, 5, None, None) == ss.SS_OK
+
+
+def pinned(a):
+    """A copy of a numpy array in pinned host memory (and the tensor that owns it)."""
+    import torch
+    t = torch.from_numpy(a).pin_memory()
+    return t.numpy(), t
+
+
+@pytest.mark.parametrize("m,E,n", [(100, 5, 700_001), (100, 9, 400_000), (250, 5, 300_003), (2048, 3, 40_000)])
+def test_host_api_pipelined_chunks_match_oracle(rt, m, E, n):
+    """The host entry point for pairs of one length in pinned memory streams the batch to the device in
+    chunks through two staging buffers, copies overlapping the filter (several chunks here, both buffers
+    reused, a ragged last chunk; E = 9 takes the two-kernel schedule inside each chunk); from pageable
+    memory it copies the batch whole.  Every pair against the oracle, both ways."""
+    import paper_1910_09020_amd as ss
+    say(f"  ss_filter_batch m={m} E={E} n={n}, pageable and pinned")
+    if m == 100:
+        b = gen.make(1, n=n, seed=77 + E)
+    elif m == 250:
+        b = gen.make(2, n=n, seed=78)
+    else:
+        b = gen.long_pairs(n, m, 300, 900)
+    want = expect(b, E=E)
+    acc, ed = ss.ss_filter_batch(b["reads"], b["refs"], b["lengths"], E)
+    check(f"ss_filter_batch pageable m={m} E={E}", (acc, ed), want)
+    pr, tr = pinned(b["reads"])
+    pf, tf = pinned(b["refs"])
+    acc2, ed2 = ss.ss_filter_batch(pr, pf, b["lengths"], E)
+    check(f"ss_filter_batch pinned m={m} E={E}", (acc2, ed2), want)
+    del tr, tf
+
+
+def test_host_api_pipelined_bad_base_in_last_chunk(rt):
+    import paper_1910_09020_amd as ss
+    L = ss.lib()
+    b = gen.make(1, n=700_001, seed=79)
+    refs, t_refs = pinned(b["refs"])
+    reads, t_reads = pinned(b["reads"])
+    refs[-3] = ord("N")
+    acc = np.full(b["n"], 7, np.uint8)
+    ed = np.full(b["n"], -9, np.int32)
+    rc = L.ss_filter_batch(reads.ctypes.data, refs.ctypes.data, b["lengths"].ctypes.data, b["n"], 5,
+                           acc.ctypes.data, ed.ctypes.data)
+    assert rc == ss.SS_EBASE
+    assert np.all(acc == 7) and np.all(ed == -9)
+    # the context is usable afterwards
+    a2, e2 = ss.ss_filter_batch(b["reads"], b["refs"], b["lengths"], 5)
+    check("after the error", (a2, e2), expect(b, E=5))

@@ -100,9 +100,89 @@ def test_empty_and_errors(rt):
     cnt = torch.full((1,), 7, dtype=torch.int64, device="cuda")
     ss.ss_verify_async(ctx, ps, db.total, db.offsets, db.lengths, None, 0, 20, out)
     with pytest.raises(ss.SSError) as ei:
-        ss.ss_verify_async(ctx, ps, db.total, db.offsets, db.lengths, None, 2, 257, out)
+        ss.ss_verify_async(ctx, ps, db.total, db.offsets, db.lengths, None, 2, ss.SS_MAX_LEN_VERIFY + 1, out)
     assert ei.value.status == ss.SS_ELEN
     res = torch.zeros(1, dtype=torch.int16, device="cuda")
     ss.ss_select_accepted_async(ctx, res, 0, None, cnt)
     torch.cuda.synchronize()
     assert int(cnt.item()) == 0
+
+
+def _levenshtein_parallel(b, threads=8):
+    """The oracle's Levenshtein distance of every pair, pairs spread over host threads."""
+    from concurrent.futures import ThreadPoolExecutor
+    def one(i):
+        o, m = int(b["offsets"][i]), int(b["lengths"][i])
+        return oracle.levenshtein(b["reads"][o:o + m], b["refs"][o:o + m])
+    with ThreadPoolExecutor(threads) as ex:
+        return np.array(list(ex.map(one, range(len(b["lengths"])))), dtype=np.int32)
+
+
+@pytest.mark.parametrize("max_len,lengths", [
+    (2048, [257, 300, 1000, 2047, 2048, 700, 1500, 2000, 257, 2048]),
+    (4096, [2049, 3000, 4096, 4095, 2500]),
+    (8192, [4097, 5000, 8192, 6000, 7777]),
+    (16384, [8193, 10000, 16384, 12000, 10000]),
+    (32768, [16385, 30000, 20000]),
+    (65536, [40000, 65536]),
+])
+def test_long_pairs_one_wavefront_each(rt, max_len, lengths):
+    """Pairs longer than 256 positions: one pair per wavefront, every word count W (2048 W >= max_len),
+    ragged lengths at and just past the word boundaries, edit rates from none to unrelated, with indels."""
+    ss, runner, torch = rt
+    print(f"  wavefront verify max_len={max_len} lengths={lengths}", flush=True)
+    b = _pairs(lengths, max_len)
+    db = runner.DeviceBatch(b)
+    ps = db.pack_stream()
+    ed = db.verify(ps, max_len=max_len)
+    torch.cuda.synchronize()
+    want = _levenshtein_parallel(b)
+    got = ed[:db.n].cpu().numpy()
+    bad = np.nonzero(got != want)[0]
+    assert len(bad) == 0, f"{len(bad)} mismatches, first {bad[:5]} got {got[bad[:5]]} want {want[bad[:5]]}"
+
+
+def test_long_pair_past_max_len_reports_minus_one(rt):
+    ss, runner, torch = rt
+    b = _pairs([3000, 1000], 11)
+    db = runner.DeviceBatch(b)
+    ps = db.pack_stream()
+    ed = db.verify(ps, max_len=2048)          # the 3,000-position pair does not fit 2,048 positions
+    torch.cuda.synchronize()
+    got = ed[:db.n].cpu().numpy()
+    assert got[0] == -1
+    assert got[1] == oracle.levenshtein(b["reads"][3000:4000], b["refs"][3000:4000])
+
+
+def test_mixed_batch_select_then_verify_short_and_long(rt):
+    """The mixed-length batch (100/150/250 bp and 10 kbp pairs, per-pair thresholds): filter with the
+    batched launch, compact the accepted indices, verify the short ones one pair per lane and the long
+    ones one pair per wavefront: distances equal the oracle's, and no pair with distance <= E was
+    rejected (the filter is lossless)."""
+    ss, runner, torch = rt
+    b = gen.make(3, n=20_000, n_long=40)
+    db = runner.DeviceBatch(b)
+    ps = db.pack_stream()
+    res = db.filter_wave(ps, int(b["E"].max()), per_pair=True)
+    torch.cuda.synchronize()
+    r = res[:db.n].cpu().numpy().astype(np.int64) & 0xFFFF
+    accepted = np.nonzero(r >> 15)[0]
+    lengths = b["lengths"]
+    short = accepted[lengths[accepted] <= 256]
+    long_ = accepted[lengths[accepted] > 256]
+    assert len(long_) > 0
+    for sel, ml in ((short, 256), (long_, 10000)):
+        idx = torch.from_numpy(sel.astype(np.int64)).cuda()
+        ed = db.verify(ps, index=idx, n=len(sel), max_len=ml)
+        torch.cuda.synchronize()
+        got = ed[:len(sel)].cpu().numpy()
+        sub = dict(reads=b["reads"], refs=b["refs"], offsets=b["offsets"][sel], lengths=lengths[sel])
+        want = _levenshtein_parallel(sub)
+        assert np.array_equal(got, want), (ml, np.nonzero(got != want)[0][:5])
+    # lossless: every pair the filter rejected has distance > E (checked on the short pairs and a sample
+    # of the long ones)
+    rejected = np.nonzero((r >> 15) == 0)[0]
+    rs = np.concatenate([rejected[lengths[rejected] <= 256][:3000], rejected[lengths[rejected] > 256][:8]])
+    sub = dict(reads=b["reads"], refs=b["refs"], offsets=b["offsets"][rs], lengths=lengths[rs])
+    dist = _levenshtein_parallel(sub)
+    assert np.all(dist > b["E"][rs])
