@@ -85,6 +85,8 @@ bool plan_items(const int32_t* lengths, const int32_t* E, int64_t n, int rsmax, 
 // Smallest slice width (1, 2, 4 or 8) whose 64 lanes hold the 2E+1 rows of
 // every pair, or 0 when some E needs more than 8 (E > 8191).
 int plan_min_slices(const int32_t* E, int64_t n);
+// SS_EINVAL / SS_ELEN for negative or oversized lengths and thresholds, else SS_OK.
+int validate_plan_inputs(const int32_t* lengths, const int32_t* E, int64_t n);
 // Resident blocks per CU of the persistent kernel for this slice width.
 int persist_blocks_per_cu(int rsmax);
 // Counter reset + persistent kernel on stream s.
