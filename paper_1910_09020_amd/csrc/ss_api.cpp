@@ -16,6 +16,7 @@
 #include "ss.h"
 #include "ss_common.h"
 #include "ss_ctx.h"
+#include "ss_trace.h"
 
 using namespace ss;
 
@@ -372,6 +373,7 @@ bool is_pinned_host(const void* p)
 int filter_host_pipelined(ss_ctx* ctx, const uint8_t* reads, const uint8_t* refs, int64_t n, int32_t m, int32_t E,
                           uint8_t* accept_out, int32_t* edits_out)
 {
+    TraceRange tr("ss_filter_batch: pinned input in chunks");
     const hipStream_t s = ctx->stream;
     // chunks of a multiple of 2048 pairs: each chunk's bases and results start 16-byte aligned
     int64_t K = std::max<int64_t>(2048, (kStageBytes / std::max<int64_t>(1, 2 * (int64_t)m)) / 2048 * 2048);
@@ -463,6 +465,7 @@ int filter_host(const uint8_t* reads, const uint8_t* refs, const int32_t* length
     if (rc != SS_OK) return rc;
     // the device's default context is shared by every host thread: one call at a time uses its buffers
     std::lock_guard<std::mutex> lk(ctx->host_mu);
+    TraceRange tr("ss_filter_batch");
     if (uniform && !E_per_pair && E <= SS_MAX_E_SLICED && lengths[0] > 0 && lengths[0] <= SS_MAX_LEN_FUSED &&
         is_pinned_host(reads) && is_pinned_host(refs))
         return filter_host_pipelined(ctx, reads, refs, n, lengths[0], E, accept_out, edits_out);

@@ -25,6 +25,7 @@
 #include "ss.h"
 #include "ss_common.h"
 #include "ss_items.h"
+#include "ss_trace.h"
 #include "ss_wave.h"
 
 namespace ss {
@@ -386,6 +387,7 @@ extern "C" int ss_plan_create_tuned(ss_ctx* ctx, const int32_t* lengths, const i
                                     const int32_t* lengths_dev, const int32_t* E_dev, uint16_t* out_dev,
                                     const char* cache_path, ss_plan** out, int32_t* chosen_slices)
 {
+    TraceRange tr("plan: autotune");
     if (!ctx || !out) return SS_EINVAL;
     int rc = validate_plan_inputs(lengths, E_per_pair, n_pairs);
     if (rc != SS_OK) return rc;

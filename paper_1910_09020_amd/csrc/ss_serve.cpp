@@ -46,6 +46,7 @@
 #include "ss_common.h"
 #include "ss_arena.h"
 #include "ss_loop.h"
+#include "ss_trace.h"
 
 using namespace ss;
 
@@ -250,6 +251,7 @@ int ensure_loop(ss_server* S)
     }
     if (__atomic_load_n(&S->H->stalled, __ATOMIC_ACQUIRE) != 0) return SS_EDEVICE;
     S->epoch++;
+    roctxMarkA("serve: launch the loop kernel");
     hipError_t e = loop::launch_loop(S->loop_rs, S->loop_grid, S->loop_lds_pad, S->H_dev, S->D, S->epoch,
                                      S->idle_ticks, S->loop_stream);
     if (e == hipSuccess) e = hipEventRecord(S->loop_ev, S->loop_stream);
@@ -262,6 +264,7 @@ int ensure_loop(ss_server* S)
 // Device-resident mode: publish the request in its slot.  Called without the lock.
 int launch_request_loop(ss_server* S, Slot& sl, int si, Request* r)
 {
+    TraceRange tr("serve: publish request to the loop");
     const Layout L(r->n, r->total, r->n_items);
     uint8_t* h = (uint8_t*)r->pin;
     if (!h) {
@@ -310,6 +313,7 @@ int launch_request_loop(ss_server* S, Slot& sl, int si, Request* r)
 // Enqueue the whole request on its slot's stream.  Called without the lock.
 int launch_request(ss_server* S, Slot& sl, Request* r)
 {
+    TraceRange tr("serve: enqueue request on its slot stream");
     const Layout L(r->n, r->total, r->n_items);
     uint8_t* h = (uint8_t*)r->pin;
     if (!h) {
@@ -484,6 +488,7 @@ void completer_main(ss_server* S)
             if (S->loop) {
                 Request* r = sl.cur;
                 if (__atomic_load_n(&S->H->fin[i], __ATOMIC_ACQUIRE) != r->gen) continue;
+                TraceRange tr("serve: hand results to the caller");
                 const uint64_t ta = S->H->t_act[i], tp = S->H->t_packed[i], td = S->H->t_done[i];
                 const bool ordered = ta <= tp && tp <= td;
                 r->ns_h2d = ordered ? (int64_t)(S->tick_ns * (double)(tp - ta)) : 0;
@@ -511,6 +516,7 @@ void completer_main(ss_server* S)
             }
             const hipError_t q = hipEventQuery(sl.done);
             if (q == hipErrorNotReady) continue;
+            TraceRange tr("serve: hand results to the caller");
             Request* r = sl.cur;
             int status = map_err(q);
             if (status == SS_OK) {
@@ -681,6 +687,7 @@ extern "C" int ss_server_submit(ss_server* S, const uint8_t* reads, const uint8_
 {
     if (!S || !ticket || n_pairs < 0) return SS_EINVAL;
     if (n_pairs > 0 && (!reads || !refs || !lengths || !E_per_pair || !accept_out || !edits_out)) return SS_EINVAL;
+    TraceRange tr("serve: submit (plan and stage)");
     int64_t T = 0;
     for (int64_t i = 0; i < n_pairs; i++) {
         if (lengths[i] < 0 || E_per_pair[i] < 0) return SS_EINVAL;
