@@ -208,14 +208,26 @@ def long_leg(torch, ss, gen, runner, oracle, n=2000, m=100_000, E=5000, steps=3)
     mism = int(np.sum((w["accept"] != acc[:k]) | (w["edits"] != ed[:k])))
     same = bool(np.array_equal(acc, pacc) and np.array_equal(ed, ped))
     ss.ss_plan_destroy(plan)
+    # banded verification of every pair (distance when within E, else E + 1): false accept rate, no false reject
+    vout = torch.empty(n, dtype=torch.int32, device="cuda")
+    vb = lambda: db.verify_banded(ps, E, out=vout)
+    vb(); torch.cuda.synchronize()
+    _, (vb_ms,) = timed_loop([vb], 1, torch)
+    vd = vout.cpu().numpy()
+    over = vd > E
+    verify = dict(banded_verify_ms=round(vb_ms, 3), pairs_over_E=int(over.sum()),
+                  false_accepts=int((acc.astype(bool) & over).sum()),
+                  false_accept_rate=float((acc.astype(bool) & over).sum() / max(1, over.sum())),
+                  false_rejects=int((~acc.astype(bool) & ~over).sum()))
     log(f"100 kbp: {n} pairs at E={E}: wave {wave_ms:.2f} ms, planned {plan_ms:.2f} ms, identical={same}, "
-        f"accepted {int(acc.sum())}, oracle mismatches {mism}/{k}")
+        f"accepted {int(acc.sum())}, oracle mismatches {mism}/{k}; banded verify {verify}")
     res = dict(workload=f"{n} pairs of {m} bp, edit rate U[3%,7%], E={E}", n_pairs=n, m=m, E=E,
                wave_ms=round(wave_ms, 3), planned_ms=round(plan_ms, 3),
                pairs_per_s=n / (1e-3 * min(wave_ms, plan_ms)),
                cells_per_s=n * m * (2 * E + 1) / (1e-3 * min(wave_ms, plan_ms)),
-               accepted=int(acc.sum()), identical_outputs=same, oracle_sample_pairs=k, oracle_sample_mismatches=mism)
-    del db, ps, out, pout
+               accepted=int(acc.sum()), identical_outputs=same, oracle_sample_pairs=k, oracle_sample_mismatches=mism,
+               verify=verify)
+    del db, ps, out, pout, vout
     torch.cuda.empty_cache()
     return res
 

@@ -65,6 +65,7 @@ const char* ss_status_str(int status);
 #define SS_MAX_LEN        (1 << 24)
 #define SS_MAX_LEN_FUSED  2048    /* fused encode-and-filter kernel: m <= 2048 */
 #define SS_MAX_LEN_VERIFY 65536   /* verification: m <= 65536 (one pair per lane up to 256) */
+#define SS_MAX_E_VERIFY_BANDED 16351  /* banded verification: 2 E + 65 <= 16 x 2048 window positions */
 /* wavefront, batched and serving paths: a bit stream of at most this many
  * bases (each plane under 4 GiB: its words are read with 32-bit offsets) */
 #define SS_MAX_STREAM_BASES (32LL * ((1LL << 30) - 64))
@@ -369,6 +370,23 @@ int ss_verify_async(ss_ctx* ctx, const uint32_t* packed, int64_t total_bases, co
                     const int32_t* lengths, const int64_t* index, int64_t n, int32_t max_len, int32_t* ed_out,
                     void* stream);
 
+/* Banded verification, any length (up to SS_MAX_LEN): ed_out[k] = the edit
+ * distance of the k-th listed pair when it is at most that pair's threshold
+ * (E_per_pair[p], or E for every pair when E_per_pair is NULL), else the
+ * threshold + 1.  E must be >= every listed threshold (it sizes the window),
+ * <= SS_MAX_E_VERIFY_BANDED (SS_ELEN beyond).  Pairs of equal length in the
+ * bit-stream layout, index as for ss_verify_async.  One pair per wavefront:
+ * Myers' bit-vector algorithm over a window of the query that follows the
+ * diagonal band |i - j| <= threshold (Ukkonen's observation that a path of
+ * cost <= k never leaves it), in 32-row words that leave the window at the
+ * bottom and enter it at the top as the band moves; rows outside the window
+ * are taken at values never below their true ones, so the distance is exact
+ * whenever it is within the threshold.  Time ~ m * threshold / 2048 per pair
+ * instead of m * m.  Asynchronous on stream. */
+int ss_verify_banded_async(ss_ctx* ctx, const uint32_t* packed, int64_t total_bases, const int64_t* offsets,
+                           const int32_t* lengths, const int32_t* E_per_pair, int32_t E, const int64_t* index,
+                           int64_t n, int32_t* ed_out, void* stream);
+
 /* Indices of the accepted pairs of n result words (bit 15 set), written to
  * index_out (device, room for n entries) in no particular order; their number
  * to *count_out (device int64, cleared by this call with a kernel, not a
@@ -474,7 +492,11 @@ int64_t ss_server_footprint(int64_t n_pairs, int64_t total_bases);
  * the result words into the staging block; the block that finishes a
  * request's last item marks the slot done, and the completion thread polls
  * those marks.  The kernel ends after 200 ms with nothing to do and is launched
- * again when a request arrives; while it runs it holds every CU it fits on.
+ * again when a request arrives.  While it runs it holds one block on every CU,
+ * so other kernels on the device wait until it has been idle for 200 ms: one
+ * loop server per device at a time (a second creation on the same device
+ * returns SS_EAGAIN until the first is destroyed), and other GPU work of the
+ * process is best kept off the device while requests flow.
  * Device memory: hbm_budget_bytes are reserved at creation as one arena; a
  * request takes the room of its four bit planes, 16 * (ceil(total_bases / 32)
  * + 2) bytes rounded up to 256, from it, and admission waits while the arena

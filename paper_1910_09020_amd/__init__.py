@@ -28,6 +28,7 @@ SS_MAX_E_PLANNED = 8191
 SS_MAX_LEN = 1 << 24
 SS_MAX_LEN_FUSED = 2048
 SS_MAX_LEN_VERIFY = 65536
+SS_MAX_E_VERIFY_BANDED = 16351
 SS_MAX_STREAM_BASES = 32 * ((1 << 30) - 64)
 SS_NOALLOC_SCRATCH_BYTES = 32 << 20
 SS_RESULT_ACCEPT = 0x8000
@@ -77,6 +78,7 @@ def lib():
         "ss_filter_sliced_async": ([vp, vp, i64, i32, i32, vp, vp], ctypes.c_int),
         "ss_filter_ascii_async": ([vp, vp, vp, i64, i32, i32, i32, vp, vp, vp], ctypes.c_int),
         "ss_verify_async": ([vp, vp, i64, vp, vp, vp, i64, i32, vp, vp], ctypes.c_int),
+        "ss_verify_banded_async": ([vp, vp, i64, vp, vp, vp, i32, vp, i64, vp, vp], ctypes.c_int),
         "ss_filter_submaze_async": ([vp, vp, i64, i32, i32, i32, vp, vp], ctypes.c_int),
         "ss_select_accepted_async": ([vp, vp, i64, vp, vp, vp], ctypes.c_int),
         "ss_pack_stream_async": ([vp, vp, vp, i64, vp, vp, vp], ctypes.c_int),
@@ -132,7 +134,7 @@ def exported_symbols():
             "ss_server_wait", "ss_server_times", "ss_server_cancel", "ss_server_release", "ss_server_set_hold",
             "ss_server_stats", "ss_server_destroy", "ss_server_footprint", "ss_server_set_slices", "ss_pack_words",
             "ss_pack", "ss_filter_batch_ex", "ss_filter_batch_pairs", "ss_filter_ascii_noalloc",
-            "ss_server_stages", "ss_server_create_loop"]
+            "ss_server_stages", "ss_server_create_loop", "ss_verify_banded_async"]
 
 
 def status_str(status: int) -> str:
@@ -276,6 +278,12 @@ def ss_filter_ascii_noalloc(ctx, reads, refs, n_pairs, m, E, out, err, stream=No
 def ss_filter_submaze_async(ctx, packed, n_pairs, m, E, sub_width, out, stream=None):
     _check(lib().ss_filter_submaze_async(ctx, _ptr(packed), int(n_pairs), int(m), int(E), int(sub_width), _ptr(out),
                                          _stream(stream)), "ss_filter_submaze_async")
+
+
+def ss_verify_banded_async(ctx, packed, total_bases, offsets, lengths, E_per_pair, E, index, n, ed_out, stream=None):
+    _check(lib().ss_verify_banded_async(ctx, _ptr(packed), int(total_bases), _ptr(offsets), _ptr(lengths),
+                                        _ptr(E_per_pair), int(E), _ptr(index), int(n), _ptr(ed_out), _stream(stream)),
+           "ss_verify_banded_async")
 
 
 def ss_verify_async(ctx, packed, total_bases, offsets, lengths, index, n, max_len, ed_out, stream=None):

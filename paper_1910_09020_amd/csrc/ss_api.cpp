@@ -190,6 +190,18 @@ extern "C" int ss_verify_async(ss_ctx* ctx, const uint32_t* packed, int64_t tota
                                  (hipStream_t)stream));
 }
 
+extern "C" int ss_verify_banded_async(ss_ctx* ctx, const uint32_t* packed, int64_t total_bases,
+                                      const int64_t* offsets, const int32_t* lengths, const int32_t* E_per_pair,
+                                      int32_t E, const int64_t* index, int64_t n, int32_t* ed_out, void* stream)
+{
+    if (!ctx || n < 0 || total_bases < 0 || E < 0) return SS_EINVAL;
+    if (E > SS_MAX_E_VERIFY_BANDED) return SS_ELEN;
+    if (n == 0) return SS_OK;
+    if (!packed || !offsets || !lengths || !ed_out) return SS_EINVAL;
+    return map_err(launch_verify_banded(packed, ss_stream_words(total_bases), offsets, lengths, E_per_pair, E, index,
+                                        n, ed_out, (hipStream_t)stream));
+}
+
 extern "C" int ss_select_accepted_async(ss_ctx* ctx, const uint16_t* results, int64_t n, int64_t* index_out,
                                         int64_t* count_out, void* stream)
 {

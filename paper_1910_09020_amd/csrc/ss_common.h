@@ -57,6 +57,10 @@ hipError_t launch_wave(const uint32_t* packed, int64_t stream_words, const int64
                        hipStream_t s);
 // Verification: exact edit distance of the listed pairs (bit-stream layout, m <= 256), and the
 // compaction of accepted pairs' indices.
+// Banded edit distance (E_per_pair may be null: E for every pair; else E >= every entry).
+hipError_t launch_verify_banded(const uint32_t* packed, int64_t stream_words, const int64_t* offsets,
+                                const int32_t* lengths, const int32_t* E_per_pair, int32_t E, const int64_t* index,
+                                int64_t n, int32_t* ed_out, hipStream_t s);
 hipError_t launch_verify(const uint32_t* packed, int64_t stream_words, const int64_t* offsets, const int32_t* lengths,
                          const int64_t* index, int64_t n, int32_t max_len, int32_t* ed_out, hipStream_t s);
 hipError_t launch_select(const uint16_t* results, int64_t n, int64_t* index_out, unsigned long long* count,

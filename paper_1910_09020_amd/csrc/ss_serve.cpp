@@ -607,6 +607,12 @@ namespace {
 
 constexpr int kLoopIdleMs = 200;     // the loop kernel ends after this long with nothing to do
 
+// Devices that hold a device-resident loop server: its kernel takes every CU
+// while it runs, so a second one on the same device would wait for the first
+// to go idle.
+std::mutex g_loop_mu;
+bool g_loop_dev[64] = {};
+
 void free_loop(ss_server* S)
 {
     if (S->loop_stream) (void)hipStreamSynchronize(S->loop_stream);
@@ -630,17 +636,33 @@ extern "C" int ss_server_create_loop(ss_ctx* ctx, size_t hbm_budget_bytes, int32
     if (!ctx || !out || n_slots < 1 || n_slots > loop::kSlots || hbm_budget_bytes < 4096) return SS_EINVAL;
     if (slices_per_lane != 1 && slices_per_lane != 2 && slices_per_lane != 4 && slices_per_lane != 8)
         return SS_EINVAL;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return SS_EDEVICE;
+    {
+        std::lock_guard<std::mutex> lk(g_loop_mu);
+        if (g_loop_dev[dev]) return SS_EAGAIN;          // one device-resident loop per device
+        g_loop_dev[dev] = true;
+    }
     ss_server* S = new (std::nothrow) ss_server();
-    if (!S) return SS_ENOMEM;
+    if (!S) {
+        std::lock_guard<std::mutex> lk(g_loop_mu);
+        g_loop_dev[dev] = false;
+        return SS_ENOMEM;
+    }
     S->ctx = ctx;
-    (void)hipGetDevice(&S->device);
+    S->device = dev;
     S->budget = hbm_budget_bytes;
     S->loop = true;
     S->loop_rs = slices_per_lane;
     S->rsmax = slices_per_lane;
     S->pool.flags = hipHostMallocCoherent | hipHostMallocMapped;
     hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, S->device) != hipSuccess) { delete S; return SS_EDEVICE; }
+    if (hipGetDeviceProperties(&prop, S->device) != hipSuccess) {
+        std::lock_guard<std::mutex> lk(g_loop_mu);
+        g_loop_dev[dev] = false;
+        delete S;
+        return SS_EDEVICE;
+    }
     {
         // One block per CU, so that a request's long items each own a CU's four SIMDs: every block
         // reserves more than half of a CU's LDS, and the dispatcher cannot stack two on one CU (with
@@ -671,6 +693,8 @@ extern "C" int ss_server_create_loop(ss_ctx* ctx, size_t hbm_budget_bytes, int32
     if (e != hipSuccess) {
         free_loop(S);
         delete S;
+        std::lock_guard<std::mutex> lk(g_loop_mu);
+        g_loop_dev[dev] = false;
         return map_err(e);
     }
     S->arena_alloc.reset(hbm_budget_bytes);
@@ -905,6 +929,8 @@ extern "C" int ss_server_destroy(ss_server* S)
         // nothing is in flight any more: the loop kernel ends at its next look at the stop word
         __atomic_store_n(&S->H->stop, 1ull, __ATOMIC_RELEASE);
         free_loop(S);
+        std::lock_guard<std::mutex> lk(g_loop_mu);
+        g_loop_dev[S->device] = false;
     }
     for (auto& sl : S->slots) {
         if (sl.stream) (void)hipStreamSynchronize(sl.stream);

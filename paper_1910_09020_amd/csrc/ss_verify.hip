@@ -177,6 +177,133 @@ __global__ __launch_bounds__(256) void k_verify_wave(const uint32_t* __restrict_
     if (lane == 0) ed_out[k] = score;
 }
 
+// Banded form, one pair per wavefront: the edit distance when it is at most the
+// pair's threshold Ep, else Ep + 1, in time proportional to m * Ep instead of
+// m * m.  The wavefront holds a window of 32-position words of the query (lane
+// L: words W L .. W L + W - 1), bottom position lo.  Every 32 columns, when the
+// window's bottom word lies wholly below the band |i - j| <= Ep for the coming
+// columns, it is dropped: its vertical deltas are added to the value B of the
+// row under the window, the other words move down one word, and a new word
+// enters at the top with vertical deltas +1.  Within a column, the row under
+// the window is taken to grow by 1 (its horizontal delta is +1, entered as the
+// bottom shift-in as for row 0 of the full form).  Every value so assumed is at
+// least the true one (a row never exceeds the row below it plus one, nor its
+// left neighbour plus one), so computed values are never below the true ones,
+// and every cell on an optimal path of cost <= Ep (which stays within Ep / 2 of
+// the diagonal) is computed from exact neighbours: D[m][m] is exact when it is
+// <= Ep.  At the end D[m][m] = B + the vertical deltas of the window's rows up
+// to m.  The window needs 2048 W >= 2 Ep + 65 positions.
+template <int W>
+__global__ __launch_bounds__(256) void k_verify_band(const uint32_t* __restrict__ pk, int64_t SW,
+                                                     const int64_t* __restrict__ offsets,
+                                                     const int32_t* __restrict__ lengths,
+                                                     const int32_t* __restrict__ Epp, int32_t E,
+                                                     const int64_t* __restrict__ index, int64_t n,
+                                                     int32_t* __restrict__ ed_out)
+{
+    const int lane = (int)(threadIdx.x & 63);
+    const int64_t k = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    if (k >= n) return;                                  // the whole wavefront
+    const int64_t p = index ? index[k] : k;
+    const int m = __builtin_amdgcn_readfirstlane(lengths[p]);
+    const int Ep = __builtin_amdgcn_readfirstlane(Epp ? Epp[p] : E);
+    const int64_t b0 = offsets[p];
+    const uint32_t* __restrict__ Q0 = pk;
+    const uint32_t* __restrict__ Q1 = pk + SW;
+    const uint32_t* __restrict__ R0 = pk + 2 * SW;
+    const uint32_t* __restrict__ R1 = pk + 3 * SW;
+    if (2 * (int64_t)Ep + 65 > 2048 * W) {
+        if (lane == 0) ed_out[k] = -1;                   // the window cannot hold this threshold's band
+        return;
+    }
+    uint32_t q0[W], q1[W], pv[W], mv[W];
+    int lo = 0;                                          // query position of the window's bottom row
+    auto load_query = [&]() {
+#pragma unroll
+        for (int w = 0; w < W; w++) {
+            const int64_t at = b0 + lo + 32 * ((int64_t)W * lane + w);
+            q0[w] = wave::bits32(Q0, SW, at);
+            q1[w] = wave::bits32(Q1, SW, at);
+        }
+    };
+    load_query();
+#pragma unroll
+    for (int w = 0; w < W; w++) {
+        pv[w] = ~0u;
+        mv[w] = 0u;
+    }
+    int B = 0;                                           // D of the row under the window, this column
+    for (int jb = 0; jb < m; jb += 32) {
+        if (lo + 32 <= jb - Ep) {
+            // drop the bottom word (lane 0, word 0): its rows' vertical deltas go into B
+            B += __builtin_amdgcn_readlane(__popc(pv[0]) - __popc(mv[0]), 0);
+            const uint32_t pn = __shfl_down(pv[0], 1), mn = __shfl_down(mv[0], 1);
+#pragma unroll
+            for (int w = 0; w + 1 < W; w++) {
+                pv[w] = pv[w + 1];
+                mv[w] = mv[w + 1];
+            }
+            pv[W - 1] = lane == 63 ? ~0u : pn;
+            mv[W - 1] = lane == 63 ? 0u : mn;
+            lo += 32;
+            load_query();
+        }
+        const uint32_t rw0 = __builtin_amdgcn_readfirstlane(wave::bits32(R0, SW, b0 + jb));
+        const uint32_t rw1 = __builtin_amdgcn_readfirstlane(wave::bits32(R1, SW, b0 + jb));
+        const int jend = m - jb < 32 ? m - jb : 32;
+        for (int jj = 0; jj < jend; jj++) {
+            const uint32_t rb0 = (uint32_t)__builtin_amdgcn_sbfe((int)rw0, jj, 1);
+            const uint32_t rb1 = (uint32_t)__builtin_amdgcn_sbfe((int)rw1, jj, 1);
+            uint32_t eq[W], sum[W], carry = 0, ones = ~0u;
+#pragma unroll
+            for (int w = 0; w < W; w++) {
+                eq[w] = wave::and_xnor(wave::and_xnor(~0u, q0[w], rb0), q1[w], rb1);
+                const uint64_t s = (uint64_t)(eq[w] & pv[w]) + pv[w] + carry;
+                sum[w] = (uint32_t)s;
+                carry = (uint32_t)(s >> 32);
+                ones &= sum[w];
+            }
+            const uint64_t G = __ballot(carry != 0u);
+            const uint64_t P = __ballot(ones == ~0u);
+            uint32_t cin = (uint32_t)((((G + (G | P)) ^ P) >> lane) & 1ull);
+            uint32_t ph[W], mh[W];
+#pragma unroll
+            for (int w = 0; w < W; w++) {
+                const uint32_t sw = sum[w] + cin;
+                cin = sw < cin ? 1u : 0u;
+                const uint32_t xh = (sw ^ pv[w]) | eq[w];
+                ph[w] = mv[w] | ~(xh | pv[w]);
+                mh[w] = pv[w] & xh;
+            }
+            const uint32_t ph_top = __shfl_up(ph[W - 1] >> 31, 1), mh_top = __shfl_up(mh[W - 1] >> 31, 1);
+            uint32_t ph_in = lane == 0 ? 1u : ph_top, mh_in = lane == 0 ? 0u : mh_top;
+#pragma unroll
+            for (int w = 0; w < W; w++) {
+                const uint32_t xv = eq[w] | mv[w];
+                const uint32_t phs = (ph[w] << 1) | ph_in, mhs = (mh[w] << 1) | mh_in;
+                ph_in = ph[w] >> 31;
+                mh_in = mh[w] >> 31;
+                pv[w] = mhs | ~(xv | phs);
+                mv[w] = phs & xv;
+            }
+            B += 1;
+        }
+    }
+    // D[m][m]: B plus the vertical deltas of the window's rows below position m
+    int part = 0;
+#pragma unroll
+    for (int w = 0; w < W; w++) {
+        const int first = lo + 32 * (W * lane + w);
+        const int keep = m - first;                      // positions of this word below m
+        const uint32_t mask = keep >= 32 ? ~0u : (keep <= 0 ? 0u : ((1u << keep) - 1u));
+        part += __popc(pv[w] & mask) - __popc(mv[w] & mask);
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) part += __shfl_xor(part, o);
+    const int D = B + part;
+    if (lane == 0) ed_out[k] = D <= Ep ? D : Ep + 1;
+}
+
 __global__ void k_zero_count(unsigned long long* count) { *count = 0ull; }
 
 // Indices of accepted pairs (result bit 15 set).  A block takes 4096 results
@@ -259,6 +386,34 @@ hipError_t launch_verify(const uint32_t* packed, int64_t stream_words, const int
     else if (max_len <= 64) launch_verify_W<2>(grid, s, packed, stream_words, offsets, lengths, index, n, ed_out);
     else if (max_len <= 128) launch_verify_W<4>(grid, s, packed, stream_words, offsets, lengths, index, n, ed_out);
     else launch_verify_W<8>(grid, s, packed, stream_words, offsets, lengths, index, n, ed_out);
+    return hipGetLastError();
+}
+
+template <int W>
+static void launch_band_W(hipStream_t s, const uint32_t* packed, int64_t SW, const int64_t* offsets,
+                          const int32_t* lengths, const int32_t* Epp, int32_t E, const int64_t* index, int64_t n,
+                          int32_t* ed_out)
+{
+    hipLaunchKernelGGL(k_verify_band<W>, dim3((unsigned)cdiv(n, 4)), dim3(256), 0, s, packed, SW, offsets, lengths,
+                       Epp, E, index, n, ed_out);
+}
+
+hipError_t launch_verify_banded(const uint32_t* packed, int64_t stream_words, const int64_t* offsets,
+                                const int32_t* lengths, const int32_t* Epp, int32_t E, const int64_t* index,
+                                int64_t n, int32_t* ed_out, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    const int64_t need = 2 * (int64_t)E + 65;             // window positions for the largest threshold
+    const int64_t SW = stream_words;
+    if (need <= 2048) launch_band_W<1>(s, packed, SW, offsets, lengths, Epp, E, index, n, ed_out);
+    else if (need <= 2 * 2048) launch_band_W<2>(s, packed, SW, offsets, lengths, Epp, E, index, n, ed_out);
+    else if (need <= 3 * 2048) launch_band_W<3>(s, packed, SW, offsets, lengths, Epp, E, index, n, ed_out);
+    else if (need <= 4 * 2048) launch_band_W<4>(s, packed, SW, offsets, lengths, Epp, E, index, n, ed_out);
+    else if (need <= 5 * 2048) launch_band_W<5>(s, packed, SW, offsets, lengths, Epp, E, index, n, ed_out);
+    else if (need <= 6 * 2048) launch_band_W<6>(s, packed, SW, offsets, lengths, Epp, E, index, n, ed_out);
+    else if (need <= 8 * 2048) launch_band_W<8>(s, packed, SW, offsets, lengths, Epp, E, index, n, ed_out);
+    else if (need <= 12 * 2048) launch_band_W<12>(s, packed, SW, offsets, lengths, Epp, E, index, n, ed_out);
+    else launch_band_W<16>(s, packed, SW, offsets, lengths, Epp, E, index, n, ed_out);
     return hipGetLastError();
 }
 

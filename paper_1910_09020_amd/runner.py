@@ -8,7 +8,8 @@ from __future__ import annotations
 import numpy as np
 import torch
 
-from . import (ss_create, ss_filter_ascii_async, ss_filter_submaze_async, ss_select_accepted_async, ss_verify_async, ss_filter_plain_async, ss_filter_sliced_async, ss_filter_wave_async,
+from . import (ss_create, ss_filter_ascii_async, ss_filter_submaze_async, ss_select_accepted_async, ss_verify_async,
+               ss_verify_banded_async, ss_filter_plain_async, ss_filter_sliced_async, ss_filter_wave_async,
                ss_pack_sliced_async, ss_pack_stream_async, ss_sliced_bytes, ss_stream_words)
 
 _ctx = {}
@@ -153,6 +154,16 @@ class DeviceBatch:
         out = torch.empty(max(1, n), dtype=torch.int32, device=_dev(self.device)) if out is None else out
         ss_verify_async(context(self.device), packed, self.total, self.offsets, self.lengths, index, n, max_len, out,
                         stream or torch.cuda.current_stream(self.device))
+        return out
+
+    def verify_banded(self, packed, E: int, per_pair: bool = False, index=None, n=None, out=None,
+                      stream=None) -> torch.Tensor:
+        """Edit distance when within the threshold (per pair, or E), else threshold + 1; int32 per entry."""
+        n = (self.n if index is None else int(index.numel())) if n is None else n
+        out = torch.empty(max(1, n), dtype=torch.int32, device=_dev(self.device)) if out is None else out
+        ss_verify_banded_async(context(self.device), packed, self.total, self.offsets, self.lengths,
+                               self.E if per_pair else None, E, index, n, out,
+                               stream or torch.cuda.current_stream(self.device))
         return out
 
     def select_accepted(self, results, index_out=None, count=None, stream=None):

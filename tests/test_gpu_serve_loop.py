@@ -181,8 +181,15 @@ def test_loop_hold_cancel_bad_base_empty_and_refusals(env):
         assert ei.value.status == ss.SS_ELEN
         with pytest.raises(ss.SSError):
             ss.ss_server_set_slices(srv, 2)
+        # one device-resident loop per device
+        with pytest.raises(ss.SSError) as ei:
+            ss.ss_server_create_loop(ctx, 1 << 20, 2, 1)
+        assert ei.value.status == ss.SS_EAGAIN
     finally:
         ss.ss_server_destroy(srv)
+    # free again once the first is gone
+    srv2 = ss.ss_server_create_loop(ctx, 1 << 20, 2, 1)
+    ss.ss_server_destroy(srv2)
 
 
 def test_loop_destroy_waits_for_requests_in_flight(env):

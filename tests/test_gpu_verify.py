@@ -186,3 +186,84 @@ def test_mixed_batch_select_then_verify_short_and_long(rt):
     sub = dict(reads=b["reads"], refs=b["refs"], offsets=b["offsets"][rs], lengths=lengths[rs])
     dist = _levenshtein_parallel(sub)
     assert np.all(dist > b["E"][rs])
+
+
+def _within(ed, E):
+    return np.where(ed <= E, ed, E + 1).astype(np.int32)
+
+
+@pytest.mark.parametrize("E", [0, 3, 10, 50, 300, 1100])
+def test_banded_ragged_lengths(rt, E):
+    """Banded verification: the distance when within E, else E + 1, for ragged lengths up to 5,000 at
+    every edit rate, with indels; E = 1,100 takes two words per lane."""
+    ss, runner, torch = rt
+    print(f"  banded verify E={E}", flush=True)
+    lengths = [0, 1, 2, 31, 32, 33, 100, 257, 700, 1000, 2047, 2048, 2049, 3000, 5000] * 2
+    b = _pairs(lengths, 40 + E)
+    db = runner.DeviceBatch(b)
+    ps = db.pack_stream()
+    ed = db.verify_banded(ps, E)
+    torch.cuda.synchronize()
+    want = _within(_levenshtein_parallel(b), E)
+    got = ed[:db.n].cpu().numpy()
+    bad = np.nonzero(got != want)[0]
+    assert len(bad) == 0, f"{len(bad)} mismatches, first {bad[:5]} got {got[bad[:5]]} want {want[bad[:5]]}"
+
+
+def test_banded_per_pair_thresholds_and_limits(rt):
+    ss, runner, torch = rt
+    lengths = [50, 400, 1200, 3000, 6000] * 4
+    b = _pairs(lengths, 77)
+    rng = np.random.default_rng(3)
+    b["E"] = rng.integers(0, 400, size=len(lengths)).astype(np.int32)
+    db = runner.DeviceBatch(b)
+    ps = db.pack_stream()
+    ed = db.verify_banded(ps, int(b["E"].max()), per_pair=True)
+    torch.cuda.synchronize()
+    want = _within(_levenshtein_parallel(b), b["E"])
+    assert np.array_equal(ed[:db.n].cpu().numpy(), want)
+    # the largest threshold the window holds, on short pairs; one past it is refused
+    ed2 = db.verify_banded(ps, ss.SS_MAX_E_VERIFY_BANDED)
+    torch.cuda.synchronize()
+    assert np.array_equal(ed2[:db.n].cpu().numpy(), _levenshtein_parallel(b))
+    with pytest.raises(ss.SSError) as ei:
+        db.verify_banded(ps, ss.SS_MAX_E_VERIFY_BANDED + 1)
+    assert ei.value.status == ss.SS_ELEN
+
+
+def test_banded_long_pairs_30kbp_and_100kbp(rt):
+    """Long pairs at thresholds that need five and six words per lane: 30 kbp at E = 4,500 and
+    100 kbp at E = 5,000 (the workload of the 100 kbp row), against the oracle's full Levenshtein."""
+    ss, runner, torch = rt
+    print("  banded verify 30 kbp E=4500 and 100 kbp E=5000", flush=True)
+    b = gen.long_pairs(4, 30000, 300, 2000, seed=91)
+    db = runner.DeviceBatch(b)
+    ps = db.pack_stream()
+    ed = db.verify_banded(ps, 4500)
+    torch.cuda.synchronize()
+    want = _within(_levenshtein_parallel(b), 4500)
+    assert np.array_equal(ed[:db.n].cpu().numpy(), want), (ed[:db.n].cpu().numpy(), want)
+    b = gen.long_pairs(2, 100000, 300, 700, seed=92)
+    db = runner.DeviceBatch(b)
+    ps = db.pack_stream()
+    ed = db.verify_banded(ps, 5000)
+    torch.cuda.synchronize()
+    want = _within(_levenshtein_parallel(b), 5000)
+    assert np.array_equal(ed[:db.n].cpu().numpy(), want), (ed[:db.n].cpu().numpy(), want)
+
+
+def test_banded_equals_full_within_threshold_on_the_mixed_batch(rt):
+    """On the mixed batch's 10 kbp pairs, the banded distance at each pair's threshold equals the full
+    distance (one pair per wavefront) clipped to threshold + 1."""
+    ss, runner, torch = rt
+    b = gen.make(3, n=2_000, n_long=200)
+    db = runner.DeviceBatch(b)
+    ps = db.pack_stream()
+    long_idx = np.nonzero(b["lengths"] > 256)[0]
+    idx = torch.from_numpy(long_idx.astype(np.int64)).cuda()
+    full = db.verify(ps, index=idx, n=len(long_idx), max_len=10000)
+    banded = db.verify_banded(ps, int(b["E"].max()), per_pair=True, index=idx, n=len(long_idx))
+    torch.cuda.synchronize()
+    f = full[:len(long_idx)].cpu().numpy()
+    E = b["E"][long_idx]
+    assert np.array_equal(banded[:len(long_idx)].cpu().numpy(), _within(f, E))
