@@ -513,6 +513,12 @@ int64_t ss_server_footprint(int64_t n_pairs, int64_t total_bases);
  * SS_EDEVICE. */
 int ss_server_create_loop(ss_ctx* ctx, size_t hbm_budget_bytes, int32_t n_slots, int32_t slices_per_lane,
                           ss_server** out);
+/* Device-resident loop only: how long (microseconds, 1 .. 60 s; 200 ms by
+ * default) the loop kernel stays resident with nothing to do before it ends
+ * and frees the CUs; a request that arrives after that pays a kernel launch.
+ * Takes effect at the next launch of the loop.  SS_EINVAL for a server of the
+ * other kind. */
+int ss_server_set_loop_idle(ss_server* server, int64_t idle_us);
 
 /* Submit one request (host arrays, copied before returning; E_per_pair is
  * required).  accept_out / edits_out (host, n_pairs entries) are written by

@@ -96,6 +96,7 @@ def lib():
                                   vp], ctypes.c_int),
         "ss_server_create": ([vp, ctypes.c_size_t, i32, ctypes.POINTER(vp)], ctypes.c_int),
         "ss_server_create_loop": ([vp, ctypes.c_size_t, i32, i32, ctypes.POINTER(vp)], ctypes.c_int),
+        "ss_server_set_loop_idle": ([vp, i64], ctypes.c_int),
         "ss_server_submit": ([vp, vp, vp, vp, vp, i64, vp, vp, ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
         "ss_server_poll": ([vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
         "ss_server_wait": ([vp, ctypes.c_uint64, i64], ctypes.c_int),
@@ -134,7 +135,7 @@ def exported_symbols():
             "ss_server_wait", "ss_server_times", "ss_server_cancel", "ss_server_release", "ss_server_set_hold",
             "ss_server_stats", "ss_server_destroy", "ss_server_footprint", "ss_server_set_slices", "ss_pack_words",
             "ss_pack", "ss_filter_batch_ex", "ss_filter_batch_pairs", "ss_filter_ascii_noalloc",
-            "ss_server_stages", "ss_server_create_loop", "ss_verify_banded_async"]
+            "ss_server_stages", "ss_server_create_loop", "ss_verify_banded_async", "ss_server_set_loop_idle"]
 
 
 def status_str(status: int) -> str:
@@ -397,6 +398,10 @@ def ss_server_create_loop(ctx, hbm_budget_bytes: int, n_slots: int = 32, slices_
     _check(lib().ss_server_create_loop(ctx, int(hbm_budget_bytes), int(n_slots), int(slices_per_lane),
                                        ctypes.byref(h)), "ss_server_create_loop")
     return h.value
+
+
+def ss_server_set_loop_idle(server, idle_us: int) -> None:
+    _check(lib().ss_server_set_loop_idle(server, int(idle_us)), "ss_server_set_loop_idle")
 
 
 def ss_server_submit(server, reads, refs, lengths, E_per_pair, accept_out, edits_out) -> int:

@@ -99,16 +99,19 @@ struct Dev {
     uint64_t adm_next;
     uint32_t quit;               // epoch of the launch whose scheduler ended the loop
     uint32_t progress;           // units finished (any slot), watched by the scheduler
+    alignas(128) uint64_t beat;  // device clock at the scheduler's last look (its heartbeat; a cache
+                                 // line of its own, away from the words the workers poll)
+    uint64_t pad_beat[15];
 };
 
 // The loop kernel on stream s: grid blocks of 256 threads (block 0 schedules).
 // It returns once nothing has been in flight for idle_ticks of the device's
 // constant-rate clock, sooner after host->stop is set, and also when requests
-// are active but no unit has finished for ten idle periods (host->stalled).
+// are active but no unit has finished for stall_ticks (host->stalled).
 // lds_pad: dynamic LDS reserved (and left unused) per block, which caps the
 // blocks a CU can hold.
 hipError_t launch_loop(int rsmax, int grid, size_t lds_pad, Host* host, Dev* dev, uint32_t epoch,
-                       uint64_t idle_ticks, hipStream_t s);
+                       uint64_t idle_ticks, uint64_t stall_ticks, hipStream_t s);
 // Static LDS bytes of one block of the loop kernel.
 size_t loop_static_lds(int rsmax);
 

@@ -23,12 +23,13 @@
 //
 // Exit: every wait here ends.  The scheduler returns once no request has been
 // active or new for idle_ticks (or once host->stop is set and nothing is
-// active), or when requests are active but no unit has finished for ten idle
-// periods (then it also sets host->stalled), and raises the launch's quit
+// active), or when requests are active but no unit has finished for
+// stall_ticks (then it also sets host->stalled), and raises the launch's quit
 // epoch.  A worker returns when it finds no unit to claim and sees that epoch,
-// or, should the scheduler have gone, after four idle periods without an
-// active slot.  A claimed unit is always run to its end before its block looks
-// again.
+// or, should the scheduler have gone, when no slot is active and the
+// scheduler's heartbeat (and the worker's own start) are older than four idle
+// periods and an eighth of the stall limit.  A claimed unit is always run to
+// its end before its block looks again.
 #include <hip/hip_runtime.h>
 
 #include "ss_items.h"
@@ -52,7 +53,8 @@ __device__ __forceinline__ uint64_t ld_system(const uint64_t* p)
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-__device__ __forceinline__ void scheduler(Host* __restrict__ H, Dev* __restrict__ D, uint32_t epoch, uint64_t idle_ticks)
+__device__ __forceinline__ void scheduler(Host* __restrict__ H, Dev* __restrict__ D, uint32_t epoch,
+                                          uint64_t idle_ticks, uint64_t stall_ticks)
 {
     const int s = (int)threadIdx.x;          // one lane per slot
     uint64_t seen = D->seen[s];
@@ -84,15 +86,16 @@ __device__ __forceinline__ void scheduler(Host* __restrict__ H, Dev* __restrict_
         const uint64_t act = ld_agent(&D->active);
         const uint32_t prog = ld_agent32(&D->progress);
         const uint64_t now = wall_clock64();
+        if (s == 0) __hip_atomic_store(&D->beat, now, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (any_fresh || act == 0 || prog != last_prog) {
             t_prog = now;
             last_prog = prog;
         }
         if (any_fresh || act != 0) {
             t_busy = now;
-            if (now - t_prog > 10 * idle_ticks) {
-                // requests are active but nothing has finished for ten idle periods: end the launch
-                // and say so (the host fails the requests in flight)
+            if (now - t_prog > stall_ticks) {
+                // requests are active but nothing has finished for stall_ticks: end the launch and
+                // say so (the host fails the requests in flight)
                 if (s == 0) __hip_atomic_store(&H->stalled, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
                 __hip_atomic_store(&D->quit, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
                 return;
@@ -108,14 +111,15 @@ __device__ __forceinline__ void scheduler(Host* __restrict__ H, Dev* __restrict_
 enum Op { OP_NONE = 0, OP_PACK = 1, OP_ITEM = 2, OP_EXIT = 3, OP_RETRY = 4 };   // RETRY: a claim past the count
 
 template <int RSMAX>
-__device__ __forceinline__ void worker(Host* __restrict__ H, Dev* __restrict__ D, uint32_t epoch, uint64_t idle_ticks)
+__device__ __forceinline__ void worker(Host* __restrict__ H, Dev* __restrict__ D, uint32_t epoch, uint64_t idle_ticks,
+                                       uint64_t stall_ticks)
 {
     __shared__ int s_op, s_slot, s_unit;
     __shared__ PItem s_item;
     __shared__ long long s_lo[4], s_hi[4];
     __shared__ uint32_t s_stage[4 * item_sweep::kStageWords];
     const int wv = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
-    uint64_t t_idle = wall_clock64();
+    const uint64_t t_start = wall_clock64();
     for (;;) {
         if (wv == 0) {
             // lane s looks at slot s
@@ -159,8 +163,15 @@ __device__ __forceinline__ void worker(Host* __restrict__ H, Dev* __restrict__ D
                 unit = __shfl(unit, L);
             } else if (__hip_atomic_load(&D->quit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch) {
                 op = OP_EXIT;
-            } else if (act == 0 && wall_clock64() - t_idle > 4 * idle_ticks) {
-                op = OP_EXIT;              // no scheduler left to activate anything
+            } else if (act == 0) {
+                // no scheduler left to activate anything (its heartbeat, and this worker's start, are
+                // old).  Looked at only while no slot is active: the heartbeat's line is rewritten on
+                // every scheduler pass, and reading it on every poll while requests are in flight
+                // doubled their device time.
+                const uint64_t beat = ld_agent(&D->beat);
+                const uint64_t last = beat > t_start ? beat : t_start;
+                const uint64_t orphan = 4 * idle_ticks > stall_ticks / 8 ? 4 * idle_ticks : stall_ticks / 8;
+                if (wall_clock64() - last > orphan) op = OP_EXIT;
             }
             if (lane == 0) {
                 s_op = op;
@@ -179,7 +190,6 @@ __device__ __forceinline__ void worker(Host* __restrict__ H, Dev* __restrict__ D
             continue;
         }
         if (op == OP_RETRY) continue;
-        t_idle = wall_clock64();
         Slot* S = &D->slot[slot];
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");     // the slot's descriptor (and planes for items)
         if (op == OP_PACK) {
@@ -242,20 +252,20 @@ __device__ __forceinline__ void worker(Host* __restrict__ H, Dev* __restrict__ D
 
 template <int RSMAX>
 __global__ __launch_bounds__(256) void k_loop(Host* __restrict__ H, Dev* __restrict__ D, uint32_t epoch,
-                                              uint64_t idle_ticks)
+                                              uint64_t idle_ticks, uint64_t stall_ticks)
 {
     if (blockIdx.x == 0) {
         // the scheduler is one wavefront; the block's other wavefronts have nothing to do
-        if (threadIdx.x < 64) scheduler(H, D, epoch, idle_ticks);
+        if (threadIdx.x < 64) scheduler(H, D, epoch, idle_ticks, stall_ticks);
         return;
     }
-    worker<RSMAX>(H, D, epoch, idle_ticks);
+    worker<RSMAX>(H, D, epoch, idle_ticks, stall_ticks);
 }
 
 }  // namespace
 
 hipError_t launch_loop(int rsmax, int grid, size_t lds_pad, Host* host, Dev* dev, uint32_t epoch,
-                       uint64_t idle_ticks, hipStream_t s)
+                       uint64_t idle_ticks, uint64_t stall_ticks, hipStream_t s)
 {
     if (grid < 2) grid = 2;
     const void* fn = rsmax == 1   ? (const void*)k_loop<1>
@@ -267,10 +277,14 @@ hipError_t launch_loop(int rsmax, int grid, size_t lds_pad, Host* host, Dev* dev
         if (e != hipSuccess) return e;
     }
     switch (rsmax) {
-    case 1: hipLaunchKernelGGL(k_loop<1>, dim3(grid), dim3(256), lds_pad, s, host, dev, epoch, idle_ticks); break;
-    case 2: hipLaunchKernelGGL(k_loop<2>, dim3(grid), dim3(256), lds_pad, s, host, dev, epoch, idle_ticks); break;
-    case 4: hipLaunchKernelGGL(k_loop<4>, dim3(grid), dim3(256), lds_pad, s, host, dev, epoch, idle_ticks); break;
-    default: hipLaunchKernelGGL(k_loop<8>, dim3(grid), dim3(256), lds_pad, s, host, dev, epoch, idle_ticks); break;
+    case 1: hipLaunchKernelGGL(k_loop<1>, dim3(grid), dim3(256), lds_pad, s, host, dev, epoch, idle_ticks,
+                                   stall_ticks); break;
+    case 2: hipLaunchKernelGGL(k_loop<2>, dim3(grid), dim3(256), lds_pad, s, host, dev, epoch, idle_ticks,
+                                   stall_ticks); break;
+    case 4: hipLaunchKernelGGL(k_loop<4>, dim3(grid), dim3(256), lds_pad, s, host, dev, epoch, idle_ticks,
+                                   stall_ticks); break;
+    default: hipLaunchKernelGGL(k_loop<8>, dim3(grid), dim3(256), lds_pad, s, host, dev, epoch, idle_ticks,
+                                   stall_ticks); break;
     }
     return hipGetLastError();
 }

@@ -220,6 +220,8 @@ struct ss_server {
     bool loop_launched = false;
     uint32_t epoch = 0;
     uint64_t idle_ticks = 0;
+    uint64_t stall_ticks = 0;        // no unit finished for this long with requests active: the loop gave up
+    uint64_t khz = 100000;           // device clock rate
     double tick_ns = 10.0;
     int64_t loop_launches = 0;
 };
@@ -253,7 +255,7 @@ int ensure_loop(ss_server* S)
     S->epoch++;
     roctxMarkA("serve: launch the loop kernel");
     hipError_t e = loop::launch_loop(S->loop_rs, S->loop_grid, S->loop_lds_pad, S->H_dev, S->D, S->epoch,
-                                     S->idle_ticks, S->loop_stream);
+                                     S->idle_ticks, S->stall_ticks, S->loop_stream);
     if (e == hipSuccess) e = hipEventRecord(S->loop_ev, S->loop_stream);
     if (e != hipSuccess) return map_err(e);
     S->loop_launched = true;
@@ -605,7 +607,8 @@ extern "C" int ss_server_create(ss_ctx* ctx, size_t hbm_budget_bytes, int32_t n_
 
 namespace {
 
-constexpr int kLoopIdleMs = 200;     // the loop kernel ends after this long with nothing to do
+constexpr int kLoopIdleMs = 200;     // the loop kernel ends after this long with nothing to do (default)
+constexpr int kLoopStallMs = 2000;   // requests active and no unit finished for this long: give up
 
 // Devices that hold a device-resident loop server: its kernel takes every CU
 // while it runs, so a second one on the same device would wait for the first
@@ -677,7 +680,9 @@ extern "C" int ss_server_create_loop(ss_ctx* ctx, size_t hbm_budget_bytes, int32
     if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, S->device) != hipSuccess || khz <= 0)
         khz = 100000;
     S->tick_ns = 1e6 / (double)khz;
+    S->khz = (uint64_t)khz;
     S->idle_ticks = (uint64_t)khz * kLoopIdleMs;
+    S->stall_ticks = (uint64_t)khz * kLoopStallMs;
     hipError_t e = hipHostMalloc((void**)&S->H, sizeof(loop::Host), hipHostMallocCoherent | hipHostMallocMapped);
     if (e == hipSuccess) {
         std::memset((void*)S->H, 0, sizeof(loop::Host));
@@ -890,6 +895,14 @@ extern "C" int ss_server_set_slices(ss_server* S, int32_t slices_per_lane)
     if (S->loop) return SS_EINVAL;       // the loop kernel's slice width is fixed at creation
     std::lock_guard<std::mutex> lk(S->mu);
     S->rsmax = slices_per_lane;
+    return SS_OK;
+}
+
+extern "C" int ss_server_set_loop_idle(ss_server* S, int64_t idle_us)
+{
+    if (!S || !S->loop || idle_us < 1 || idle_us > 60ll * 1000 * 1000) return SS_EINVAL;
+    std::lock_guard<std::mutex> lk(S->loop_mu);
+    S->idle_ticks = std::max<uint64_t>(1, S->khz * (uint64_t)idle_us / 1000);   // takes effect at the next launch
     return SS_OK;
 }
 

@@ -208,3 +208,48 @@ def test_loop_destroy_waits_for_requests_in_flight(env):
         assert np.array_equal(a, wa) and np.array_equal(e, we)
         done += 1
     assert done >= 1
+
+
+def test_loop_relaunch_race_with_a_tiny_idle_time(env):
+    """With the loop's idle time at 20 microseconds the kernel ends between requests over and over, so
+    requests are published just as it ends (the host launches it again when it finds the last launch
+    done with a request waiting); requests come from four threads at random gaps.  Every result
+    equals the oracle's."""
+    import random
+    import threading
+    ss, ctx = env
+    print("loop server: 20 us idle time, 4 submitting threads", flush=True)
+    srv = ss.ss_server_create_loop(ctx, 1 << 28, 8, 1)
+    try:
+        ss.ss_server_set_loop_idle(srv, 20)
+        reqs = [request(900 + i, max_pairs=64, max_len=1500) for i in range(48)]
+        subs = [None] * len(reqs)
+        errors = []
+
+        def work(k):
+            rng = random.Random(k)
+            try:
+                for i in range(k, len(reqs), 4):
+                    time.sleep(rng.choice([0, 0, 0.00005, 0.0003, 0.002]))
+                    subs[i] = submit(ss, srv, reqs[i])
+            except Exception as ex:          # reported below
+                errors.append(repr(ex))
+
+        th = [threading.Thread(target=work, args=(k,)) for k in range(4)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+        assert not errors, errors
+        for r, (t, a, e) in zip(reqs, subs):
+            assert ss.ss_server_wait(srv, t, 60_000_000) == ss.SS_OK
+            wa, we = want(r)
+            assert np.array_equal(a, wa) and np.array_equal(e, we)
+    finally:
+        ss.ss_server_destroy(srv)
+    with pytest.raises(ss.SSError):
+        host = ss.ss_server_create(ctx, 1 << 20, 2)
+        try:
+            ss.ss_server_set_loop_idle(host, 100)      # not a loop server
+        finally:
+            ss.ss_server_destroy(host)
