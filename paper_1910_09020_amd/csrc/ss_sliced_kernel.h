@@ -108,16 +108,6 @@ __device__ __forceinline__ void sweep_group(LD&& ld, int m, int64_t g, int64_t n
     // chunks c in [EC, ct) never touch a query index outside [0, m)
     const int ct = (m - B - E >= 0) ? (m - B - E) / B + 1 : 0;
     auto put = [](uint32_t (&d)[B], const uint4& v) { d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w; };
-    auto fetch = [&](uint32_t (&d0)[B], uint32_t (&d1)[B], int c) {
-        if (c >= 0 && c < nch) {
-            put(d0, ld(0, c));
-            put(d1, ld(1, c));
-        } else {
-#pragma unroll
-            for (int e = 0; e < B; e++) { d0[e] = 0u; d1[e] = 0u; }
-        }
-    };
-
     SweepState<E> st;
     st.init();
 
@@ -146,21 +136,65 @@ __device__ __forceinline__ void sweep_group(LD&& ld, int m, int64_t g, int64_t n
     };
 
     static_assert(MODE == MAIN_CIRC, "one window: the circular form");
-    constexpr int W = 2 * EC + 1;
-    uint32_t q0w[W][B], q1w[W][B];              // slot (c mod W) holds chunk c
+    // The loads run one chunk ahead of the columns.  Chunk c0's columns read
+    // query chunks c0-EC .. c0+EC and reference chunk c0; before they start,
+    // query chunk c0+EC+1 and reference chunk c0+1 are issued, so a wavefront
+    // always has a chunk in flight while it computes (issued in the same step
+    // and consumed at once, every chunk would wait out a full memory latency).
+    // In the steady loop every step issues the same four loads with no
+    // condition, so the compiler's wait for the data of chunk c0 counts
+    // exactly the four younger loads instead of draining them all; the last
+    // chunks, whose prefetches would fall past the end, run after it.
+    // Slots of chunks outside [0, nch) are only ever read by masked columns,
+    // which clear those cells: they start at zero and are not refilled.
+    constexpr int W = 2 * EC + 2;               // even: chunk parity is static in the unrolled loops
+    uint32_t q0w[W][B], q1w[W][B];              // slot (c mod W) holds query chunk c
+    uint4 rf0[2], rf1[2];                       // reference chunk c in [c & 1]
 #pragma unroll
-    for (int c = -EC; c < EC; c++) fetch(q0w[(c + W) % W], q1w[(c + W) % W], c);
-    for (int cb = 0; cb < nch; cb += W) {
+    for (int i = 0; i < W; i++) {
+#pragma unroll
+        for (int e = 0; e < B; e++) { q0w[i][e] = 0u; q1w[i][e] = 0u; }
+    }
+    auto load_q = [&](int slot, int c) {
+        put(q0w[slot], ld(0, c));
+        put(q1w[slot], ld(1, c));
+    };
+#pragma unroll
+    for (int c = 0; c <= EC; c++)
+        if (c < nch) load_q(c % W, c);
+    if (nch > 0) {                              // m = 0: nothing to read (the planes may be absent)
+        rf0[0] = ld(2, 0);
+        rf1[0] = ld(3, 0);
+    }
+    // chunk c0 at unrolled position u (c0 = u mod W)
+    auto columns = [&](int c0, int u) {
+        auto w0 = [&](int o) { const int d = floordiv(o, B); return q0w[(u + d + 2 * W) % W][o - d * B]; };
+        auto w1 = [&](int o) { const int d = floordiv(o, B); return q1w[(u + d + 2 * W) % W][o - d * B]; };
+        run_chunk(c0, !(c0 >= EC && c0 < ct), rf0[u & 1], rf1[u & 1], w0, w1);
+    };
+    const int nsteady = nch - EC - 1;           // chunks whose next query and reference chunks exist
+    int cb = 0;
+    for (; cb + W <= nsteady; cb += W) {
 #pragma unroll
         for (int u = 0; u < W; u++) {
             const int c0 = cb + u;
-            if (c0 < nch) {
-                fetch(q0w[(u + EC) % W], q1w[(u + EC) % W], c0 + EC);
-                const uint4 rr0 = ld(2, c0), rr1 = ld(3, c0);
-                auto w0 = [&](int o) { const int d = floordiv(o, B); return q0w[(u + d + 2 * W) % W][o - d * B]; };
-                auto w1 = [&](int o) { const int d = floordiv(o, B); return q1w[(u + d + 2 * W) % W][o - d * B]; };
-                run_chunk(c0, !(c0 >= EC && c0 < ct), rr0, rr1, w0, w1);
+            load_q((u + EC + 1) % W, c0 + EC + 1);
+            rf0[(u + 1) & 1] = ld(2, c0 + 1);
+            rf1[(u + 1) & 1] = ld(3, c0 + 1);
+            columns(c0, u);
+        }
+    }
+    // fewer than W + EC + 1 chunks remain
+#pragma unroll
+    for (int u = 0; u < W + EC + 1; u++) {
+        const int c0 = cb + u;
+        if (c0 < nch) {
+            if (c0 + EC + 1 < nch) load_q((u + EC + 1) % W, c0 + EC + 1);
+            if (c0 + 1 < nch) {
+                rf0[(u + 1) & 1] = ld(2, c0 + 1);
+                rf1[(u + 1) & 1] = ld(3, c0 + 1);
             }
+            columns(c0, u);
         }
     }
 
