@@ -163,7 +163,8 @@ extern "C" int ss_filter_ascii_async(ss_ctx* ctx, const uint8_t* reads, const ui
     // The fused kernel in wave mode (aligned pairs of up to a few hundred bases) beats the two kernels;
     // in block mode it does not for aligned inputs (250 bp: 2.2-2.4 ms against 1.7 ms), so with the
     // automatic tile those go to the chunked schedule.  A tile the caller gives asks for the fused kernel.
-    if (E <= kMaxEFused && (tile_groups > 0 || U > 0 || !contiguous))
+    // (pairs of length 0 take the chunked schedule: the sweep reads nothing and writes each result)
+    if (E <= kMaxEFused && m > 0 && (tile_groups > 0 || U > 0 || !contiguous))
         return map_err(launch_fused(reads, refs, n_pairs, m, E, tile_groups, out, err, s));
     // chunks of whole groups; slot offsets keep the encoder's and the sweep's alignment
     const int64_t per_pair = std::max<int64_t>(1, ss_sliced_bytes(32, m) / 32);
@@ -408,27 +409,36 @@ int filter_host_pipelined(ss_ctx* ctx, const uint8_t* reads, const uint8_t* refs
     SS_TRY(hipMemsetAsync(d_err, 0, 4, s));
     // host threads for the expansion of the results
     Crew crew(n >= (1 << 20) ? host_threads() : 1);
+    // once work is enqueued, an error returns only after both streams have drained: the copies read
+    // the caller's arrays and write the staging buffers, which must not be in use after the return
+    auto drain = [&](int rc) {
+        (void)hipStreamSynchronize(ctx->copy_stream);
+        (void)hipStreamSynchronize(s);
+        return rc;
+    };
+#define SS_TRY_DRAIN(expr)                               \
+    do {                                                 \
+        const hipError_t e_ = (expr);                    \
+        if (e_ != hipSuccess) return drain(map_err(e_)); \
+    } while (0)
     for (int64_t i = 0; i < nchunks; i++) {
         const int b = (int)(i & 1);
         const int64_t s0 = i * K, k = std::min(K, n - s0);
         uint8_t* ds = (uint8_t*)ctx->dstage[b].p;
-        if (i >= 2) SS_TRY(hipStreamWaitEvent(ctx->copy_stream, ctx->ev_used[b], 0));   // chunk i-2 was filtered
-        SS_TRY(hipMemcpyAsync(ds, reads + s0 * m, (size_t)(k * m), hipMemcpyHostToDevice, ctx->copy_stream));
-        SS_TRY(hipMemcpyAsync(ds + side, refs + s0 * m, (size_t)(k * m), hipMemcpyHostToDevice, ctx->copy_stream));
-        SS_TRY(hipEventRecord(ctx->ev_h2d[b], ctx->copy_stream));
-        SS_TRY(hipStreamWaitEvent(s, ctx->ev_h2d[b], 0));
+        if (i >= 2) SS_TRY_DRAIN(hipStreamWaitEvent(ctx->copy_stream, ctx->ev_used[b], 0));   // chunk i-2 was filtered
+        SS_TRY_DRAIN(hipMemcpyAsync(ds, reads + s0 * m, (size_t)(k * m), hipMemcpyHostToDevice, ctx->copy_stream));
+        SS_TRY_DRAIN(hipMemcpyAsync(ds + side, refs + s0 * m, (size_t)(k * m), hipMemcpyHostToDevice, ctx->copy_stream));
+        SS_TRY_DRAIN(hipEventRecord(ctx->ev_h2d[b], ctx->copy_stream));
+        SS_TRY_DRAIN(hipStreamWaitEvent(s, ctx->ev_h2d[b], 0));
         const int rc = ss_filter_ascii_async(ctx, ds, ds + side, k, m, E, 0, d_res + s0, d_err, s);
-        if (rc != SS_OK) {
-            (void)hipStreamSynchronize(s);
-            (void)hipStreamSynchronize(ctx->copy_stream);
-            return rc;
-        }
-        SS_TRY(hipEventRecord(ctx->ev_used[b], s));
+        if (rc != SS_OK) return drain(rc);
+        SS_TRY_DRAIN(hipEventRecord(ctx->ev_used[b], s));
     }
     uint8_t* hr = (uint8_t*)ctx->hres.p;
-    SS_TRY(hipMemcpyAsync(hr, d_res, (size_t)n * 2, hipMemcpyDeviceToHost, s));
-    SS_TRY(hipMemcpyAsync(hr + err_at, d_err, 4, hipMemcpyDeviceToHost, s));
-    SS_TRY(hipStreamSynchronize(s));
+    SS_TRY_DRAIN(hipMemcpyAsync(hr, d_res, (size_t)n * 2, hipMemcpyDeviceToHost, s));
+    SS_TRY_DRAIN(hipMemcpyAsync(hr + err_at, d_err, 4, hipMemcpyDeviceToHost, s));
+    SS_TRY_DRAIN(hipStreamSynchronize(s));
+#undef SS_TRY_DRAIN
     uint32_t h_err = 0;
     std::memcpy(&h_err, hr + err_at, 4);
     if (h_err & 2u) return SS_EDEVICE;   // a bounded wait inside the fused kernel gave up
@@ -482,72 +492,79 @@ int filter_host(const uint8_t* reads, const uint8_t* refs, const int32_t* length
         is_pinned_host(reads) && is_pinned_host(refs))
         return filter_host_pipelined(ctx, reads, refs, n, lengths[0], E, accept_out, edits_out);
     hipStream_t s = ctx->stream;
-    SS_TRY(ctx->reads.ensure((size_t)std::max<int64_t>(total, 1)));
-    SS_TRY(ctx->refs.ensure((size_t)std::max<int64_t>(total, 1)));
-    SS_TRY(ctx->results.ensure((size_t)n * 2 + 16));
-    SS_TRY(ctx->err.ensure(16));
-    uint32_t* d_err = (uint32_t*)ctx->err.p;
-    uint16_t* d_res = (uint16_t*)ctx->results.p;
-    if (total > 0) {
-        SS_TRY(hipMemcpyAsync(ctx->reads.p, reads, (size_t)total, hipMemcpyHostToDevice, s));
-        SS_TRY(hipMemcpyAsync(ctx->refs.p, refs, (size_t)total, hipMemcpyHostToDevice, s));
-    }
-    SS_TRY(hipMemsetAsync(d_err, 0, 4, s));
-
-    const bool sliced = uniform && !E_per_pair && E <= SS_MAX_E_SLICED;
-    if (sliced && lengths[0] <= SS_MAX_LEN_FUSED) {
-        // encode and filter in one call; the alphabet check is read before any output is written
-        rc = ss_filter_ascii_async(ctx, (const uint8_t*)ctx->reads.p, (const uint8_t*)ctx->refs.p, n, lengths[0],
-                                   E, 0, d_res, d_err, s);
-        if (rc != SS_OK) return rc;
-    } else if (sliced) {
-        const int32_t m = lengths[0];
-        SS_TRY(ctx->packed.ensure((size_t)std::max<int64_t>(ss_sliced_bytes(n, m), 16)));
-        rc = ss_pack_sliced_async(ctx, (const uint8_t*)ctx->reads.p, (const uint8_t*)ctx->refs.p, nullptr, nullptr,
-                                  n, m, (uint32_t*)ctx->packed.p, d_err, s);
-        if (rc != SS_OK) return rc;
-    } else {
-        SS_TRY(ctx->packed.ensure((size_t)ss_stream_words(total) * 16));
-        SS_TRY(ctx->offsets.ensure((size_t)n * 8));
-        SS_TRY(ctx->lengths.ensure((size_t)n * 4));
-        SS_TRY(hipMemcpyAsync(ctx->offsets.p, off.data(), (size_t)n * 8, hipMemcpyHostToDevice, s));
-        SS_TRY(hipMemcpyAsync(ctx->lengths.p, lengths, (size_t)n * 4, hipMemcpyHostToDevice, s));
-        if (E_per_pair) {
-            SS_TRY(ctx->epp.ensure((size_t)n * 4));
-            SS_TRY(hipMemcpyAsync(ctx->epp.p, E_per_pair, (size_t)n * 4, hipMemcpyHostToDevice, s));
+    // an error after work was enqueued returns once the stream has drained: its copies read the
+    // caller's arrays (and the offsets built here) and write the context's buffers
+    auto run = [&]() -> int {
+        SS_TRY(ctx->reads.ensure((size_t)std::max<int64_t>(total, 1)));
+        SS_TRY(ctx->refs.ensure((size_t)std::max<int64_t>(total, 1)));
+        SS_TRY(ctx->results.ensure((size_t)n * 2 + 16));
+        SS_TRY(ctx->err.ensure(16));
+        uint32_t* d_err = (uint32_t*)ctx->err.p;
+        uint16_t* d_res = (uint16_t*)ctx->results.p;
+        if (total > 0) {
+            SS_TRY(hipMemcpyAsync(ctx->reads.p, reads, (size_t)total, hipMemcpyHostToDevice, s));
+            SS_TRY(hipMemcpyAsync(ctx->refs.p, refs, (size_t)total, hipMemcpyHostToDevice, s));
         }
-        rc = ss_pack_stream_async(ctx, (const uint8_t*)ctx->reads.p, (const uint8_t*)ctx->refs.p, total,
-                                  (uint32_t*)ctx->packed.p, d_err, s);
-        if (rc != SS_OK) return rc;
-    }
-    uint32_t h_err = 0;
-    SS_TRY(hipMemcpyAsync(&h_err, d_err, 4, hipMemcpyDeviceToHost, s));
-    SS_TRY(hipStreamSynchronize(s));
-    if (h_err & 2u) return SS_EDEVICE;   // a bounded wait inside the fused kernel gave up
-    if (h_err) return SS_EBASE;
+        SS_TRY(hipMemsetAsync(d_err, 0, 4, s));
 
-    if (sliced && lengths[0] <= SS_MAX_LEN_FUSED) {
-        rc = SS_OK;     // filtered above
-    } else if (sliced) {
-        rc = ss_filter_sliced_async(ctx, (const uint32_t*)ctx->packed.p, n, lengths[0], E, d_res, s);
-    } else {
-        rc = ss_filter_wave_async(ctx, (const uint32_t*)ctx->packed.p, total, (const int64_t*)ctx->offsets.p,
-                                  (const int32_t*)ctx->lengths.p, E_per_pair ? (const int32_t*)ctx->epp.p : nullptr,
-                                  n, Emax, d_res, s);
-    }
-    if (rc != SS_OK) return rc;
-    SS_TRY(ctx->hres.ensure((size_t)n * 2 + 16));
-    const uint16_t* res = (const uint16_t*)ctx->hres.p;
-    SS_TRY(hipMemcpyAsync(ctx->hres.p, d_res, (size_t)n * 2, hipMemcpyDeviceToHost, s));
-    SS_TRY(hipStreamSynchronize(s));
-    Crew crew(n >= (1 << 20) ? host_threads() : 1);
-    crew.parallel((size_t)n, [&](size_t a, size_t e) {
-        for (size_t i = a; i < e; i++) {
-            accept_out[i] = (uint8_t)(res[i] >> 15);
-            edits_out[i] = (int32_t)(res[i] & SS_RESULT_COUNT);
+        const bool sliced = uniform && !E_per_pair && E <= SS_MAX_E_SLICED;
+        if (sliced && lengths[0] <= SS_MAX_LEN_FUSED) {
+            // encode and filter in one call; the alphabet check is read before any output is written
+            rc = ss_filter_ascii_async(ctx, (const uint8_t*)ctx->reads.p, (const uint8_t*)ctx->refs.p, n, lengths[0],
+                                       E, 0, d_res, d_err, s);
+            if (rc != SS_OK) return rc;
+        } else if (sliced) {
+            const int32_t m = lengths[0];
+            SS_TRY(ctx->packed.ensure((size_t)std::max<int64_t>(ss_sliced_bytes(n, m), 16)));
+            rc = ss_pack_sliced_async(ctx, (const uint8_t*)ctx->reads.p, (const uint8_t*)ctx->refs.p, nullptr, nullptr,
+                                      n, m, (uint32_t*)ctx->packed.p, d_err, s);
+            if (rc != SS_OK) return rc;
+        } else {
+            SS_TRY(ctx->packed.ensure((size_t)ss_stream_words(total) * 16));
+            SS_TRY(ctx->offsets.ensure((size_t)n * 8));
+            SS_TRY(ctx->lengths.ensure((size_t)n * 4));
+            SS_TRY(hipMemcpyAsync(ctx->offsets.p, off.data(), (size_t)n * 8, hipMemcpyHostToDevice, s));
+            SS_TRY(hipMemcpyAsync(ctx->lengths.p, lengths, (size_t)n * 4, hipMemcpyHostToDevice, s));
+            if (E_per_pair) {
+                SS_TRY(ctx->epp.ensure((size_t)n * 4));
+                SS_TRY(hipMemcpyAsync(ctx->epp.p, E_per_pair, (size_t)n * 4, hipMemcpyHostToDevice, s));
+            }
+            rc = ss_pack_stream_async(ctx, (const uint8_t*)ctx->reads.p, (const uint8_t*)ctx->refs.p, total,
+                                      (uint32_t*)ctx->packed.p, d_err, s);
+            if (rc != SS_OK) return rc;
         }
-    });
-    return SS_OK;
+        uint32_t h_err = 0;
+        SS_TRY(hipMemcpyAsync(&h_err, d_err, 4, hipMemcpyDeviceToHost, s));
+        SS_TRY(hipStreamSynchronize(s));
+        if (h_err & 2u) return SS_EDEVICE;   // a bounded wait inside the fused kernel gave up
+        if (h_err) return SS_EBASE;
+
+        if (sliced && lengths[0] <= SS_MAX_LEN_FUSED) {
+            rc = SS_OK;     // filtered above
+        } else if (sliced) {
+            rc = ss_filter_sliced_async(ctx, (const uint32_t*)ctx->packed.p, n, lengths[0], E, d_res, s);
+        } else {
+            rc = ss_filter_wave_async(ctx, (const uint32_t*)ctx->packed.p, total, (const int64_t*)ctx->offsets.p,
+                                      (const int32_t*)ctx->lengths.p, E_per_pair ? (const int32_t*)ctx->epp.p : nullptr,
+                                      n, Emax, d_res, s);
+        }
+        if (rc != SS_OK) return rc;
+        SS_TRY(ctx->hres.ensure((size_t)n * 2 + 16));
+        const uint16_t* res = (const uint16_t*)ctx->hres.p;
+        SS_TRY(hipMemcpyAsync(ctx->hres.p, d_res, (size_t)n * 2, hipMemcpyDeviceToHost, s));
+        SS_TRY(hipStreamSynchronize(s));
+        Crew crew(n >= (1 << 20) ? host_threads() : 1);
+        crew.parallel((size_t)n, [&](size_t a, size_t e) {
+            for (size_t i = a; i < e; i++) {
+                accept_out[i] = (uint8_t)(res[i] >> 15);
+                edits_out[i] = (int32_t)(res[i] & SS_RESULT_COUNT);
+            }
+        });
+        return SS_OK;
+    };
+    rc = run();
+    if (rc != SS_OK) (void)hipStreamSynchronize(s);
+    return rc;
 }
 
 }  // namespace

@@ -68,9 +68,10 @@ extern "C" int ss_filter_ascii_noalloc(ss_ctx* ctx, const uint8_t* reads, const 
     const hipStream_t s = (hipStream_t)stream;
     // the same schedule as ss_filter_ascii_async with the automatic tile: the fused kernel (no scratch)
     // in its wave mode, or for unaligned inputs; else the two kernels over chunks that fit the scratch
-    if (E <= kMaxEFused && (U > 0 || !contiguous))
+    // (pairs of length 0 take the two kernels: the sweep reads nothing and writes each result)
+    if (E <= kMaxEFused && m > 0 && (U > 0 || !contiguous))
         return map_err(launch_fused(reads, refs, n_pairs, m, E, 0, out, err, s));
-    const int64_t group_bytes = ss_sliced_bytes(32, m);          // one group's encoding
+    const int64_t group_bytes = std::max<int64_t>(1, ss_sliced_bytes(32, m));   // one group's encoding (0 at m = 0)
     static_assert(SS_NOALLOC_SCRATCH_BYTES >= 4LL * ((SS_MAX_LEN_FUSED + 3) / 4) * 64 * 16,
                   "the scratch holds a whole layout block of the longest pairs");
     // chunks of whole 64-group layout blocks, so that each chunk's encoding is laid out on its own

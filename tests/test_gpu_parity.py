@@ -129,6 +129,37 @@ def test_degenerate_pairs(rt):
             run_all(rt, sub, E, kernels=("sliced", "fused"))
 
 
+def test_zero_length_pairs_on_the_equal_length_paths(rt):
+    """Pairs of length 0 through the sliced sweep, the one-call entry (aligned and unaligned inputs)
+    and the entry that allocates nothing: every pair is accepted with count 0, as the oracle gives;
+    the sweep reads nothing (the planes of length 0 are empty)."""
+    import torch
+    import paper_1910_09020_amd as ss
+    n = 100
+    b = dict(n=n, reads=np.zeros(0, np.uint8), refs=np.zeros(0, np.uint8),
+             offsets=np.zeros(n, np.int64), lengths=np.zeros(n, np.int32), E=None)
+    db = rt.DeviceBatch(b)
+    ctx = rt.context()
+    buf = torch.full((64,), ord("A"), dtype=torch.uint8, device="cuda")
+    for E in (0, 5, 9):
+        say(f"  m=0 n={n} E={E}")
+        want = expect(b, E=E)
+        assert np.all(want[0] == 1) and np.all(want[1] == 0)
+        pk = db.pack_sliced()
+        check(f"sliced m=0 E={E}", rt.results_numpy(db.filter_sliced(pk, E), n), want)
+        check(f"one call m=0 E={E}", rt.results_numpy(db.filter_fused(E), n), want)
+        for off in (0, 1):
+            for entry in (ss.ss_filter_ascii_async, ss.ss_filter_ascii_noalloc):
+                out = torch.full((n + 8,), -1, dtype=torch.int16, device="cuda")
+                if entry is ss.ss_filter_ascii_async:
+                    entry(ctx, buf[off:], buf[off:], n, 0, E, 0, out, db.err)
+                else:
+                    entry(ctx, buf[off:], buf[off:], n, 0, E, out, db.err)
+                torch.cuda.synchronize()
+                check(f"{entry.__name__} m=0 E={E} offset {off}", rt.results_numpy(out, n), want)
+    assert db.err_bits() == 0
+
+
 def test_mixed_lengths_per_pair_E(rt):
     import torch
     b = gen.make(3, n=3000, n_long=6)
