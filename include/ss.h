@@ -340,7 +340,10 @@ int ss_pack(ss_ctx* ctx, const uint8_t* ascii, int64_t bases, uint32_t* packed, 
  * is ASCII, build the Equation 1 rows, walk, decide and write), enqueued on
  * stream; the caller synchronises.  Device arrays (offsets, lengths, thresholds)
  * cannot be checked on the host: the caller guarantees that every pair lies
- * inside its buffers and that each E_per_pair[i] <= E.  Buffers the context
+ * inside its buffers and that each E_per_pair[i] <= E.  Without offsets (pairs
+ * back to back at i * length) the bit-stream kernels (plain, wavefront,
+ * persistent) need n_pairs * length <= read_bases (and <= ref_bases when the
+ * references follow the queries' offsets): SS_EINVAL otherwise.  Buffers the context
  * owns (encodings of ASCII input) are reused by the next call on the context:
  * calls on one context must be ordered (one stream). */
 int ss_filter_batch_ex(ss_ctx* ctx, const ss_batch_desc* desc, void* stream);

@@ -124,6 +124,12 @@ extern "C" int ss_filter_batch_ex(ss_ctx* ctx, const ss_batch_desc* d, void* str
 
     // the remaining kernels read the two sides as bit streams; every check comes before any work
     if (d->read_bases > SS_MAX_STREAM_BASES || d->ref_bases > SS_MAX_STREAM_BASES) return SS_ELEN;
+    if (uniform && !d->offsets && d->length > 0) {
+        // pairs back to back at i * length must lie inside the bases the caller declared
+        // (n_pairs * length <= bases, compared by division: the product may not fit)
+        if (d->n_pairs > d->read_bases / d->length || (!uneq && d->n_pairs > d->ref_bases / d->length))
+            return SS_EINVAL;
+    }
     if (k == SS_KERNEL_PLAIN) {
         if (uneq) return SS_EINVAL;                  // one length per pair
         if (d->E > SS_MAX_E_PLAIN) return SS_ELEN;

@@ -237,6 +237,14 @@ def test_descriptor_errors(rt):
     assert rc(flags=0x60) == ss.SS_EINVAL and rc(flags=0x3) == ss.SS_EINVAL and rc(flags=0x100) == ss.SS_EINVAL
     assert rc(E=ss.SS_MAX_E + 1) == ss.SS_ELEN
     assert rc(offsets=None) == ss.SS_EINVAL                                            # several lengths need arrays
+    # pairs back to back at i * length beyond the declared bases (bit-stream kernels)
+    for kern in (ss.SS_KERNEL_PLAIN, ss.SS_KERNEL_WAVE):
+        assert rc(flags=ss.SS_INPUT_ASCII | kern, offsets=None, lengths=None, length=100,
+                  read_bases=100 * D.n - 1) == ss.SS_EINVAL
+        assert rc(flags=ss.SS_INPUT_ASCII | kern, offsets=None, lengths=None, length=100,
+                  ref_bases=100 * D.n - 1) == ss.SS_EINVAL
+        assert rc(flags=ss.SS_INPUT_ASCII | kern, offsets=None, lengths=None, length=1 << 20,
+                  n_pairs=1 << 62) == ss.SS_EINVAL                                     # the product overflows
     assert rc(n_pairs=0) == ss.SS_OK
     torch.cuda.synchronize()
     assert bool((D.out == -7).all())                                                   # nothing was written
