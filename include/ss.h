@@ -376,7 +376,8 @@ int ss_verify_async(ss_ctx* ctx, const uint32_t* packed, int64_t total_bases, co
 /* Banded verification, any length (up to SS_MAX_LEN): ed_out[k] = the edit
  * distance of the k-th listed pair when it is at most that pair's threshold
  * (E_per_pair[p], or E for every pair when E_per_pair is NULL), else the
- * threshold + 1.  E must be >= every listed threshold (it sizes the window),
+ * threshold + 1.  E must be >= every listed threshold (it sizes the window;
+ * a pair whose threshold needs a wider window than E's gets -1),
  * <= SS_MAX_E_VERIFY_BANDED (SS_ELEN beyond).  Pairs of equal length in the
  * bit-stream layout, index as for ss_verify_async.  One pair per wavefront:
  * Myers' bit-vector algorithm over a window of the query that follows the
