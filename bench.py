@@ -432,7 +432,7 @@ def serving_leg(a, ss, gen, runner, oracle, mode=None, seconds=None):
     for t in D.tickets:
         rc = ss.ss_server_wait(srv, int(t), -1)
         assert rc == ss.SS_OK, rc
-    lat, svc, wait, lag, stages = [], [], [], [], []
+    lat, svc, wait, lag, dlag, stages = [], [], [], [], [], []
     done_last = 0
     for i in range(nreq):
         sub, adm, done = ss.ss_server_times(srv, int(D.tickets[i]))
@@ -441,17 +441,20 @@ def serving_leg(a, ss, gen, runner, oracle, mode=None, seconds=None):
         svc.append((done - adm) / 1e6)
         wait.append((adm - sub) / 1e6)
         lag.append((sub - due) / 1e6)
+        dlag.append((int(D.call_ns[i]) - due) / 1e6)
         stages.append(ss.ss_server_stages(srv, int(D.tickets[i])))
         done_last = max(done_last, done)
     lat = np.array(lat)
-    # where the time of a request goes: submission lag, queue, host enqueue, device spans (copy in,
-    # encode + filter, copy out), and the rest of the service time (waiting on the device behind other
-    # slots' work, and the completion thread's polling); means over all requests and over those at or
-    # above the p99 latency
+    # where the time of a request goes: the driver's lag behind the schedule (due time to its submit
+    # call), the submission itself (planning and staging inside ss_server_submit), queue, host enqueue,
+    # device spans (copy in, encode + filter, copy out), and the rest of the service time (waiting on
+    # the device behind other slots' work, and the completion thread's polling); means over all
+    # requests and over those at or above the p99 latency
     st = np.array(stages, dtype=np.float64) / 1e6
-    parts = np.stack([np.array(lag), np.array(wait), st[:, 0], st[:, 1], st[:, 2], st[:, 3],
-                      np.array(svc) - st.sum(axis=1)], axis=1)
-    names = ["submit_lag", "queue", "host_enqueue", "copy_in", "encode_filter", "copy_out", "device_wait_and_poll"]
+    parts = np.stack([np.array(dlag), np.array(lag) - np.array(dlag), np.array(wait), st[:, 0], st[:, 1], st[:, 2],
+                      st[:, 3], np.array(svc) - st.sum(axis=1)], axis=1)
+    names = ["driver_lag", "submit", "queue", "host_enqueue", "copy_in", "encode_filter", "copy_out",
+             "device_wait_and_poll"]
     tail = lat >= np.percentile(lat, 99)
     breakdown = {"all_mean_ms": dict(zip(names, [round(float(x), 4) for x in parts.mean(axis=0)])),
                  "p99_tail_mean_ms": dict(zip(names, [round(float(x), 4) for x in parts[tail].mean(axis=0)])),
@@ -482,7 +485,8 @@ def serving_leg(a, ss, gen, runner, oracle, mode=None, seconds=None):
                pairs_per_s=pairs / span, p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
                max_ms=float(lat.max()), service_p50_ms=pct(svc, 50), service_p99_ms=pct(svc, 99),
                queue_p50_ms=pct(wait, 50), queue_p99_ms=pct(wait, 99), submit_lag_p50_ms=pct(lag, 50),
-               submit_lag_p99_ms=pct(lag, 99), slots=a.serve_loop_slots if mode == "loop" else a.serve_slots,
+               submit_lag_p99_ms=pct(lag, 99), driver_lag_p50_ms=pct(dlag, 50), driver_lag_p99_ms=pct(dlag, 99),
+               slots=a.serve_loop_slots if mode == "loop" else a.serve_slots,
                hbm_budget_bytes=budget, stats=st,
                hw_queues=os.environ.get("GPU_MAX_HW_QUEUES", "HIP default"), distinct_requests=pool or nreq,
                breakdown=breakdown,
@@ -494,7 +498,8 @@ def serving_leg(a, ss, gen, runner, oracle, mode=None, seconds=None):
         f"p99 {res['p99_ms']:.3f} ms, service p50/p99 {res['service_p50_ms']:.3f}/{res['service_p99_ms']:.3f} ms, "
         f"tail breakdown {breakdown['p99_tail_mean_ms']}, "
         f"queue p50/p99 {res['queue_p50_ms']:.3f}/{res['queue_p99_ms']:.3f} ms, submit lag p50/p99 "
-        f"{res['submit_lag_p50_ms']:.3f}/{res['submit_lag_p99_ms']:.3f} ms, stats {st}, oracle mismatches {mism}")
+        f"{res['submit_lag_p50_ms']:.3f}/{res['submit_lag_p99_ms']:.3f} ms (of which the driver's "
+        f"{res['driver_lag_p50_ms']:.3f}/{res['driver_lag_p99_ms']:.3f} ms), stats {st}, oracle mismatches {mism}")
     return res
 
 

@@ -66,7 +66,7 @@ def _load():
     lib.ssgen_request_fill.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32, vp, vp, vp, vp]
     lib.ssgen_request_fill.restype = ctypes.c_int
     lib.ssgen_drive.argtypes = [ctypes.c_uint64, vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
-                                vp, vp, ctypes.c_int, ctypes.c_int64, ctypes.c_int64, vp, vp, vp, vp, vp, vp]
+                                vp, vp, ctypes.c_int, ctypes.c_int64, ctypes.c_int64, vp, vp, vp, vp, vp, vp, vp]
     lib.ssgen_drive.restype = ctypes.c_int64
     lib.ssgen_drive_free.argtypes = [ctypes.c_int64, vp, vp]
     lib.ssgen_drive_free.restype = None
@@ -160,6 +160,7 @@ class Drive:
         self.n = n
         self.tickets = np.zeros(n, np.uint64)
         self.due_ns = np.zeros(n, np.int64)
+        self.call_ns = np.zeros(n, np.int64)      # when the submitter called submit
         self.pairs = np.zeros(n, np.int32)
         self.bases = np.zeros(n, np.int64)
         self._acc = (ctypes.c_void_p * max(n, 1))()
@@ -188,7 +189,7 @@ def drive(seed: int, arrivals_s: np.ndarray, submit_fn_ptr: int, server: int, th
     n = len(arr)
     D = Drive(n)
     got = lib.ssgen_drive(seed, _p(arr), n, max_pairs, min_len, max_len, ctypes.c_void_p(submit_fn_ptr),
-                          ctypes.c_void_p(server), threads, pool, t0_ns, _p(D.tickets), _p(D.due_ns), _p(D.pairs),
+                          ctypes.c_void_p(server), threads, pool, t0_ns, _p(D.tickets), _p(D.due_ns), _p(D.call_ns), _p(D.pairs),
                           _p(D.bases), ctypes.cast(D._acc, ctypes.c_void_p), ctypes.cast(D._ed, ctypes.c_void_p))
     D.submitted = int(got)
     return D

@@ -539,7 +539,7 @@ typedef struct {
     _Atomic int stop_gen;
     const double* arrivals; int64_t t0_ns;
     ssgen_submit_fn submit; void* server;
-    uint64_t* tickets; int64_t* due_ns; int32_t* pairs; int64_t* bases;
+    uint64_t* tickets; int64_t* due_ns; int64_t* call_ns; int32_t* pairs; int64_t* bases;
     uint8_t** accept_out; int32_t** edits_out;
     _Atomic int64_t next;
     _Atomic int failed;          /* first failing status, 0 if none */
@@ -644,6 +644,7 @@ static void* drive_worker(void* arg)
         D->pairs[i] = q->n;
         D->bases[i] = q->total;
         sleep_until(due);
+        D->call_ns[i] = mono_ns();
         const int rc = D->submit(D->server, q->reads, q->refs, q->lengths, q->E, q->n, D->accept_out[i],
                                  D->edits_out[i], &D->tickets[i]);
         if (D->n_pool <= 0) {
@@ -663,7 +664,8 @@ static void* drive_worker(void* arg)
 
 /* Runs the whole schedule; returns the number of requests submitted, or
  * -1 + (status of a failed submission).  Per request (n_req entries, indexed
- * by schedule position): ticket, due time (CLOCK_MONOTONIC ns), pairs, bases,
+ * by schedule position): ticket, due time and time of the submit call
+ * (CLOCK_MONOTONIC ns), pairs, bases,
  * and output buffers owned here until ssgen_drive_free.  pool > 0: requests
  * 0..pool-1 are generated (on `threads` threads) before the schedule starts,
  * and position i replays request i mod pool, submitted by `threads`
@@ -674,7 +676,8 @@ static void* drive_worker(void* arg)
  * (0 = 100 ms after the pool or the head start is ready). */
 int64_t ssgen_drive(uint64_t seed, const double* arrivals, int64_t n_req, int32_t max_pairs, int32_t min_len,
                     int32_t max_len, ssgen_submit_fn submit, void* server, int threads, int64_t pool,
-                    int64_t t0_ns, uint64_t* tickets, int64_t* due_ns, int32_t* pairs, int64_t* bases,
+                    int64_t t0_ns, uint64_t* tickets, int64_t* due_ns, int64_t* call_ns, int32_t* pairs,
+                    int64_t* bases,
                     uint8_t** accept_out, int32_t** edits_out)
 {
     if (threads < 1) threads = 1;
@@ -682,7 +685,7 @@ int64_t ssgen_drive(uint64_t seed, const double* arrivals, int64_t n_req, int32_
     drive_ctx D;
     D.seed = seed; D.n_req = n_req; D.max_pairs = max_pairs; D.min_len = min_len; D.max_len = max_len;
     D.arrivals = arrivals; D.submit = submit; D.server = server;
-    D.tickets = tickets; D.due_ns = due_ns; D.pairs = pairs; D.bases = bases;
+    D.tickets = tickets; D.due_ns = due_ns; D.call_ns = call_ns; D.pairs = pairs; D.bases = bases;
     D.accept_out = accept_out; D.edits_out = edits_out;
     for (int64_t i = 0; i < n_req; i++) { accept_out[i] = NULL; edits_out[i] = NULL; }
     D.n_pool = pool > 0 ? pool : 0;

@@ -112,7 +112,8 @@ def test_ragged_lengths(rt, m):
         refs[p * m:(p + 1) * m] = rng.choice(np.frombuffer(b"ACGT", np.uint8), size=m)
     b = dict(n=n, reads=reads, refs=refs, offsets=np.arange(n, dtype=np.int64) * m,
              lengths=np.full(n, m, np.int32), E=None)
-    for E in (0, 1, 2, 5, 9, 16, 31, 32):
+    # every window size of the single-window sweep (E = 0; 1..4; 5..7) and of the three-part one
+    for E in (0, 1, 2, 3, 4, 5, 6, 7, 9, 16, 31, 32):
         run_all(rt, b, E)
 
 
