@@ -210,6 +210,31 @@ def test_loop_destroy_waits_for_requests_in_flight(env):
     assert done >= 1
 
 
+def test_loop_staging_beyond_the_pinned_region(env):
+    """Staging is taken at submission: with the server on hold, 90 requests of about 0.3 MB of
+    staging each outgrow the 16 MiB region pinned at creation (the smallest, for a 4 MiB budget),
+    so the later ones take blocks pinned on demand.  Released, every result equals the oracle's,
+    and the region's ranges are reused by the next requests."""
+    ss, ctx = env
+    print("loop server: 90 held requests past the staging region, then 20 more", flush=True)
+    srv = ss.ss_server_create_loop(ctx, 4 << 20, 16, 1)
+    try:
+        ss.ss_server_set_hold(srv, True)
+        reqs = [request(1000 + i, max_pairs=256, max_len=4000) for i in range(90)]
+        staged = sum(2 * len(r["reads"]) + 24 * r["n"] for r in reqs)      # a lower bound of the staging
+        assert staged > 20 << 20, staged
+        subs = [submit(ss, srv, r) for r in reqs]
+        ss.ss_server_set_hold(srv, False)
+        more = [request(1100 + i, max_pairs=256, max_len=4000) for i in range(20)]
+        subs += [submit(ss, srv, r) for r in more]
+        for r, (t, a, e) in zip(reqs + more, subs):
+            assert ss.ss_server_wait(srv, t, 60_000_000) == ss.SS_OK
+            wa, we = want(r)
+            assert np.array_equal(a, wa) and np.array_equal(e, we)
+    finally:
+        ss.ss_server_destroy(srv)
+
+
 def test_loop_relaunch_race_with_a_tiny_idle_time(env):
     """With the loop's idle time at 20 microseconds the kernel ends between requests over and over, so
     requests are published just as it ends (the host launches it again when it finds the last launch
