@@ -60,10 +60,10 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def timed_loop(fns, steps, torch):
+def timed_loop(fns, steps, torch, means=None):
     """Run each callable in fns per step, bracketed by HIP events on the current stream (the stream
     every callable here launches on).  Returns (wall seconds for all steps, [median ms per
-    callable over the steps])."""
+    callable over the steps]); means, if a list, receives the mean ms per callable."""
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(fns) + 1)] for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -74,8 +74,10 @@ def timed_loop(fns, steps, torch):
             evs[s][i + 1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    per = [float(np.median([evs[s][i].elapsed_time(evs[s][i + 1]) for s in range(steps)])) for i in range(len(fns))]
-    return wall, per
+    ms = [[evs[s][i].elapsed_time(evs[s][i + 1]) for s in range(steps)] for i in range(len(fns))]
+    if means is not None:
+        means[:] = [float(np.mean(x)) for x in ms]
+    return wall, [float(np.median(x)) for x in ms]
 
 
 def verify_leg(torch, runner, db, out, n, E, steps):
@@ -623,13 +625,17 @@ def main():
     for _ in range(a.warmup):
         step()
     torch.cuda.synchronize()
-    wall, (step_ms,) = timed_loop([step], a.steps, torch)
+    step_mean = [0.0]
+    wall, (step_ms,) = timed_loop([step], a.steps, torch, means=step_mean)
     ms_per_step = 1e3 * wall / a.steps
     value = n / (ms_per_step / 1e3)
     if a.steps < 10:
-        _, (step_ms,) = timed_loop([step], 10, torch)       # the kernel's median over at least 10 launches
+        # the kernel's median (and mean) over at least 10 launches
+        _, (step_ms,) = timed_loop([step], 10, torch, means=step_mean)
+    step_mean_ms = step_mean[0]
     acc, ed = runner.results_numpy(out, n)
-    log(f"step {ms_per_step:.4f} ms (sweep E={E} on resident planes; kernel median {step_ms:.4f} ms) "
+    log(f"step {ms_per_step:.4f} ms (sweep E={E} on resident planes; kernel median {step_ms:.4f} ms, "
+        f"mean {step_mean_ms:.4f} ms) "
         f"{value / 1e9:.2f} G pairs/s; encode {pack_ms:.4f} ms")
 
     # the one-call path from ASCII in HBM (encode + filter in one kernel up to E = 5)
@@ -777,9 +783,10 @@ def main():
             f"{cpu['gpu_over_oracle']:.0f}x ({threads} threads), {cpu['gpu_over_oracle_one_thread']:.0f}x (1 thread)")
 
     # roofline of the step's kernel: algorithmic bytes per launch (2-bit planes of both sequences,
-    # m/2 bytes per pair, plus the 2-byte result) over its median launch time from HIP events
+    # m/2 bytes per pair, plus the 2-byte result) over its mean launch time from HIP events on its
+    # stream over the timed steps (the median is reported beside it)
     bytes_ = n * (m // 2 + 2)
-    achieved = bytes_ / (step_ms * 1e-3) / 1e9
+    achieved = bytes_ / (step_mean_ms * 1e-3) / 1e9
     traffic = measured_traffic("k_sliced_E%d" % E, profile="sliced_sweep_100bp_E5_pmc.md") if n == 30_000_000 else None
     line = {
         "metric": "filtered pairs/sec at 1 GPU (100bp E=5)",
@@ -798,6 +805,7 @@ def main():
                                "one threshold's launch over the batch encoded once in 2-bit planes resident in HBM",
                    "n_pairs": n, "m": m, "E": E, "kernel": "lane-sliced column sweep (k_sliced<%d>)" % E},
         "step_kernel_median_ms": round(step_ms, 4),
+        "step_kernel_mean_ms": round(step_mean_ms, 4),
         "encode_ms": round(pack_ms, 4),
         "encode_plus_step_pairs_per_s": n / (1e-3 * (pack_ms + step_ms)),
         "one_call_ascii": one_call,
@@ -806,7 +814,7 @@ def main():
         "plain": plain,
         "roofline": {"bound": "hbm", "kernel": "lane-sliced column sweep (k_sliced<%d>)" % E, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "algorithmic_bytes": bytes_,
+                     "algorithmic_bytes": bytes_, "duration": "mean of the step's HIP events over the timed steps",
                      "bytes_rule": "2-bit planes of read and reference (m/2 B) + 2 B result per pair"},
         "sclk": sclk,
         "cpu_baseline": cpu,
