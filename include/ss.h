@@ -535,6 +535,26 @@ int ss_server_set_loop_idle(ss_server* server, int64_t idle_us);
 int ss_server_submit(ss_server* server, const uint8_t* reads, const uint8_t* refs, const int32_t* lengths,
                      const int32_t* E_per_pair, int64_t n_pairs, uint8_t* accept_out, int32_t* edits_out,
                      ss_ticket* ticket);
+/* Submission without the copy of the bases (either kind of server).
+ * ss_server_stage_alloc returns a block of `bytes` bytes of pinned host memory
+ * from the server's staging (mapped to the device), or NULL when bytes is 0 or
+ * the staging is full.  The caller writes a request's bases into it (the reads
+ * concatenated from its start, the references concatenated from refs_offset,
+ * a multiple of 16 recommended) and hands it to ss_server_submit_staged, which
+ * checks and plans the request as ss_server_submit does but reads the bases
+ * from the block on the device instead of copying them: the block then
+ * belongs to the request and returns to the staging when the request is done
+ * or cancelled (the caller must not touch it again).  On any status other
+ * than SS_OK the block stays the caller's; ss_server_stage_free returns a
+ * block that was never submitted (SS_EINVAL for any other pointer).  SS_EINVAL
+ * too when the two sides do not fit the block apart (refs_offset < the total
+ * of lengths, or past the block's end).  Blocks still held at
+ * ss_server_destroy are freed with the server. */
+void* ss_server_stage_alloc(ss_server* server, size_t bytes);
+int ss_server_stage_free(ss_server* server, void* block);
+int ss_server_submit_staged(ss_server* server, void* block, size_t refs_offset, const int32_t* lengths,
+                            const int32_t* E_per_pair, int64_t n_pairs, uint8_t* accept_out, int32_t* edits_out,
+                            ss_ticket* ticket);
 /* *done = 1 once the request has finished (or was cancelled). */
 int ss_server_poll(ss_server* server, ss_ticket ticket, int* done);
 /* Wait up to timeout_us (negative: no limit).  Returns the request's status

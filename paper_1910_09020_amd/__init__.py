@@ -98,6 +98,10 @@ def lib():
         "ss_server_create_loop": ([vp, ctypes.c_size_t, i32, i32, ctypes.POINTER(vp)], ctypes.c_int),
         "ss_server_set_loop_idle": ([vp, i64], ctypes.c_int),
         "ss_server_submit": ([vp, vp, vp, vp, vp, i64, vp, vp, ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
+        "ss_server_stage_alloc": ([vp, ctypes.c_size_t], vp),
+        "ss_server_stage_free": ([vp, vp], ctypes.c_int),
+        "ss_server_submit_staged": ([vp, vp, ctypes.c_size_t, vp, vp, i64, vp, vp, ctypes.POINTER(ctypes.c_uint64)],
+                                    ctypes.c_int),
         "ss_server_poll": ([vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
         "ss_server_wait": ([vp, ctypes.c_uint64, i64], ctypes.c_int),
         "ss_server_times": ([vp, ctypes.c_uint64, vp, vp, vp], ctypes.c_int),
@@ -135,7 +139,8 @@ def exported_symbols():
             "ss_server_wait", "ss_server_times", "ss_server_cancel", "ss_server_release", "ss_server_set_hold",
             "ss_server_stats", "ss_server_destroy", "ss_server_footprint", "ss_server_set_slices", "ss_pack_words",
             "ss_pack", "ss_filter_batch_ex", "ss_filter_batch_pairs", "ss_filter_ascii_noalloc",
-            "ss_server_stages", "ss_server_create_loop", "ss_verify_banded_async", "ss_server_set_loop_idle"]
+            "ss_server_stages", "ss_server_create_loop", "ss_verify_banded_async", "ss_server_set_loop_idle",
+            "ss_server_stage_alloc", "ss_server_stage_free", "ss_server_submit_staged"]
 
 
 def status_str(status: int) -> str:
@@ -411,6 +416,31 @@ def ss_server_submit(server, reads, refs, lengths, E_per_pair, accept_out, edits
     rc = lib().ss_server_submit(server, _ptr(reads), _ptr(refs), _ptr(lengths), _ptr(E_per_pair), n,
                                 _ptr(accept_out), _ptr(edits_out), ctypes.byref(t))
     _check(rc, "ss_server_submit")
+    return t.value
+
+
+def ss_server_stage_alloc(server, nbytes: int):
+    """A block of the server's pinned staging (its address, or None when the staging is full)."""
+    return lib().ss_server_stage_alloc(server, int(nbytes))
+
+
+def ss_server_stage_free(server, block) -> None:
+    _check(lib().ss_server_stage_free(server, block), "ss_server_stage_free")
+
+
+def stage_view(block, nbytes: int):
+    """A writable numpy view of nbytes of a staging block."""
+    return np.ctypeslib.as_array((ctypes.c_uint8 * int(nbytes)).from_address(int(block)))
+
+
+def ss_server_submit_staged(server, block, refs_offset: int, lengths, E_per_pair, accept_out, edits_out) -> int:
+    """Submit a request whose bases were written into a staging block (reads from its start, refs from
+    refs_offset); on success the block belongs to the server."""
+    n = len(lengths)
+    t = ctypes.c_uint64(0)
+    rc = lib().ss_server_submit_staged(server, block, int(refs_offset), _ptr(lengths), _ptr(E_per_pair), n,
+                                       _ptr(accept_out), _ptr(edits_out), ctypes.byref(t))
+    _check(rc, "ss_server_submit_staged")
     return t.value
 
 

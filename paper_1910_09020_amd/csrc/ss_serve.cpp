@@ -106,6 +106,11 @@ struct Request {
     void* pin = nullptr;
     size_t pin_cls = 0;
     std::vector<uint8_t> page;
+    // a staged submission (ss_server_submit_staged): the bases stay in the caller's block of the
+    // server's staging (reads at its start, refs at owned_refs), which returns to the pool when the
+    // request is done; the staging above then holds only the per-pair arrays
+    uint8_t* owned = nullptr;
+    size_t owned_cls = 0, owned_refs = 0;
     uint8_t* stage = nullptr;      // where results come back (set at launch)
     uint8_t* accept_out = nullptr;
     int32_t* edits_out = nullptr;
@@ -233,6 +238,8 @@ struct ss_server {
     ss_ctx* ctx = nullptr;
     PinnedPool pool;
     CopyCrew copier{3};              // submissions stage large requests' bases with three helpers
+    std::mutex blocks_mu;            // blocks of the staging handed to callers (ss_server_stage_alloc):
+    std::unordered_map<void*, std::pair<size_t, size_t>> blocks;    // block -> (pool class, bytes)
     int device = 0;
     size_t budget = 0;
     size_t used = 0;                 // sum of the footprints of requests in flight
@@ -284,6 +291,9 @@ size_t footprint_of(int64_t n, int64_t T)
 
 // Bytes of a request's staging: the device layout's inputs, results, error word.
 size_t stage_bytes(const Layout& L, int64_t n) { return L.in_bytes + al((size_t)n * 2) + 256; }
+// Layout of a request's host staging: the device layout, or for a staged submission the same
+// per-pair arrays without the bases (which stay in the caller's block)
+Layout stage_layout(const Request* r) { return Layout(r->n, r->owned ? 0 : r->total, r->n_items); }
 
 // Device-resident mode: a request's device memory is its four bit planes.
 size_t loop_footprint(int64_t T) { return al((size_t)(cdiv(T, 32) + 2) * 16); }
@@ -315,7 +325,7 @@ int ensure_loop(ss_server* S)
 int launch_request_loop(ss_server* S, Slot& sl, int si, Request* r)
 {
     TraceRange tr("serve: publish request to the loop");
-    const Layout L(r->n, r->total, r->n_items);
+    const Layout L = stage_layout(r);
     uint8_t* h = (uint8_t*)r->pin;
     if (!h) {
         const size_t need = stage_bytes(L, r->n);
@@ -337,8 +347,17 @@ int launch_request_loop(ss_server* S, Slot& sl, int si, Request* r)
     hipError_t e = hipHostGetDevicePointer((void**)&hd, h, 0);
     if (e != hipSuccess) return map_err(e);
     loop::Desc& d = S->H->desc[si];
-    d.reads = hd + L.reads;
-    d.refs = hd + L.refs;
+    if (r->owned) {
+        // staged: the kernel reads the bases from the caller's block
+        uint8_t* od = nullptr;
+        e = hipHostGetDevicePointer((void**)&od, r->owned, 0);
+        if (e != hipSuccess) return map_err(e);
+        d.reads = od;
+        d.refs = od + r->owned_refs;
+    } else {
+        d.reads = hd + L.reads;
+        d.refs = hd + L.refs;
+    }
     d.offsets = (const int64_t*)(hd + L.offsets);
     d.lengths = (const int32_t*)(hd + L.lengths);
     d.E = (const int32_t*)(hd + L.E);
@@ -364,11 +383,12 @@ int launch_request_loop(ss_server* S, Slot& sl, int si, Request* r)
 int launch_request(ss_server* S, Slot& sl, Request* r)
 {
     TraceRange tr("serve: enqueue request on its slot stream");
-    const Layout L(r->n, r->total, r->n_items);
+    const Layout L(r->n, r->total, r->n_items);      // on the device
+    const Layout Ls = stage_layout(r);                // in the host staging
     uint8_t* h = (uint8_t*)r->pin;
     if (!h) {
         // pageable staging: copy into the slot's own pinned buffer first
-        const size_t need = stage_bytes(L, r->n);
+        const size_t need = stage_bytes(Ls, r->n);
         if (sl.pinned_cap < need) {
             if (sl.pinned) (void)hipHostFree(sl.pinned);
             sl.pinned = nullptr;
@@ -379,7 +399,7 @@ int launch_request(ss_server* S, Slot& sl, Request* r)
             sl.pinned_cap = want;
         }
         h = (uint8_t*)sl.pinned;
-        std::memcpy(h, r->page.data(), L.in_bytes);
+        std::memcpy(h, r->page.data(), Ls.in_bytes);
     }
     r->stage = h;
     const int64_t t0 = now_ns();
@@ -391,7 +411,17 @@ int launch_request(ss_server* S, Slot& sl, Request* r)
     sl.arena_cap = r->footprint;
     uint8_t* d = (uint8_t*)arena;
     e = hipEventRecord(sl.ev[0], s);
-    if (e == hipSuccess) e = hipMemcpyAsync(d, h, L.in_bytes, hipMemcpyHostToDevice, s);
+    if (r->owned) {
+        // staged: the two sides straight from the caller's block, then the per-pair arrays
+        if (e == hipSuccess && r->total)
+            e = hipMemcpyAsync(d + L.reads, r->owned, (size_t)r->total, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess && r->total)
+            e = hipMemcpyAsync(d + L.refs, r->owned + r->owned_refs, (size_t)r->total, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(d + L.offsets, h + Ls.offsets, L.in_bytes - L.offsets, hipMemcpyHostToDevice, s);
+    } else if (e == hipSuccess) {
+        e = hipMemcpyAsync(d, h, L.in_bytes, hipMemcpyHostToDevice, s);
+    }
     if (e == hipSuccess) e = hipMemsetAsync(d + L.err, 0, 4, s);
     if (e == hipSuccess) e = hipEventRecord(sl.ev[1], s);
     if (e == hipSuccess)
@@ -405,7 +435,7 @@ int launch_request(ss_server* S, Slot& sl, Request* r)
                            (const int32_t*)(d + L.E), (uint16_t*)(d + L.results), s);
     }
     if (e == hipSuccess) e = hipEventRecord(sl.ev[2], s);
-    const size_t hres = L.in_bytes, herr = L.in_bytes + al((size_t)r->n * 2);
+    const size_t hres = Ls.in_bytes, herr = Ls.in_bytes + al((size_t)r->n * 2);
     if (e == hipSuccess && r->n)
         e = hipMemcpyAsync(h + hres, d + L.results, (size_t)r->n * 2, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipMemcpyAsync(h + herr, d + L.err, 4, hipMemcpyDeviceToHost, s);
@@ -435,6 +465,19 @@ int admit_slot(ss_server* S, Request* r)
     return -1;
 }
 
+// Return a request's pinned staging (and a staged submission's block) to the pool.
+void release_staging(ss_server* S, Request* r)
+{
+    if (r->pin) {
+        S->pool.put(r->pin, r->pin_cls);
+        r->pin = nullptr;
+    }
+    if (r->owned) {
+        S->pool.put(r->owned, r->owned_cls);
+        r->owned = nullptr;
+    }
+}
+
 void finish(ss_server* S, Request* r, int status)
 {
     // lock held
@@ -445,7 +488,7 @@ void finish(ss_server* S, Request* r, int status)
     r->status = status;
     r->state = DONE;
     r->t_done = now_ns();
-    if (r->pin) { S->pool.put(r->pin, r->pin_cls); r->pin = nullptr; }
+    release_staging(S, r);
     r->page.clear();
     r->page.shrink_to_fit();
     r->stage = nullptr;
@@ -521,8 +564,10 @@ void completer_main(ss_server* S)
                 for (int i : busy) {
                     Slot& sl = S->slots[(size_t)i];
                     Request* r = sl.cur;
-                    // the staging block stays with the request: a kernel may still write into it
+                    // the staging block (and a staged submission's block) stays with the request: a
+                    // kernel may still read or write it
                     r->pin = nullptr;
+                    r->owned = nullptr;
                     sl.cur = nullptr;
                     sl.launched = false;
                     S->running--;
@@ -544,7 +589,7 @@ void completer_main(ss_server* S)
                 r->ns_h2d = ordered ? (int64_t)(S->tick_ns * (double)(tp - ta)) : 0;
                 r->ns_compute = (int64_t)(S->tick_ns * (double)(td - (ordered ? tp : ta)));
                 r->ns_d2h = 0;
-                const Layout L(r->n, r->total, r->n_items);
+                const Layout L = stage_layout(r);
                 const uint16_t* res = (const uint16_t*)(r->stage + L.in_bytes);
                 int status = SS_OK;
                 if (S->H->err[i]) {
@@ -576,7 +621,7 @@ void completer_main(ss_server* S)
                 r->ns_h2d = (int64_t)(1e6 * ms[0]);
                 r->ns_compute = (int64_t)(1e6 * ms[1]);
                 r->ns_d2h = (int64_t)(1e6 * ms[2]);
-                const Layout L(r->n, r->total, r->n_items);
+                const Layout L = stage_layout(r);
                 const uint8_t* h = r->stage;
                 const uint16_t* res = (const uint16_t*)(h + L.in_bytes);
                 uint32_t err = 0;
@@ -760,9 +805,14 @@ extern "C" int ss_server_create_loop(ss_ctx* ctx, size_t hbm_budget_bytes, int32
     return SS_OK;
 }
 
-extern "C" int ss_server_submit(ss_server* S, const uint8_t* reads, const uint8_t* refs, const int32_t* lengths,
-                                const int32_t* E_per_pair, int64_t n_pairs, uint8_t* accept_out, int32_t* edits_out,
-                                ss_ticket* ticket)
+namespace {
+
+// Submission shared by ss_server_submit and ss_server_submit_staged.  block: a staged submission's
+// block of the server's staging (NULL: copy reads and refs into staging), block_bytes its size and
+// refs_off where its refs start.  The request takes the block only when it returns SS_OK.
+int submit_impl(ss_server* S, const uint8_t* reads, const uint8_t* refs, uint8_t* block, size_t block_cls,
+                size_t block_bytes, size_t refs_off, const int32_t* lengths, const int32_t* E_per_pair,
+                int64_t n_pairs, uint8_t* accept_out, int32_t* edits_out, ss_ticket* ticket)
 {
     if (!S || !ticket || n_pairs < 0) return SS_EINVAL;
     if (n_pairs > 0 && (!reads || !refs || !lengths || !E_per_pair || !accept_out || !edits_out)) return SS_EINVAL;
@@ -774,6 +824,8 @@ extern "C" int ss_server_submit(ss_server* S, const uint8_t* reads, const uint8_
         T += lengths[i];
     }
     if (T > SS_MAX_STREAM_BASES) return SS_ELEN;
+    if (block && (refs_off < (size_t)T || refs_off > block_bytes || block_bytes - refs_off < (size_t)T))
+        return SS_EINVAL;            // the two sides must lie in the block, apart
     if (S->loop && cdiv(cdiv(T, 32) + 2, loop::kPackWords) > loop::kMaxUnits) return SS_ELEN;
     Request* r = nullptr;
     try {
@@ -804,7 +856,8 @@ extern "C" int ss_server_submit(ss_server* S, const uint8_t* reads, const uint8_
             return SS_ELEN;
         }
         r->n_items = (int64_t)items.size();
-        const Layout L(n_pairs, T, r->n_items);
+        // the staging layout (as stage_layout gives it once the request holds the block)
+        const Layout L(n_pairs, block ? 0 : T, r->n_items);
         const size_t need = stage_bytes(L, n_pairs);
         uint8_t* h = (uint8_t*)S->pool.get(need, &r->pin_cls);
         if (h) {
@@ -813,7 +866,7 @@ extern "C" int ss_server_submit(ss_server* S, const uint8_t* reads, const uint8_
             r->page.resize(need);
             h = r->page.data();
         }
-        if (T) {
+        if (T && !block) {
             S->copier.copy(h + L.reads, reads, (size_t)T);
             S->copier.copy(h + L.refs, refs, (size_t)T);
         }
@@ -838,6 +891,11 @@ extern "C" int ss_server_submit(ss_server* S, const uint8_t* reads, const uint8_
         delete r;
         return S->broken ? SS_EDEVICE : SS_EINVAL;
     }
+    if (block) {
+        r->owned = block;            // from here the request returns it to the pool
+        r->owned_cls = block_cls;
+        r->owned_refs = refs_off;
+    }
     r->id = S->next_id++;
     S->reqs[r->id] = r;
     *ticket = r->id;
@@ -848,6 +906,66 @@ extern "C" int ss_server_submit(ss_server* S, const uint8_t* reads, const uint8_
     S->queue.push_back(r);
     S->cv_work.notify_all();
     return SS_OK;
+}
+
+}  // namespace
+
+extern "C" int ss_server_submit(ss_server* S, const uint8_t* reads, const uint8_t* refs, const int32_t* lengths,
+                                const int32_t* E_per_pair, int64_t n_pairs, uint8_t* accept_out, int32_t* edits_out,
+                                ss_ticket* ticket)
+{
+    return submit_impl(S, reads, refs, nullptr, 0, 0, 0, lengths, E_per_pair, n_pairs, accept_out, edits_out, ticket);
+}
+
+extern "C" void* ss_server_stage_alloc(ss_server* S, size_t bytes)
+{
+    if (!S || bytes == 0) return nullptr;
+    size_t cls = 0;
+    void* p = S->pool.get(bytes, &cls);
+    if (!p) return nullptr;
+    std::lock_guard<std::mutex> lk(S->blocks_mu);
+    S->blocks[p] = std::make_pair(cls, bytes);
+    return p;
+}
+
+extern "C" int ss_server_stage_free(ss_server* S, void* block)
+{
+    if (!S || !block) return SS_EINVAL;
+    size_t cls = 0;
+    {
+        std::lock_guard<std::mutex> lk(S->blocks_mu);
+        auto it = S->blocks.find(block);
+        if (it == S->blocks.end()) return SS_EINVAL;
+        cls = it->second.first;
+        S->blocks.erase(it);
+    }
+    S->pool.put(block, cls);
+    return SS_OK;
+}
+
+extern "C" int ss_server_submit_staged(ss_server* S, void* block, size_t refs_offset, const int32_t* lengths,
+                                       const int32_t* E_per_pair, int64_t n_pairs, uint8_t* accept_out,
+                                       int32_t* edits_out, ss_ticket* ticket)
+{
+    if (!S || !block) return SS_EINVAL;
+    std::pair<size_t, size_t> info;
+    {
+        // out of the registry while the submission runs (back in if it fails): once submitted, the
+        // request may finish and the pool hand the same address out again
+        std::lock_guard<std::mutex> lk(S->blocks_mu);
+        auto it = S->blocks.find(block);
+        if (it == S->blocks.end()) return SS_EINVAL;
+        info = it->second;
+        S->blocks.erase(it);
+    }
+    uint8_t* b = (uint8_t*)block;
+    const int rc = submit_impl(S, b, b + std::min(refs_offset, info.second), b, info.first, info.second, refs_offset,
+                               lengths, E_per_pair, n_pairs, accept_out, edits_out, ticket);
+    if (rc != SS_OK) {
+        std::lock_guard<std::mutex> lk(S->blocks_mu);
+        S->blocks[block] = info;
+    }
+    return rc;
 }
 
 extern "C" int ss_server_poll(ss_server* S, ss_ticket t, int* done)
@@ -911,7 +1029,7 @@ extern "C" int ss_server_cancel(ss_server* S, ss_ticket t)
     S->queue.erase(std::remove(S->queue.begin(), S->queue.end(), r), S->queue.end());
     r->state = CANCELLED;
     r->t_done = now_ns();
-    if (r->pin) { S->pool.put(r->pin, r->pin_cls); r->pin = nullptr; }
+    release_staging(S, r);
     r->page.clear();
     S->cv_done.notify_all();
     return SS_OK;
@@ -978,7 +1096,7 @@ extern "C" int ss_server_destroy(ss_server* S)
         for (Request* r : S->queue) {
             r->state = CANCELLED;
             r->t_done = now_ns();
-            if (r->pin) { S->pool.put(r->pin, r->pin_cls); r->pin = nullptr; }
+            release_staging(S, r);
         }
         S->queue.clear();
         S->hold = false;
@@ -1004,6 +1122,12 @@ extern "C" int ss_server_destroy(ss_server* S)
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
     }
     for (auto& kv : S->reqs) delete kv.second;
+    {
+        // blocks a caller took and never submitted or freed
+        std::lock_guard<std::mutex> lk(S->blocks_mu);
+        for (auto& kv : S->blocks) S->pool.put(kv.first, kv.second.first);
+        S->blocks.clear();
+    }
     S->pool.release_all();
     delete S;
     return SS_OK;

@@ -136,3 +136,39 @@ def test_bad_base_and_empty(env):
         assert ss.ss_server_wait(srv, t0, 1000) == ss.SS_OK
     finally:
         ss.ss_server_destroy(srv)
+
+
+def test_staged_submissions_on_slot_streams(env):
+    """Staged submissions (bases written into blocks of the server's staging, copied to the device
+    from there on the slot's stream) mixed with copied ones, with the slots full: every result
+    equals the oracle's; a bad base in a staged request is reported with the outputs untouched."""
+    ss, ctx = env
+    print("host server: staged submissions", flush=True)
+    srv = ss.ss_server_create(ctx, 1 << 28, 4)
+    try:
+        def staged(r):
+            T = len(r["reads"])
+            roff = (T + 15) // 16 * 16
+            blk = ss.ss_server_stage_alloc(srv, roff + max(T, 1))
+            assert blk
+            v = ss.stage_view(blk, roff + T)
+            v[:T] = r["reads"]
+            v[roff:roff + T] = r["refs"]
+            acc = np.full(r["n"], 255, np.uint8)
+            ed = np.full(r["n"], -1, np.int32)
+            return ss.ss_server_submit_staged(srv, blk, roff, r["lengths"], r["E"], acc, ed), acc, ed
+
+        reqs = [request(1300 + i, max_pairs=512, max_len=6000) for i in range(24)]
+        subs = [staged(r) if i % 2 else submit(ss, srv, r) for i, r in enumerate(reqs)]
+        for r, (t, a, e) in zip(reqs, subs):
+            assert ss.ss_server_wait(srv, t, 60_000_000) == ss.SS_OK
+            wa, we = want(r)
+            assert np.array_equal(a, wa) and np.array_equal(e, we)
+        bad = dict(reqs[3])
+        bad["refs"] = bad["refs"].copy()
+        bad["refs"][5] = ord("N")
+        t, a, e = staged(bad)
+        assert ss.ss_server_wait(srv, t, 60_000_000) == ss.SS_EBASE
+        assert np.all(a == 255) and np.all(e == -1)
+    finally:
+        ss.ss_server_destroy(srv)

@@ -235,6 +235,70 @@ def test_loop_staging_beyond_the_pinned_region(env):
         ss.ss_server_destroy(srv)
 
 
+def submit_staged(ss, srv, r):
+    """Write the request's bases into a block of the server's staging and submit it without a copy."""
+    T = len(r["reads"])
+    roff = (T + 15) // 16 * 16
+    blk = ss.ss_server_stage_alloc(srv, roff + max(T, 1))
+    assert blk
+    v = ss.stage_view(blk, roff + T)
+    v[:T] = r["reads"]
+    v[roff:roff + T] = r["refs"]
+    acc = np.full(r["n"], 255, np.uint8)
+    ed = np.full(r["n"], -1, np.int32)
+    t = ss.ss_server_submit_staged(srv, blk, roff, r["lengths"], r["E"], acc, ed)
+    return t, acc, ed
+
+
+def test_loop_staged_submissions(env):
+    """Requests whose bases are written into blocks of the server's staging and read from there on the
+    device (no copy at submission), mixed with copied ones: every result equals the oracle's.
+    Refusals leave the block with the caller; a submitted block is no longer the caller's."""
+    ss, ctx = env
+    print("loop server: staged submissions", flush=True)
+    srv = ss.ss_server_create_loop(ctx, 1 << 28, 16, 1)
+    try:
+        reqs = [request(1200 + i, max_pairs=512, max_len=6000) for i in range(30)]
+        subs = [(submit_staged if i % 3 else submit)(ss, srv, r) for i, r in enumerate(reqs)]
+        for r, (t, a, e) in zip(reqs, subs):
+            assert ss.ss_server_wait(srv, t, 60_000_000) == ss.SS_OK
+            wa, we = want(r)
+            assert np.array_equal(a, wa) and np.array_equal(e, we)
+        # refusals: the sides overlap, or the references run past the block
+        r = reqs[0]
+        T = len(r["reads"])
+        blk = ss.ss_server_stage_alloc(srv, 2 * T + 16)
+        acc = np.zeros(r["n"], np.uint8)
+        ed = np.zeros(r["n"], np.int32)
+        L = ss.lib()
+        for roff in (T - 1, T + 32):
+            rc = L.ss_server_submit_staged(srv, blk, roff, ss._ptr(r["lengths"]), ss._ptr(r["E"]), r["n"],
+                                           ss._ptr(acc), ss._ptr(ed), ss.ctypes.byref(ss.ctypes.c_uint64(0)))
+            assert rc == ss.SS_EINVAL
+        ss.ss_server_stage_free(srv, blk)                 # still the caller's after the refusals
+        with pytest.raises(ss.SSError):
+            ss.ss_server_stage_free(srv, blk)             # not twice
+        with pytest.raises(ss.SSError):
+            ss.ss_server_stage_free(srv, 4096)            # not a block of the staging
+        t, a, e = submit_staged(ss, srv, reqs[1])
+        assert ss.ss_server_wait(srv, t, 60_000_000) == ss.SS_OK
+        # held and cancelled: the block returns to the staging with the request
+        ss.ss_server_set_hold(srv, True)
+        t2, _, _ = submit_staged(ss, srv, reqs[2])
+        assert ss.ss_server_cancel(srv, t2) == ss.SS_OK
+        ss.ss_server_set_hold(srv, False)
+        # an empty staged request completes at once
+        z = dict(reads=np.zeros(0, np.uint8), refs=np.zeros(0, np.uint8), lengths=np.zeros(0, np.int32),
+                 E=np.zeros(0, np.int32), n=0)
+        tz, _, _ = submit_staged(ss, srv, z)
+        assert ss.ss_server_wait(srv, tz, 1000) == ss.SS_OK
+        assert ss.ss_server_stage_alloc(srv, 0) is None
+        left = ss.ss_server_stage_alloc(srv, 1 << 20)     # held at destroy: freed with the server
+        assert left
+    finally:
+        ss.ss_server_destroy(srv)
+
+
 def test_loop_relaunch_race_with_a_tiny_idle_time(env):
     """With the loop's idle time at 20 microseconds the kernel ends between requests over and over, so
     requests are published just as it ends (the host launches it again when it finds the last launch
