@@ -425,11 +425,18 @@ def serving_leg(a, ss, gen, runner, oracle, mode=None, seconds=None):
         ss.ss_server_set_slices(srv, a.serve_slices)
     submit_ptr = ctypes.cast(ss.lib().ss_server_submit, ctypes.c_void_p).value
     pool = min(nreq, a.serve_pool)
+    # on the fly, requests are generated into blocks of the server's pinned staging and submitted without
+    # a copy (ss_server_submit_staged), unless --serve-copy asks for the copying submission
+    staged = None
+    if pool == 0 and not getattr(a, "serve_copy", False):
+        L = ss.lib()
+        staged = tuple(ctypes.cast(f, ctypes.c_void_p).value
+                       for f in (L.ss_server_stage_alloc, L.ss_server_stage_free, L.ss_server_submit_staged))
     # on the fly: generator threads run up to 2,048 requests ahead of the clock (a head start of as many
     # before it starts), and 8 submitter threads hand each request over at its due time
     # (12 generator threads leave the server's threads cores of their own on a 16-core host share)
     D = gen.drive(seed, arr, submit_ptr, srv, threads=12 if pool == 0 else min(16, max(4, os.cpu_count() or 1)),
-                  pool=pool)
+                  pool=pool, staged=staged)
     assert D.submitted == nreq, f"submission failed: {D.submitted}"
     for t in D.tickets:
         rc = ss.ss_server_wait(srv, int(t), -1)
@@ -492,8 +499,10 @@ def serving_leg(a, ss, gen, runner, oracle, mode=None, seconds=None):
                hbm_budget_bytes=budget, stats=st,
                hw_queues=os.environ.get("GPU_MAX_HW_QUEUES", "HIP default"), distinct_requests=pool or nreq,
                breakdown=breakdown,
-               generation=("every request generated from its own seed, up to 2,048 ahead of the clock" if not pool else
-                           f"{pool} requests generated before the clock, replayed in a cycle"),
+               generation=(f"every request generated from its own seed, up to {512 if staged else 2048} ahead of "
+                           "the clock" if not pool else f"{pool} requests generated before the clock, replayed in a cycle"),
+               submission=("staged: generated into blocks of the server's pinned staging, submitted without a copy "
+                           "(ss_server_submit_staged)" if staged else "copied into staging (ss_server_submit)"),
                slices_per_lane=a.serve_slices,
                oracle_checked_requests=int(len(chk)), oracle_mismatches=mism)
     log(f"serving ({mode}): {nreq} requests, {pairs} pairs in {span:.2f}s, p50 {res['p50_ms']:.3f} ms, "
@@ -580,6 +589,9 @@ def main():
     ap.add_argument("--serve-pool", type=int, default=0,
                     help="0 (default): every request generated from its own seed, ahead of its arrival; N > 0: "
                          "N distinct requests generated before the clock starts and replayed in a cycle")
+    ap.add_argument("--serve-copy", action="store_true",
+                    help="submit requests with ss_server_submit (bases copied into staging) instead of generating "
+                         "them into the server's staging")
     ap.add_argument("--serve-only", action="store_true", help="run only the serving leg (diagnostics)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-sclk", action="store_true")

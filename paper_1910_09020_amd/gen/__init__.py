@@ -66,7 +66,8 @@ def _load():
     lib.ssgen_request_fill.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32, vp, vp, vp, vp]
     lib.ssgen_request_fill.restype = ctypes.c_int
     lib.ssgen_drive.argtypes = [ctypes.c_uint64, vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
-                                vp, vp, ctypes.c_int, ctypes.c_int64, ctypes.c_int64, vp, vp, vp, vp, vp, vp, vp]
+                                vp, vp, ctypes.c_int, ctypes.c_int64, ctypes.c_int64, vp, vp, vp, vp, vp, vp, vp,
+                                vp, vp, vp]
     lib.ssgen_drive.restype = ctypes.c_int64
     lib.ssgen_drive_free.argtypes = [ctypes.c_int64, vp, vp]
     lib.ssgen_drive_free.restype = None
@@ -180,17 +181,20 @@ class Drive:
 
 
 def drive(seed: int, arrivals_s: np.ndarray, submit_fn_ptr: int, server: int, threads: int = 8, pool: int = 0,
-          t0_ns: int = 0, max_pairs: int = 4096, min_len: int = 100, max_len: int = 10000) -> Drive:
+          t0_ns: int = 0, max_pairs: int = 4096, min_len: int = 100, max_len: int = 10000, staged=None) -> Drive:
     """Generate and submit the requests of a schedule natively (submit_fn_ptr: address of a function with
     the signature of ss_server_submit; server: its first argument).  pool > 0: requests 0..pool-1 are
-    generated before the clock starts and schedule position i replays request i mod pool."""
+    generated before the clock starts and schedule position i replays request i mod pool.  staged:
+    addresses of (ss_server_stage_alloc, ss_server_stage_free, ss_server_submit_staged) to generate each
+    request into the server's staging and submit it without a copy (on the fly only)."""
     lib = _load()
     arr = np.ascontiguousarray(arrivals_s, dtype=np.float64)
     n = len(arr)
     D = Drive(n)
     got = lib.ssgen_drive(seed, _p(arr), n, max_pairs, min_len, max_len, ctypes.c_void_p(submit_fn_ptr),
                           ctypes.c_void_p(server), threads, pool, t0_ns, _p(D.tickets), _p(D.due_ns), _p(D.call_ns), _p(D.pairs),
-                          _p(D.bases), ctypes.cast(D._acc, ctypes.c_void_p), ctypes.cast(D._ed, ctypes.c_void_p))
+                          _p(D.bases), ctypes.cast(D._acc, ctypes.c_void_p), ctypes.cast(D._ed, ctypes.c_void_p),
+                          *[ctypes.c_void_p(x) for x in (staged or (None, None, None))])
     D.submitted = int(got)
     return D
 

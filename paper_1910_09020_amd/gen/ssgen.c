@@ -522,11 +522,21 @@ typedef int (*ssgen_submit_fn)(void* server, const uint8_t* reads, const uint8_t
                                const int32_t* E, int64_t n, uint8_t* accept_out, int32_t* edits_out,
                                uint64_t* ticket);
 
+/* staged submission: a block of the server's staging, freed back to it, and the submit that hands
+ * a block over (signatures of ss_server_stage_alloc, ss_server_stage_free, ss_server_submit_staged) */
+typedef void* (*ssgen_stage_alloc_fn)(void* server, size_t bytes);
+typedef int (*ssgen_stage_free_fn)(void* server, void* block);
+typedef int (*ssgen_submit_staged_fn)(void* server, void* block, size_t refs_offset, const int32_t* lengths,
+                                      const int32_t* E, int64_t n, uint8_t* accept_out, int32_t* edits_out,
+                                      uint64_t* ticket);
+
 typedef struct {
     int32_t n;
     int64_t total;
     uint8_t* reads; uint8_t* refs;
     int32_t* lengths; int32_t* E;
+    void* block;                 /* staged: reads and refs live in this block of the server's staging */
+    size_t roff;                 /* where refs start in it */
 } pool_req;
 
 typedef struct {
@@ -539,6 +549,7 @@ typedef struct {
     _Atomic int stop_gen;
     const double* arrivals; int64_t t0_ns;
     ssgen_submit_fn submit; void* server;
+    ssgen_stage_alloc_fn stage_alloc; ssgen_stage_free_fn stage_free; ssgen_submit_staged_fn submit_staged;
     uint64_t* tickets; int64_t* due_ns; int64_t* call_ns; int32_t* pairs; int64_t* bases;
     uint8_t** accept_out; int32_t** edits_out;
     _Atomic int64_t next;
@@ -577,8 +588,19 @@ static void make_request(drive_ctx* D, int64_t id, pool_req* q)
     q->total = ssgen_request_plan(D->seed, id, n, D->min_len, D->max_len, q->lengths, q->E);
     int64_t o = 0;
     for (int32_t k = 0; k < n; k++) { offsets[k] = o; o += q->lengths[k]; }
-    q->reads = (uint8_t*)malloc((size_t)(q->total > 0 ? q->total : 1));
-    q->refs = (uint8_t*)malloc((size_t)(q->total > 0 ? q->total : 1));
+    q->block = NULL;
+    if (D->stage_alloc && D->n_pool == 0) {
+        /* generated straight into the server's staging (no copy at submission) */
+        q->roff = (size_t)((q->total + 15) / 16 * 16);
+        q->block = D->stage_alloc(D->server, q->roff + (size_t)(q->total > 0 ? q->total : 1));
+    }
+    if (q->block) {
+        q->reads = (uint8_t*)q->block;
+        q->refs = (uint8_t*)q->block + q->roff;
+    } else {
+        q->reads = (uint8_t*)malloc((size_t)(q->total > 0 ? q->total : 1));
+        q->refs = (uint8_t*)malloc((size_t)(q->total > 0 ? q->total : 1));
+    }
     ssgen_request_fill(D->seed, id, n, offsets, q->lengths, q->reads, q->refs);
     free(offsets);
 }
@@ -645,11 +667,19 @@ static void* drive_worker(void* arg)
         D->bases[i] = q->total;
         sleep_until(due);
         D->call_ns[i] = mono_ns();
-        const int rc = D->submit(D->server, q->reads, q->refs, q->lengths, q->E, q->n, D->accept_out[i],
-                                 D->edits_out[i], &D->tickets[i]);
+        const int rc = q->block ? D->submit_staged(D->server, q->block, q->roff, q->lengths, q->E, q->n,
+                                                   D->accept_out[i], D->edits_out[i], &D->tickets[i])
+                                : D->submit(D->server, q->reads, q->refs, q->lengths, q->E, q->n, D->accept_out[i],
+                                            D->edits_out[i], &D->tickets[i]);
         if (D->n_pool <= 0) {
             pool_req* own = &D->ring[i % D->lead];
-            free(own->reads); free(own->refs); free(own->lengths); free(own->E);
+            if (own->block) {
+                if (rc != 0) D->stage_free(D->server, own->block);   /* refused: still ours */
+                own->block = NULL;                                    /* else the server's now */
+            } else {
+                free(own->reads); free(own->refs);
+            }
+            free(own->lengths); free(own->E);
             atomic_store(&D->ring_pos[i % D->lead], -1);
         }
         if (rc != 0) {
@@ -672,26 +702,38 @@ static void* drive_worker(void* arg)
  * submitters.  pool = 0: every position's request is generated from its own
  * seed on the fly by `threads` generator threads, running up to
  * min(n_req, 2048) positions ahead of the submissions (the first ones before
- * the clock starts), and submitted by 8 submitters.  t0_ns: schedule time zero
- * (0 = 100 ms after the pool or the head start is ready). */
+ * the clock starts), and submitted by 8 submitters.  With stage_alloc,
+ * stage_free and submit_staged given (pool = 0 only), each request is
+ * generated into a block of the server's staging and handed over without a
+ * copy (a request falls back to submit when the staging is full), 512 ahead.
+ * t0_ns: schedule time zero (0 = 100 ms after the pool or the head start is
+ * ready). */
 int64_t ssgen_drive(uint64_t seed, const double* arrivals, int64_t n_req, int32_t max_pairs, int32_t min_len,
                     int32_t max_len, ssgen_submit_fn submit, void* server, int threads, int64_t pool,
                     int64_t t0_ns, uint64_t* tickets, int64_t* due_ns, int64_t* call_ns, int32_t* pairs,
                     int64_t* bases,
-                    uint8_t** accept_out, int32_t** edits_out)
+                    uint8_t** accept_out, int32_t** edits_out, ssgen_stage_alloc_fn stage_alloc,
+                    ssgen_stage_free_fn stage_free, ssgen_submit_staged_fn submit_staged)
 {
     if (threads < 1) threads = 1;
     if (threads > 64) threads = 64;
     drive_ctx D;
     D.seed = seed; D.n_req = n_req; D.max_pairs = max_pairs; D.min_len = min_len; D.max_len = max_len;
     D.arrivals = arrivals; D.submit = submit; D.server = server;
+    /* staged only with all three functions, and only on the fly (a replayed pool is submitted many times) */
+    const int staged = stage_alloc && stage_free && submit_staged && pool <= 0;
+    D.stage_alloc = staged ? stage_alloc : NULL;
+    D.stage_free = staged ? stage_free : NULL;
+    D.submit_staged = staged ? submit_staged : NULL;
     D.tickets = tickets; D.due_ns = due_ns; D.call_ns = call_ns; D.pairs = pairs; D.bases = bases;
     D.accept_out = accept_out; D.edits_out = edits_out;
     for (int64_t i = 0; i < n_req; i++) { accept_out[i] = NULL; edits_out[i] = NULL; }
     D.n_pool = pool > 0 ? pool : 0;
     D.pool = (pool_req*)calloc((size_t)(D.n_pool > 0 ? D.n_pool : 1), sizeof(pool_req));
     atomic_store(&D.next_pool, 0);
-    D.lead = D.n_pool > 0 ? 1 : (n_req < 2048 ? (n_req > 0 ? n_req : 1) : 2048);
+    /* staged: the ring holds server staging, so it runs 512 ahead instead of 2,048 */
+    const int64_t lead_max = staged ? 512 : 2048;
+    D.lead = D.n_pool > 0 ? 1 : (n_req < lead_max ? (n_req > 0 ? n_req : 1) : lead_max);
     D.ring = (pool_req*)calloc((size_t)D.lead, sizeof(pool_req));
     D.ring_pos = (_Atomic int64_t*)malloc(sizeof(_Atomic int64_t) * (size_t)D.lead);
     for (int64_t k = 0; k < D.lead; k++) atomic_store(&D.ring_pos[k], -1);
@@ -724,7 +766,9 @@ int64_t ssgen_drive(uint64_t seed, const double* arrivals, int64_t n_req, int32_
     for (int64_t k = 0; k < D.lead; k++) {
         /* requests generated but never submitted (a submission failed) */
         if (D.n_pool == 0 && atomic_load(&D.ring_pos[k]) != -1) {
-            free(D.ring[k].reads); free(D.ring[k].refs); free(D.ring[k].lengths); free(D.ring[k].E);
+            if (D.ring[k].block) D.stage_free(D.server, D.ring[k].block);
+            else { free(D.ring[k].reads); free(D.ring[k].refs); }
+            free(D.ring[k].lengths); free(D.ring[k].E);
         }
     }
     free(D.ring);
