@@ -71,6 +71,33 @@ def test_host_plan_invariants(spl):
     assert keys == sorted(keys)
 
 
+@pytest.mark.parametrize("spl", [1, 8])
+def test_host_plan_order_is_the_plain_sort(spl):
+    """The permutation is exactly the plain sort of the pairs by (shape class in order of first
+    appearance, 256-pair chunk of one-lane classes in input order, length descending, threshold
+    descending, input position), on lengths up to the limit and many ties."""
+    rng = np.random.default_rng(19100)
+    for trial in range(6):
+        n = int(rng.integers(500, 3000))
+        lengths = rng.choice(np.array([0, 1, 100, 250, 10_000, (1 << 24) - 1, 1 << 24], np.int32), n)
+        if trial % 2:
+            lengths = rng.integers(0, (1 << 24) + 1, n).astype(np.int32)
+        E = rng.choice(np.array([0, 1, 5, 15, 16, 100, 127, 128, 1000, 4000], np.int32), n)
+        items, perm = ss.ss_plan_items_host(lengths, E, spl)
+        slices = (2 * int(E.max()) + 1 + 31) // 32
+        rsmax = max(spl, min(r for r in (1, 2, 4, 8) if 64 * r >= slices))
+        shapes = [_shape_for(int(e), rsmax) for e in E]
+        cid, seen, key = {}, {}, []
+        for i in range(n):
+            c = cid.setdefault(shapes[i], len(cid))
+            chunk = 0
+            if shapes[i][0] == 1:
+                chunk = seen.get(c, 0) // 256
+                seen[c] = seen.get(c, 0) + 1
+            key.append((c, chunk, -int(lengths[i]), -int(E[i]), i))
+        assert perm.tolist() == [k[4] for k in sorted(key)], trial
+
+
 def test_host_plan_errors():
     lengths = np.full(4, 100, np.int32)
     with pytest.raises(ss.SSError) as e:
