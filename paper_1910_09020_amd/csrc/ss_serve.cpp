@@ -169,6 +169,7 @@ struct PinnedPool {
     }
     void* get(size_t need, size_t* cls)
     {
+        if (need == 0 || need > cap) return nullptr;     // (also keeps the class doubling below from overflowing)
         {
             std::lock_guard<std::mutex> lk(mu);
             const size_t r = std::max<size_t>(4096, (need + 4095) & ~(size_t)4095);

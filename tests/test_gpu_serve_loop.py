@@ -293,6 +293,7 @@ def test_loop_staged_submissions(env):
         tz, _, _ = submit_staged(ss, srv, z)
         assert ss.ss_server_wait(srv, tz, 1000) == ss.SS_OK
         assert ss.ss_server_stage_alloc(srv, 0) is None
+        assert ss.ss_server_stage_alloc(srv, 1 << 62) is None    # beyond the staging's cap
         left = ss.ss_server_stage_alloc(srv, 1 << 20)     # held at destroy: freed with the server
         assert left
     finally:
