@@ -537,8 +537,9 @@ int ss_server_submit(ss_server* server, const uint8_t* reads, const uint8_t* ref
                      ss_ticket* ticket);
 /* Submission without the copy of the bases (either kind of server).
  * ss_server_stage_alloc returns a block of `bytes` bytes of pinned host memory
- * from the server's staging (mapped to the device), or NULL when bytes is 0 or
- * the staging is full.  The caller writes a request's bases into it (the reads
+ * from the server's staging (mapped to the device on a device-resident loop
+ * server, whose kernel reads it there; copied from by DMA on the other kind),
+ * or NULL when bytes is 0 or the staging is full.  The caller writes a request's bases into it (the reads
  * concatenated from its start, the references concatenated from refs_offset,
  * a multiple of 16 recommended) and hands it to ss_server_submit_staged, which
  * checks and plans the request as ss_server_submit does but reads the bases
