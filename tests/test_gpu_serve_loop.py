@@ -303,8 +303,9 @@ def test_loop_staged_submissions(env):
 def test_loop_relaunch_race_with_a_tiny_idle_time(env):
     """With the loop's idle time at 20 microseconds the kernel ends between requests over and over, so
     requests are published just as it ends (the host launches it again when it finds the last launch
-    done with a request waiting); requests come from four threads at random gaps.  Every result
-    equals the oracle's."""
+    done with a request waiting); requests come from four threads at random gaps, two of them
+    submitting staged (taking, filling and handing over blocks of the staging concurrently).  Every
+    result equals the oracle's."""
     import random
     import threading
     ss, ctx = env
@@ -321,7 +322,7 @@ def test_loop_relaunch_race_with_a_tiny_idle_time(env):
             try:
                 for i in range(k, len(reqs), 4):
                     time.sleep(rng.choice([0, 0, 0.00005, 0.0003, 0.002]))
-                    subs[i] = submit(ss, srv, reqs[i])
+                    subs[i] = (submit_staged if k % 2 else submit)(ss, srv, reqs[i])
             except Exception as ex:          # reported below
                 errors.append(repr(ex))
 
