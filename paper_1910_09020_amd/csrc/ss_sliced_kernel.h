@@ -79,10 +79,14 @@ struct SweepState {
 
 // Window loop variants.
 enum { MAIN_CIRC = 0, MAIN_SHIFT4 = 1 };
-// Thresholds up to this sweep with one window over the whole pair; above it
-// the window's registers cost more occupancy than the reloads at the seams of
-// the three-part sweep (sweep_group_seams) cost traffic (measured per E).
-constexpr int kMaxESingleWindow = 7;
+// Thresholds that sweep with one window over the whole pair, its loads running
+// a chunk ahead; the others take the three-part sweep (sweep_group_seams) with
+// four-chunk steps.  Chosen per E from measurements on 30 M x 100 bp and
+// 10 M x 250 bp, one window against three parts: E = 8..10 6-15% faster,
+// E = 11 and 12 up to 8% and 5% slower, E = 13..16 5-8% faster, E = 18 and 20
+// three times slower (from E = 17 the window's ring is 12 chunks and the
+// registers pass 240 VGPRs).
+constexpr bool single_window(int E) { return E <= 10 || (E >= 13 && E <= 16); }
 
 // Column sweep of group g (pairs 32g .. 32g+31); writes the group's results.
 // ld(plane, c) returns the four words of chunk c of a plane (Q0, Q1, R0, R1)
@@ -205,11 +209,9 @@ __device__ __forceinline__ void sweep_group(LD&& ld, int m, int64_t g, int64_t n
 // chunks whose columns see a query index outside [0, m) (the first EC and the
 // last few) run through a checked loop with a window of its own, reloading the
 // few chunks it shares with the interior, where that register-lean form is
-// faster than the single window above; interior chunks run unchecked with the
-// query window held in registers:
-//   MAIN_CIRC  : slot = chunk mod W with the loop unrolled W chunks, so every
-//                register index is static and the window never moves;
-//   MAIN_SHIFT4: four chunks per step, the window shifts by four chunks.
+// faster than the single window above; interior chunks run unchecked, four
+// per step (MAIN_SHIFT4: their loads issued together, the window shifting by
+// four chunks).
 template <int E, int MODE, bool SUB = false, class LD>
 __device__ __forceinline__ void sweep_group_seams(LD&& ld, int m, int64_t g, int64_t n_pairs,
                                             uint16_t* __restrict__ out, int sub_width = 0)
@@ -268,29 +270,8 @@ __device__ __forceinline__ void sweep_group_seams(LD&& ld, int m, int64_t g, int
     const int ct = (m - B - E >= 0) ? (m - B - E) / B + 1 : 0;
     auto always = [](int) { return ~0u; };
     if (ct > EC) {
-        if constexpr (MODE == MAIN_CIRC) {
-            uint32_t q0w[W][B], q1w[W][B];
-#pragma unroll
-            for (int c = 0; c < 2 * EC; c++) { put(q0w[c % W], ld(0, c)); put(q1w[c % W], ld(1, c)); }
-            for (int cb = 0; cb < ct; cb += W) {
-#pragma unroll
-                for (int u = 0; u < W; u++) {
-                    const int c0 = cb + u;
-                    if (c0 >= EC && c0 < ct) {
-                        if (c0 + EC < nch) { put(q0w[(u + EC) % W], ld(0, c0 + EC)); put(q1w[(u + EC) % W], ld(1, c0 + EC)); }
-                        const uint4 rr0 = ld(2, c0), rr1 = ld(3, c0);
-#pragma unroll
-                        for (int t = 0; t < B; t++) {
-                            if (SUB && B * c0 + t == next_sub) { st.restart(); next_sub += sub_width; }
-                            st.template column<false>(comp(rr0, t), comp(rr1, t),
-                                      [&](int r) { const int o = t + r - E, d = floordiv(o, B); return q0w[(u + d + 2 * W) % W][o - d * B]; },
-                                      [&](int r) { const int o = t + r - E, d = floordiv(o, B); return q1w[(u + d + 2 * W) % W][o - d * B]; },
-                                      always);
-                        }
-                    }
-                }
-            }
-        } else {
+        static_assert(MODE == MAIN_SHIFT4, "three parts: four chunks per step");
+        {
             constexpr int U = 4;
             constexpr int NW = 2 * EC + U;          // slot i holds chunk cb - EC + i
             uint32_t q0w[NW][B], q1w[NW][B];
@@ -352,7 +333,7 @@ __global__ __launch_bounds__(256) void k_sliced(const uint32_t* __restrict__ pk,
         const v4u x = __builtin_nontemporal_load(base + ((int64_t)plane * nch + c) * Gb);
         return make_uint4(x.x, x.y, x.z, x.w);
     };
-    if constexpr (E <= kMaxESingleWindow)
+    if constexpr (single_window(E))
         sweep_group<E, MODE, SUB>(ld, m, g, n_pairs, out, sub_width);
     else
         sweep_group_seams<E, MODE, SUB>(ld, m, g, n_pairs, out, sub_width);
@@ -365,7 +346,7 @@ hipError_t launch_sliced_E(const uint32_t* packed, int64_t n_pairs, int32_t m, i
     const int64_t G = cdiv(n_pairs, 32);
     const int threads = 256;
     const int64_t blocks = cdiv(G, threads);
-    constexpr int mode = E <= 10 ? MAIN_CIRC : MAIN_SHIFT4;
+    constexpr int mode = single_window(E) ? MAIN_CIRC : MAIN_SHIFT4;
     if (sub_width > 0 && sub_width < m)
         hipLaunchKernelGGL((k_sliced<E, mode, true>), dim3((unsigned)blocks), dim3(threads), 0, s, packed, G, m,
                            n_pairs, out, sub_width);
