@@ -94,7 +94,7 @@ def test_config1_sweep(rt, E):
     run_all(rt, gen.make(1, n=20000 + 7), E)
 
 
-@pytest.mark.parametrize("E", [0, 1, 3, 8, 13, 20, 25])
+@pytest.mark.parametrize("E", [0, 1, 3, 8, 10, 11, 12, 13, 16, 17, 20, 25])
 def test_config2_sweep(rt, E):
     run_all(rt, gen.make(2, n=4000 + 19), E)
 
@@ -112,8 +112,9 @@ def test_ragged_lengths(rt, m):
         refs[p * m:(p + 1) * m] = rng.choice(np.frombuffer(b"ACGT", np.uint8), size=m)
     b = dict(n=n, reads=reads, refs=refs, offsets=np.arange(n, dtype=np.int64) * m,
              lengths=np.full(n, m, np.int32), E=None)
-    # every window size of the single-window sweep (E = 0; 1..4; 5..7) and of the three-part one
-    for E in (0, 1, 2, 3, 4, 5, 6, 7, 9, 16, 31, 32):
+    # every window size of the one-window sweep (E = 0; 1..4; 5..8; 9, 10; 13..16) and of the
+    # three-part one (E = 11, 12; 17..20; 29..32), with each form's first and last threshold
+    for E in (0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 16, 17, 20, 29, 31, 32):
         run_all(rt, b, E)
 
 
