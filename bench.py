@@ -650,7 +650,7 @@ def main():
         f"mean {step_mean_ms:.4f} ms) "
         f"{value / 1e9:.2f} G pairs/s; encode {pack_ms:.4f} ms")
 
-    # the one-call path from ASCII in HBM (encode + filter in one kernel up to E = 5)
+    # the one-call path from ASCII in HBM (encode + filter in one kernel up to E = 10)
     out1 = torch.empty(n, dtype=torch.int16, device="cuda")
     one = lambda: db.filter_fused(E, out=out1)
     one()
@@ -659,7 +659,7 @@ def main():
     _, (one_ms,) = timed_loop([one], max(10, a.steps), torch)
     db.check_err("one-call")
     one_call = dict(entry="ss_filter_ascii_async", kernel=("fused encode + sweep (k_fused<%d, true>)" % E
-                                                             if E <= 5 else "encode + sweep in chunks"),
+                                                             if E <= 10 else "encode + sweep in chunks"),
                     ms=round(one_ms, 4), pairs_per_s=n / (1e-3 * one_ms),
                     identical_outputs=bool(torch.equal(out[:n], out1[:n])),
                     ascii_bytes_read=n * 2 * m,

@@ -180,7 +180,7 @@ int ss_filter_submaze_async(ss_ctx* ctx, const uint32_t* packed, int64_t n_pairs
  * results are identical to ss_pack_sliced_async followed by
  * ss_filter_sliced_async (Equation 1 operands, Section 2.4 walk); the schedule
  * depends on E:
- *   E <= 5 : one fused kernel.  Three wavefronts of each workgroup encode
+ *   E <= 10: one fused kernel.  Three wavefronts of each workgroup encode
  *            tiles of tile_groups groups of 32 pairs into one of two on-chip
  *            buffers while the fourth sweeps the previous tile from the other
  *            (for 16-byte aligned reads and refs and m <= 224 each encoding
@@ -190,7 +190,7 @@ int ss_filter_submaze_async(ss_ctx* ctx, const uint32_t* packed, int64_t n_pairs
  *            With tile_groups = 0 and 16-byte aligned reads and refs the
  *            fused kernel runs only in the first form (m <= 224); longer
  *            aligned pairs take the two kernels below, which are faster there.
- *   E > 5  : the two kernels over chunks of about 400 MB of packed data, kept
+ *   E > 10 : the two kernels over chunks of about 400 MB of packed data, kept
  *            in a buffer owned by ctx (allocated on first use, grown when a
  *            longer m needs it): calls that take this schedule on one context
  *            must be ordered (one stream), or use one context per stream.

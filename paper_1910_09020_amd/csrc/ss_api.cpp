@@ -141,10 +141,9 @@ extern "C" int ss_filter_sliced_async(ss_ctx* ctx, const uint32_t* packed, int64
     return map_err(launch_sliced(packed, n_pairs, m, E, out, (hipStream_t)stream));
 }
 
-// Thresholds up to kMaxEFused run the fused kernel; above it, where the
-// sweep's registers leave the fused kernel too few waves, encode and sweep run
-// as two kernels over chunks whose packed form (about 400 MB) stays in the
-// device's cache between the two.
+// Thresholds up to kMaxEFused (up to 10% of a 100 bp read) run the fused
+// kernel; above it encode and sweep run as two kernels over chunks whose
+// packed form (about 400 MB) stays in the device's cache between the two.
 constexpr int64_t kChunkPackedBytes = 400ll << 20;
 
 extern "C" int ss_filter_ascii_async(ss_ctx* ctx, const uint8_t* reads, const uint8_t* refs, int64_t n_pairs,

@@ -12,7 +12,7 @@ namespace ss {
 constexpr int kChunk = 4;              // positions per chunk in the lane-sliced layout
 constexpr int kMaxESliced = 32;
 constexpr int kMaxEPlain = 31;
-constexpr int kMaxEFused = 5;                  // fused encode + sweep kernel (larger E: chunked two kernels)
+constexpr int kMaxEFused = 10;                 // fused encode + sweep kernel (larger E: chunked two kernels)
 constexpr int64_t kMaxFusedLds = 160 * 1024;   // LDS per workgroup on gfx950
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }

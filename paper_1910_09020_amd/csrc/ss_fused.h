@@ -1,4 +1,4 @@
-// Fused encode-and-sweep kernel (the one-call path for E <= 5): the encoder of
+// Fused encode-and-sweep kernel (the one-call path for E <= 10): the encoder of
 // ss_tile.h writes each tile of pairs into on-chip memory, where the column
 // sweep of Section 2.4 runs on it; the packed encoding never reaches device
 // memory.
@@ -41,34 +41,51 @@ __device__ __forceinline__ uint32_t quad_or(uint32_t x)
 // position j + vb + i, vb = sh - E.  A column's "some row is free" is the OR
 // over the group's lanes of each lane's own OR, so every lane keeps the same
 // count (the thermometer Tm, as in SweepState).
-// Bit-sliced counts of three binary digits, each at most S (1 <= S <= 7).
-// sat3: count == S (for a count <= S, the AND of the digits S has set).
-template <int S>
-__device__ __forceinline__ uint32_t sat3(uint32_t b0, uint32_t b1, uint32_t b2)
+// Bit-sliced counts in ND binary digits (digit d of count s is bit s of word d),
+// each count at most S; ND is the bit width of S.
+constexpr int count_digits(int S) { return S < 2 ? 1 : 1 + count_digits(S >> 1); }
+
+// count == S (for a count <= S, the AND of the digits S has set)
+template <int S, int ND>
+__device__ __forceinline__ uint32_t sat_eq(const uint32_t (&c)[ND])
 {
     uint32_t r = ~0u;
-    if (S & 1) r &= b0;
-    if (S & 2) r &= b1;
-    if (S & 4) r &= b2;
+#pragma unroll
+    for (int d = 0; d < ND; d++)
+        if ((S >> d) & 1) r &= c[d];
     return r;
 }
 
-// min(a + b, S) for counts a, b <= S
-template <int S>
-__device__ __forceinline__ void sat_add3(uint32_t (&a)[3], const uint32_t (&b)[3])
+// count + 1 where inc is set (counts below S only: the caller masks inc)
+template <int ND>
+__device__ __forceinline__ void digits_inc(uint32_t (&c)[ND], uint32_t inc)
 {
-    const uint32_t s0 = a[0] ^ b[0], k0 = a[0] & b[0];
-    const uint32_t s1 = a[1] ^ b[1] ^ k0, k1 = __builtin_amdgcn_bitop3_b32(a[1], b[1], k0, 0xE8);   // majority
-    const uint32_t s2 = a[2] ^ b[2] ^ k1, k2 = __builtin_amdgcn_bitop3_b32(a[2], b[2], k1, 0xE8);
-    // ge: the 4-bit sum (k2 s2 s1 s0) >= S, from the low digit up
+#pragma unroll
+    for (int d = 0; d < ND; d++) {
+        const uint32_t k = c[d] & inc;
+        c[d] ^= inc;
+        inc = k;
+    }
+}
+
+// min(a + b, S) for counts a, b <= S
+template <int S, int ND>
+__device__ __forceinline__ void sat_add(uint32_t (&a)[ND], const uint32_t (&b)[ND])
+{
+    uint32_t sum[ND];
+    uint32_t k = 0u;                      // carry into digit d
+#pragma unroll
+    for (int d = 0; d < ND; d++) {
+        sum[d] = a[d] ^ b[d] ^ k;
+        k = __builtin_amdgcn_bitop3_b32(a[d], b[d], k, 0xE8);   // majority
+    }
+    // ge: the (ND+1)-digit sum (k sum) >= S, from the low digit up
     uint32_t ge = ~0u;
-    ge = (S & 1) ? (s0 & ge) : (s0 | ge);
-    ge = (S & 2) ? (s1 & ge) : (s1 | ge);
-    ge = (S & 4) ? (s2 & ge) : (s2 | ge);
-    ge |= k2;
-    a[0] = (S & 1) ? (s0 | ge) : (s0 & ~ge);
-    a[1] = (S & 2) ? (s1 | ge) : (s1 & ~ge);
-    a[2] = (S & 4) ? (s2 | ge) : (s2 & ~ge);
+#pragma unroll
+    for (int d = 0; d < ND; d++) ge = ((S >> d) & 1) ? (sum[d] & ge) : (sum[d] | ge);
+    ge |= k;
+#pragma unroll
+    for (int d = 0; d < ND; d++) a[d] = ((S >> d) & 1) ? (sum[d] | ge) : (sum[d] & ~ge);
 }
 
 template <int E, int LPG, int CPI, bool DB = false>
@@ -81,9 +98,9 @@ struct TileSweep {
     static constexpr int EC = (E + B - 1) / B;
     // DB: instead of a thermometer updated by every lane at every column, each
     // column's OR word goes to dead[j] in LDS, and at the end the group's LPG
-    // lanes count a share of the columns each (saturating binary digits) and add
-    // the shares up through DPP (finish)
-    static_assert(!DB || (E + 1 <= 7 && LPG == 4), "counted words: E <= 6, four lanes per group");
+    // lanes count a share of the columns each (binary digits saturating at
+    // E + 1) and add the shares up through DPP (finish)
+    static_assert(!DB || LPG == 4, "counted words: four lanes per group");
     uint32_t S[SL];
     uint32_t Tm[DB ? 1 : E + 1];
     uint32_t* dead = nullptr;                 // DB: this group's column words
@@ -140,26 +157,23 @@ struct TileSweep {
     {
         if constexpr (DB) {
             constexpr int SAT = E + 1;
+            constexpr int ND = count_digits(SAT);
             tile::WaveSync()();               // the column words stored above, before they are read
-            uint32_t c[3] = {0u, 0u, 0u};     // count of columns with no row free, saturating at E + 1
+            uint32_t c[ND];                   // count of columns with no row free, saturating at E + 1
+#pragma unroll
+            for (int d = 0; d < ND; d++) c[d] = 0u;
             const int q = (m + LPG - 1) / LPG;
             const int j1 = min(m, (h + 1) * q);
-            for (int j = h * q; j < j1; j++) {
-                const uint32_t inc = ~dead[j] & ~sat3<SAT>(c[0], c[1], c[2]);
-                const uint32_t k0 = c[0] & inc;
-                c[0] ^= inc;
-                c[2] = __builtin_amdgcn_bitop3_b32(c[2], c[1], k0, 0x78);   // c2 ^ (c1 & k0)
-                c[1] ^= k0;
-            }
-            uint32_t o[3];
+            for (int j = h * q; j < j1; j++) digits_inc<ND>(c, ~dead[j] & ~sat_eq<SAT, ND>(c));
+            uint32_t o[ND];
 #pragma unroll
-            for (int k = 0; k < 3; k++) o[k] = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)c[k], 0xB1, 0xF, 0xF, false);
-            sat_add3<SAT>(c, o);
+            for (int d = 0; d < ND; d++) o[d] = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)c[d], 0xB1, 0xF, 0xF, false);
+            sat_add<SAT, ND>(c, o);
 #pragma unroll
-            for (int k = 0; k < 3; k++) o[k] = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)c[k], 0x4E, 0xF, 0xF, false);
-            sat_add3<SAT>(c, o);
+            for (int d = 0; d < ND; d++) o[d] = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)c[d], 0x4E, 0xF, 0xF, false);
+            sat_add<SAT, ND>(c, o);
             tile::WaveSync()();               // the reads above, before the group's next columns are stored
-            if (h == 0) write_digits<3>(c, ~sat3<SAT>(c[0], c[1], c[2]), g, n_pairs, out);
+            if (h == 0) write_digits<ND>(c, ~sat_eq<SAT, ND>(c), g, n_pairs, out);
         } else {
             if (h == 0) write_group<E>(Tm, g, n_pairs, out);
         }

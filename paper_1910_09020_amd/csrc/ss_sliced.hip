@@ -112,6 +112,8 @@ hipError_t launch_sliced_hi(int E, const uint32_t* packed, int64_t n, int32_t m,
                            hipStream_t s);
 hipError_t launch_fused_lo(int E, const uint8_t* reads, const uint8_t* refs, int64_t n, int32_t m, int T, int GB,
                           int U, int fast, size_t shmem, uint16_t* out, uint32_t* err, hipStream_t s);
+hipError_t launch_fused_mid(int E, const uint8_t* reads, const uint8_t* refs, int64_t n, int32_t m, int T, int GB,
+                           int U, int fast, size_t shmem, uint16_t* out, uint32_t* err, hipStream_t s);
 
 hipError_t launch_pack_sliced(const uint8_t* reads, const uint8_t* refs, const int64_t* offsets,
                               const int64_t* index, int64_t n_pairs, int32_t m, uint32_t* packed,
@@ -222,7 +224,8 @@ hipError_t launch_fused(const uint8_t* reads, const uint8_t* refs, int64_t n_pai
     if (shmem == 0) return hipErrorInvalidValue;
     const int fast = U > 0 ? tile::fast_mode(m, U, true, tile::kWaveQ, 64)
                            : tile::fast_mode(m, GB, contiguous, tile::kFusedQ, tile::kFusedThreads);
-    return launch_fused_lo(E, reads, refs, n_pairs, m, T, GB, U, fast, shmem, out, err, s);
+    if (E <= 5) return launch_fused_lo(E, reads, refs, n_pairs, m, T, GB, U, fast, shmem, out, err, s);
+    return launch_fused_mid(E, reads, refs, n_pairs, m, T, GB, U, fast, shmem, out, err, s);
 }
 
 }  // namespace ss

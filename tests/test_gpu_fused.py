@@ -143,7 +143,7 @@ def test_argument_errors(rt):
 
 def test_unaligned_bases_take_the_byte_path(rt):
     """Inputs that start 1 byte past a 16-byte boundary cannot use the vector-load path; the result
-    must not change (fused schedule at E <= 5, chunked above)."""
+    must not change (fused schedule at E <= 10, chunked above)."""
     import torch
     import paper_1910_09020_amd as ss
     b = gen.make(1, n=5000 + 3)
