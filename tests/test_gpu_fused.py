@@ -179,7 +179,9 @@ def test_many_tiles_per_block(rt, aligned):
     rd[off:off + n * m].copy_(torch.from_numpy(b["reads"]))
     rf[off:off + n * m].copy_(torch.from_numpy(b["refs"]))
     err = torch.zeros(1, dtype=torch.int32, device=d)
-    for E in (0, 3, 5):
+    # E = 0: one row; 3, 5, 6: column words counted in three binary digits (wave mode), 7 and 10 in
+    # four; block mode counts every threshold with the per-column thermometer
+    for E in (0, 3, 5, 6, 7, 10):
         exp = want(b, E)
         for tile in (1, 2, 6):
             say(f"  fused n={n} E={E} tile_groups={tile} aligned={aligned}")
@@ -188,3 +190,20 @@ def test_many_tiles_per_block(rt, aligned):
             torch.cuda.synchronize()
             assert int(err.item()) == 0
             check(f"E={E} tile={tile} aligned={aligned}", rt.results_numpy(out, n), exp)
+
+
+@pytest.mark.parametrize("E", [6, 8, 10])
+def test_block_mode_above_five(rt, E):
+    """Pairs of 250 bp with an explicit tile take the fused kernel's block mode (the three encoding
+    wavefronts share barriers with the sweeping one); at thresholds above 5 its count is the
+    per-column thermometer.  Every pair must equal the oracle's result."""
+    import torch
+    b = uniform(250, 24 * 32 * 3 + 11, seed=250 + E)
+    db = rt.DeviceBatch(b)
+    exp = want(b, E)
+    for tile in (1, 8):
+        say(f"  fused n={db.n} m=250 E={E} tile_groups={tile}")
+        out = db.filter_fused(E, tile_groups=tile)
+        torch.cuda.synchronize()
+        db.check_err(f"fused m=250 E={E} tile={tile}")
+        check(f"m=250 E={E} tile={tile}", rt.results_numpy(out, db.n), exp)
