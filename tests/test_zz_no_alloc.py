@@ -32,8 +32,9 @@ def _device(torch, b, off=0):
 
 
 @pytest.mark.parametrize("m,E,n1,n2,off", [
-    (100, 7, 1_500_007, 60_013, 0),     # two kernels over scratch chunks (several chunks, then one)
+    (100, 11, 1_500_007, 60_013, 0),    # two kernels over scratch chunks (several chunks, then one)
     (100, 3, 400_000, 5_000, 0),        # fused kernel, no scratch
+    (100, 8, 300_000, 4_001, 0),        # fused kernel above E = 5 (four count digits)
     (250, 4, 300_001, 20_000, 0),       # aligned 250 bp: the chunked schedule
     (100, 5, 200_000, 33, 1),           # unaligned inputs: the fused kernel
 ])
