@@ -144,11 +144,11 @@ extern "C" int ss_filter_sliced_async(ss_ctx* ctx, const uint32_t* packed, int64
 // Thresholds up to kMaxEFused (up to 10% of a 100 bp read) run the fused
 // kernel; above it (and for aligned pairs longer than the fused kernel's wave
 // mode takes) encode and sweep run as two kernels over chunks of packed data.
-// Chunk size, measured on 10 M x 250 bp and 30 M x 100 bp: at E <= 5 the sweep
-// is bound by memory and a 192 MB chunk, which stays in the device's 256 MB
-// cache between the two kernels, is 6-8% faster than 400 MB; at higher E the
-// sweep is bound by VALU, and each extra launch's partly filled last wave
-// costs more than the cache saves (E = 25: 400 MB 2.06 ms, 192 MB 2.29 ms).
+// Chunk size, measured on 10 M x 250 bp and 30 M x 100 bp: up to E = 8 the
+// sweep is light and a 192 MB chunk, which stays in the device's 256 MB cache
+// between the two kernels, is 4-8% faster than 400 MB; from E = 9 the sweep's
+// VALU work grows and each extra launch's partly filled last wave costs more
+// than the cache saves (E = 10: 1.70 -> 1.73 ms, E = 25: 2.06 -> 2.29 ms).
 constexpr int64_t kChunkPackedBytes = 400ll << 20;
 constexpr int64_t kChunkPackedBytesLowE = 192ll << 20;
 
@@ -173,7 +173,7 @@ extern "C" int ss_filter_ascii_async(ss_ctx* ctx, const uint8_t* reads, const ui
         return map_err(launch_fused(reads, refs, n_pairs, m, E, tile_groups, out, err, s));
     // chunks of whole groups; slot offsets keep the encoder's and the sweep's alignment
     const int64_t per_pair = std::max<int64_t>(1, ss_sliced_bytes(32, m) / 32);
-    const int64_t chunk_bytes = E <= 5 ? kChunkPackedBytesLowE : kChunkPackedBytes;
+    const int64_t chunk_bytes = E <= 8 ? kChunkPackedBytesLowE : kChunkPackedBytes;
     const int64_t chunk = std::min<int64_t>(n_pairs, std::max<int64_t>(32, (chunk_bytes / per_pair) / 32 * 32));
     SS_TRY(ctx->chunk.ensure((size_t)ss_sliced_bytes(chunk, m)));
     for (int64_t s0 = 0; s0 < n_pairs; s0 += chunk) {
