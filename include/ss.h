@@ -190,8 +190,8 @@ int ss_filter_submaze_async(ss_ctx* ctx, const uint32_t* packed, int64_t n_pairs
  *            With tile_groups = 0 and 16-byte aligned reads and refs the
  *            fused kernel runs only in the first form (m <= 224); longer
  *            aligned pairs take the two kernels below, which are faster there.
- *   E > 10 : the two kernels over chunks of packed data (192 MB at E <= 8,
- *            for the longer aligned pairs above; 400 MB otherwise), kept
+ *   E > 10 (and the longer aligned pairs above): the two kernels over
+ *            chunks of packed data (192 MB up to E = 8, 400 MB above), kept
  *            in a buffer owned by ctx (allocated on first use, grown when a
  *            longer m needs it): calls that take this schedule on one context
  *            must be ordered (one stream), or use one context per stream.
