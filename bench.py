@@ -128,7 +128,8 @@ def verify_leg(torch, runner, db, out, n, E, steps):
 
 def sweep_leg(torch, ss, gen, runner, config, Es, steps, batch=None, plain_and_wave=False):
     """Threshold sweep on one resident batch: the two-kernel path encodes once and sweeps each E;
-    the one-call path (fused up to E = 5, chunked above) runs per E.  plain_and_wave: also the
+    the one-call path (fused up to E = 10, chunked above) runs per E; and the range call sweeps every E
+    with thresholds sharing passes over the planes (outputs checked equal).  plain_and_wave: also the
     one-pair-per-lane kernel and the wavefront-cooperative kernel on the bit-stream encoding, per E,
     with outputs checked equal to the sweep's.  Mean ms per launch."""
     b = batch if batch is not None else gen.make(config, threads=min(16, os.cpu_count() or 1))
@@ -141,14 +142,18 @@ def sweep_leg(torch, ss, gen, runner, config, Es, steps, batch=None, plain_and_w
     torch.cuda.synchronize()
     _, (enc_ms,) = timed_loop([lambda: db.pack_sliced(packed=packed)], steps, torch)
     ps = db.pack_stream() if plain_and_wave else None
+    rng = db.filter_sliced_range(packed, Es[0], Es[-1])
+    torch.cuda.synchronize()
     per_E = {}
     same = True
     same_pw = True
+    same_rng = True
     for E in Es:
         db.filter_sliced(packed, E, out=out)
         db.filter_fused(E, out=out1)
         torch.cuda.synchronize()
         same = same and bool(torch.equal(out, out1))
+        same_rng = same_rng and bool(torch.equal(out, rng[E - Es[0], :n]))
         _, (sw_ms, one_ms) = timed_loop([lambda: db.filter_sliced(packed, E, out=out),
                                          lambda: db.filter_fused(E, out=out1)], steps, torch)
         per_E[E] = dict(sweep_ms=round(sw_ms, 4), one_call_ms=round(one_ms, 4))
@@ -162,21 +167,27 @@ def sweep_leg(torch, ss, gen, runner, config, Es, steps, batch=None, plain_and_w
             _, (pl_ms, wv_ms) = timed_loop([lambda: db.filter_plain(ps, E, out=out1),
                                             lambda: db.filter_wave(ps, E, out=out1)], steps, torch)
             per_E[E].update(plain_ms=round(pl_ms, 4), wave_ms=round(wv_ms, 4))
+    _, (rng_ms,) = timed_loop([lambda: db.filter_sliced_range(packed, Es[0], Es[-1], out=rng)], steps, torch)
     db.check_err(f"sweep config {config}")
     total_sweep = enc_ms + sum(v["sweep_ms"] for v in per_E.values())
     log(f"sweep config {config} ({n} x {m} bp): encode {enc_ms:.3f} ms, E={Es[0]}..{Es[-1]} "
-        f"sweeps {sum(v['sweep_ms'] for v in per_E.values()):.3f} ms, identical={same}")
+        f"sweeps {sum(v['sweep_ms'] for v in per_E.values()):.3f} ms, identical={same}; "
+        f"range call {rng_ms:.3f} ms, identical={same_rng}")
     res = dict(n_pairs=n, m=m, encode_ms=round(enc_ms, 4), per_E=per_E,
                whole_sweep_ms=round(total_sweep, 4),
                whole_sweep_pair_thresholds_per_s=n * len(Es) / (1e-3 * total_sweep),
-               one_call_equals_two_kernel=same)
+               one_call_equals_two_kernel=same,
+               range_call=dict(entry="ss_filter_sliced_range_async", ms=round(rng_ms, 4),
+                               identical_to_per_E=same_rng,
+                               whole_sweep_ms=round(enc_ms + rng_ms, 4),
+                               pair_thresholds_per_s=n * len(Es) / (1e-3 * (enc_ms + rng_ms))))
     if plain_and_wave:
         pl = sum(v["plain_ms"] for v in per_E.values())
         wv = sum(v["wave_ms"] for v in per_E.values())
         res.update(plain_all_E_ms=round(pl, 4), wave_all_E_ms=round(wv, 4), plain_and_wave_identical=same_pw)
         log(f"sweep config {config}: one pair per lane {pl:.3f} ms, wavefront-cooperative {wv:.3f} ms over "
             f"E={Es[0]}..{Es[-1]} on the bit stream, identical={same_pw}")
-    del db, packed, out, out1, ps
+    del db, packed, out, out1, ps, rng
     torch.cuda.empty_cache()
     return res
 

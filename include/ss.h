@@ -163,6 +163,20 @@ int ss_pack_sliced_async(ss_ctx* ctx, const uint8_t* reads, const uint8_t* refs,
 int ss_filter_sliced_async(ss_ctx* ctx, const uint32_t* packed, int64_t n_pairs, int32_t m,
                            int32_t E, uint16_t* out, void* stream);
 
+/* Filter a lane-sliced buffer at every threshold E_lo..E_hi (0 <= E_lo <=
+ * E_hi <= SS_MAX_E_SLICED; a threshold sweep as in the paper's evaluation):
+ * the result words of threshold E go to out + (E - E_lo) * out_stride
+ * (device; n_pairs words each, in slot order), each equal to
+ * ss_filter_sliced_async's at that threshold (Equation 1 rows, Section 2.4
+ * walk).  Runs of thresholds that fit one kernel's registers (0..4 and
+ * 5..7) share one pass over the buffer, every threshold keeping its own row
+ * states and count over the same loaded words; the others take a pass each.
+ *   out        : 16-byte aligned; out_stride >= n_pairs, a multiple of 8
+ *   SS_EINVAL for a bad argument or alignment, SS_ELEN for E_hi or m past
+ *   the limits.  Asynchronous on stream. */
+int ss_filter_sliced_range_async(ss_ctx* ctx, const uint32_t* packed, int64_t n_pairs, int32_t m, int32_t E_lo,
+                                 int32_t E_hi, uint16_t* out, int64_t out_stride, void* stream);
+
 /* Snake-on-Chip's decomposition (Section 2.5) over a lane-sliced buffer: the
  * maze is cut into non-overlapping sub-mazes of sub_width columns (>= 1; the
  * last may be narrower) solved independently by the same walk, each starting

@@ -76,6 +76,7 @@ def lib():
         "ss_stream_words": ([i64], i64),
         "ss_pack_sliced_async": ([vp, vp, vp, vp, vp, i64, i32, vp, vp, vp], ctypes.c_int),
         "ss_filter_sliced_async": ([vp, vp, i64, i32, i32, vp, vp], ctypes.c_int),
+        "ss_filter_sliced_range_async": ([vp, vp, i64, i32, i32, i32, vp, i64, vp], ctypes.c_int),
         "ss_filter_ascii_async": ([vp, vp, vp, i64, i32, i32, i32, vp, vp, vp], ctypes.c_int),
         "ss_verify_async": ([vp, vp, i64, vp, vp, vp, i64, i32, vp, vp], ctypes.c_int),
         "ss_verify_banded_async": ([vp, vp, i64, vp, vp, vp, i32, vp, i64, vp, vp], ctypes.c_int),
@@ -140,7 +141,8 @@ def exported_symbols():
             "ss_server_stats", "ss_server_destroy", "ss_server_footprint", "ss_server_set_slices", "ss_pack_words",
             "ss_pack", "ss_filter_batch_ex", "ss_filter_batch_pairs", "ss_filter_ascii_noalloc",
             "ss_server_stages", "ss_server_create_loop", "ss_verify_banded_async", "ss_server_set_loop_idle",
-            "ss_server_stage_alloc", "ss_server_stage_free", "ss_server_submit_staged"]
+            "ss_server_stage_alloc", "ss_server_stage_free", "ss_server_submit_staged",
+            "ss_filter_sliced_range_async"]
 
 
 def status_str(status: int) -> str:
@@ -243,6 +245,12 @@ def ss_stream_words(total_bases: int) -> int:
 def ss_pack_sliced_async(ctx, reads, refs, offsets, index, n_pairs, m, packed, err, stream=None):
     _check(lib().ss_pack_sliced_async(ctx, _ptr(reads), _ptr(refs), _ptr(offsets), _ptr(index), int(n_pairs),
                                       int(m), _ptr(packed), _ptr(err), _stream(stream)), "ss_pack_sliced_async")
+
+
+def ss_filter_sliced_range_async(ctx, packed, n_pairs, m, E_lo, E_hi, out, out_stride, stream=None):
+    _check(lib().ss_filter_sliced_range_async(ctx, _ptr(packed), int(n_pairs), int(m), int(E_lo), int(E_hi),
+                                              _ptr(out), int(out_stride), _stream(stream)),
+           "ss_filter_sliced_range_async")
 
 
 def ss_filter_sliced_async(ctx, packed, n_pairs, m, E, out, stream=None):

@@ -141,6 +141,30 @@ extern "C" int ss_filter_sliced_async(ss_ctx* ctx, const uint32_t* packed, int64
     return map_err(launch_sliced(packed, n_pairs, m, E, out, (hipStream_t)stream));
 }
 
+extern "C" int ss_filter_sliced_range_async(ss_ctx* ctx, const uint32_t* packed, int64_t n_pairs, int32_t m,
+                                            int32_t E_lo, int32_t E_hi, uint16_t* out, int64_t out_stride,
+                                            void* stream)
+{
+    if (!ctx || n_pairs < 0 || m < 0 || E_lo < 0 || E_hi < E_lo || out_stride < n_pairs) return SS_EINVAL;
+    if (E_hi > SS_MAX_E_SLICED || m > SS_MAX_LEN) return SS_ELEN;
+    if (n_pairs == 0) return SS_OK;
+    if (!out || (m > 0 && !packed)) return SS_EINVAL;
+    if ((((uintptr_t)packed | (uintptr_t)out) & 15u) != 0 || (out_stride & 7) != 0) return SS_EINVAL;
+    const hipStream_t s = (hipStream_t)stream;
+    for (int E = E_lo; E <= E_hi;) {
+        uint16_t* o = out + (int64_t)(E - E_lo) * out_stride;
+        const int span = sliced_multi_span(E);
+        if (span > 0 && E + span - 1 <= E_hi) {
+            SS_TRY(launch_sliced_multi_group(E, packed, n_pairs, m, o, out_stride, s));
+            E += span;
+        } else {
+            SS_TRY(launch_sliced(packed, n_pairs, m, E, o, s));
+            E++;
+        }
+    }
+    return SS_OK;
+}
+
 // Thresholds up to kMaxEFused (up to 10% of a 100 bp read) run the fused
 // kernel; above it (and for aligned pairs longer than the fused kernel's wave
 // mode takes) encode and sweep run as two kernels over chunks of packed data.

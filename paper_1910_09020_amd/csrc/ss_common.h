@@ -25,6 +25,11 @@ hipError_t launch_pack_sliced(const uint8_t* reads, const uint8_t* refs, const i
 // sub_width > 0: Snake-on-Chip sub-mazes of that many columns (Section 2.5)
 hipError_t launch_sliced(const uint32_t* packed, int64_t n_pairs, int32_t m, int32_t E, uint16_t* out,
                          hipStream_t s, int sub_width = 0);
+// Several thresholds in one pass: sliced_multi_span(E) thresholds from E (0 when no pass starts
+// at E); launch_sliced_multi_group writes threshold E+k's results at out + k * out_stride.
+int sliced_multi_span(int E_first);
+hipError_t launch_sliced_multi_group(int E_first, const uint32_t* packed, int64_t n_pairs, int32_t m, uint16_t* out,
+                                     int64_t out_stride, hipStream_t s);
 // Fused encode + sweep of pairs stored back to back (pair i at byte i*m).
 // tile_groups: groups of 32 pairs per block (0: automatic).
 hipError_t launch_fused(const uint8_t* reads, const uint8_t* refs, int64_t n_pairs, int32_t m, int32_t E,

@@ -9,8 +9,8 @@ import numpy as np
 import torch
 
 from . import (ss_create, ss_filter_ascii_async, ss_filter_submaze_async, ss_select_accepted_async, ss_verify_async,
-               ss_verify_banded_async, ss_filter_plain_async, ss_filter_sliced_async, ss_filter_wave_async,
-               ss_pack_sliced_async, ss_pack_stream_async, ss_sliced_bytes, ss_stream_words)
+               ss_verify_banded_async, ss_filter_plain_async, ss_filter_sliced_async, ss_filter_sliced_range_async,
+               ss_filter_wave_async, ss_pack_sliced_async, ss_pack_stream_async, ss_sliced_bytes, ss_stream_words)
 
 _ctx = {}
 
@@ -113,6 +113,16 @@ class DeviceBatch:
         out = self.new_out(n) if out is None else out
         ss_filter_sliced_async(context(self.device), packed, n, m, E, out,
                                stream or torch.cuda.current_stream(self.device))
+        return out
+
+    def filter_sliced_range(self, packed, E_lo: int, E_hi: int, out=None, stream=None) -> torch.Tensor:
+        """Results of every threshold E_lo..E_hi: row E - E_lo of the returned (E_hi - E_lo + 1, stride)
+        tensor holds threshold E's n result words."""
+        stride = (self.n + 7) // 8 * 8
+        if out is None:
+            out = torch.empty((E_hi - E_lo + 1, stride), dtype=torch.int16, device=_dev(self.device))
+        ss_filter_sliced_range_async(context(self.device), packed, self.n, self.uniform_m, E_lo, E_hi, out, stride,
+                                     stream or torch.cuda.current_stream(self.device))
         return out
 
     def filter_submaze(self, packed, E: int, sub_width: int, out=None, stream=None) -> torch.Tensor:

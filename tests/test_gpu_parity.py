@@ -4,6 +4,7 @@ The bar is bit-exact equality of the accept bit and the reported obstacle
 count (integer arithmetic only).  Inputs are the seeded workloads of
 ``paper_1910_09020_amd.gen`` plus hand-made edge cases.
 """
+import ctypes
 import sys
 
 import numpy as np
@@ -45,6 +46,20 @@ def check(name, got, want):
     wa, we = want
     bad = np.nonzero((ga != wa) | (ge != we))[0]
     assert len(bad) == 0, f"{name}: {len(bad)} mismatches, first {bad[:5]} got {ge[bad[:5]]} want {we[bad[:5]]}"
+
+
+def uniform_batch(m, n, seed):
+    """n pairs of length m: references with ~6% substitutions, every fifth one unrelated."""
+    rng = np.random.default_rng(seed)
+    A = np.frombuffer(b"ACGT", np.uint8)
+    reads = rng.choice(A, size=n * m)
+    refs = reads.copy()
+    flip = rng.random(n * m) < 0.06
+    refs[flip] = rng.choice(A, size=int(flip.sum()))
+    for p in range(0, n, 5):
+        refs[p * m:(p + 1) * m] = rng.choice(A, size=m)
+    return dict(n=n, reads=reads, refs=refs, offsets=np.arange(n, dtype=np.int64) * m,
+                lengths=np.full(n, m, np.int32), E=None)
 
 
 def run_all(rt, b, E, kernels=("sliced", "fused", "plain", "wave")):
@@ -298,3 +313,46 @@ def test_host_api_pipelined_bad_base_in_last_chunk(rt):
     # the context is usable afterwards
     a2, e2 = ss.ss_filter_batch(b["reads"], b["refs"], b["lengths"], 5)
     check("after the error", (a2, e2), expect(b, E=5))
+
+
+@pytest.mark.parametrize("m", [1, 7, 33, 100, 129, 250])
+def test_sliced_range_matches_each_threshold(rt, m):
+    """ss_filter_sliced_range_async: thresholds sharing a pass (0..4, 5..7) and those that take
+    their own must give each threshold's ss_filter_sliced_async result and the oracle's, over ranges
+    that start and end inside a shared run."""
+    import torch
+    b = uniform_batch(m, 24 * 32 * 2 + 13, seed=900 + m)
+    db = rt.DeviceBatch(b)
+    pk = db.pack_sliced()
+    for lo, hi in ((0, 10), (0, 25), (3, 9), (5, 7), (0, 4), (6, 12), (11, 13), (4, 4)):
+        say(f"  range n={db.n} m={m} E={lo}..{hi}")
+        rng = db.filter_sliced_range(pk, lo, hi)
+        torch.cuda.synchronize()
+        for E in range(lo, hi + 1):
+            one = db.filter_sliced(pk, E)
+            torch.cuda.synchronize()
+            assert torch.equal(rng[E - lo, :db.n], one[:db.n]), f"m={m} E={E} range {lo}..{hi}"
+    for E in (0, 2, 4, 5, 7, 9):
+        rng = db.filter_sliced_range(pk, E, E if E not in (0, 5) else {0: 4, 5: 7}[E])
+        torch.cuda.synchronize()
+        check(f"range m={m} E={E}", rt.results_numpy(rng[0], db.n), expect(b, E=E))
+
+
+def test_sliced_range_argument_errors(rt):
+    import torch
+    import paper_1910_09020_amd as ss
+    L = ss.lib()
+    ctx = rt.context(0)
+    pk = torch.zeros(1 << 16, dtype=torch.int32, device="cuda")
+    out = torch.zeros(4096, dtype=torch.int16, device="cuda")
+    p = lambda t, off=0: ctypes.c_void_p(t.data_ptr() + off)
+    call = lambda n, m, lo, hi, stride, off=0: L.ss_filter_sliced_range_async(ctx, p(pk), n, m, lo, hi, p(out, off),
+                                                                           stride, None)
+    assert call(0, 100, 0, 10, 0) == ss.SS_OK
+    assert call(100, 100, 3, 2, 104) == ss.SS_EINVAL      # empty range
+    assert call(100, 100, -1, 2, 104) == ss.SS_EINVAL
+    assert call(100, 100, 0, 33, 104) == ss.SS_ELEN       # past the sweep's threshold limit
+    assert call(100, 100, 0, 2, 96) == ss.SS_EINVAL       # stride below n_pairs
+    assert call(100, 100, 0, 2, 101) == ss.SS_EINVAL      # stride not a multiple of 8
+    assert call(100, 100, 0, 2, 104, off=2) == ss.SS_EINVAL   # misaligned output
+    torch.cuda.synchronize()
